@@ -1,0 +1,227 @@
+/*
+ * mpcg.h -- C ABI of the MI355X (gfx950) mixed-precision conjugate-gradient
+ * library.
+ *
+ * Method: conjugate gradients for Ax = b with A sparse symmetric positive
+ * definite (paper section 3, updates of x, r, p and the alpha/beta formulas),
+ * where each iteration's SpMV, inner products and vector updates run in a
+ * precision chosen per iteration by a policy (section 4.2 assigns precisions to
+ * the matrix-vector product and the inner products; here the controlled triple is
+ * {SpMV, dot, axpy}).  alpha, beta, the residual replacement and the convergence
+ * test are fp64.  Policies: fixed, the tabular Q-learning policy of section 4.1
+ * (greedy inference as Algorithm 2, epsilon-greedy training as Algorithm 1), and
+ * an MLP policy.
+ *
+ * Conventions for every entry point:
+ *   - Return value: MPCG_OK (0) or a negative error code; a solve returns its
+ *     convergence status through mpcg_result.status.  No C++ exception crosses
+ *     this boundary.  mpcg_last_error() gives a message for the calling thread.
+ *   - "device pointer": memory allocated on the GPU the library runs on (e.g. a
+ *     torch tensor's data_ptr()).  "host pointer": ordinary CPU memory.
+ *   - Handles are not thread-safe.  All work of a matrix handle is enqueued on
+ *     the stream given at creation, in order; entry points that return host data
+ *     synchronise that stream before returning.
+ *   - The library never frees caller memory; handles own what they allocate.
+ *   - Formats: MPCG_FP16 = 0, MPCG_BF16 = 1, MPCG_FP32 = 2, MPCG_FP64 = 3.
+ *     An action is a = 16*f_spmv + 4*f_dot + f_axpy  (0..63).
+ *   - Vector "tier": vectors of an iteration whose axpy format is fp64 are stored
+ *     as double, otherwise as float (tier64 = 1 / 0).
+ */
+#ifndef MPCG_H
+#define MPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPCG_OK 0
+#define MPCG_ERR_INVALID (-1)     /* bad argument (NULL, size, enum)            */
+#define MPCG_ERR_CSR (-2)         /* malformed CSR input                        */
+#define MPCG_ERR_DEVICE (-3)      /* HIP runtime error                          */
+#define MPCG_ERR_NOMEM (-4)       /* device or host allocation failed           */
+
+/* mpcg_result.status */
+#define MPCG_CONVERGED 0          /* true fp64 relative residual <= tol          */
+#define MPCG_MAXIT 1              /* iteration budget exhausted                  */
+#define MPCG_CONVERGED_FALLBACK 2 /* converged after the fp64 fallback restart   */
+#define MPCG_BREAKDOWN 3          /* breakdown (nu <= 0 or non-finite scalars)   */
+
+#define MPCG_FP16 0
+#define MPCG_BF16 1
+#define MPCG_FP32 2
+#define MPCG_FP64 3
+
+#define MPCG_MEM_HOST 0
+#define MPCG_MEM_DEVICE 1
+
+#define MPCG_POLICY_FIXED 0       /* one action every iteration                  */
+#define MPCG_POLICY_QTABLE 1      /* greedy over a Q-table (Algorithm 2)         */
+#define MPCG_POLICY_QTABLE_TRAIN 2/* epsilon-greedy + Q-learning (Algorithm 1)   */
+#define MPCG_POLICY_MLP 3         /* greedy over MLP logits                      */
+
+/* history flag bits (per iteration) */
+#define MPCG_FLAG_REPLACED 1
+#define MPCG_FLAG_EXPLORED 2
+#define MPCG_FLAG_FALLBACK 4
+#define MPCG_FLAG_SWITCH 8
+
+#define MPCG_MLP_IN 16
+#define MPCG_MLP_HIDDEN 128
+#define MPCG_N_ACTIONS 64
+
+typedef struct mpcg_matrix mpcg_matrix;
+typedef struct mpcg_policy mpcg_policy;
+
+/*
+ * Policy description (section 4.1).  State s = (j*b_it + i)*2 + stag with the
+ * iteration bin i = min(k / ceil(t_bin/b_it), b_it-1), the residual bin
+ * j = #{ t : rho <= res_edges[t] } over the b_res-1 decreasing thresholds, and
+ * stag = [k >= w_stag and rho_k >= rho_{k-w_stag}].  Reward (section 4.1):
+ * w1*min(-log10 rho', -log10 eps_min) - w2*(c[f_s]+c[f_d]+c[f_a]) + w3 on
+ * convergence; a breakdown ends the episode with -w2*cost - w3.  Q update:
+ * Q += lr*(R + gamma*max Q(s',.) - Q) (terminal: without the max term).
+ */
+typedef struct {
+    int32_t kind;              /* MPCG_POLICY_*                                  */
+    int32_t fixed_action;      /* used by MPCG_POLICY_FIXED                      */
+    int32_t t_bin;             /* iteration-bin horizon (1000)                   */
+    int32_t b_it;              /* iteration bins (5)                             */
+    int32_t b_res;             /* residual bins (10), <= 17                      */
+    int32_t w_stag;            /* stagnation window (10)                         */
+    double res_edges[16];      /* b_res-1 thresholds, strictly decreasing        */
+    double lr, gamma;          /* Q-learning rate and discount (0.1, 0.9)        */
+    double w1, w2, w3;         /* reward weights (1.0, 0.1, 10.0)                */
+    double eps_min;            /* residual floor of the accuracy term (1e-16)    */
+    double cost[4];            /* c(fp16), c(bf16), c(fp32), c(fp64)             */
+    uint64_t seed;             /* exploration draws                              */
+    int32_t replace_period;    /* R seen by the MLP features                     */
+    int32_t reserved;
+} mpcg_policy_desc;
+
+typedef struct {
+    int32_t replace_period;    /* R: true-residual replacement every R iterations
+                                  (0: only when the recursive residual <= tol)  */
+    int32_t fallback;          /* 1: restart as fp64 CG on breakdown/stagnation */
+    int32_t chunk;             /* iterations enqueued between done-flag polls
+                                  (0: library default)                          */
+    int32_t reserved;
+} mpcg_solve_opts;
+
+typedef struct {
+    int32_t status;            /* MPCG_CONVERGED ... MPCG_BREAKDOWN              */
+    int32_t iters;             /* iterations performed                           */
+    int32_t n_replace;         /* true-residual replacements                     */
+    int32_t fallback_at;       /* iteration of the fp64 fallback, -1 if none     */
+    double relres_true;        /* ||b - A x||_2 / ||b||_2 in fp64, final x       */
+    double cost_sum;           /* sum over iterations of the policy's op costs   */
+    double time_ms;            /* device time from first enqueue to done         */
+    int32_t slots;             /* kernel slots enqueued (diagnostic)             */
+    int32_t reserved;
+} mpcg_result;
+
+/* ---------------------------------------------------------------- matrices */
+
+/*
+ * Copies a CSR matrix (row_ptr int32[n+1], col int32[nnz], val double[nnz]) to
+ * the device and builds the fp32, bf16 and fp16 shadows (fp16 with an exact
+ * power-of-two scale per row that puts the row's largest magnitude in
+ * (2^14, 2^15]; Table 1 ranges).  mem_kind says where the three arrays live
+ * (MPCG_MEM_HOST or MPCG_MEM_DEVICE).  stream: a hipStream_t (NULL: the null
+ * stream) on which this handle's work runs.  Validation: 1 <= n, nnz < 2^31,
+ * row_ptr[0] = 0, row_ptr[n] = nnz, row_ptr non-decreasing, 0 <= col < n,
+ * columns strictly increasing within a row, values finite, every row has a
+ * positive diagonal entry (host arrays only; device arrays are checked for
+ * sizes).  Error: MPCG_ERR_CSR with a message naming the first bad row.
+ */
+int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                    const double *val, int mem_kind, void *stream, mpcg_matrix **out);
+
+/* Frees the handle and everything it owns.  NULL is a no-op. */
+int mpcg_destroy(mpcg_matrix *A);
+
+/* Copies the shadows to host arrays: float[nnz], uint16 bf16 bits[nnz],
+ * uint16 fp16 bits[nnz] (row-scaled values), int8 row exponents[n]. */
+int mpcg_get_shadows(mpcg_matrix *A, float *f32, uint16_t *bf16, uint16_t *f16, int8_t *rexp);
+
+/* ---------------------------------------------------------------- policies */
+
+/* Creates a policy; Q-table (n_states x 64, zero) and rollout log live on the device. */
+int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out);
+int mpcg_policy_destroy(mpcg_policy *P);
+/* Host double[n_states*64] in/out, n_states = b_res*b_it*2. */
+int mpcg_policy_set_qtable(mpcg_policy *P, const double *q);
+int mpcg_policy_get_qtable(mpcg_policy *P, double *q);
+/* Episode index and exploration rate used by the next training solves. */
+int mpcg_policy_set_episode(mpcg_policy *P, int64_t episode, double epsilon);
+/* MLP weights, host float arrays: W1[128][16], b1[128], W2[128][128], b2[128],
+ * W3[64][128], b3[64].  Weights are used as given (bf16-representable values
+ * are expected; the decision path computes in fp32). */
+int mpcg_policy_set_mlp(mpcg_policy *P, const float *W1, const float *b1, const float *W2,
+                        const float *b2, const float *W3, const float *b3);
+/* Rollout log of (features, action, reward, done, next features) per decision,
+ * capacity entries on the device; 0 disables.  Appends across solves. */
+int mpcg_policy_rollouts_enable(mpcg_policy *P, int32_t capacity);
+int mpcg_policy_rollouts_count(mpcg_policy *P, int32_t *n);
+int mpcg_policy_get_rollouts(mpcg_policy *P, float *feat, float *next_feat, int32_t *act,
+                             float *rew, uint8_t *done, int32_t cap, int32_t *n_out);
+int mpcg_policy_rollouts_reset(mpcg_policy *P);
+/*
+ * Evaluates the policy's greedy decision on m given states, on the device:
+ * k[m] iteration, rho[m] relative residual, stag[m] flag, and for MLP policies
+ * feat[m][16] features (may be NULL otherwise).  Writes state[m] and action[m]
+ * (host arrays).  Used to check that decisions are bit-exact for identical states.
+ */
+int mpcg_policy_decide(mpcg_policy *P, int32_t m, const int64_t *k, const double *rho,
+                       const int32_t *stag, const float *feat, int32_t *state, int32_t *action);
+
+/* Attaches a policy (not owned; must outlive the solves).  NULL: fixed fp64. */
+int mpcg_set_policy(mpcg_matrix *A, mpcg_policy *P);
+int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *opts);
+
+/* ---------------------------------------------------------------- solves */
+
+/*
+ * Solves A x = b.  b (double[n]) and x (double[n]) are device pointers; x is
+ * read as the initial guess and overwritten with the result.  Stops when the
+ * true fp64 relative residual is <= tol (checked at each replacement), after
+ * maxit iterations, or on breakdown.  Runs on the handle's stream with no host
+ * synchronisation inside an iteration; returns after the solve is complete.
+ * res (host) receives the summary.  tol > 0 and maxit >= 0 are required.
+ */
+int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t maxit,
+               mpcg_result *res);
+
+/*
+ * History of the last solve, host arrays (any may be NULL):
+ *   rho[cap]     relative residual rho_k, k = 0..iters (the true one where replaced)
+ *   act[cap]     action of iteration k, k = 0..iters-1
+ *   flags[cap]   MPCG_FLAG_* of iteration k
+ *   rep_k[rep_cap], rep_rho[rep_cap]  iteration and true relres of each replacement
+ * n_hist (host int32, may be NULL) receives iters+1.
+ */
+int mpcg_get_history(mpcg_matrix *A, double *rho, uint8_t *act, uint8_t *flags, int32_t cap,
+                     int32_t *rep_k, double *rep_rho, int32_t rep_cap, int32_t *n_hist);
+
+/* ---------------------------------------------------------------- single ops
+ * The hot-path kernels one at a time, on the handle's stream (device pointers).
+ * p, q, u, v, y are float[n] (tier64 = 0) or double[n] (tier64 = 1).
+ */
+/* q = SpMV_f(A, p): row fma chain in CSR order, accumulated in fp32 (f <= 2) or
+ * fp64 (f = 3), output rounded to the tier. */
+int mpcg_op_spmv(mpcg_matrix *A, int fmt, int tier64, const void *p, void *q);
+/* *out (host) = dot_f(u, v): operands rounded to f, products in the accumulation
+ * format, pairwise sum over the zero-padded power-of-two length. */
+int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out);
+/* y = rd_f(fma(alpha, u, y)) (tier of f) */
+int mpcg_op_axpy(mpcg_matrix *A, int fmt, double alpha, const void *u, void *y);
+/* r (double[n], device) = b - A x in fp64 */
+int mpcg_op_residual(mpcg_matrix *A, const double *b, const double *x, double *r);
+
+const char *mpcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPCG_H */

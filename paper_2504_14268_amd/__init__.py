@@ -1,0 +1,298 @@
+"""Python binding of libmpcg.so (include/mpcg.h): argument marshalling only.
+
+Every step of the solver runs in the HIP kernels of the library; torch supplies
+device memory and the stream.  Importing this package does not need a GPU; any
+call that reaches the library raises if libmpcg.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from decimal import Decimal, getcontext
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpcg.so")
+
+FP16, BF16, FP32, FP64 = 0, 1, 2, 3
+FORMATS = {"fp16": FP16, "bf16": BF16, "fp32": FP32, "fp64": FP64}
+POLICY_FIXED, POLICY_QTABLE, POLICY_QTABLE_TRAIN, POLICY_MLP = 0, 1, 2, 3
+CONVERGED, MAXIT, CONVERGED_FALLBACK, BREAKDOWN = 0, 1, 2, 3
+FLAG_REPLACED, FLAG_EXPLORED, FLAG_FALLBACK, FLAG_SWITCH = 1, 2, 4, 8
+COSTS = {"C1": (0.8, 0.6, 1.0, 2.0), "C2": (0.5, 0.4, 1.5, 3.0)}
+
+
+def action(f_spmv: int, f_dot: int, f_axpy: int) -> int:
+    return 16 * f_spmv + 4 * f_dot + f_axpy
+
+
+def decode(a: int):
+    return (a >> 4) & 3, (a >> 2) & 3, a & 3
+
+
+class PolicyDesc(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("fixed_action", C.c_int32), ("t_bin", C.c_int32),
+        ("b_it", C.c_int32), ("b_res", C.c_int32), ("w_stag", C.c_int32),
+        ("res_edges", C.c_double * 16),
+        ("lr", C.c_double), ("gamma", C.c_double),
+        ("w1", C.c_double), ("w2", C.c_double), ("w3", C.c_double), ("eps_min", C.c_double),
+        ("cost", C.c_double * 4), ("seed", C.c_uint64),
+        ("replace_period", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("replace_period", C.c_int32), ("fallback", C.c_int32),
+                ("chunk", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("n_replace", C.c_int32),
+                ("fallback_at", C.c_int32), ("relres_true", C.c_double), ("cost_sum", C.c_double),
+                ("time_ms", C.c_double), ("slots", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libmpcg.so not built at {LIB_PATH}: run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.mpcg_last_error.restype = C.c_char_p
+        sig = {
+            "mpcg_create_csr": [i64, i64, vp, vp, vp, C.c_int, vp, C.POINTER(vp)],
+            "mpcg_destroy": [vp],
+            "mpcg_get_shadows": [vp, vp, vp, vp, vp],
+            "mpcg_policy_create": [C.POINTER(PolicyDesc), C.POINTER(vp)],
+            "mpcg_policy_destroy": [vp],
+            "mpcg_policy_set_qtable": [vp, vp],
+            "mpcg_policy_get_qtable": [vp, vp],
+            "mpcg_policy_set_episode": [vp, i64, d],
+            "mpcg_policy_set_mlp": [vp, vp, vp, vp, vp, vp, vp],
+            "mpcg_policy_rollouts_enable": [vp, i32],
+            "mpcg_policy_rollouts_count": [vp, C.POINTER(i32)],
+            "mpcg_policy_rollouts_reset": [vp],
+            "mpcg_policy_get_rollouts": [vp, vp, vp, vp, vp, vp, i32, C.POINTER(i32)],
+            "mpcg_policy_decide": [vp, i32, vp, vp, vp, vp, vp, vp],
+            "mpcg_set_policy": [vp, vp],
+            "mpcg_set_options": [vp, C.POINTER(SolveOpts)],
+            "mpcg_solve": [vp, vp, vp, d, i32, C.POINTER(Result)],
+            "mpcg_get_history": [vp, vp, vp, vp, i32, vp, vp, i32, C.POINTER(i32)],
+            "mpcg_op_spmv": [vp, C.c_int, C.c_int, vp, vp],
+            "mpcg_op_dot": [vp, C.c_int, C.c_int, vp, vp, C.POINTER(d)],
+            "mpcg_op_axpy": [vp, C.c_int, d, vp, vp],
+            "mpcg_op_residual": [vp, vp, vp, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class MPCGError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().mpcg_last_error().decode(errors="replace")
+        raise MPCGError(f"{what} failed ({rc}): {msg}")
+
+
+def _np_ptr(a: np.ndarray):
+    return C.c_void_p(a.ctypes.data)
+
+
+def _t_ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def residual_edges(b_res: int = 10, eps_min_exp: int = 16):
+    """Nearest doubles to 10^(-j*delta), delta = eps_min_exp / b_res, j = 1..b_res-1."""
+    getcontext().prec = 60
+    return [float(Decimal(10) ** (Decimal(-eps_min_exp * j) / Decimal(b_res))) for j in range(1, b_res)]
+
+
+class Policy:
+    """A precision policy (fixed, Q-table greedy, Q-table training, MLP)."""
+
+    def __init__(self, kind=POLICY_FIXED, fixed_action=63, t_bin=1000, b_it=5, b_res=10, w_stag=10,
+                 lr=0.1, gamma=0.9, w=(1.0, 0.1, 10.0), eps_min=1e-16, cost="C1", seed=0,
+                 replace_period=50):
+        d = PolicyDesc()
+        d.kind, d.fixed_action, d.t_bin, d.b_it, d.b_res, d.w_stag = kind, fixed_action, t_bin, b_it, b_res, w_stag
+        for i, e in enumerate(residual_edges(b_res, int(round(-np.log10(eps_min))))):
+            d.res_edges[i] = e
+        d.lr, d.gamma = lr, gamma
+        d.w1, d.w2, d.w3 = w
+        d.eps_min = eps_min
+        costs = COSTS[cost] if isinstance(cost, str) else cost
+        for i in range(4):
+            d.cost[i] = costs[i]
+        d.seed = seed
+        d.replace_period = replace_period
+        self.desc = d
+        self.n_states = b_res * b_it * 2
+        h = C.c_void_p()
+        _check(lib().mpcg_policy_create(C.byref(d), C.byref(h)), "mpcg_policy_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            lib().mpcg_policy_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_qtable(self, q):
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(self.n_states, 64)
+        _check(lib().mpcg_policy_set_qtable(self.h, _np_ptr(q)), "set_qtable")
+
+    def qtable(self):
+        q = np.empty((self.n_states, 64))
+        _check(lib().mpcg_policy_get_qtable(self.h, _np_ptr(q)), "get_qtable")
+        return q
+
+    def set_episode(self, episode: int, epsilon: float):
+        _check(lib().mpcg_policy_set_episode(self.h, episode, epsilon), "set_episode")
+
+    def set_mlp(self, w: dict):
+        arrs = [np.ascontiguousarray(w[k], dtype=np.float32) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+        self._mlp_keep = arrs
+        _check(lib().mpcg_policy_set_mlp(self.h, *[_np_ptr(a) for a in arrs]), "set_mlp")
+
+    def rollouts_enable(self, capacity: int):
+        _check(lib().mpcg_policy_rollouts_enable(self.h, capacity), "rollouts_enable")
+
+    def rollouts_reset(self):
+        _check(lib().mpcg_policy_rollouts_reset(self.h), "rollouts_reset")
+
+    def rollouts(self, cap: int | None = None):
+        n = C.c_int32(0)
+        _check(lib().mpcg_policy_rollouts_count(self.h, C.byref(n)), "rollouts_count")
+        m = n.value if cap is None else min(cap, n.value)
+        out = dict(feat=np.zeros((m, 16), np.float32), next=np.zeros((m, 16), np.float32),
+                   act=np.zeros(m, np.int32), rew=np.zeros(m, np.float32), done=np.zeros(m, np.uint8))
+        if m:
+            got = C.c_int32(0)
+            _check(lib().mpcg_policy_get_rollouts(self.h, _np_ptr(out["feat"]), _np_ptr(out["next"]),
+                                                  _np_ptr(out["act"]), _np_ptr(out["rew"]),
+                                                  _np_ptr(out["done"]), m, C.byref(got)), "get_rollouts")
+        return out
+
+    def decide(self, k, rho, stag, feat=None):
+        k = np.ascontiguousarray(k, dtype=np.int64)
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        stag = np.ascontiguousarray(stag, dtype=np.int32)
+        m = k.size
+        st = np.zeros(m, np.int32)
+        ac = np.zeros(m, np.int32)
+        fp = None
+        if feat is not None:
+            feat = np.ascontiguousarray(feat, dtype=np.float32).reshape(m, 16)
+            fp = _np_ptr(feat)
+        _check(lib().mpcg_policy_decide(self.h, m, _np_ptr(k), _np_ptr(rho), _np_ptr(stag), fp,
+                                        _np_ptr(st), _np_ptr(ac)), "policy_decide")
+        return st, ac
+
+
+class Matrix:
+    """A CSR matrix on the device with its shadows; solves run on `stream`."""
+
+    def __init__(self, A, stream=None):
+        rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(A.col, dtype=np.int32)
+        v = np.ascontiguousarray(A.val, dtype=np.float64)
+        self.n, self.nnz = int(A.n), int(rp[-1])
+        self._stream = stream
+        h = C.c_void_p()
+        _check(lib().mpcg_create_csr(self.n, self.nnz, _np_ptr(rp), _np_ptr(ci), _np_ptr(v), 0,
+                                     _stream_handle(stream), C.byref(h)), "mpcg_create_csr")
+        self.h = h
+        self.policy = None
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            lib().mpcg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_policy(self, policy: Policy | None):
+        _check(lib().mpcg_set_policy(self.h, policy.h if policy is not None else None), "set_policy")
+        self.policy = policy
+
+    def set_options(self, replace_period=50, fallback=False, chunk=0):
+        o = SolveOpts(replace_period, int(fallback), chunk, 0)
+        _check(lib().mpcg_set_options(self.h, C.byref(o)), "set_options")
+
+    def solve(self, b, x, tol=1e-8, maxit=1000) -> dict:
+        """b, x: float64 device tensors of length n; x is the initial guess and the result."""
+        assert b.dtype.is_floating_point and b.element_size() == 8 and b.is_contiguous() and b.numel() == self.n
+        assert x.dtype == b.dtype and x.is_contiguous() and x.numel() == self.n and x.is_cuda and b.is_cuda
+        r = Result()
+        _check(lib().mpcg_solve(self.h, _t_ptr(b), _t_ptr(x), tol, maxit, C.byref(r)), "mpcg_solve")
+        return r.as_dict()
+
+    def history(self, cap: int | None = None):
+        n = C.c_int32(0)
+        _check(lib().mpcg_get_history(self.h, None, None, None, 0, None, None, 0, C.byref(n)), "history")
+        k1 = n.value
+        cap = k1 if cap is None else cap
+        rho = np.zeros(k1)
+        act = np.zeros(max(k1 - 1, 1), np.uint8)
+        flg = np.zeros(max(k1 - 1, 1), np.uint8)
+        rep_k = np.zeros(k1 + 1, np.int32)
+        rep_rho = np.zeros(k1 + 1)
+        _check(lib().mpcg_get_history(self.h, _np_ptr(rho), _np_ptr(act), _np_ptr(flg), k1,
+                                      _np_ptr(rep_k), _np_ptr(rep_rho), k1 + 1, C.byref(n)), "history")
+        return dict(rho=rho, actions=act[:k1 - 1], flags=flg[:k1 - 1], rep_k=rep_k, rep_rho=rep_rho)
+
+    def shadows(self):
+        f32 = np.zeros(self.nnz, np.float32)
+        bf = np.zeros(self.nnz, np.uint16)
+        hf = np.zeros(self.nnz, np.uint16)
+        e = np.zeros(self.n, np.int8)
+        _check(lib().mpcg_get_shadows(self.h, _np_ptr(f32), _np_ptr(bf), _np_ptr(hf), _np_ptr(e)), "shadows")
+        return f32, bf, hf, e
+
+    def op_spmv(self, fmt, tier64, p, q):
+        _check(lib().mpcg_op_spmv(self.h, fmt, tier64, _t_ptr(p), _t_ptr(q)), "op_spmv")
+
+    def op_dot(self, fmt, tier64, u, v) -> float:
+        out = C.c_double(0.0)
+        _check(lib().mpcg_op_dot(self.h, fmt, tier64, _t_ptr(u), _t_ptr(v), C.byref(out)), "op_dot")
+        return out.value
+
+    def op_axpy(self, fmt, alpha, u, y):
+        _check(lib().mpcg_op_axpy(self.h, fmt, alpha, _t_ptr(u), _t_ptr(y)), "op_axpy")
+
+    def op_residual(self, b, x, r):
+        _check(lib().mpcg_op_residual(self.h, _t_ptr(b), _t_ptr(x), _t_ptr(r)), "op_residual")

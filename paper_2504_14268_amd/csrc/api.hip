@@ -1,0 +1,710 @@
+// api.hip -- host engine and C ABI (include/mpcg.h).
+//
+// The engine keeps every vector, the control block and the histories on the
+// device.  A solve enqueues a start kernel, then slots of (K1, K2, K3) in chunks;
+// after each chunk it copies the 4-byte mode word to pinned memory and checks
+// the previous chunk's word, so the GPU always has a chunk queued and the host
+// never waits inside an iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "mpcg.h"
+
+using namespace mpcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? MPCG_ERR_NOMEM : MPCG_ERR_DEVICE,            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+template <typename T>
+hipError_t dmalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void **)p, count * sizeof(T));
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct mpcg_policy {
+  mpcg_policy_desc desc{};
+  int n_states = 0;
+  double *d_q = nullptr;
+  float *d_mlp = nullptr;   // W1 | b1 | W2 | b2 | W3 | b3
+  bool has_mlp = false;
+  int32_t roll_cap = 0;
+  float *d_rf = nullptr, *d_rn = nullptr, *d_rr = nullptr;
+  int32_t *d_ra = nullptr, *d_rcount = nullptr;
+  uint8_t *d_rd = nullptr;
+  int64_t episode = 0;
+  double epsilon = 0.0;
+
+  PolicyDev device_struct() const {
+    PolicyDev p{};
+    p.kind = desc.kind;
+    p.fixed_action = desc.fixed_action;
+    p.t_bin = desc.t_bin;
+    p.b_it = desc.b_it;
+    p.b_res = desc.b_res;
+    p.w_stag = desc.w_stag;
+    for (int i = 0; i < kMaxEdges; ++i) p.edges[i] = desc.res_edges[i];
+    p.q = d_q;
+    p.lr = desc.lr;
+    p.gamma = desc.gamma;
+    p.w1 = desc.w1;
+    p.w2 = desc.w2;
+    p.w3 = desc.w3;
+    p.eps_min = desc.eps_min;
+    for (int i = 0; i < 4; ++i) p.cost[i] = desc.cost[i];
+    p.epsilon = epsilon;
+    p.seed = desc.seed;
+    p.episode = episode;
+    if (has_mlp) {
+      p.W1 = d_mlp;
+      p.b1 = p.W1 + kMlpH * kMlpIn;
+      p.W2 = p.b1 + kMlpH;
+      p.b2 = p.W2 + kMlpH * kMlpH;
+      p.W3 = p.b2 + kMlpH;
+      p.b3 = p.W3 + kNAct * kMlpH;
+    }
+    p.replace_period = desc.replace_period;
+    p.roll_cap = roll_cap;
+    p.roll_feat = d_rf;
+    p.roll_next = d_rn;
+    p.roll_act = d_ra;
+    p.roll_rew = d_rr;
+    p.roll_done = d_rd;
+    p.roll_n = d_rcount;
+    return p;
+  }
+
+  void release() {
+    dfree(d_q);
+    dfree(d_mlp);
+    dfree(d_rf);
+    dfree(d_rn);
+    dfree(d_rr);
+    dfree(d_ra);
+    dfree(d_rcount);
+    dfree(d_rd);
+  }
+};
+
+static const int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kNAct * kMlpH + kNAct;
+
+struct mpcg_matrix {
+  int n = 0, nnz = 0, nnz_pad = 0;
+  hipStream_t stream = nullptr;
+  int *d_rp = nullptr, *d_ci = nullptr;
+  double *d_v64 = nullptr;
+  float *d_v32 = nullptr;
+  uint16_t *d_vbf = nullptr, *d_vh = nullptr;
+  int8_t *d_rexp = nullptr;
+  // workspace
+  double *d_xhi = nullptr;
+  float *d_r32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr, *d_xlo32 = nullptr;
+  double *d_r64 = nullptr, *d_p64 = nullptr, *d_q64 = nullptr, *d_xlo64 = nullptr;
+  double *d_part = nullptr, *d_scalar = nullptr;
+  unsigned *d_tickets = nullptr;
+  Ctl *d_ctl = nullptr;
+  Ctl *h_ctl = nullptr;        // pinned
+  int32_t *h_flag = nullptr;   // pinned [2]
+  PolicyDev *d_pol = nullptr;
+  PolicyDev *h_pol = nullptr;  // pinned staging
+  // history
+  int cap_it = -1, cap_rep = 0;
+  double *d_hrho = nullptr, *d_reprho = nullptr;
+  uint8_t *d_hact = nullptr, *d_hflag = nullptr;
+  int32_t *d_repk = nullptr;
+  int last_iters = -1, last_nrep = 0;
+  // policy
+  mpcg_policy *pol = nullptr;
+  mpcg_policy *defpol = nullptr;
+  mpcg_solve_opts opts{50, 0, 32, 0};
+  hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_chunk[2] = {nullptr, nullptr};
+  int P1 = 0, G1 = 0, P2 = 0;
+
+  Mat mat() const {
+    Mat m;
+    m.n = n;
+    m.nnz = nnz;
+    m.rp = d_rp;
+    m.ci = d_ci;
+    m.v64 = d_v64;
+    m.v32 = d_v32;
+    m.vbf = d_vbf;
+    m.vh = d_vh;
+    m.rexp = d_rexp;
+    return m;
+  }
+
+  void release() {
+    dfree(d_rp); dfree(d_ci); dfree(d_v64); dfree(d_v32); dfree(d_vbf); dfree(d_vh); dfree(d_rexp);
+    dfree(d_xhi); dfree(d_r32); dfree(d_p32); dfree(d_q32); dfree(d_xlo32);
+    dfree(d_r64); dfree(d_p64); dfree(d_q64); dfree(d_xlo64);
+    dfree(d_part); dfree(d_scalar); dfree(d_tickets); dfree(d_ctl); dfree(d_pol);
+    dfree(d_hrho); dfree(d_reprho); dfree(d_hact); dfree(d_hflag); dfree(d_repk);
+    if (h_ctl) (void)hipHostFree(h_ctl);
+    if (h_flag) (void)hipHostFree(h_flag);
+    if (h_pol) (void)hipHostFree(h_pol);
+    h_ctl = nullptr; h_flag = nullptr; h_pol = nullptr;
+    for (hipEvent_t *e : {&ev_start, &ev_end, &ev_chunk[0], &ev_chunk[1]})
+      if (*e) { (void)hipEventDestroy(*e); *e = nullptr; }
+    if (defpol) { defpol->release(); delete defpol; defpol = nullptr; }
+  }
+};
+
+static void default_desc(mpcg_policy_desc *d) {
+  std::memset(d, 0, sizeof(*d));
+  d->kind = MPCG_POLICY_FIXED;
+  d->fixed_action = 63;
+  d->t_bin = 1000;
+  d->b_it = 5;
+  d->b_res = 10;
+  d->w_stag = 10;
+  for (int j = 1; j < 10; ++j) d->res_edges[j - 1] = std::pow(10.0, -1.6 * j);
+  d->lr = 0.1;
+  d->gamma = 0.9;
+  d->w1 = 1.0;
+  d->w2 = 0.1;
+  d->w3 = 10.0;
+  d->eps_min = 1e-16;
+  const double c1[4] = {0.8, 0.6, 1.0, 2.0};
+  for (int i = 0; i < 4; ++i) d->cost[i] = c1[i];
+  d->replace_period = 50;
+}
+
+static int policy_alloc(mpcg_policy *P) {
+  P->n_states = P->desc.b_res * P->desc.b_it * 2;
+  HIP_TRY(dmalloc(&P->d_q, (size_t)P->n_states * kNAct));
+  HIP_TRY(hipMemset(P->d_q, 0, sizeof(double) * (size_t)P->n_states * kNAct));
+  HIP_TRY(dmalloc(&P->d_rcount, 1));
+  HIP_TRY(hipMemset(P->d_rcount, 0, sizeof(int32_t)));
+  return MPCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+static int ensure_ws(mpcg_matrix *A) {
+  if (A->d_xhi) return MPCG_OK;
+  const size_t n = (size_t)A->n;
+  HIP_TRY(dmalloc(&A->d_xhi, n));
+  HIP_TRY(dmalloc(&A->d_r32, n)); HIP_TRY(dmalloc(&A->d_p32, n));
+  HIP_TRY(dmalloc(&A->d_q32, n)); HIP_TRY(dmalloc(&A->d_xlo32, n));
+  HIP_TRY(dmalloc(&A->d_r64, n)); HIP_TRY(dmalloc(&A->d_p64, n));
+  HIP_TRY(dmalloc(&A->d_q64, n)); HIP_TRY(dmalloc(&A->d_xlo64, n));
+  return MPCG_OK;
+}
+
+static int ensure_hist(mpcg_matrix *A, int maxit) {
+  if (A->cap_it >= maxit) return MPCG_OK;
+  dfree(A->d_hrho); dfree(A->d_hact); dfree(A->d_hflag); dfree(A->d_repk); dfree(A->d_reprho);
+  const int cap = std::max(maxit, 16);
+  HIP_TRY(dmalloc(&A->d_hrho, (size_t)cap + 1));
+  HIP_TRY(dmalloc(&A->d_hact, (size_t)cap));
+  HIP_TRY(dmalloc(&A->d_hflag, (size_t)cap));
+  HIP_TRY(dmalloc(&A->d_repk, (size_t)cap + 1));
+  HIP_TRY(dmalloc(&A->d_reprho, (size_t)cap + 1));
+  A->cap_it = cap;
+  A->cap_rep = cap + 1;
+  return MPCG_OK;
+}
+
+static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
+  KArgs a{};
+  a.A = A->mat();
+  a.v.b = b;
+  a.v.xout = x;
+  a.v.xhi = A->d_xhi;
+  a.v.r32 = A->d_r32; a.v.p32 = A->d_p32; a.v.q32 = A->d_q32; a.v.xlo32 = A->d_xlo32;
+  a.v.r64 = A->d_r64; a.v.p64 = A->d_p64; a.v.q64 = A->d_q64; a.v.xlo64 = A->d_xlo64;
+  a.ctl = A->d_ctl;
+  a.pol = A->d_pol;
+  a.h.rho = A->d_hrho;
+  a.h.act = A->d_hact;
+  a.h.flag = A->d_hflag;
+  a.h.rep_k = A->d_repk;
+  a.h.rep_rho = A->d_reprho;
+  a.h.cap_it = A->cap_it;
+  a.h.cap_rep = A->cap_rep;
+  a.part = A->d_part;
+  a.tickets = A->d_tickets;
+  a.P1 = A->P1;
+  a.G1 = A->G1;
+  a.P2 = A->P2;
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *mpcg_last_error(void) { return g_err.c_str(); }
+
+static int validate_csr(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v) {
+  if (rp[0] != 0) return fail(MPCG_ERR_CSR, "row_ptr[0] != 0");
+  if ((int64_t)rp[n] != nnz) return fail(MPCG_ERR_CSR, "row_ptr[n] != nnz");
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t s = rp[i], t = rp[i + 1];
+    if (t < s) return fail(MPCG_ERR_CSR, "row_ptr decreases at row " + std::to_string(i));
+    bool diag = false;
+    for (int32_t k = s; k < t; ++k) {
+      if (ci[k] < 0 || ci[k] >= n) return fail(MPCG_ERR_CSR, "column out of range in row " + std::to_string(i));
+      if (k > s && ci[k] <= ci[k - 1])
+        return fail(MPCG_ERR_CSR, "columns not strictly increasing in row " + std::to_string(i));
+      if (!std::isfinite(v[k])) return fail(MPCG_ERR_CSR, "non-finite value in row " + std::to_string(i));
+      if (ci[k] == i) {
+        if (!(v[k] > 0.0)) return fail(MPCG_ERR_CSR, "non-positive diagonal in row " + std::to_string(i));
+        diag = true;
+      }
+    }
+    if (!diag) return fail(MPCG_ERR_CSR, "missing diagonal in row " + std::to_string(i));
+  }
+  return MPCG_OK;
+}
+
+int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, const double *val,
+                    int mem_kind, void *stream, mpcg_matrix **out) {
+  if (!out) return fail(MPCG_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!row_ptr || !col || !val) return fail(MPCG_ERR_INVALID, "NULL CSR array");
+  if (n < 1 || nnz < 1 || n >= (int64_t)1 << 31 || nnz >= ((int64_t)1 << 31) - 64)
+    return fail(MPCG_ERR_INVALID, "n and nnz must be in [1, 2^31)");
+  if (mem_kind != MPCG_MEM_HOST && mem_kind != MPCG_MEM_DEVICE) return fail(MPCG_ERR_INVALID, "bad mem_kind");
+  std::vector<int32_t> hrp, hci;
+  std::vector<double> hv;
+  const int32_t *rp = row_ptr, *ci = col;
+  const double *v = val;
+  if (mem_kind == MPCG_MEM_DEVICE) {
+    hrp.resize(n + 1);
+    hci.resize(nnz);
+    hv.resize(nnz);
+    HIP_TRY(hipMemcpy(hrp.data(), row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hci.data(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hv.data(), val, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    rp = hrp.data();
+    ci = hci.data();
+    v = hv.data();
+  }
+  int rc = validate_csr(n, nnz, rp, ci, v);
+  if (rc) return rc;
+
+  mpcg_matrix *A = new (std::nothrow) mpcg_matrix();
+  if (!A) return fail(MPCG_ERR_NOMEM, "host allocation failed");
+  auto bail = [&](int code) {
+    A->release();
+    delete A;
+    return code;
+  };
+#define TRY_A(expr)                                                                             \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return bail(fail(e_ == hipErrorOutOfMemory ? MPCG_ERR_NOMEM : MPCG_ERR_DEVICE,            \
+                       std::string(#expr) + ": " + hipGetErrorString(e_)));                     \
+  } while (0)
+  A->n = (int)n;
+  A->nnz = (int)nnz;
+  A->nnz_pad = round_up((int)nnz, 8) + 8;
+  A->stream = (hipStream_t)stream;
+  A->P1 = (A->n + kRowsPerBlock - 1) / kRowsPerBlock;
+  A->G1 = round_up(A->P1, 8);
+  A->P2 = (A->n + kVecBlock - 1) / kVecBlock;
+  if (A->P1 > 64 * kVecBlock) return bail(fail(MPCG_ERR_INVALID, "n too large for the partial reduction"));
+  const size_t np = (size_t)A->nnz_pad;
+  TRY_A(dmalloc(&A->d_rp, (size_t)n + 1));
+  TRY_A(dmalloc(&A->d_ci, np));
+  TRY_A(dmalloc(&A->d_v64, np));
+  TRY_A(dmalloc(&A->d_v32, np));
+  TRY_A(dmalloc(&A->d_vbf, np));
+  TRY_A(dmalloc(&A->d_vh, np));
+  TRY_A(dmalloc(&A->d_rexp, (size_t)n));
+  TRY_A(hipMemsetAsync(A->d_ci, 0, sizeof(int) * np, A->stream));
+  TRY_A(hipMemsetAsync(A->d_v64, 0, sizeof(double) * np, A->stream));
+  TRY_A(hipMemsetAsync(A->d_v32, 0, sizeof(float) * np, A->stream));
+  TRY_A(hipMemsetAsync(A->d_vbf, 0, sizeof(uint16_t) * np, A->stream));
+  TRY_A(hipMemsetAsync(A->d_vh, 0, sizeof(uint16_t) * np, A->stream));
+  const hipMemcpyKind kind = mem_kind == MPCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  TRY_A(hipMemcpyAsync(A->d_rp, row_ptr, sizeof(int32_t) * (n + 1), kind, A->stream));
+  TRY_A(hipMemcpyAsync(A->d_ci, col, sizeof(int32_t) * nnz, kind, A->stream));
+  TRY_A(hipMemcpyAsync(A->d_v64, val, sizeof(double) * nnz, kind, A->stream));
+  launch_shadows(A->n, A->d_rp, A->d_v64, A->d_v32, A->d_vbf, A->d_vh, A->d_rexp, A->stream);
+  TRY_A(hipGetLastError());
+  TRY_A(dmalloc(&A->d_part, (size_t)std::max(A->P1, A->P2) + 64));
+  TRY_A(dmalloc(&A->d_scalar, 8));
+  TRY_A(dmalloc(&A->d_tickets, 8));
+  TRY_A(hipMemsetAsync(A->d_tickets, 0, sizeof(unsigned) * 8, A->stream));
+  TRY_A(dmalloc(&A->d_ctl, 1));
+  TRY_A(dmalloc(&A->d_pol, 1));
+  TRY_A(hipHostMalloc((void **)&A->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  TRY_A(hipHostMalloc((void **)&A->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+  TRY_A(hipHostMalloc((void **)&A->h_pol, sizeof(PolicyDev), hipHostMallocDefault));
+  TRY_A(hipEventCreate(&A->ev_start));
+  TRY_A(hipEventCreate(&A->ev_end));
+  TRY_A(hipEventCreateWithFlags(&A->ev_chunk[0], hipEventDisableTiming));
+  TRY_A(hipEventCreateWithFlags(&A->ev_chunk[1], hipEventDisableTiming));
+  A->defpol = new (std::nothrow) mpcg_policy();
+  if (!A->defpol) return bail(fail(MPCG_ERR_NOMEM, "host allocation failed"));
+  default_desc(&A->defpol->desc);
+  rc = policy_alloc(A->defpol);
+  if (rc) return bail(rc);
+  TRY_A(hipStreamSynchronize(A->stream));
+#undef TRY_A
+  *out = A;
+  return MPCG_OK;
+}
+
+int mpcg_destroy(mpcg_matrix *A) {
+  if (!A) return MPCG_OK;
+  if (A->stream) (void)hipStreamSynchronize(A->stream);
+  A->release();
+  delete A;
+  return MPCG_OK;
+}
+
+int mpcg_get_shadows(mpcg_matrix *A, float *f32, uint16_t *bf16, uint16_t *f16, int8_t *rexp) {
+  if (!A) return fail(MPCG_ERR_INVALID, "A is NULL");
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  if (f32) HIP_TRY(hipMemcpy(f32, A->d_v32, sizeof(float) * A->nnz, hipMemcpyDeviceToHost));
+  if (bf16) HIP_TRY(hipMemcpy(bf16, A->d_vbf, sizeof(uint16_t) * A->nnz, hipMemcpyDeviceToHost));
+  if (f16) HIP_TRY(hipMemcpy(f16, A->d_vh, sizeof(uint16_t) * A->nnz, hipMemcpyDeviceToHost));
+  if (rexp) HIP_TRY(hipMemcpy(rexp, A->d_rexp, A->n, hipMemcpyDeviceToHost));
+  return MPCG_OK;
+}
+
+// ---------------------------------------------------------------- policies
+int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out) {
+  if (!desc || !out) return fail(MPCG_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  if (desc->kind < 0 || desc->kind > 3) return fail(MPCG_ERR_INVALID, "bad policy kind");
+  if (desc->fixed_action < 0 || desc->fixed_action > 63) return fail(MPCG_ERR_INVALID, "bad fixed_action");
+  if (desc->b_it < 1 || desc->b_res < 1 || desc->b_res > kMaxEdges + 1 || desc->t_bin < 1 || desc->w_stag < 1)
+    return fail(MPCG_ERR_INVALID, "bad bin parameters");
+  mpcg_policy *P = new (std::nothrow) mpcg_policy();
+  if (!P) return fail(MPCG_ERR_NOMEM, "host allocation failed");
+  P->desc = *desc;
+  int rc = policy_alloc(P);
+  if (rc) {
+    P->release();
+    delete P;
+    return rc;
+  }
+  *out = P;
+  return MPCG_OK;
+}
+
+int mpcg_policy_destroy(mpcg_policy *P) {
+  if (!P) return MPCG_OK;
+  (void)hipDeviceSynchronize();
+  P->release();
+  delete P;
+  return MPCG_OK;
+}
+
+int mpcg_policy_set_qtable(mpcg_policy *P, const double *q) {
+  if (!P || !q) return fail(MPCG_ERR_INVALID, "NULL argument");
+  HIP_TRY(hipMemcpy(P->d_q, q, sizeof(double) * (size_t)P->n_states * kNAct, hipMemcpyHostToDevice));
+  return MPCG_OK;
+}
+
+int mpcg_policy_get_qtable(mpcg_policy *P, double *q) {
+  if (!P || !q) return fail(MPCG_ERR_INVALID, "NULL argument");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(q, P->d_q, sizeof(double) * (size_t)P->n_states * kNAct, hipMemcpyDeviceToHost));
+  return MPCG_OK;
+}
+
+int mpcg_policy_set_episode(mpcg_policy *P, int64_t episode, double epsilon) {
+  if (!P) return fail(MPCG_ERR_INVALID, "P is NULL");
+  if (!(epsilon >= 0.0 && epsilon <= 1.0)) return fail(MPCG_ERR_INVALID, "epsilon must be in [0, 1]");
+  P->episode = episode;
+  P->epsilon = epsilon;
+  return MPCG_OK;
+}
+
+int mpcg_policy_set_mlp(mpcg_policy *P, const float *W1, const float *b1, const float *W2, const float *b2,
+                        const float *W3, const float *b3) {
+  if (!P || !W1 || !b1 || !W2 || !b2 || !W3 || !b3) return fail(MPCG_ERR_INVALID, "NULL argument");
+  if (!P->d_mlp) HIP_TRY(dmalloc(&P->d_mlp, (size_t)kMlpParams));
+  std::vector<float> h(kMlpParams);
+  float *w = h.data();
+  std::memcpy(w, W1, sizeof(float) * kMlpH * kMlpIn); w += kMlpH * kMlpIn;
+  std::memcpy(w, b1, sizeof(float) * kMlpH); w += kMlpH;
+  std::memcpy(w, W2, sizeof(float) * kMlpH * kMlpH); w += kMlpH * kMlpH;
+  std::memcpy(w, b2, sizeof(float) * kMlpH); w += kMlpH;
+  std::memcpy(w, W3, sizeof(float) * kNAct * kMlpH); w += kNAct * kMlpH;
+  std::memcpy(w, b3, sizeof(float) * kNAct);
+  HIP_TRY(hipMemcpy(P->d_mlp, h.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+  P->has_mlp = true;
+  return MPCG_OK;
+}
+
+int mpcg_policy_rollouts_enable(mpcg_policy *P, int32_t capacity) {
+  if (!P || capacity < 0) return fail(MPCG_ERR_INVALID, "bad argument");
+  HIP_TRY(hipDeviceSynchronize());
+  dfree(P->d_rf); dfree(P->d_rn); dfree(P->d_rr); dfree(P->d_ra); dfree(P->d_rd);
+  P->roll_cap = 0;
+  if (capacity > 0) {
+    HIP_TRY(dmalloc(&P->d_rf, (size_t)capacity * kMlpIn));
+    HIP_TRY(dmalloc(&P->d_rn, (size_t)capacity * kMlpIn));
+    HIP_TRY(dmalloc(&P->d_rr, (size_t)capacity));
+    HIP_TRY(dmalloc(&P->d_ra, (size_t)capacity));
+    HIP_TRY(dmalloc(&P->d_rd, (size_t)capacity));
+    P->roll_cap = capacity;
+  }
+  HIP_TRY(hipMemset(P->d_rcount, 0, sizeof(int32_t)));
+  return MPCG_OK;
+}
+
+int mpcg_policy_rollouts_count(mpcg_policy *P, int32_t *n) {
+  if (!P || !n) return fail(MPCG_ERR_INVALID, "NULL argument");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(n, P->d_rcount, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (*n > P->roll_cap) *n = P->roll_cap;
+  return MPCG_OK;
+}
+
+int mpcg_policy_rollouts_reset(mpcg_policy *P) {
+  if (!P) return fail(MPCG_ERR_INVALID, "P is NULL");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemset(P->d_rcount, 0, sizeof(int32_t)));
+  return MPCG_OK;
+}
+
+int mpcg_policy_get_rollouts(mpcg_policy *P, float *feat, float *next_feat, int32_t *act, float *rew,
+                             uint8_t *done, int32_t cap, int32_t *n_out) {
+  if (!P) return fail(MPCG_ERR_INVALID, "P is NULL");
+  int32_t n = 0;
+  int rc = mpcg_policy_rollouts_count(P, &n);
+  if (rc) return rc;
+  n = std::min(n, cap);
+  if (n > 0) {
+    if (feat) HIP_TRY(hipMemcpy(feat, P->d_rf, sizeof(float) * n * kMlpIn, hipMemcpyDeviceToHost));
+    if (next_feat) HIP_TRY(hipMemcpy(next_feat, P->d_rn, sizeof(float) * n * kMlpIn, hipMemcpyDeviceToHost));
+    if (act) HIP_TRY(hipMemcpy(act, P->d_ra, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    if (rew) HIP_TRY(hipMemcpy(rew, P->d_rr, sizeof(float) * n, hipMemcpyDeviceToHost));
+    if (done) HIP_TRY(hipMemcpy(done, P->d_rd, n, hipMemcpyDeviceToHost));
+  }
+  if (n_out) *n_out = n;
+  return MPCG_OK;
+}
+
+int mpcg_policy_decide(mpcg_policy *P, int32_t m, const int64_t *k, const double *rho, const int32_t *stag,
+                       const float *feat, int32_t *state, int32_t *action) {
+  if (!P || m < 0 || (m > 0 && (!k || !rho || !stag || !state || !action)))
+    return fail(MPCG_ERR_INVALID, "bad argument");
+  if (P->desc.kind == MPCG_POLICY_MLP && (!feat || !P->has_mlp))
+    return fail(MPCG_ERR_INVALID, "MLP policy needs weights and features");
+  if (m == 0) return MPCG_OK;
+  PolicyDev *dP = nullptr;
+  int64_t *dk = nullptr;
+  double *drho = nullptr;
+  int32_t *dst = nullptr, *ds = nullptr, *da = nullptr;
+  float *df = nullptr;
+  int rc = MPCG_OK;
+  PolicyDev hp = P->device_struct();
+  hipError_t e = dmalloc(&dP, 1);
+  if (e == hipSuccess) e = dmalloc(&dk, m);
+  if (e == hipSuccess) e = dmalloc(&drho, m);
+  if (e == hipSuccess) e = dmalloc(&dst, m);
+  if (e == hipSuccess) e = dmalloc(&ds, m);
+  if (e == hipSuccess) e = dmalloc(&da, m);
+  if (e == hipSuccess && feat) e = dmalloc(&df, (size_t)m * kMlpIn);
+  if (e == hipSuccess) e = hipMemcpy(dP, &hp, sizeof(hp), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dk, k, sizeof(int64_t) * m, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(drho, rho, sizeof(double) * m, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dst, stag, sizeof(int32_t) * m, hipMemcpyHostToDevice);
+  if (e == hipSuccess && feat) e = hipMemcpy(df, feat, sizeof(float) * m * kMlpIn, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    launch_policy_decide(dP, m, dk, drho, dst, df, ds, da, nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(state, ds, sizeof(int32_t) * m, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(action, da, sizeof(int32_t) * m, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) rc = fail(MPCG_ERR_DEVICE, std::string("policy_decide: ") + hipGetErrorString(e));
+  dfree(dP); dfree(dk); dfree(drho); dfree(dst); dfree(ds); dfree(da); dfree(df);
+  return rc;
+}
+
+int mpcg_set_policy(mpcg_matrix *A, mpcg_policy *P) {
+  if (!A) return fail(MPCG_ERR_INVALID, "A is NULL");
+  if (P && P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
+  A->pol = P;
+  return MPCG_OK;
+}
+
+int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
+  if (!A || !o) return fail(MPCG_ERR_INVALID, "NULL argument");
+  if (o->replace_period < 0 || o->chunk < 0) return fail(MPCG_ERR_INVALID, "negative option");
+  A->opts = *o;
+  return MPCG_OK;
+}
+
+// ---------------------------------------------------------------- solve
+int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t maxit, mpcg_result *res) {
+  if (!A || !b || !x || !res) return fail(MPCG_ERR_INVALID, "NULL argument");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MPCG_ERR_INVALID, "tol must be positive and finite");
+  if (maxit < 0 || maxit > (1 << 29)) return fail(MPCG_ERR_INVALID, "maxit out of range");
+  int rc = ensure_ws(A);
+  if (rc) return rc;
+  rc = ensure_hist(A, maxit);
+  if (rc) return rc;
+  mpcg_policy *P = A->pol ? A->pol : A->defpol;
+  if (P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
+  hipStream_t st = A->stream;
+  HIP_TRY(hipStreamSynchronize(st));   // staging buffers below are reused
+
+  *A->h_pol = P->device_struct();
+  HIP_TRY(hipMemcpyAsync(A->d_pol, A->h_pol, sizeof(PolicyDev), hipMemcpyHostToDevice, st));
+  Ctl &c = *A->h_ctl;
+  std::memset(&c, 0, sizeof(Ctl));
+  c.mode = M_INIT;
+  c.tier = 1;
+  c.action = 63;
+  c.maxit = maxit;
+  c.status = -1;
+  c.fallback_at = -1;
+  c.prev_action = 63;
+  c.R = A->opts.replace_period;
+  c.fallback_enabled = A->opts.fallback ? 1 : 0;
+  c.tol = tol;
+  HIP_TRY(hipMemcpyAsync(A->d_ctl, A->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+
+  const KArgs a = make_args(A, b, x);
+  HIP_TRY(hipEventRecord(A->ev_start, st));
+  launch_start(a, st);
+  HIP_TRY(hipGetLastError());
+  const int64_t max_slots = 2 * (int64_t)maxit + 16;
+  const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
+  int64_t slots = 0;
+  int ci = 0;
+  bool done = false;
+  while (slots < max_slots) {
+    const int m = (int)std::min<int64_t>(chunk, max_slots - slots);
+    for (int s = 0; s < m; ++s) launch_slot(a, st);
+    HIP_TRY(hipGetLastError());
+    slots += m;
+    const int idx = ci & 1;
+    HIP_TRY(hipMemcpyAsync(&A->h_flag[idx], &A->d_ctl->mode, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(A->ev_chunk[idx], st));
+    if (ci > 0) {
+      const int pidx = (ci - 1) & 1;
+      HIP_TRY(hipEventSynchronize(A->ev_chunk[pidx]));
+      if (A->h_flag[pidx] == M_DONE) {
+        done = true;
+        break;
+      }
+    }
+    ci++;
+  }
+  if (!done) {
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpy(&A->h_flag[0], &A->d_ctl->mode, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (A->h_flag[0] != M_DONE) return fail(MPCG_ERR_DEVICE, "solver did not reach a final state");
+  }
+  launch_finish(a, st);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(A->ev_end, st));
+  HIP_TRY(hipMemcpyAsync(A->h_ctl, A->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, A->ev_start, A->ev_end));
+  const Ctl &r = *A->h_ctl;
+  std::memset(res, 0, sizeof(*res));
+  res->status = r.status;
+  res->iters = r.k;
+  res->n_replace = r.nrep;
+  res->fallback_at = r.fell_back ? r.fallback_at : -1;
+  res->relres_true = r.relres_true;
+  res->cost_sum = r.cost_sum;
+  res->time_ms = ms;
+  res->slots = (int32_t)slots;
+  A->last_iters = r.k;
+  A->last_nrep = r.nrep;
+  return MPCG_OK;
+}
+
+int mpcg_get_history(mpcg_matrix *A, double *rho, uint8_t *act, uint8_t *flags, int32_t cap, int32_t *rep_k,
+                     double *rep_rho, int32_t rep_cap, int32_t *n_hist) {
+  if (!A) return fail(MPCG_ERR_INVALID, "A is NULL");
+  if (A->last_iters < 0) return fail(MPCG_ERR_INVALID, "no solve yet");
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  const int k = A->last_iters;
+  if (rho) HIP_TRY(hipMemcpy(rho, A->d_hrho, sizeof(double) * std::min(k + 1, cap), hipMemcpyDeviceToHost));
+  if (act && k > 0) HIP_TRY(hipMemcpy(act, A->d_hact, std::min(k, cap), hipMemcpyDeviceToHost));
+  if (flags && k > 0) HIP_TRY(hipMemcpy(flags, A->d_hflag, std::min(k, cap), hipMemcpyDeviceToHost));
+  const int nr = std::min(std::min(A->last_nrep, A->cap_rep), rep_cap);
+  if (rep_k && nr > 0) HIP_TRY(hipMemcpy(rep_k, A->d_repk, sizeof(int32_t) * nr, hipMemcpyDeviceToHost));
+  if (rep_rho && nr > 0) HIP_TRY(hipMemcpy(rep_rho, A->d_reprho, sizeof(double) * nr, hipMemcpyDeviceToHost));
+  if (n_hist) *n_hist = k + 1;
+  return MPCG_OK;
+}
+
+// ---------------------------------------------------------------- single ops
+int mpcg_op_spmv(mpcg_matrix *A, int fmt, int tier64, const void *p, void *q) {
+  if (!A || !p || !q || fmt < 0 || fmt > 3 || (tier64 != 0 && tier64 != 1))
+    return fail(MPCG_ERR_INVALID, "bad argument");
+  launch_op_spmv(A->mat(), fmt, tier64, p, q, A->P1, A->G1, A->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  return MPCG_OK;
+}
+
+int mpcg_op_residual(mpcg_matrix *A, const double *b, const double *x, double *r) {
+  if (!A || !b || !x || !r) return fail(MPCG_ERR_INVALID, "bad argument");
+  launch_op_residual(A->mat(), b, x, r, A->P1, A->G1, A->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  return MPCG_OK;
+}
+
+int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out) {
+  if (!A || !u || !v || !out || fmt < 0 || fmt > 3 || (tier64 != 0 && tier64 != 1))
+    return fail(MPCG_ERR_INVALID, "bad argument");
+  launch_op_dot(A->n, fmt, tier64, u, v, A->d_part, &A->d_tickets[3], A->P2, A->d_scalar, A->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, A->d_scalar, sizeof(double), hipMemcpyDeviceToHost, A->stream));
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  return MPCG_OK;
+}
+
+int mpcg_op_axpy(mpcg_matrix *A, int fmt, double alpha, const void *u, void *y) {
+  if (!A || !u || !y || fmt < 0 || fmt > 3) return fail(MPCG_ERR_INVALID, "bad argument");
+  launch_op_axpy(A->n, fmt, alpha, u, y, A->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  return MPCG_OK;
+}
+
+}  // extern "C"
