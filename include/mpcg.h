@@ -106,8 +106,28 @@ typedef struct {
     int32_t fallback;          /* 1: restart as fp64 CG on breakdown/stagnation */
     int32_t chunk;             /* iterations enqueued between done-flag polls
                                   (0: library default)                          */
-    int32_t reserved;
+    int32_t profile;           /* 1: time every kernel launch of the solve with
+                                  HIP events on the handle's stream (see
+                                  mpcg_get_profile); adds event overhead        */
 } mpcg_solve_opts;
+
+/* Per-kernel timing of the last solve made with opts.profile = 1.  A "slot" is
+ * one iteration's launch sequence: K1 = SpMV with the fused nu = p.q partial
+ * (fp64 residual in start/replacement slots), K2 = x/r update with the
+ * sigma' = r.r partial, KS = one-block scalar and policy step, K3 = direction
+ * update.  Times are sums of event-bracketed launch durations in ms. */
+typedef struct {
+    int32_t n_iter_slots;      /* slots that ran a CG iteration                  */
+    int32_t n_resid_slots;     /* slots that ran an fp64 residual (start/replace) */
+    int32_t n_idle_slots;      /* slots enqueued after the solve had finished    */
+    int32_t reserved;
+    double k1_iter_ms;         /* K1 over iteration slots                        */
+    double k2_iter_ms;         /* K2 over iteration slots                        */
+    double ks_iter_ms;         /* KS over iteration slots                        */
+    double k3_iter_ms;         /* K3 over iteration slots                        */
+    double resid_ms;           /* all launches of residual slots                 */
+    double idle_ms;            /* all launches of idle slots                     */
+} mpcg_profile;
 
 typedef struct {
     int32_t status;            /* MPCG_CONVERGED ... MPCG_BREAKDOWN              */
@@ -218,6 +238,9 @@ int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *
 int mpcg_op_axpy(mpcg_matrix *A, int fmt, double alpha, const void *u, void *y);
 /* r (double[n], device) = b - A x in fp64 */
 int mpcg_op_residual(mpcg_matrix *A, const double *b, const double *x, double *r);
+
+/* Copies the per-kernel timing of the last profiled solve (zeros otherwise). */
+int mpcg_get_profile(mpcg_matrix *A, mpcg_profile *out);
 
 const char *mpcg_last_error(void);
 

@@ -45,7 +45,17 @@ class PolicyDesc(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("replace_period", C.c_int32), ("fallback", C.c_int32),
-                ("chunk", C.c_int32), ("reserved", C.c_int32)]
+                ("chunk", C.c_int32), ("profile", C.c_int32)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("n_iter_slots", C.c_int32), ("n_resid_slots", C.c_int32),
+                ("n_idle_slots", C.c_int32), ("reserved", C.c_int32),
+                ("k1_iter_ms", C.c_double), ("k2_iter_ms", C.c_double), ("ks_iter_ms", C.c_double),
+                ("k3_iter_ms", C.c_double), ("resid_ms", C.c_double), ("idle_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class Result(C.Structure):
@@ -92,6 +102,7 @@ def lib():
             "mpcg_op_dot": [vp, C.c_int, C.c_int, vp, vp, C.POINTER(d)],
             "mpcg_op_axpy": [vp, C.c_int, d, vp, vp],
             "mpcg_op_residual": [vp, vp, vp, vp],
+            "mpcg_get_profile": [vp, C.POINTER(Profile)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -249,8 +260,8 @@ class Matrix:
         _check(lib().mpcg_set_policy(self.h, policy.h if policy is not None else None), "set_policy")
         self.policy = policy
 
-    def set_options(self, replace_period=50, fallback=False, chunk=0):
-        o = SolveOpts(replace_period, int(fallback), chunk, 0)
+    def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False):
+        o = SolveOpts(replace_period, int(fallback), chunk, int(profile))
         _check(lib().mpcg_set_options(self.h, C.byref(o)), "set_options")
 
     def solve(self, b, x, tol=1e-8, maxit=1000) -> dict:
@@ -260,6 +271,11 @@ class Matrix:
         r = Result()
         _check(lib().mpcg_solve(self.h, _t_ptr(b), _t_ptr(x), tol, maxit, C.byref(r)), "mpcg_solve")
         return r.as_dict()
+
+    def profile(self) -> dict:
+        pr = Profile()
+        _check(lib().mpcg_get_profile(self.h, C.byref(pr)), "get_profile")
+        return pr.as_dict()
 
     def history(self, cap: int | None = None):
         n = C.c_int32(0)

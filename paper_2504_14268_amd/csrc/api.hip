@@ -133,8 +133,7 @@ struct mpcg_matrix {
   double *d_xhi = nullptr;
   float *d_r32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr, *d_xlo32 = nullptr;
   double *d_r64 = nullptr, *d_p64 = nullptr, *d_q64 = nullptr, *d_xlo64 = nullptr;
-  double *d_part = nullptr, *d_scalar = nullptr;
-  unsigned *d_tickets = nullptr;
+  double *d_part0 = nullptr, *d_part1 = nullptr, *d_part2 = nullptr, *d_scalar = nullptr;
   Ctl *d_ctl = nullptr;
   Ctl *h_ctl = nullptr;        // pinned
   int32_t *h_flag = nullptr;   // pinned [2]
@@ -146,12 +145,18 @@ struct mpcg_matrix {
   uint8_t *d_hact = nullptr, *d_hflag = nullptr;
   int32_t *d_repk = nullptr;
   int last_iters = -1, last_nrep = 0;
+  // profiling
+  int8_t *d_slotlog = nullptr;
+  int slot_cap = 0;
+  std::vector<hipEvent_t> pev;
+  std::vector<float> t1, t2, ts, t3;
+  mpcg_profile prof{};
   // policy
   mpcg_policy *pol = nullptr;
   mpcg_policy *defpol = nullptr;
   mpcg_solve_opts opts{50, 0, 32, 0};
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_chunk[2] = {nullptr, nullptr};
-  int P1 = 0, G1 = 0, P2 = 0;
+  int G1 = 0, P2 = 0;
 
   Mat mat() const {
     Mat m;
@@ -171,8 +176,10 @@ struct mpcg_matrix {
     dfree(d_rp); dfree(d_ci); dfree(d_v64); dfree(d_v32); dfree(d_vbf); dfree(d_vh); dfree(d_rexp);
     dfree(d_xhi); dfree(d_r32); dfree(d_p32); dfree(d_q32); dfree(d_xlo32);
     dfree(d_r64); dfree(d_p64); dfree(d_q64); dfree(d_xlo64);
-    dfree(d_part); dfree(d_scalar); dfree(d_tickets); dfree(d_ctl); dfree(d_pol);
-    dfree(d_hrho); dfree(d_reprho); dfree(d_hact); dfree(d_hflag); dfree(d_repk);
+    dfree(d_part0); dfree(d_part1); dfree(d_part2); dfree(d_scalar); dfree(d_ctl); dfree(d_pol);
+    dfree(d_hrho); dfree(d_reprho); dfree(d_hact); dfree(d_hflag); dfree(d_repk); dfree(d_slotlog);
+    for (hipEvent_t e : pev) (void)hipEventDestroy(e);
+    pev.clear();
     if (h_ctl) (void)hipHostFree(h_ctl);
     if (h_flag) (void)hipHostFree(h_flag);
     if (h_pol) (void)hipHostFree(h_pol);
@@ -237,6 +244,26 @@ static int ensure_hist(mpcg_matrix *A, int maxit) {
   HIP_TRY(dmalloc(&A->d_reprho, (size_t)cap + 1));
   A->cap_it = cap;
   A->cap_rep = cap + 1;
+  dfree(A->d_slotlog);
+  A->slot_cap = 2 * cap + 16;
+  HIP_TRY(dmalloc(&A->d_slotlog, (size_t)A->slot_cap));
+  return MPCG_OK;
+}
+
+// Elapsed times of the three launches of each slot of a completed chunk.
+static int collect_chunk(mpcg_matrix *A, int pool_idx, int chunk, int64_t first, int m) {
+  for (int s = 0; s < m; ++s) {
+    hipEvent_t *e = &A->pev[((size_t)pool_idx * chunk + s) * 5];
+    float a = 0, b = 0, c = 0, d = 0;
+    HIP_TRY(hipEventElapsedTime(&a, e[0], e[1]));
+    HIP_TRY(hipEventElapsedTime(&b, e[1], e[2]));
+    HIP_TRY(hipEventElapsedTime(&c, e[2], e[3]));
+    HIP_TRY(hipEventElapsedTime(&d, e[3], e[4]));
+    A->t1[first + s] = a;
+    A->t2[first + s] = b;
+    A->ts[first + s] = c;
+    A->t3[first + s] = d;
+  }
   return MPCG_OK;
 }
 
@@ -257,9 +284,9 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
   a.h.rep_rho = A->d_reprho;
   a.h.cap_it = A->cap_it;
   a.h.cap_rep = A->cap_rep;
-  a.part = A->d_part;
-  a.tickets = A->d_tickets;
-  a.P1 = A->P1;
+  a.part0 = A->d_part0;
+  a.part1 = A->d_part1;
+  a.part2 = A->d_part2;
   a.G1 = A->G1;
   a.P2 = A->P2;
   return a;
@@ -338,10 +365,9 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   A->nnz = (int)nnz;
   A->nnz_pad = round_up((int)nnz, 8) + 8;
   A->stream = (hipStream_t)stream;
-  A->P1 = (A->n + kRowsPerBlock - 1) / kRowsPerBlock;
-  A->G1 = round_up(A->P1, 8);
   A->P2 = (A->n + kVecBlock - 1) / kVecBlock;
-  if (A->P1 > 64 * kVecBlock) return bail(fail(MPCG_ERR_INVALID, "n too large for the partial reduction"));
+  A->G1 = round_up(A->P2, 8);
+  if (A->P2 > 64 * kVecBlock) return bail(fail(MPCG_ERR_INVALID, "n too large for the partial reduction"));
   const size_t np = (size_t)A->nnz_pad;
   TRY_A(dmalloc(&A->d_rp, (size_t)n + 1));
   TRY_A(dmalloc(&A->d_ci, np));
@@ -361,10 +387,10 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   TRY_A(hipMemcpyAsync(A->d_v64, val, sizeof(double) * nnz, kind, A->stream));
   launch_shadows(A->n, A->d_rp, A->d_v64, A->d_v32, A->d_vbf, A->d_vh, A->d_rexp, A->stream);
   TRY_A(hipGetLastError());
-  TRY_A(dmalloc(&A->d_part, (size_t)std::max(A->P1, A->P2) + 64));
+  TRY_A(dmalloc(&A->d_part0, (size_t)A->P2 + 64));
+  TRY_A(dmalloc(&A->d_part1, (size_t)A->P2 + 64));
+  TRY_A(dmalloc(&A->d_part2, (size_t)A->P2 + 64));
   TRY_A(dmalloc(&A->d_scalar, 8));
-  TRY_A(dmalloc(&A->d_tickets, 8));
-  TRY_A(hipMemsetAsync(A->d_tickets, 0, sizeof(unsigned) * 8, A->stream));
   TRY_A(dmalloc(&A->d_ctl, 1));
   TRY_A(dmalloc(&A->d_pol, 1));
   TRY_A(hipHostMalloc((void **)&A->h_ctl, sizeof(Ctl), hipHostMallocDefault));
@@ -601,26 +627,68 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   c.tol = tol;
   HIP_TRY(hipMemcpyAsync(A->d_ctl, A->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
 
-  const KArgs a = make_args(A, b, x);
+  KArgs a = make_args(A, b, x);
+  const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
+  const bool prof = A->opts.profile != 0;
+  std::memset(&A->prof, 0, sizeof(A->prof));
+  if (prof) {
+    a.slot_log = A->d_slotlog;
+    const size_t need = (size_t)2 * chunk * 5;
+    while (A->pev.size() < need) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      A->pev.push_back(e);
+    }
+    A->t1.assign(A->slot_cap, 0.0f);
+    A->t2.assign(A->slot_cap, 0.0f);
+    A->ts.assign(A->slot_cap, 0.0f);
+    A->t3.assign(A->slot_cap, 0.0f);
+  }
   HIP_TRY(hipEventRecord(A->ev_start, st));
   launch_start(a, st);
   HIP_TRY(hipGetLastError());
   const int64_t max_slots = 2 * (int64_t)maxit + 16;
-  const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
   int64_t slots = 0;
   int ci = 0;
   bool done = false;
+  int64_t chunk_first[2] = {0, 0};
+  int chunk_m[2] = {0, 0};
+  bool pending[2] = {false, false};
   while (slots < max_slots) {
     const int m = (int)std::min<int64_t>(chunk, max_slots - slots);
-    for (int s = 0; s < m; ++s) launch_slot(a, st);
+    const int idx = ci & 1;
+    chunk_first[idx] = slots;
+    chunk_m[idx] = m;
+    for (int s = 0; s < m; ++s) {
+      if (prof) {
+        hipEvent_t *e = &A->pev[((size_t)idx * chunk + s) * 5];
+        a.slot = (int)(slots + s);
+        HIP_TRY(hipEventRecord(e[0], st));
+        launch_k1(a, st);
+        HIP_TRY(hipEventRecord(e[1], st));
+        launch_k2(a, st);
+        HIP_TRY(hipEventRecord(e[2], st));
+        launch_ks(a, st);
+        HIP_TRY(hipEventRecord(e[3], st));
+        launch_k3(a, st);
+        HIP_TRY(hipEventRecord(e[4], st));
+      } else {
+        launch_slot(a, st);
+      }
+    }
     HIP_TRY(hipGetLastError());
     slots += m;
-    const int idx = ci & 1;
+    pending[idx] = true;
     HIP_TRY(hipMemcpyAsync(&A->h_flag[idx], &A->d_ctl->mode, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(A->ev_chunk[idx], st));
     if (ci > 0) {
       const int pidx = (ci - 1) & 1;
       HIP_TRY(hipEventSynchronize(A->ev_chunk[pidx]));
+      if (prof && pending[pidx]) {
+        int rc2 = collect_chunk(A, pidx, chunk, chunk_first[pidx], chunk_m[pidx]);
+        if (rc2) return rc2;
+      }
+      pending[pidx] = false;
       if (A->h_flag[pidx] == M_DONE) {
         done = true;
         break;
@@ -628,11 +696,19 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
     }
     ci++;
   }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (prof) {
+    for (int i = 0; i < 2; ++i)
+      if (pending[i]) {
+        int rc2 = collect_chunk(A, i, chunk, chunk_first[i], chunk_m[i]);
+        if (rc2) return rc2;
+      }
+  }
   if (!done) {
-    HIP_TRY(hipStreamSynchronize(st));
     HIP_TRY(hipMemcpy(&A->h_flag[0], &A->d_ctl->mode, sizeof(int32_t), hipMemcpyDeviceToHost));
     if (A->h_flag[0] != M_DONE) return fail(MPCG_ERR_DEVICE, "solver did not reach a final state");
   }
+  a.slot_log = nullptr;
   launch_finish(a, st);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(A->ev_end, st));
@@ -652,6 +728,33 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   res->slots = (int32_t)slots;
   A->last_iters = r.k;
   A->last_nrep = r.nrep;
+  if (prof) {
+    std::vector<int8_t> modes((size_t)slots);
+    HIP_TRY(hipMemcpy(modes.data(), A->d_slotlog, (size_t)slots, hipMemcpyDeviceToHost));
+    mpcg_profile &pr = A->prof;
+    for (int64_t s = 0; s < slots; ++s) {
+      const double all = (double)A->t1[s] + A->t2[s] + A->ts[s] + A->t3[s];
+      if (modes[s] == M_ITER) {
+        pr.n_iter_slots++;
+        pr.k1_iter_ms += A->t1[s];
+        pr.k2_iter_ms += A->t2[s];
+        pr.ks_iter_ms += A->ts[s];
+        pr.k3_iter_ms += A->t3[s];
+      } else if (modes[s] == M_DONE) {
+        pr.n_idle_slots++;
+        pr.idle_ms += all;
+      } else {
+        pr.n_resid_slots++;
+        pr.resid_ms += all;
+      }
+    }
+  }
+  return MPCG_OK;
+}
+
+int mpcg_get_profile(mpcg_matrix *A, mpcg_profile *out) {
+  if (!A || !out) return fail(MPCG_ERR_INVALID, "NULL argument");
+  *out = A->prof;
   return MPCG_OK;
 }
 
@@ -675,7 +778,7 @@ int mpcg_get_history(mpcg_matrix *A, double *rho, uint8_t *act, uint8_t *flags, 
 int mpcg_op_spmv(mpcg_matrix *A, int fmt, int tier64, const void *p, void *q) {
   if (!A || !p || !q || fmt < 0 || fmt > 3 || (tier64 != 0 && tier64 != 1))
     return fail(MPCG_ERR_INVALID, "bad argument");
-  launch_op_spmv(A->mat(), fmt, tier64, p, q, A->P1, A->G1, A->stream);
+  launch_op_spmv(A->mat(), fmt, tier64, p, q, A->stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(A->stream));
   return MPCG_OK;
@@ -683,7 +786,7 @@ int mpcg_op_spmv(mpcg_matrix *A, int fmt, int tier64, const void *p, void *q) {
 
 int mpcg_op_residual(mpcg_matrix *A, const double *b, const double *x, double *r) {
   if (!A || !b || !x || !r) return fail(MPCG_ERR_INVALID, "bad argument");
-  launch_op_residual(A->mat(), b, x, r, A->P1, A->G1, A->stream);
+  launch_op_residual(A->mat(), b, x, r, A->stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(A->stream));
   return MPCG_OK;
@@ -692,7 +795,7 @@ int mpcg_op_residual(mpcg_matrix *A, const double *b, const double *x, double *r
 int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out) {
   if (!A || !u || !v || !out || fmt < 0 || fmt > 3 || (tier64 != 0 && tier64 != 1))
     return fail(MPCG_ERR_INVALID, "bad argument");
-  launch_op_dot(A->n, fmt, tier64, u, v, A->d_part, &A->d_tickets[3], A->P2, A->d_scalar, A->stream);
+  launch_op_dot(A->n, fmt, tier64, u, v, A->d_part2, A->P2, A->d_scalar, A->stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(out, A->d_scalar, sizeof(double), hipMemcpyDeviceToHost, A->stream));
   HIP_TRY(hipStreamSynchronize(A->stream));

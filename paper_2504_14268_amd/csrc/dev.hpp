@@ -158,24 +158,6 @@ __device__ __forceinline__ A block_tree(A v) {
   return t;
 }
 
-// "Last block" hand-off: each block publishes its subtree sum; the block that
-// arrives last (integer ticket, agent scope) returns true and may read all
-// partials.  The ticket is reset for the next launch.
-__device__ __forceinline__ bool publish_partial(double *part, int idx, double val, unsigned *ticket,
-                                                unsigned nblocks) {
-  __shared__ int amlast;
-  if (threadIdx.x == 0) {
-    part[idx] = val;
-    __threadfence();
-    unsigned t = atomicAdd(ticket, 1u);
-    amlast = (t == nblocks - 1u);
-  }
-  __syncthreads();
-  const bool last = amlast != 0;
-  if (last) __threadfence();
-  return last;
-}
-
 // Pairwise sum of P partials (P >= 1) by one block, as the tree over
 // next_pow2(P) zero-padded leaves.  Segments of kVecBlock partials are aligned
 // subtrees; their sums combine by recursive halving.
@@ -198,12 +180,63 @@ __device__ A reduce_partials(const double *part, int P) {
   if (threadIdx.x == 0) {
     for (int len = nseg; len > 1; len >>= 1)
       for (int i = 0; i < len / 2; ++i) seg[i] = seg[2 * i] + seg[2 * i + 1];
-    seg[0] = seg[0];
   }
   __syncthreads();
   total = seg[0];
   __syncthreads();
   return total;
+}
+
+// Pairwise sum of P partials by one wavefront, no barrier: with Pp =
+// next_pow2(P) zero-padded leaves, lane t reduces the aligned chunk
+// [t*c, (t+1)*c), c = Pp/64, in registers and the lanes combine by butterfly.
+// Every lane returns the total.  Requires Pp <= 64*64.
+template <typename A, int C>
+__device__ __forceinline__ A lane_chunk_tree(const double *part, int base, int P) {
+  if constexpr (C > 16) {   // aligned 16-leaf subtrees, then their pairwise sum
+    A s[C / 16];
+#pragma unroll
+    for (int i = 0; i < C / 16; ++i) s[i] = lane_chunk_tree<A, 16>(part, base + 16 * i, P);
+#pragma unroll
+    for (int len = C / 16; len > 1; len >>= 1)
+#pragma unroll
+      for (int i = 0; i < len / 2; ++i) s[i] = s[2 * i] + s[2 * i + 1];
+    return s[0];
+  } else {
+    A v[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) v[i] = (base + i < P) ? (A)part[base + i] : (A)0;
+#pragma unroll
+    for (int len = C; len > 1; len >>= 1)
+#pragma unroll
+      for (int i = 0; i < len / 2; ++i) v[i] = v[2 * i] + v[2 * i + 1];
+    return v[0];
+  }
+}
+
+constexpr int kWaveReduceMax = 64 * 64;
+
+template <typename A>
+__device__ __forceinline__ A wave_reduce_partials(const double *part, int P) {
+  int Pp = 1;
+  while (Pp < P) Pp <<= 1;
+  const int lane = threadIdx.x & 63;
+  A v;
+  if (Pp <= 64) {
+    v = (lane < P) ? (A)part[lane] : (A)0;
+  } else {
+    const int c = Pp >> 6;
+    const int base = lane * c;
+    switch (c) {
+    case 2: v = lane_chunk_tree<A, 2>(part, base, P); break;
+    case 4: v = lane_chunk_tree<A, 4>(part, base, P); break;
+    case 8: v = lane_chunk_tree<A, 8>(part, base, P); break;
+    case 16: v = lane_chunk_tree<A, 16>(part, base, P); break;
+    case 32: v = lane_chunk_tree<A, 32>(part, base, P); break;
+    default: v = lane_chunk_tree<A, 64>(part, base, P); break;
+    }
+  }
+  return wave_tree(v);
 }
 
 // ---------------------------------------------------------------------------

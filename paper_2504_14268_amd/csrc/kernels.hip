@@ -1,15 +1,19 @@
 // kernels.hip -- gfx950 kernels of the mixed-precision CG iteration.
 //
-// One CG iteration is one "slot" of three launches on one stream:
+// One CG iteration is one "slot" of four launches on one stream:
 //   K1  SpMV q = A_fs p in the LDS-staged CSR form, fused partial of nu = p.q
 //       (or, in the other modes: the fp64 residual b - A x_hi of a start,
 //       restart, replacement or final check, fused with its squared norm);
-//   K2  x_lo += alpha p, r -= alpha q and the partial of sigma' = r.r;
+//   K2  every block reduces K1's partials to nu and alpha = sigma/nu itself,
+//       then x_lo += alpha p, r -= alpha q and the partial of sigma' = r.r;
+//   KS  one block: the final reductions and the scalar step -- alpha, beta, rho,
+//       convergence and replacement tests, the policy's state, reward, Q update
+//       and next action; the only writer of the control block;
 //   K3  p = r + beta p (or fold x_lo into x_hi, or p = r after a start), with
 //       the conversion of r and p when the next action changes the tier.
-// The block that finishes a reduction last (integer ticket) runs the scalar
-// step: alpha, beta, rho, convergence and replacement tests, the policy's
-// state, reward, Q update and next action.  The host only enqueues slots.
+// No kernel communicates between its own workgroups: kernel boundaries order
+// every hand-off, so no workgroup pays a device-wide cache write-back.  The host
+// only enqueues slots.
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -80,50 +84,99 @@ __device__ __forceinline__ void load_vals8(const Mat &A, int c, typename AccT<FS
   }
 }
 
-// LDS capacity (entries) of one staging window: 32 KiB of values + gathered x.
-template <typename Acc> struct Cap { static constexpr int value = 16384 / sizeof(Acc); };
+// LDS capacity (entries) of one staging window per 256 rows: 8 KiB of values
+// (accumulation type) and their column indices.
+template <typename Acc> struct Cap { static constexpr int value = 8192 / sizeof(Acc); };
+constexpr int kRPT = 2;                                  // rows per thread in K1
+constexpr int kLdsDoubles = kRPT * 2 * 8192 / 8;
 
-// Row accumulators of a block of kRowsPerBlock rows starting at r0: the fma
-// chain over each row in CSR order (thread = row).  The block's nonzeros are
-// staged through LDS in windows: aligned 8-entry groups of values and column
-// indices are read with vector loads, x[col] is gathered once per entry.
-template <int FS, typename V>
-__device__ typename AccT<FS>::type spmv_rows(const Mat &A, const V *__restrict__ x, int r0, int rows,
-                                             void *lds_raw) {
-  using Acc = typename AccT<FS>::type;
-  constexpr int CAP = Cap<Acc>::value;
-  Acc *lv = (Acc *)lds_raw;
-  Acc *lx = lv + CAP;
-  const int tid = threadIdx.x;
-  const int ks = A.rp[r0], ke = A.rp[r0 + rows];
-  int my_s = 0, my_e = 0;
-  if (tid < rows) {
-    my_s = A.rp[r0 + tid];
-    my_e = A.rp[r0 + tid + 1];
+template <typename A>
+__device__ __forceinline__ void lds_store8(A *p, const A (&v)[8]) {
+  if constexpr (sizeof(A) == 4) {
+    *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+    *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) *(double2 *)(p + 2 * j) = make_double2(v[2 * j], v[2 * j + 1]);
   }
-  Acc acc = (Acc)0;
-  for (int w0 = ks; w0 < ke; w0 += CAP) {
-    const int w1 = min(w0 + CAP, ke);
-    for (int c = (w0 & ~7) + tid * 8; c < w1; c += kBlock * 8) {
+}
+
+// Row accumulators of RPT*kRowsPerBlock consecutive rows starting at r0: thread
+// t owns rows r0 + t + j*kRowsPerBlock (j < RPT) and runs each row's fma chain
+// in CSR order.  The rows' values and column indices are staged through LDS in
+// windows that start at 8-aligned positions (aligned 8-entry groups, vector
+// loads and vector LDS stores).  x is gathered in the row loop: lane t reads
+// the k-th column of its own row, so on banded and stencil matrices a
+// wavefront's gathers fall on neighbouring addresses.  Gathers are issued eight
+// at a time ahead of their fma chain.
+template <int FS, int RPT, typename V>
+__device__ __forceinline__ void spmv_rows(const Mat &A, const V *__restrict__ x, int r0, int nrows,
+                                          void *lds_raw, typename AccT<FS>::type (&acc)[RPT]) {
+  using Acc = typename AccT<FS>::type;
+  constexpr int CAP = Cap<Acc>::value * RPT;
+  Acc *lv = (Acc *)lds_raw;
+  int *lc = (int *)(lv + CAP);
+  const int tid = threadIdx.x;
+  const int ks = A.rp[r0], ke = A.rp[r0 + nrows];
+  int my_s[RPT], my_e[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int lr = tid + j * kRowsPerBlock;
+    my_s[j] = 0;
+    my_e[j] = 0;
+    if (lr < nrows) {
+      my_s[j] = A.rp[r0 + lr];
+      my_e[j] = A.rp[r0 + lr + 1];
+    }
+    acc[j] = (Acc)0;
+  }
+  for (int wb = ks & ~7; wb < ke; wb += CAP) {
+    const int we = min(wb + CAP, ke);
+    for (int c = wb + tid * 8; c < we; c += kBlock * 8) {
       Acc v[8];
       load_vals8<FS>(A, c, v);
-      const int4 ca = *(const int4 *)(A.ci + c), cb = *(const int4 *)(A.ci + c + 4);
-      const int cols[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+      lds_store8(lv + (c - wb), v);
+      *(int4 *)(lc + (c - wb)) = *(const int4 *)(A.ci + c);
+      *(int4 *)(lc + (c - wb) + 4) = *(const int4 *)(A.ci + c + 4);
+    }
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int kk = c + j;
-        if (kk >= w0 && kk < w1) {
-          lv[kk - w0] = v[j];
-          lx[kk - w0] = to_acc<Acc>(x[cols[j]]);
+    for (int j = 0; j < RPT; ++j) {
+      const int lo = max(my_s[j], wb), hi = min(my_e[j], we);
+      for (int kk = lo; kk < hi; kk += 8) {
+        const int cnt = hi - kk;
+        Acc xv[8], vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (u < cnt) {
+            vv[u] = lv[kk - wb + u];
+            xv[u] = to_acc<Acc>(x[lc[kk - wb + u]]);
+          }
         }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (u < cnt) acc[j] = fma_acc(vv[u], xv[u], acc[j]);
       }
     }
     __syncthreads();
-    const int lo = max(my_s, w0), hi = min(my_e, w1);
-    for (int kk = lo; kk < hi; ++kk) acc = fma_acc(lv[kk - w0], lx[kk - w0], acc);
-    __syncthreads();
   }
-  return acc;
+}
+
+// Sums of RPT 256-row subtrees at once (one LDS round): each thread holds one
+// leaf per subtree.
+template <int RPT, typename A>
+__device__ __forceinline__ void block_tree_multi(const A (&leaf)[RPT], double (&out)[RPT]) {
+  __shared__ A ws[RPT][kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const A v = wave_tree(leaf[j]);
+    if (lane == 0) ws[j][wave] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) out[j] = (double)((ws[j][0] + ws[j][1]) + (ws[j][2] + ws[j][3]));
+  __syncthreads();
 }
 
 // q_i = rd_tier(2^{e_i} acc) (e_i = 0 unless fp16)
@@ -144,6 +197,27 @@ __device__ __forceinline__ double dot_leaf_block(V u, V v, bool valid) {
   return (double)block_tree(l);
 }
 
+template <int FD, int RPT, typename V>
+__device__ __forceinline__ void dot_leaf_multi(const V (&u)[RPT], const V (&v)[RPT], const bool (&valid)[RPT],
+                                               double (&out)[RPT]) {
+  using A = typename AccT<FD>::type;
+  A l[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) l[j] = valid[j] ? dot_leaf<FD>(u[j], v[j]) : (A)0;
+  block_tree_multi<RPT>(l, out);
+}
+
+template <int RPT, typename V>
+__device__ __forceinline__ void dot_leaf_multi_rt(int fd, const V (&u)[RPT], const V (&v)[RPT],
+                                                  const bool (&valid)[RPT], double (&out)[RPT]) {
+  switch (fd) {
+  case FP16: dot_leaf_multi<FP16, RPT>(u, v, valid, out); break;
+  case BF16: dot_leaf_multi<BF16, RPT>(u, v, valid, out); break;
+  case FP32: dot_leaf_multi<FP32, RPT>(u, v, valid, out); break;
+  default: dot_leaf_multi<FP64, RPT>(u, v, valid, out); break;
+  }
+}
+
 template <typename V>
 __device__ __forceinline__ double dot_leaf_block_rt(int fd, V u, V v, bool valid) {
   switch (fd) {
@@ -154,14 +228,33 @@ __device__ __forceinline__ double dot_leaf_block_rt(int fd, V u, V v, bool valid
   }
 }
 
-__device__ __forceinline__ double reduce_partials_rt(int fd, const double *part, int P) {
-  return fd == FP64 ? reduce_partials<double>(part, P) : (double)reduce_partials<float>(part, P);
+// Pairwise total of P partials, identical in every thread of the block; per
+// wavefront without a barrier when P is small enough (block-uniform choice).
+template <typename A>
+__device__ __forceinline__ double partials_total(const double *part, int P) {
+  if (P <= kWaveReduceMax) return (double)wave_reduce_partials<A>(part, P);
+  return (double)reduce_partials<A>(part, P);
 }
 
-__device__ __forceinline__ bool publish(double *part, int idx, double val, unsigned *ticket, int nblocks) {
-  const bool last = publish_partial(part, idx, val, ticket, (unsigned)nblocks);
-  if (last && threadIdx.x == 0) *ticket = 0u;
-  return last;
+__device__ __forceinline__ double reduce_partials_rt(int fd, const double *part, int P) {
+  return fd == FP64 ? partials_total<double>(part, P) : partials_total<float>(part, P);
+}
+
+// Sum of eight consecutive sibling subtrees in the accumulation format of fd.
+__device__ __forceinline__ double tree8_rt(int fd, const double (&s)[8]) {
+  if (fd == FP64) return tree8(s);
+  float f[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) f[j] = (float)s[j];
+  return (double)tree8(f);
+}
+
+// XCD-aware order: consecutive workgroups land on different XCDs, so XCD x gets
+// the contiguous range of groups [x*per, (x+1)*per) (its gathers share its L2).
+__device__ __forceinline__ int xcd_group(int G) {
+  const int per = G >> 3;
+  const int b = blockIdx.x;
+  return (b & 7) * per + (b >> 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -293,8 +386,14 @@ __device__ int argmax64f(const float *v) {
 }
 
 // ---------------------------------------------------------------------------
-// scalar step (thread 0 of a last block)
+// scalar step (KS): the control block and the policy description live in LDS
+// for the duration of the step.
 // ---------------------------------------------------------------------------
+struct Sx {
+  Ctl *ctl;
+  const PolicyDev *pol;
+  Hist h;
+};
 __device__ void set_done(Ctl *c) {
   c->mode = M_DONE;
   c->k2op = K2_NONE;
@@ -304,7 +403,7 @@ __device__ void set_done(Ctl *c) {
 // Install the next action.  After a start/restart r is in the fp64 container
 // and K3 copies it into the new tier; otherwise K3 applies p = r + beta p in the
 // old tier and converts r, p if the tier changes.
-__device__ void apply_decision(const KArgs &a, int na, int ex, bool from_init) {
+__device__ void apply_decision(const Sx &a, int na, int ex, bool from_init) {
   Ctl *c = a.ctl;
   const int k = c->k;
   if (from_init && k >= c->maxit) {
@@ -335,7 +434,7 @@ __device__ void apply_decision(const KArgs &a, int na, int ex, bool from_init) {
 
 // Start / restart: rho_0 from the fp64 residual, first action.  Returns 1 when
 // the decision needs the block's MLP forward (features left in s_feat).
-__device__ int init_t0(const KArgs &a, double s64, float *s_feat) {
+__device__ int init_t0(const Sx &a, double s64, float *s_feat) {
   Ctl *c = a.ctl;
   const PolicyDev *P = a.pol;
   const int k = c->k;
@@ -376,7 +475,7 @@ __device__ int init_t0(const KArgs &a, double s64, float *s_feat) {
 
 // End of an iteration (or of a failed one): history, beta, training update,
 // rollout, convergence / breakdown / fallback / budget, next action.
-__device__ int finish_t0(const KArgs &a, bool completed, bool broke, bool converged, bool stagnated,
+__device__ int finish_t0(const Sx &a, bool completed, bool broke, bool converged, bool stagnated,
                          float *s_feat) {
   Ctl *c = a.ctl;
   const PolicyDev *P = a.pol;
@@ -463,7 +562,7 @@ __device__ int finish_t0(const KArgs &a, bool completed, bool broke, bool conver
 
 // Block-level wrappers: thread 0 runs the scalar step; the block joins for an
 // MLP decision.
-__device__ void finish_block(const KArgs &a, bool completed, bool broke, bool converged, bool stagnated) {
+__device__ void finish_block(const Sx &a, bool completed, bool broke, bool converged, bool stagnated) {
   __shared__ int s_need;
   __shared__ float s_feat[kMlpIn], s_logits[kNAct];
   if (threadIdx.x == 0) s_need = finish_t0(a, completed, broke, converged, stagnated, s_feat);
@@ -474,7 +573,7 @@ __device__ void finish_block(const KArgs &a, bool completed, bool broke, bool co
   }
 }
 
-__device__ void init_block(const KArgs &a, double s64) {
+__device__ void init_block(const Sx &a, double s64) {
   __shared__ int s_need;
   __shared__ float s_feat[kMlpIn], s_logits[kNAct];
   if (threadIdx.x == 0) s_need = init_t0(a, s64, s_feat);
@@ -485,7 +584,7 @@ __device__ void init_block(const KArgs &a, double s64) {
   }
 }
 
-__device__ void replace_block(const KArgs &a, double s64) {
+__device__ void replace_block(const Sx &a, double s64) {
   __shared__ int s_f[3];
   if (threadIdx.x == 0) {
     Ctl *c = a.ctl;
@@ -519,108 +618,123 @@ __device__ void replace_block(const KArgs &a, double s64) {
 }
 
 // ---------------------------------------------------------------------------
-// K1
+// K1: SpMV (or fp64 residual) over a group of kGroupRows rows; one partial per
+// group = the pairwise sum of its eight 256-row subtrees.
 // ---------------------------------------------------------------------------
+constexpr int kGroupBlocks = kVecBlock / kRowsPerBlock;   // 8 row blocks = 2048 rows
+
 template <int FS, int TIER>
-__device__ void k1_iter(const KArgs &a, int blk, void *lds) {
+__device__ __forceinline__ void k1_iter(const KArgs &a, int g, void *lds) {
   using V = typename TierT<TIER>::type;
   const V *p;
   V *q;
   if constexpr (TIER) { p = a.v.p64; q = a.v.q64; } else { p = a.v.p32; q = a.v.q32; }
-  const int r0 = blk * kRowsPerBlock;
-  const int rows = min(kRowsPerBlock, a.A.n - r0);
   const int fd = (a.ctl->action >> 2) & 3;
-  const auto acc = spmv_rows<FS>(a.A, p, r0, rows, lds);
-  const int i = r0 + threadIdx.x;
-  const bool valid = threadIdx.x < rows;
-  V qi = (V)0, pi = (V)0;
-  if (valid) {
-    qi = spmv_out<FS, V>(a.A, i, acc);
-    q[i] = qi;
-    pi = p[i];
-  }
-  const double part = dot_leaf_block_rt(fd, pi, qi, valid);
-  if (publish(a.part, blk, part, &a.tickets[0], a.P1)) {
-    const double nu = reduce_partials_rt(fd, a.part, a.P1);
-    __shared__ int s_broke;
-    if (threadIdx.x == 0) {
-      Ctl *c = a.ctl;
-      const double alpha = c->sigma / nu;
-      const bool broke = !(nu > 0.0 && isfinite(nu)) || !isfinite(alpha);
-      if (!broke) {
-        c->alpha = alpha;
-        c->k2op = K2_AXPY;
-        c->k3op = K3_NONE;
-      }
-      s_broke = broke;
+  const int n = a.A.n;
+  double sub[8];
+#pragma unroll 1
+  for (int sb = 0; sb < kGroupBlocks / kRPT; ++sb) {
+    const int r0 = (g * kGroupBlocks + sb * kRPT) * kRowsPerBlock;
+    if (r0 >= n) {            // zero-padded subtrees
+#pragma unroll
+      for (int j = 0; j < kRPT; ++j) sub[sb * kRPT + j] = 0.0;
+      continue;
     }
-    __syncthreads();
-    if (s_broke) finish_block(a, false, true, false, false);
+    const int nrows = min(kRPT * kRowsPerBlock, n - r0);
+    typename AccT<FS>::type acc[kRPT];
+    spmv_rows<FS, kRPT>(a.A, p, r0, nrows, lds, acc);
+    V qi[kRPT], pi[kRPT];
+    bool valid[kRPT];
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = threadIdx.x + j * kRowsPerBlock;
+      valid[j] = lr < nrows;
+      qi[j] = (V)0;
+      pi[j] = (V)0;
+      if (valid[j]) {
+        qi[j] = spmv_out<FS, V>(a.A, r0 + lr, acc[j]);
+        q[r0 + lr] = qi[j];
+        pi[j] = p[r0 + lr];
+      }
+    }
+    double s2[kRPT];
+    dot_leaf_multi_rt<kRPT>(fd, pi, qi, valid, s2);
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) sub[sb * kRPT + j] = s2[j];
   }
+  if (threadIdx.x == 0) a.part1[g] = tree8_rt(fd, sub);
 }
 
-// fp64 residual r = b - A x_hi with its squared norm (start, replacement, final).
-__device__ void k1_residual(const KArgs &a, int blk, int mode, void *lds) {
-  const int r0 = blk * kRowsPerBlock;
-  const int rows = min(kRowsPerBlock, a.A.n - r0);
-  const double acc = spmv_rows<FP64>(a.A, (const double *)a.v.xhi, r0, rows, lds);
-  double leaf = 0.0;
-  if (threadIdx.x < rows) {
-    const int i = r0 + threadIdx.x;
-    const double r = a.v.b[i] - acc;
-    leaf = r * r;
-    if (mode == M_INIT) {
-      a.v.r64[i] = r;
-    } else if (mode == M_REPLACE) {
-      if (a.ctl->tier) a.v.r64[i] = r; else a.v.r32[i] = (float)r;
+// fp64 residual r = b - A x_hi with the partial of its squared norm (start,
+// replacement, final check); a replacement also stores r in the current tier.
+__device__ __forceinline__ void k1_residual(const KArgs &a, int g, int mode, void *lds) {
+  const int n = a.A.n;
+  double sub[8];
+#pragma unroll 1
+  for (int sb = 0; sb < kGroupBlocks / kRPT; ++sb) {
+    const int r0 = (g * kGroupBlocks + sb * kRPT) * kRowsPerBlock;
+    if (r0 >= n) {
+#pragma unroll
+      for (int j = 0; j < kRPT; ++j) sub[sb * kRPT + j] = 0.0;
+      continue;
     }
-  }
-  const double part = block_tree(leaf);
-  if (publish(a.part, blk, part, &a.tickets[0], a.P1)) {
-    const double s64 = reduce_partials<double>(a.part, a.P1);
-    if (mode == M_INIT) {
-      init_block(a, s64);
-    } else if (mode == M_REPLACE) {
-      replace_block(a, s64);
-    } else if (threadIdx.x == 0) {
-      a.ctl->relres_true = sqrt(s64) / a.ctl->bnorm;
-      set_done(a.ctl);
+    const int nrows = min(kRPT * kRowsPerBlock, n - r0);
+    double acc[kRPT];
+    spmv_rows<FP64, kRPT>(a.A, (const double *)a.v.xhi, r0, nrows, lds, acc);
+    double leaf[kRPT];
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = threadIdx.x + j * kRowsPerBlock;
+      leaf[j] = 0.0;
+      if (lr < nrows) {
+        const int i = r0 + lr;
+        const double r = a.v.b[i] - acc[j];
+        leaf[j] = r * r;
+        if (mode == M_INIT) {
+          a.v.r64[i] = r;
+        } else if (mode == M_REPLACE) {
+          if (a.ctl->tier) a.v.r64[i] = r; else a.v.r32[i] = (float)r;
+        }
+      }
     }
+    double s2[kRPT];
+    block_tree_multi<kRPT>(leaf, s2);
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) sub[sb * kRPT + j] = s2[j];
   }
+  if (threadIdx.x == 0) a.part1[g] = tree8(sub);
 }
 
 __global__ __launch_bounds__(kBlock) void k_slot1(KArgs a) {
   const int mode = a.ctl->mode;
+  if (a.slot_log && blockIdx.x == 0 && threadIdx.x == 0) a.slot_log[a.slot] = (int8_t)mode;
   if (mode == M_DONE) return;
-  // XCD-aware order: consecutive workgroups go to different XCDs, so give each
-  // XCD a contiguous range of row blocks (their x gathers share its L2).
-  const int per = a.G1 >> 3;
-  const int b = blockIdx.x;
-  const int blk = (b & 7) * per + (b >> 3);
-  if (blk >= a.P1) return;
-  __shared__ double lds[4096];
+  const int g = xcd_group(a.G1);
+  if (g >= a.P2) return;
+  __shared__ double lds[kLdsDoubles];
   if (mode == M_ITER) {
     const int fs = (a.ctl->action >> 4) & 3, tier = a.ctl->tier;
     switch (fs * 2 + tier) {
-    case 0: k1_iter<FP16, 0>(a, blk, lds); break;
-    case 1: k1_iter<FP16, 1>(a, blk, lds); break;
-    case 2: k1_iter<BF16, 0>(a, blk, lds); break;
-    case 3: k1_iter<BF16, 1>(a, blk, lds); break;
-    case 4: k1_iter<FP32, 0>(a, blk, lds); break;
-    case 5: k1_iter<FP32, 1>(a, blk, lds); break;
-    case 6: k1_iter<FP64, 0>(a, blk, lds); break;
-    default: k1_iter<FP64, 1>(a, blk, lds); break;
+    case 0: k1_iter<FP16, 0>(a, g, lds); break;
+    case 1: k1_iter<FP16, 1>(a, g, lds); break;
+    case 2: k1_iter<BF16, 0>(a, g, lds); break;
+    case 3: k1_iter<BF16, 1>(a, g, lds); break;
+    case 4: k1_iter<FP32, 0>(a, g, lds); break;
+    case 5: k1_iter<FP32, 1>(a, g, lds); break;
+    case 6: k1_iter<FP64, 0>(a, g, lds); break;
+    default: k1_iter<FP64, 1>(a, g, lds); break;
     }
   } else {
-    k1_residual(a, blk, mode, lds);
+    k1_residual(a, g, mode, lds);
   }
 }
 
 // ---------------------------------------------------------------------------
-// K2: x_lo = axpy(alpha, p, x_lo), r = axpy(-alpha, q, r), sigma' = dot(r, r)
+// K2: nu (redundantly per block), alpha, x_lo = axpy(alpha, p, x_lo),
+// r = axpy(-alpha, q, r), partial of sigma' = dot(r, r).
 // ---------------------------------------------------------------------------
 template <int FA, int FD>
-__device__ void k2_body(const KArgs &a) {
+__device__ __forceinline__ void k2_body(const KArgs &a) {
   constexpr int TIER = (FA == FP64);
   using V = typename TierT<TIER>::type;
   using Acc = typename AccT<FD>::type;
@@ -628,22 +742,38 @@ __device__ void k2_body(const KArgs &a) {
   const V *p, *q;
   if constexpr (TIER) { xlo = a.v.xlo64; r = a.v.r64; p = a.v.p64; q = a.v.q64; }
   else { xlo = a.v.xlo32; r = a.v.r32; p = a.v.p32; q = a.v.q32; }
-  const double alpha = a.ctl->alpha;
   const int n = a.A.n;
   const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
-  Acc l[8];
-  if (base + 8 <= n) {
-    V pv[8], qv[8], rv[8], xv[8];
-    load8(p + base, pv);
+  const bool full = base + 8 <= n;
+  double nu = 0.0;
+  if constexpr (TIER) nu = partials_total<Acc>(a.part1, a.P2);   // fp64 tier: registers first
+  V pv[8], qv[8], rv[8], xv[8];
+  if (full) {                       // fp32 tier: streaming loads first, they stay
+    load8(p + base, pv);            // in flight while the wave reduces nu
     load8(q + base, qv);
     load8(r + base, rv);
     load8(xlo + base, xv);
+  } else {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      xv[j] = axpy1<FA>(alpha, pv[j], xv[j]);
-      rv[j] = axpy1<FA>(-alpha, qv[j], rv[j]);
-      l[j] = dot_leaf<FD>(rv[j], rv[j]);
+      const int i = base + j;
+      pv[j] = i < n ? p[i] : (V)0;
+      qv[j] = i < n ? q[i] : (V)0;
+      rv[j] = i < n ? r[i] : (V)0;
+      xv[j] = i < n ? xlo[i] : (V)0;
     }
+  }
+  if constexpr (!TIER) nu = partials_total<Acc>(a.part1, a.P2);
+  const double alpha = a.ctl->sigma / nu;
+  if (!(nu > 0.0 && isfinite(nu)) || !isfinite(alpha)) return;   // breakdown: KS handles it
+  Acc l[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    xv[j] = axpy1<FA>(alpha, pv[j], xv[j]);
+    rv[j] = axpy1<FA>(-alpha, qv[j], rv[j]);
+    l[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], rv[j]) : (Acc)0;
+  }
+  if (full) {
     store8(xlo + base, xv);
     store8(r + base, rv);
   } else {
@@ -651,44 +781,19 @@ __device__ void k2_body(const KArgs &a) {
     for (int j = 0; j < 8; ++j) {
       const int i = base + j;
       if (i < n) {
-        xlo[i] = axpy1<FA>(alpha, p[i], xlo[i]);
-        const V ri = axpy1<FA>(-alpha, q[i], r[i]);
-        r[i] = ri;
-        l[j] = dot_leaf<FD>(ri, ri);
-      } else {
-        l[j] = (Acc)0;
+        xlo[i] = xv[j];
+        r[i] = rv[j];
       }
     }
   }
   const Acc t = block_tree(tree8(l));
-  if (publish(a.part, blockIdx.x, (double)t, &a.tickets[1], a.P2)) {
-    const double sig = (double)reduce_partials<Acc>(a.part, a.P2);
-    __shared__ int s_fin;
-    if (threadIdx.x == 0) {
-      Ctl *c = a.ctl;
-      c->sig_new = sig;
-      c->k += 1;
-      const int k = c->k;
-      const double rho = sqrt(sig) / c->bnorm;
-      c->rho_new = rho;
-      const bool rep = (c->R > 0 && k % c->R == 0) || rho <= c->tol || !isfinite(sig);
-      if (rep) {
-        c->mode = M_REPLACE;
-        c->k2op = K2_NONE;
-        c->k3op = K3_FOLD;
-        s_fin = 0;
-      } else {
-        s_fin = 1;
-      }
-    }
-    __syncthreads();
-    if (s_fin) finish_block(a, true, false, false, false);
-  }
+  if (threadIdx.x == 0) a.part2[blockIdx.x] = (double)t;
 }
 
 __global__ __launch_bounds__(kBlock) void k_slot2(KArgs a) {
-  if (a.ctl->k2op != K2_AXPY) return;
-  const int act = a.ctl->action;
+  const Ctl *c = a.ctl;
+  if (c->mode != M_ITER) return;
+  const int act = c->action;
   switch (((act & 3) << 2) | ((act >> 2) & 3)) {
   case 0: k2_body<FP16, FP16>(a); break;
   case 1: k2_body<FP16, BF16>(a); break;
@@ -710,6 +815,92 @@ __global__ __launch_bounds__(kBlock) void k_slot2(KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// KS: one block; final reductions and the scalar / policy step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void copy_words(void *dst, const void *src, int bytes) {
+  uint64_t *d = (uint64_t *)dst;
+  const uint64_t *s = (const uint64_t *)src;
+  for (int i = threadIdx.x; i < bytes / 8; i += kBlock) d[i] = s[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scalar(KArgs a) {
+  __shared__ Ctl sc;
+  __shared__ PolicyDev sp;
+  static_assert(sizeof(Ctl) % 8 == 0 && sizeof(PolicyDev) % 8 == 0, "word copies");
+  copy_words(&sc, a.ctl, sizeof(Ctl));
+  copy_words(&sp, a.pol, sizeof(PolicyDev));
+  __syncthreads();
+  const int mode = sc.mode;
+  if (mode == M_DONE) return;
+  const Sx x{&sc, &sp, a.h};
+  Ctl *c = &sc;
+  if (mode == M_ITER) {
+    const int fd = (c->action >> 2) & 3;
+    const double nu = reduce_partials_rt(fd, a.part1, a.P2);
+    const double sig = reduce_partials_rt(fd, a.part2, a.P2);
+    const double alpha = c->sigma / nu;
+    if (!(nu > 0.0 && isfinite(nu)) || !isfinite(alpha)) {
+      finish_block(x, false, true, false, false);
+    } else {
+      __shared__ int s_fin;
+      if (threadIdx.x == 0) {
+        c->alpha = alpha;
+        c->sig_new = sig;
+        c->k += 1;
+        const int k = c->k;
+        const double rho = sqrt(sig) / c->bnorm;
+        c->rho_new = rho;
+        const bool rep = (c->R > 0 && k % c->R == 0) || rho <= c->tol || !isfinite(sig);
+        if (rep) {
+          c->mode = M_REPLACE;
+          c->k2op = K2_NONE;
+          c->k3op = K3_FOLD;
+          s_fin = 0;
+        } else {
+          s_fin = 1;
+        }
+      }
+      __syncthreads();
+      if (s_fin) finish_block(x, true, false, false, false);
+    }
+  } else {
+    bool skip = false;
+    if (mode == M_INIT && c->bnorm_ready == 0) {
+      const double bb = partials_total<double>(a.part0, a.P2);
+      __shared__ int s_zero;
+      if (threadIdx.x == 0) {
+        c->bnorm = sqrt(bb);
+        c->bnorm_ready = 1;
+        s_zero = 0;
+        if (c->bnorm == 0.0) {
+          c->zero_solution = 1;
+          a.h.rho[0] = 0.0;
+          c->status = 0;
+          c->relres_true = 0.0;
+          set_done(c);
+          s_zero = 1;
+        }
+      }
+      __syncthreads();
+      skip = s_zero != 0;
+    }
+    if (!skip) {
+      const double s64 = partials_total<double>(a.part1, a.P2);
+      if (mode == M_INIT) {
+        init_block(x, s64);
+      } else if (mode == M_REPLACE) {
+        replace_block(x, s64);
+      } else if (threadIdx.x == 0) {   // M_FINAL
+        c->relres_true = sqrt(s64) / c->bnorm;
+        set_done(c);
+      }
+    }
+  }
+  __syncthreads();
+  copy_words(a.ctl, &sc, sizeof(Ctl));
+}
+
+// ---------------------------------------------------------------------------
 // K3: p = rd_fa(fma(beta, p, r)) [+ tier switch], fold, or p = r after a start
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void fold1(double *xhi, int i, double xl) {
@@ -718,7 +909,7 @@ __device__ __forceinline__ void fold1(double *xhi, int i, double xl) {
 }
 
 template <int FA>
-__device__ void k3_xpay(const KArgs &a, bool sw) {
+__device__ __forceinline__ void k3_xpay(const KArgs &a, bool sw) {
   constexpr int TIER = (FA == FP64);
   using V = typename TierT<TIER>::type;
   V *p, *r, *xlo;
@@ -797,7 +988,7 @@ __global__ __launch_bounds__(kBlock) void k_slot3(KArgs a) {
 // ---------------------------------------------------------------------------
 // start / finish
 // ---------------------------------------------------------------------------
-// x_hi = x0, x_lo = 0, ||b|| (pairwise fp64).
+// x_hi = x0, x_lo = 0, partials of b.b (pairwise fp64) for ||b||.
 __global__ __launch_bounds__(kBlock) void k_start(KArgs a) {
   const int n = a.A.n;
   const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
@@ -815,20 +1006,7 @@ __global__ __launch_bounds__(kBlock) void k_start(KArgs a) {
     }
   }
   const double t = block_tree(tree8(l));
-  if (publish(a.part, blockIdx.x, t, &a.tickets[2], a.P2)) {
-    const double bb = reduce_partials<double>(a.part, a.P2);
-    if (threadIdx.x == 0) {
-      Ctl *c = a.ctl;
-      c->bnorm = sqrt(bb);
-      if (c->bnorm == 0.0) {
-        c->zero_solution = 1;
-        a.h.rho[0] = 0.0;
-        c->status = 0;
-        c->relres_true = 0.0;
-        set_done(c);
-      }
-    }
-  }
+  if (threadIdx.x == 0) a.part0[blockIdx.x] = t;
 }
 
 // x = x_hi + x_lo; requests the final true-residual check after a budget stop
@@ -867,15 +1045,15 @@ __global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const 
     const uint64_t u = (uint64_t)__double_as_longlong(mx);
     const int ef = (int)((u >> 52) & 0x7ff);
     const uint64_t mant = u & 0xFFFFFFFFFFFFFull;
-    int c;
+    int cexp;
     if (ef == 0) {   // fp64 subnormal maximum
       int ee;
       const double m = frexp(mx, &ee);
-      c = (m == 0.5) ? ee - 1 : ee;
+      cexp = (m == 0.5) ? ee - 1 : ee;
     } else {
-      c = (ef - 1023) + (mant != 0 ? 1 : 0);
+      cexp = (ef - 1023) + (mant != 0 ? 1 : 0);
     }
-    e = c - 15;
+    e = cexp - 15;
     e = e < -128 ? -128 : (e > 127 ? 127 : e);
   }
   rexp[i] = (int8_t)e;
@@ -891,35 +1069,32 @@ __global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const 
 // single-op kernels (same device code paths as the solver)
 // ---------------------------------------------------------------------------
 template <int FS, int TIER>
-__global__ __launch_bounds__(kBlock) void k_op_spmv(Mat A, const void *pv, void *qv, int P1, int G1) {
+__global__ __launch_bounds__(kBlock) void k_op_spmv(Mat A, const void *pv, void *qv, int P, int G) {
   using V = typename TierT<TIER>::type;
-  const int per = G1 >> 3;
-  const int b = blockIdx.x;
-  const int blk = (b & 7) * per + (b >> 3);
-  if (blk >= P1) return;
-  __shared__ double lds[4096];
+  const int blk = xcd_group(G);
+  if (blk >= P) return;
+  __shared__ double lds[kLdsDoubles];
   const int r0 = blk * kRowsPerBlock;
   const int rows = min(kRowsPerBlock, A.n - r0);
-  const auto acc = spmv_rows<FS>(A, (const V *)pv, r0, rows, lds);
-  if (threadIdx.x < rows) ((V *)qv)[r0 + threadIdx.x] = spmv_out<FS, V>(A, r0 + threadIdx.x, acc);
+  typename AccT<FS>::type acc[1];
+  spmv_rows<FS, 1>(A, (const V *)pv, r0, rows, lds, acc);
+  if (threadIdx.x < rows) ((V *)qv)[r0 + threadIdx.x] = spmv_out<FS, V>(A, r0 + threadIdx.x, acc[0]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_op_residual(Mat A, const double *b, const double *x, double *r,
-                                                         int P1, int G1) {
-  const int per = G1 >> 3;
-  const int bb = blockIdx.x;
-  const int blk = (bb & 7) * per + (bb >> 3);
-  if (blk >= P1) return;
-  __shared__ double lds[4096];
+                                                         int P, int G) {
+  const int blk = xcd_group(G);
+  if (blk >= P) return;
+  __shared__ double lds[kLdsDoubles];
   const int r0 = blk * kRowsPerBlock;
   const int rows = min(kRowsPerBlock, A.n - r0);
-  const double acc = spmv_rows<FP64>(A, x, r0, rows, lds);
-  if (threadIdx.x < rows) r[r0 + threadIdx.x] = b[r0 + threadIdx.x] - acc;
+  double acc[1];
+  spmv_rows<FP64, 1>(A, x, r0, rows, lds, acc);
+  if (threadIdx.x < rows) r[r0 + threadIdx.x] = b[r0 + threadIdx.x] - acc[0];
 }
 
 template <int FD, int TIER>
-__global__ __launch_bounds__(kBlock) void k_op_dot(int n, const void *uv, const void *vv, double *part,
-                                                    unsigned *ticket, int P2, double *out) {
+__global__ __launch_bounds__(kBlock) void k_op_dot(int n, const void *uv, const void *vv, double *part) {
   using V = typename TierT<TIER>::type;
   using Acc = typename AccT<FD>::type;
   const V *u = (const V *)uv, *v = (const V *)vv;
@@ -930,10 +1105,12 @@ __global__ __launch_bounds__(kBlock) void k_op_dot(int n, const void *uv, const 
     l[j] = (i < n) ? dot_leaf<FD>(u[i], v[i]) : (Acc)0;
   }
   const Acc t = block_tree(tree8(l));
-  if (publish(part, blockIdx.x, (double)t, ticket, P2)) {
-    const double s = (double)reduce_partials<Acc>(part, P2);
-    if (threadIdx.x == 0) *out = s;
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = (double)t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_op_dot_final(int fd, const double *part, int P, double *out) {
+  const double s = reduce_partials_rt(fd, part, P);
+  if (threadIdx.x == 0) *out = s;
 }
 
 template <int FA>
@@ -972,15 +1149,22 @@ __global__ __launch_bounds__(kBlock) void k_policy_decide(const PolicyDev *P, in
 // ---------------------------------------------------------------------------
 void launch_start(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_start, dim3(a.P2), dim3(kBlock), 0, s, a); }
 
+void launch_k1(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_slot1, dim3(a.G1), dim3(kBlock), 0, s, a); }
+void launch_k2(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_slot2, dim3(a.P2), dim3(kBlock), 0, s, a); }
+void launch_ks(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, a); }
+void launch_k3(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_slot3, dim3(a.P2), dim3(kBlock), 0, s, a); }
+
 void launch_slot(const KArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_slot1, dim3(a.G1), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_slot2, dim3(a.P2), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_slot3, dim3(a.P2), dim3(kBlock), 0, s, a);
+  launch_k1(a, s);
+  launch_k2(a, s);
+  launch_ks(a, s);
+  launch_k3(a, s);
 }
 
 void launch_finish(const KArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(a.P2), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_slot1, dim3(a.G1), dim3(kBlock), 0, s, a);
+  launch_k1(a, s);
+  launch_ks(a, s);
 }
 
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,
@@ -989,27 +1173,32 @@ void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t 
                      rexp);
 }
 
-void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, int P1, int G1, hipStream_t s) {
+void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipStream_t s) {
+  const int P = (A.n + kRowsPerBlock - 1) / kRowsPerBlock;
+  const int G = (P + 7) / 8 * 8;
+#define MPCG_SPMV(FS, T) hipLaunchKernelGGL((k_op_spmv<FS, T>), dim3(G), dim3(kBlock), 0, s, A, p, q, P, G)
   switch (fs * 2 + tier) {
-  case 0: hipLaunchKernelGGL((k_op_spmv<FP16, 0>), dim3(G1), dim3(kBlock), 0, s, A, p, q, P1, G1); break;
-  case 1: hipLaunchKernelGGL((k_op_spmv<FP16, 1>), dim3(G1), dim3(kBlock), 0, s, A, p, q, P1, G1); break;
-  case 2: hipLaunchKernelGGL((k_op_spmv<BF16, 0>), dim3(G1), dim3(kBlock), 0, s, A, p, q, P1, G1); break;
-  case 3: hipLaunchKernelGGL((k_op_spmv<BF16, 1>), dim3(G1), dim3(kBlock), 0, s, A, p, q, P1, G1); break;
-  case 4: hipLaunchKernelGGL((k_op_spmv<FP32, 0>), dim3(G1), dim3(kBlock), 0, s, A, p, q, P1, G1); break;
-  case 5: hipLaunchKernelGGL((k_op_spmv<FP32, 1>), dim3(G1), dim3(kBlock), 0, s, A, p, q, P1, G1); break;
-  case 6: hipLaunchKernelGGL((k_op_spmv<FP64, 0>), dim3(G1), dim3(kBlock), 0, s, A, p, q, P1, G1); break;
-  default: hipLaunchKernelGGL((k_op_spmv<FP64, 1>), dim3(G1), dim3(kBlock), 0, s, A, p, q, P1, G1); break;
+  case 0: MPCG_SPMV(FP16, 0); break;
+  case 1: MPCG_SPMV(FP16, 1); break;
+  case 2: MPCG_SPMV(BF16, 0); break;
+  case 3: MPCG_SPMV(BF16, 1); break;
+  case 4: MPCG_SPMV(FP32, 0); break;
+  case 5: MPCG_SPMV(FP32, 1); break;
+  case 6: MPCG_SPMV(FP64, 0); break;
+  default: MPCG_SPMV(FP64, 1); break;
   }
+#undef MPCG_SPMV
 }
 
-void launch_op_residual(const Mat &A, const double *b, const double *x, double *r, int P1, int G1,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_op_residual, dim3(G1), dim3(kBlock), 0, s, A, b, x, r, P1, G1);
+void launch_op_residual(const Mat &A, const double *b, const double *x, double *r, hipStream_t s) {
+  const int P = (A.n + kRowsPerBlock - 1) / kRowsPerBlock;
+  const int G = (P + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_op_residual, dim3(G), dim3(kBlock), 0, s, A, b, x, r, P, G);
 }
 
-void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double *part, unsigned *ticket,
-                   int P2, double *out, hipStream_t s) {
-#define MPCG_DOT(FD, T) hipLaunchKernelGGL((k_op_dot<FD, T>), dim3(P2), dim3(kBlock), 0, s, n, u, v, part, ticket, P2, out)
+void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double *part, int P2, double *out,
+                   hipStream_t s) {
+#define MPCG_DOT(FD, T) hipLaunchKernelGGL((k_op_dot<FD, T>), dim3(P2), dim3(kBlock), 0, s, n, u, v, part)
   switch (fd * 2 + tier) {
   case 0: MPCG_DOT(FP16, 0); break;
   case 1: MPCG_DOT(FP16, 1); break;
@@ -1021,6 +1210,7 @@ void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double
   default: MPCG_DOT(FP64, 1); break;
   }
 #undef MPCG_DOT
+  hipLaunchKernelGGL(k_op_dot_final, dim3(1), dim3(kBlock), 0, s, fd, part, P2, out);
 }
 
 void launch_op_axpy(int n, int fa, double alpha, const void *u, void *y, hipStream_t s) {

@@ -72,7 +72,7 @@ struct Ctl {
   int32_t maxit, status, fell_back, fallback_at;
   int32_t nrep, nrep_since, s, explored;
   int32_t prev_action, R, fallback_enabled, k3_fa;
-  int32_t zero_solution, pad0, pad1, pad2;
+  int32_t zero_solution, bnorm_ready, pad1, pad2;
   double tol, bnorm, sigma, sig_new, alpha, beta, rho_new, last_true, cost_sum, relres_true;
   double rep_hist[3];
   float feat[kMlpIn];
@@ -85,10 +85,13 @@ struct KArgs {
   Ctl *ctl;
   const PolicyDev *pol;
   Hist h;
-  double *part;        // block partial sums
-  unsigned *tickets;   // one ticket per kernel kind
-  int P1, G1;          // SpMV row blocks, launched blocks (multiple of 8)
-  int P2;              // vector blocks
+  double *part0;       // partials of b.b (start)
+  double *part1;       // K1 partials (nu or ||r64||^2), one per 2048-row group
+  double *part2;       // K2 partials (sigma'), one per 2048-element block
+  int P2;              // 2048-element groups = K1 groups = vector blocks
+  int G1;              // K1 workgroups launched (P2 rounded up to 8)
+  int8_t *slot_log;    // optional: K1 records the mode of each slot (profiling)
+  int slot;            // index of this slot (with slot_log)
 };
 
 }  // namespace mpcg

@@ -5,14 +5,17 @@
 namespace mpcg {
 void launch_start(const KArgs &a, hipStream_t s);
 void launch_slot(const KArgs &a, hipStream_t s);
+void launch_k1(const KArgs &a, hipStream_t s);
+void launch_k2(const KArgs &a, hipStream_t s);
+void launch_ks(const KArgs &a, hipStream_t s);
+void launch_k3(const KArgs &a, hipStream_t s);
 void launch_finish(const KArgs &a, hipStream_t s);
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,
                     int8_t *rexp, hipStream_t s);
-void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, int P1, int G1, hipStream_t s);
-void launch_op_residual(const Mat &A, const double *b, const double *x, double *r, int P1, int G1,
-                        hipStream_t s);
-void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double *part, unsigned *ticket,
-                   int P2, double *out, hipStream_t s);
+void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipStream_t s);
+void launch_op_residual(const Mat &A, const double *b, const double *x, double *r, hipStream_t s);
+void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double *part, int P2, double *out,
+                   hipStream_t s);
 void launch_op_axpy(int n, int fa, double alpha, const void *u, void *y, hipStream_t s);
 void launch_policy_decide(const PolicyDev *P, int m, const int64_t *k, const double *rho, const int32_t *stag,
                           const float *feat, int32_t *state, int32_t *action, hipStream_t s);
