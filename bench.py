@@ -47,12 +47,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def spmv_bytes(n: int, nnz: int, fs: int, vec_bytes: int) -> int:
-    """Algorithmic bytes of one SpMV+nu launch: each CSR entry once (value +
-    int32 index), row pointers, the input vector once, the output once; fp16
-    adds the one-byte row exponents."""
+def ka_bytes(n: int, nnz: int, fs: int, vec_bytes: int) -> int:
+    """Algorithmic bytes of one iteration launch of KA (SpMV q = A p with the
+    p.q partial): each CSR entry once (value + int32 index), the row pointers,
+    p read once and q written once; fp16 adds the one-byte row exponents."""
     val = {0: 2, 1: 2, 2: 4, 3: 8}[fs]
-    b = nnz * (val + 4) + 4 * (n + 1) + n * vec_bytes + n * vec_bytes
+    b = nnz * (val + 4) + 4 * (n + 1) + 2 * n * vec_bytes
     if fs == 0:
         b += n
     return b
@@ -133,18 +133,22 @@ def main():
     prof = m.profile()
     rp64 = solve(pol_fp64, 0, profile=True)
     prof64 = m.profile()
-    k1_us = prof["k1_iter_ms"] / prof["n_iter_slots"] * 1e3
-    k2_us = prof["k2_iter_ms"] / prof["n_iter_slots"] * 1e3
-    k3_us = prof["k3_iter_ms"] / prof["n_iter_slots"] * 1e3
-    ks_us = prof["ks_iter_ms"] / prof["n_iter_slots"] * 1e3
-    k1_64_us = prof64["k1_iter_ms"] / prof64["n_iter_slots"] * 1e3
-    bytes_k1 = spmv_bytes(A.n, A.nnz, M.BF16, 4)
-    bytes_k1_64 = spmv_bytes(A.n, A.nnz, M.FP64, 8)
-    bytes_k2 = 6 * A.n * 4
-    bytes_k3 = 3 * A.n * 4
+    k1_us = prof["ka_iter_ms"] / prof["n_iter_slots"] * 1e3
+    k2_us = prof["kb_iter_ms"] / prof["n_iter_slots"] * 1e3
+    k3_us = prof["kx_iter_ms"] / prof["n_iter_slots"] * 1e3
+    k1_64_us = prof64["ka_iter_ms"] / prof64["n_iter_slots"] * 1e3
+    k2_64_us = prof64["kb_iter_ms"] / prof64["n_iter_slots"] * 1e3
+    k3_64_us = prof64["kx_iter_ms"] / prof64["n_iter_slots"] * 1e3
+    bytes_k1 = ka_bytes(A.n, A.nnz, M.BF16, 4)
+    bytes_k1_64 = ka_bytes(A.n, A.nnz, M.FP64, 8)
+    bytes_k2 = 6 * A.n * 4      # p, q, r, x_lo read; r, x_lo written
+    bytes_k2_64 = 6 * A.n * 8
+    bytes_k3 = 3 * A.n * 4      # p, r read; p written
+    bytes_k3_64 = 3 * A.n * 8
     achieved = bytes_k1 / (k1_us * 1e-6) / 1e9
-    log(f"[bench] profile mixed: K1 {k1_us:.2f} us ({achieved:.0f} GB/s)  K2 {k2_us:.2f} us  KS {ks_us:.2f} us  K3 {k3_us:.2f} us  "
-        f"profiled solve {rp['time_ms']:.2f} ms; fp64 K1 {k1_64_us:.2f} us")
+    log(f"[bench] profile mixed: KA {k1_us:.2f} us ({achieved:.0f} GB/s)  KB {k2_us:.2f} us  KX {k3_us:.2f} us  "
+        f"profiled solve {rp['time_ms']:.2f} ms; fp64 KA {k1_64_us:.2f} us KB {k2_64_us:.2f} us "
+        f"KX {k3_64_us:.2f} us")
 
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -179,7 +183,7 @@ def main():
         "setup_ms": round(setup_ms, 1),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_slot1 (SpMV bf16 + fused p.q), iteration slots",
+            "kernel": "k_a: CSR SpMV (bf16 values, fp32 accumulation) with the fused p.q partial",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -190,10 +194,11 @@ def main():
             "launches": prof["n_iter_slots"],
         },
         "kernels": {
-            "k2_axpy_dot": {"avg_us": round(k2_us, 3), "GB/s": round(bytes_k2 / (k2_us * 1e-6) / 1e9, 1)},
-            "k3_xpay": {"avg_us": round(k3_us, 3), "GB/s": round(bytes_k3 / (k3_us * 1e-6) / 1e9, 1)},
-            "ks_scalar": {"avg_us": round(ks_us, 3)},
-            "k1_fp64": {"avg_us": round(k1_64_us, 3), "GB/s": round(bytes_k1_64 / (k1_64_us * 1e-6) / 1e9, 1)},
+            "kb_axpy_dot": {"avg_us": round(k2_us, 3), "GB/s": round(bytes_k2 / (k2_us * 1e-6) / 1e9, 1)},
+            "kx_direction": {"avg_us": round(k3_us, 3), "GB/s": round(bytes_k3 / (k3_us * 1e-6) / 1e9, 1)},
+            "ka_fp64": {"avg_us": round(k1_64_us, 3), "GB/s": round(bytes_k1_64 / (k1_64_us * 1e-6) / 1e9, 1)},
+            "kb_fp64": {"avg_us": round(k2_64_us, 3), "GB/s": round(bytes_k2_64 / (k2_64_us * 1e-6) / 1e9, 1)},
+            "kx_fp64": {"avg_us": round(k3_64_us, 3), "GB/s": round(bytes_k3_64 / (k3_64_us * 1e-6) / 1e9, 1)},
             "profiled_solve_ms": round(rp["time_ms"], 3),
         },
     }

@@ -111,20 +111,21 @@ typedef struct {
                                   mpcg_get_profile); adds event overhead        */
 } mpcg_solve_opts;
 
-/* Per-kernel timing of the last solve made with opts.profile = 1.  A "slot" is
- * one iteration's launch sequence: K1 = SpMV with the fused nu = p.q partial
- * (fp64 residual in start/replacement slots), K2 = x/r update with the
- * sigma' = r.r partial, KS = one-block scalar and policy step, K3 = direction
- * update.  Times are sums of event-bracketed launch durations in ms. */
+/* Per-kernel timing of the last solve made with opts.profile = 1.  One CG
+ * iteration ("slot") is three launches: KA = SpMV with the fused nu = p.q
+ * partial; KB = scalar step (alpha) + x/r update with the sigma' = r.r
+ * partial; KX = scalar step (beta, policy) + direction update.  Policies that
+ * write shared state or evaluate an MLP add two one-block step kernels (KS).
+ * Times are sums of event-bracketed launch durations in ms. */
 typedef struct {
-    int32_t n_iter_slots;      /* slots that ran a CG iteration                  */
-    int32_t n_resid_slots;     /* slots that ran an fp64 residual (start/replace) */
+    int32_t n_iter_slots;      /* slots whose KA ran a CG iteration              */
+    int32_t n_resid_slots;     /* slots whose KA ran an fp64 residual            */
     int32_t n_idle_slots;      /* slots enqueued after the solve had finished    */
     int32_t reserved;
-    double k1_iter_ms;         /* K1 over iteration slots                        */
-    double k2_iter_ms;         /* K2 over iteration slots                        */
-    double ks_iter_ms;         /* KS over iteration slots                        */
-    double k3_iter_ms;         /* K3 over iteration slots                        */
+    double ka_iter_ms;         /* KA over iteration slots                        */
+    double kb_iter_ms;         /* KB over iteration slots                        */
+    double kx_iter_ms;         /* KX over iteration slots                        */
+    double ks_iter_ms;         /* step kernels over iteration slots              */
     double resid_ms;           /* all launches of residual slots                 */
     double idle_ms;            /* all launches of idle slots                     */
 } mpcg_profile;

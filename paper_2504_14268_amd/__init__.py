@@ -51,8 +51,9 @@ class SolveOpts(C.Structure):
 class Profile(C.Structure):
     _fields_ = [("n_iter_slots", C.c_int32), ("n_resid_slots", C.c_int32),
                 ("n_idle_slots", C.c_int32), ("reserved", C.c_int32),
-                ("k1_iter_ms", C.c_double), ("k2_iter_ms", C.c_double), ("ks_iter_ms", C.c_double),
-                ("k3_iter_ms", C.c_double), ("resid_ms", C.c_double), ("idle_ms", C.c_double)]
+                ("ka_iter_ms", C.c_double), ("kb_iter_ms", C.c_double), ("kx_iter_ms", C.c_double),
+                ("ks_iter_ms", C.c_double),
+                ("resid_ms", C.c_double), ("idle_ms", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}

@@ -1,7 +1,8 @@
 // api.hip -- host engine and C ABI (include/mpcg.h).
 //
-// The engine keeps every vector, the control block and the histories on the
-// device.  A solve enqueues a start kernel, then slots of (K1, K2, K3) in chunks;
+// The engine keeps every vector, the control blocks and the histories on the
+// device.  A solve enqueues a start kernel, then iteration slots (KA, KB; with
+// one-block step kernels between them for policies that need them) in chunks;
 // after each chunk it copies the 4-byte mode word to pinned memory and checks
 // the previous chunk's word, so the GPU always has a chunk queued and the host
 // never waits inside an iteration.
@@ -131,10 +132,10 @@ struct mpcg_matrix {
   int8_t *d_rexp = nullptr;
   // workspace
   double *d_xhi = nullptr;
-  float *d_r32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr, *d_xlo32 = nullptr;
-  double *d_r64 = nullptr, *d_p64 = nullptr, *d_q64 = nullptr, *d_xlo64 = nullptr;
+  float *d_r32 = nullptr, *d_q32 = nullptr, *d_xlo32 = nullptr, *d_p32 = nullptr;
+  double *d_r64 = nullptr, *d_q64 = nullptr, *d_xlo64 = nullptr, *d_p64 = nullptr;
   double *d_part0 = nullptr, *d_part1 = nullptr, *d_part2 = nullptr, *d_scalar = nullptr;
-  Ctl *d_ctl = nullptr;
+  Ctl *d_ctl = nullptr;        // [2]
   Ctl *h_ctl = nullptr;        // pinned
   int32_t *h_flag = nullptr;   // pinned [2]
   PolicyDev *d_pol = nullptr;
@@ -149,7 +150,7 @@ struct mpcg_matrix {
   int8_t *d_slotlog = nullptr;
   int slot_cap = 0;
   std::vector<hipEvent_t> pev;
-  std::vector<float> t1, t2, ts, t3;
+  std::vector<float> ta, tb, tx, ts;
   mpcg_profile prof{};
   // policy
   mpcg_policy *pol = nullptr;
@@ -250,19 +251,24 @@ static int ensure_hist(mpcg_matrix *A, int maxit) {
   return MPCG_OK;
 }
 
-// Elapsed times of the three launches of each slot of a completed chunk.
-static int collect_chunk(mpcg_matrix *A, int pool_idx, int chunk, int64_t first, int m) {
+// Elapsed times of the launches of each slot of a completed chunk: KA, KB and
+// (policies with one-block steps) the two step kernels.
+static int collect_chunk(mpcg_matrix *A, int pool_idx, int chunk, int per_slot, int64_t first, int m) {
   for (int s = 0; s < m; ++s) {
-    hipEvent_t *e = &A->pev[((size_t)pool_idx * chunk + s) * 5];
-    float a = 0, b = 0, c = 0, d = 0;
-    HIP_TRY(hipEventElapsedTime(&a, e[0], e[1]));
-    HIP_TRY(hipEventElapsedTime(&b, e[1], e[2]));
-    HIP_TRY(hipEventElapsedTime(&c, e[2], e[3]));
-    HIP_TRY(hipEventElapsedTime(&d, e[3], e[4]));
-    A->t1[first + s] = a;
-    A->t2[first + s] = b;
-    A->ts[first + s] = c;
-    A->t3[first + s] = d;
+    hipEvent_t *e = &A->pev[((size_t)pool_idx * chunk + s) * per_slot];
+    float t[5] = {0, 0, 0, 0, 0};
+    for (int j = 0; j + 1 < per_slot; ++j) HIP_TRY(hipEventElapsedTime(&t[j], e[j], e[j + 1]));
+    if (per_slot == 4) {          // KA, KB, KX
+      A->ta[first + s] = t[0];
+      A->tb[first + s] = t[1];
+      A->tx[first + s] = t[2];
+      A->ts[first + s] = 0.0f;
+    } else {                      // KA, step, KB, step, KX
+      A->ta[first + s] = t[0];
+      A->tb[first + s] = t[2];
+      A->tx[first + s] = t[4];
+      A->ts[first + s] = t[1] + t[3];
+    }
   }
   return MPCG_OK;
 }
@@ -273,8 +279,10 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
   a.v.b = b;
   a.v.xout = x;
   a.v.xhi = A->d_xhi;
-  a.v.r32 = A->d_r32; a.v.p32 = A->d_p32; a.v.q32 = A->d_q32; a.v.xlo32 = A->d_xlo32;
-  a.v.r64 = A->d_r64; a.v.p64 = A->d_p64; a.v.q64 = A->d_q64; a.v.xlo64 = A->d_xlo64;
+  a.v.r32 = A->d_r32; a.v.q32 = A->d_q32; a.v.xlo32 = A->d_xlo32;
+  a.v.r64 = A->d_r64; a.v.q64 = A->d_q64; a.v.xlo64 = A->d_xlo64;
+  a.v.p32 = A->d_p32;
+  a.v.p64 = A->d_p64;
   a.ctl = A->d_ctl;
   a.pol = A->d_pol;
   a.h.rho = A->d_hrho;
@@ -391,7 +399,7 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   TRY_A(dmalloc(&A->d_part1, (size_t)A->P2 + 64));
   TRY_A(dmalloc(&A->d_part2, (size_t)A->P2 + 64));
   TRY_A(dmalloc(&A->d_scalar, 8));
-  TRY_A(dmalloc(&A->d_ctl, 1));
+  TRY_A(dmalloc(&A->d_ctl, 2));
   TRY_A(dmalloc(&A->d_pol, 1));
   TRY_A(hipHostMalloc((void **)&A->h_ctl, sizeof(Ctl), hipHostMallocDefault));
   TRY_A(hipHostMalloc((void **)&A->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
@@ -628,21 +636,23 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   HIP_TRY(hipMemcpyAsync(A->d_ctl, A->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
 
   KArgs a = make_args(A, b, x);
+  a.slow = (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->desc.kind == MPCG_POLICY_MLP || P->roll_cap > 0) ? 1 : 0;
+  const int per_slot = a.slow ? 6 : 4;
   const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
   const bool prof = A->opts.profile != 0;
   std::memset(&A->prof, 0, sizeof(A->prof));
   if (prof) {
     a.slot_log = A->d_slotlog;
-    const size_t need = (size_t)2 * chunk * 5;
+    const size_t need = (size_t)2 * chunk * per_slot;
     while (A->pev.size() < need) {
       hipEvent_t e;
       HIP_TRY(hipEventCreate(&e));
       A->pev.push_back(e);
     }
-    A->t1.assign(A->slot_cap, 0.0f);
-    A->t2.assign(A->slot_cap, 0.0f);
+    A->ta.assign(A->slot_cap, 0.0f);
+    A->tb.assign(A->slot_cap, 0.0f);
+    A->tx.assign(A->slot_cap, 0.0f);
     A->ts.assign(A->slot_cap, 0.0f);
-    A->t3.assign(A->slot_cap, 0.0f);
   }
   HIP_TRY(hipEventRecord(A->ev_start, st));
   launch_start(a, st);
@@ -661,17 +671,24 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
     chunk_m[idx] = m;
     for (int s = 0; s < m; ++s) {
       if (prof) {
-        hipEvent_t *e = &A->pev[((size_t)idx * chunk + s) * 5];
+        hipEvent_t *e = &A->pev[((size_t)idx * chunk + s) * per_slot];
         a.slot = (int)(slots + s);
-        HIP_TRY(hipEventRecord(e[0], st));
-        launch_k1(a, st);
-        HIP_TRY(hipEventRecord(e[1], st));
-        launch_k2(a, st);
-        HIP_TRY(hipEventRecord(e[2], st));
-        launch_ks(a, st);
-        HIP_TRY(hipEventRecord(e[3], st));
-        launch_k3(a, st);
-        HIP_TRY(hipEventRecord(e[4], st));
+        int ei = 0;
+        HIP_TRY(hipEventRecord(e[ei++], st));
+        launch_ka(a, st);
+        HIP_TRY(hipEventRecord(e[ei++], st));
+        if (a.slow) {
+          launch_step_b(a, st);
+          HIP_TRY(hipEventRecord(e[ei++], st));
+        }
+        launch_kb(a, st);
+        HIP_TRY(hipEventRecord(e[ei++], st));
+        if (a.slow) {
+          launch_step_x(a, st);
+          HIP_TRY(hipEventRecord(e[ei++], st));
+        }
+        launch_kx(a, st);
+        HIP_TRY(hipEventRecord(e[ei++], st));
       } else {
         launch_slot(a, st);
       }
@@ -685,7 +702,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
       const int pidx = (ci - 1) & 1;
       HIP_TRY(hipEventSynchronize(A->ev_chunk[pidx]));
       if (prof && pending[pidx]) {
-        int rc2 = collect_chunk(A, pidx, chunk, chunk_first[pidx], chunk_m[pidx]);
+        int rc2 = collect_chunk(A, pidx, chunk, per_slot, chunk_first[pidx], chunk_m[pidx]);
         if (rc2) return rc2;
       }
       pending[pidx] = false;
@@ -700,7 +717,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   if (prof) {
     for (int i = 0; i < 2; ++i)
       if (pending[i]) {
-        int rc2 = collect_chunk(A, i, chunk, chunk_first[i], chunk_m[i]);
+        int rc2 = collect_chunk(A, i, chunk, per_slot, chunk_first[i], chunk_m[i]);
         if (rc2) return rc2;
       }
   }
@@ -712,7 +729,8 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   launch_finish(a, st);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(A->ev_end, st));
-  HIP_TRY(hipMemcpyAsync(A->h_ctl, A->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  // The finishing KB leaves the final state in ctl[1].
+  HIP_TRY(hipMemcpyAsync(A->h_ctl, A->d_ctl + 1, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, A->ev_start, A->ev_end));
@@ -733,13 +751,13 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
     HIP_TRY(hipMemcpy(modes.data(), A->d_slotlog, (size_t)slots, hipMemcpyDeviceToHost));
     mpcg_profile &pr = A->prof;
     for (int64_t s = 0; s < slots; ++s) {
-      const double all = (double)A->t1[s] + A->t2[s] + A->ts[s] + A->t3[s];
+      const double all = (double)A->ta[s] + A->tb[s] + A->tx[s] + A->ts[s];
       if (modes[s] == M_ITER) {
         pr.n_iter_slots++;
-        pr.k1_iter_ms += A->t1[s];
-        pr.k2_iter_ms += A->t2[s];
+        pr.ka_iter_ms += A->ta[s];
+        pr.kb_iter_ms += A->tb[s];
+        pr.kx_iter_ms += A->tx[s];
         pr.ks_iter_ms += A->ts[s];
-        pr.k3_iter_ms += A->t3[s];
       } else if (modes[s] == M_DONE) {
         pr.n_idle_slots++;
         pr.idle_ms += all;

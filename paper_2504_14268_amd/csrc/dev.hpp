@@ -187,58 +187,6 @@ __device__ A reduce_partials(const double *part, int P) {
   return total;
 }
 
-// Pairwise sum of P partials by one wavefront, no barrier: with Pp =
-// next_pow2(P) zero-padded leaves, lane t reduces the aligned chunk
-// [t*c, (t+1)*c), c = Pp/64, in registers and the lanes combine by butterfly.
-// Every lane returns the total.  Requires Pp <= 64*64.
-template <typename A, int C>
-__device__ __forceinline__ A lane_chunk_tree(const double *part, int base, int P) {
-  if constexpr (C > 16) {   // aligned 16-leaf subtrees, then their pairwise sum
-    A s[C / 16];
-#pragma unroll
-    for (int i = 0; i < C / 16; ++i) s[i] = lane_chunk_tree<A, 16>(part, base + 16 * i, P);
-#pragma unroll
-    for (int len = C / 16; len > 1; len >>= 1)
-#pragma unroll
-      for (int i = 0; i < len / 2; ++i) s[i] = s[2 * i] + s[2 * i + 1];
-    return s[0];
-  } else {
-    A v[C];
-#pragma unroll
-    for (int i = 0; i < C; ++i) v[i] = (base + i < P) ? (A)part[base + i] : (A)0;
-#pragma unroll
-    for (int len = C; len > 1; len >>= 1)
-#pragma unroll
-      for (int i = 0; i < len / 2; ++i) v[i] = v[2 * i] + v[2 * i + 1];
-    return v[0];
-  }
-}
-
-constexpr int kWaveReduceMax = 64 * 64;
-
-template <typename A>
-__device__ __forceinline__ A wave_reduce_partials(const double *part, int P) {
-  int Pp = 1;
-  while (Pp < P) Pp <<= 1;
-  const int lane = threadIdx.x & 63;
-  A v;
-  if (Pp <= 64) {
-    v = (lane < P) ? (A)part[lane] : (A)0;
-  } else {
-    const int c = Pp >> 6;
-    const int base = lane * c;
-    switch (c) {
-    case 2: v = lane_chunk_tree<A, 2>(part, base, P); break;
-    case 4: v = lane_chunk_tree<A, 4>(part, base, P); break;
-    case 8: v = lane_chunk_tree<A, 8>(part, base, P); break;
-    case 16: v = lane_chunk_tree<A, 16>(part, base, P); break;
-    case 32: v = lane_chunk_tree<A, 32>(part, base, P); break;
-    default: v = lane_chunk_tree<A, 64>(part, base, P); break;
-    }
-  }
-  return wave_tree(v);
-}
-
 // ---------------------------------------------------------------------------
 // Policy arithmetic.
 // ---------------------------------------------------------------------------

@@ -1,19 +1,26 @@
 // kernels.hip -- gfx950 kernels of the mixed-precision CG iteration.
 //
-// One CG iteration is one "slot" of four launches on one stream:
-//   K1  SpMV q = A_fs p in the LDS-staged CSR form, fused partial of nu = p.q
-//       (or, in the other modes: the fp64 residual b - A x_hi of a start,
-//       restart, replacement or final check, fused with its squared norm);
-//   K2  every block reduces K1's partials to nu and alpha = sigma/nu itself,
-//       then x_lo += alpha p, r -= alpha q and the partial of sigma' = r.r;
-//   KS  one block: the final reductions and the scalar step -- alpha, beta, rho,
-//       convergence and replacement tests, the policy's state, reward, Q update
-//       and next action; the only writer of the control block;
-//   K3  p = r + beta p (or fold x_lo into x_hi, or p = r after a start), with
-//       the conversion of r and p when the next action changes the tier.
-// No kernel communicates between its own workgroups: kernel boundaries order
-// every hand-off, so no workgroup pays a device-wide cache write-back.  The host
-// only enqueues slots.
+// One CG iteration is three launches on one stream:
+//   KA  SpMV q = A_fs p in the LDS-staged CSR form with the fused partial of
+//       nu = p.q (in the other modes: the fp64 residual b - A x_hi of a start,
+//       replacement or final check, with its squared norm).  KA only reads the
+//       control block.
+//   KB  scalar step on KA's partials (nu -> alpha, breakdown; or the start /
+//       replacement bookkeeping), then x_lo += alpha p, r -= alpha q and the
+//       partial of sigma' = r.r (or an elementwise step: p = r after a start,
+//       the direction update after a replacement, a fold of x_lo into x_hi).
+//   KX  scalar step on KB's partials (sigma' -> rho, replacement test, beta,
+//       the policy's state, update and next action), then the direction update
+//       p = rd_fa(fma(beta, p, r)) with a change of vector tier if the next
+//       action needs one (or a fold of x_lo into x_hi).
+// Every workgroup of KB and KX computes the scalar step identically from the
+// partials; workgroup 0 commits it (control block, histories).  The control
+// block is double-buffered (KA and KB read ctl[0], KB writes ctl[1], KX reads
+// ctl[1] and writes ctl[0]), so no kernel reads a value its own workgroups
+// write.  No kernel communicates between its own workgroups; kernel boundaries
+// order every hand-off.  Policies whose step writes shared state (Q-learning
+// updates, rollout logs) or evaluates the MLP run each step once, in a
+// one-block kernel (KS) before KB and before KX.  The host only enqueues launches.
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -109,8 +116,8 @@ __device__ __forceinline__ void lds_store8(A *p, const A (&v)[8]) {
 // the k-th column of its own row, so on banded and stencil matrices a
 // wavefront's gathers fall on neighbouring addresses.  Gathers are issued eight
 // at a time ahead of their fma chain.
-template <int FS, int RPT, typename V>
-__device__ __forceinline__ void spmv_rows(const Mat &A, const V *__restrict__ x, int r0, int nrows,
+template <int FS, int RPT, typename G>
+__device__ __forceinline__ void spmv_rows(const Mat &A, const G &gather, int r0, int nrows,
                                           void *lds_raw, typename AccT<FS>::type (&acc)[RPT]) {
   using Acc = typename AccT<FS>::type;
   constexpr int CAP = Cap<Acc>::value * RPT;
@@ -150,7 +157,7 @@ __device__ __forceinline__ void spmv_rows(const Mat &A, const V *__restrict__ x,
         for (int u = 0; u < 8; ++u) {
           if (u < cnt) {
             vv[u] = lv[kk - wb + u];
-            xv[u] = to_acc<Acc>(x[lc[kk - wb + u]]);
+            xv[u] = gather.template get<Acc>(lc[kk - wb + u]);
           }
         }
 #pragma unroll
@@ -159,6 +166,29 @@ __device__ __forceinline__ void spmv_rows(const Mat &A, const V *__restrict__ x,
       }
     }
     __syncthreads();
+  }
+}
+
+// Gather of the SpMV's operand.
+template <typename V>
+struct GatherPlain {
+  const V *p;
+  __device__ __forceinline__ V value(int c) const { return p[c]; }
+  template <typename Acc> __device__ __forceinline__ Acc get(int c) const { return to_acc<Acc>(p[c]); }
+};
+
+// p_new = rd_fa(fma_acc(rd_acc(beta), p, r)) in the tier of fa
+template <typename Vo>
+__device__ __forceinline__ Vo xpay_rt(int fa, double beta, Vo p, Vo r) {
+  if constexpr (sizeof(Vo) == 8) {
+    return __builtin_fma(beta, p, r);
+  } else {
+    const float t = __builtin_fmaf((float)beta, p, r);
+    switch (fa) {
+    case FP16: return rd_f16_from_f32(t);
+    case BF16: return rd_bf16_from_f32(t);
+    default: return t;
+    }
   }
 }
 
@@ -228,11 +258,9 @@ __device__ __forceinline__ double dot_leaf_block_rt(int fd, V u, V v, bool valid
   }
 }
 
-// Pairwise total of P partials, identical in every thread of the block; per
-// wavefront without a barrier when P is small enough (block-uniform choice).
+// Pairwise total of P partials, identical in every thread of the block.
 template <typename A>
 __device__ __forceinline__ double partials_total(const double *part, int P) {
-  if (P <= kWaveReduceMax) return (double)wave_reduce_partials<A>(part, P);
   return (double)reduce_partials<A>(part, P);
 }
 
@@ -332,8 +360,10 @@ __device__ void roll_log(const PolicyDev *P, const float *f, const float *fn, in
   P->roll_done[i] = (uint8_t)done;
 }
 
+template <bool FULL>
 __device__ int decide_scalar(const PolicyDev *P, int s, int k, int *explored) {
   *explored = 0;
+  if constexpr (!FULL) return P->kind == POL_QTABLE ? q_argmax(&P->q[s * kNAct]) : P->fixed_action;
   switch (P->kind) {
   case POL_FIXED: return P->fixed_action;
   case POL_QTABLE: return q_argmax(&P->q[s * kNAct]);
@@ -393,17 +423,18 @@ struct Sx {
   Ctl *ctl;
   const PolicyDev *pol;
   Hist h;
+  bool writer;   // commits histories, Q updates and rollouts
 };
 __device__ void set_done(Ctl *c) {
   c->mode = M_DONE;
-  c->k2op = K2_NONE;
-  c->k3op = K3_NONE;
+    c->k3op = K3_NONE;
 }
 
 // Install the next action.  After a start/restart r is in the fp64 container
 // and K3 copies it into the new tier; otherwise K3 applies p = r + beta p in the
 // old tier and converts r, p if the tier changes.
-__device__ void apply_decision(const Sx &a, int na, int ex, bool from_init) {
+template <bool FULL>
+__device__ __forceinline__ void apply_decision(const Sx &a, int na, int ex, bool from_init) {
   Ctl *c = a.ctl;
   const int k = c->k;
   if (from_init && k >= c->maxit) {
@@ -420,26 +451,28 @@ __device__ void apply_decision(const Sx &a, int na, int ex, bool from_init) {
     c->k3op = K3_XPAY;
     c->k3switch = (nt != c->tier);
     c->tier_old = c->tier;
-    if (c->k3switch) a.h.flag[k - 1] |= FL_SWITCH;
+    if (c->k3switch && a.writer) a.h.flag[k - 1] |= FL_SWITCH;
   }
   c->tier = nt;
   c->action = na;
   c->explored = ex;
-  c->k2op = K2_NONE;
-  a.h.act[k] = (uint8_t)na;
-  a.h.flag[k] = ex ? FL_EXPLORED : 0;
+    if (a.writer) {
+    a.h.act[k] = (uint8_t)na;
+    a.h.flag[k] = ex ? FL_EXPLORED : 0;
+  }
   c->cost_sum += policy_cost(a.pol, na);
   c->mode = M_ITER;
 }
 
 // Start / restart: rho_0 from the fp64 residual, first action.  Returns 1 when
 // the decision needs the block's MLP forward (features left in s_feat).
-__device__ int init_t0(const Sx &a, double s64, float *s_feat) {
+template <bool FULL>
+__device__ __forceinline__ int init_t0(const Sx &a, double s64, float *s_feat) {
   Ctl *c = a.ctl;
   const PolicyDev *P = a.pol;
   const int k = c->k;
   const double rt = sqrt(s64) / c->bnorm;
-  a.h.rho[k] = rt;
+  if (a.writer) a.h.rho[k] = rt;
   c->last_true = rt;
   c->nrep_since = 0;
   if (rt <= c->tol) {
@@ -458,34 +491,38 @@ __device__ int init_t0(const Sx &a, double s64, float *s_feat) {
   const int stag = (k >= P->w_stag) && (rt >= a.h.rho[k - P->w_stag]);
   const int s = policy_state(P, k, rt, stag);
   c->s = s;
-  if (P->kind == POL_MLP || P->roll_cap > 0) mlp_features(P, k, a.h.rho, stag, rt, c->prev_action, c->feat);
+  if constexpr (FULL)
+    if (P->kind == POL_MLP || P->roll_cap > 0) mlp_features(P, k, a.h.rho, stag, rt, c->prev_action, c->feat);
   if (c->fell_back) {
-    apply_decision(a, 63, 0, true);
+    apply_decision<FULL>(a, 63, 0, true);
     return 0;
   }
-  if (P->kind == POL_MLP) {
-    for (int i = 0; i < kMlpIn; ++i) s_feat[i] = c->feat[i];
-    return 1;
+  if constexpr (FULL) {
+    if (P->kind == POL_MLP) {
+      for (int i = 0; i < kMlpIn; ++i) s_feat[i] = c->feat[i];
+      return 1;
+    }
   }
   int ex = 0;
-  const int na = decide_scalar(P, s, k, &ex);
-  apply_decision(a, na, ex, true);
+  const int na = decide_scalar<FULL>(P, s, k, &ex);
+  apply_decision<FULL>(a, na, ex, true);
   return 0;
 }
 
 // End of an iteration (or of a failed one): history, beta, training update,
 // rollout, convergence / breakdown / fallback / budget, next action.
-__device__ int finish_t0(const Sx &a, bool completed, bool broke, bool converged, bool stagnated,
+template <bool FULL>
+__device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke, bool converged, bool stagnated,
                          float *s_feat) {
   Ctl *c = a.ctl;
   const PolicyDev *P = a.pol;
   const int k = c->k;
   const bool active = !c->fell_back;
-  const bool training = active && P->kind == POL_QTRAIN;
-  const bool want_feat = active && (P->kind == POL_MLP || P->roll_cap > 0);
+  const bool training = FULL && active && P->kind == POL_QTRAIN;
+  const bool want_feat = FULL && active && (P->kind == POL_MLP || P->roll_cap > 0);
   const int act = c->action, s = c->s;
   const double rho = c->rho_new;
-  if (completed) a.h.rho[k] = rho;
+  if (completed && a.writer) a.h.rho[k] = rho;
   double beta = 0.0;
   if (completed && !broke && !converged) {
     beta = c->sig_new / c->sigma;
@@ -501,8 +538,8 @@ __device__ int finish_t0(const Sx &a, bool completed, bool broke, bool converged
   }
   if (converged) {
     const double rw = policy_reward(P, act, rho, true);
-    if (training) q_update(P, s, act, rw);
-    if (active) roll_log(P, c->feat, c->feat_next, act, rw, 1);
+    if (training && a.writer) q_update(P, s, act, rw);
+    if (FULL && active && a.writer) roll_log(P, c->feat, c->feat_next, act, rw, 1);
     c->status = c->fell_back ? 2 : 0;
     c->relres_true = rho;
     set_done(c);
@@ -510,8 +547,8 @@ __device__ int finish_t0(const Sx &a, bool completed, bool broke, bool converged
   }
   if (broke || (stagnated && c->fallback_enabled && !c->fell_back)) {
     const double rw = -P->w2 * policy_cost(P, act) - P->w3;
-    if (training) q_update(P, s, act, rw);
-    if (active) roll_log(P, c->feat, c->feat_next, act, rw, 1);
+    if (training && a.writer) q_update(P, s, act, rw);
+    if (FULL && active && a.writer) roll_log(P, c->feat, c->feat_next, act, rw, 1);
     if (!c->fallback_enabled || c->fell_back) {
       c->status = 3;
       set_done(c);
@@ -519,20 +556,19 @@ __device__ int finish_t0(const Sx &a, bool completed, bool broke, bool converged
     }
     c->fell_back = 1;
     c->fallback_at = k;
-    a.h.flag[completed ? k - 1 : k] |= FL_FALLBACK;
+    if (a.writer) a.h.flag[completed ? k - 1 : k] |= FL_FALLBACK;
     c->prev_action = act;
     c->mode = M_INIT;
-    c->k2op = K2_NONE;
-    c->k3op = K3_FOLD;
+        c->k3op = K3_FOLD;
     return 0;
   }
   {
     const double rw = policy_reward(P, act, rho, false);
-    if (training) {
+    if (training && a.writer) {
       const double *row = &P->q[s_next * kNAct];
       q_update(P, s, act, rw + P->gamma * row[q_argmax(row)]);
     }
-    if (active) roll_log(P, c->feat, c->feat_next, act, rw, 0);
+    if (FULL && active && a.writer) roll_log(P, c->feat, c->feat_next, act, rw, 0);
   }
   if (k >= c->maxit) {
     c->status = 1;
@@ -547,55 +583,64 @@ __device__ int finish_t0(const Sx &a, bool completed, bool broke, bool converged
   if (want_feat)
     for (int i = 0; i < kMlpIn; ++i) c->feat[i] = c->feat_next[i];
   if (c->fell_back) {
-    apply_decision(a, 63, 0, false);
+    apply_decision<FULL>(a, 63, 0, false);
     return 0;
   }
-  if (P->kind == POL_MLP) {
-    for (int i = 0; i < kMlpIn; ++i) s_feat[i] = c->feat[i];
-    return 1;
+  if constexpr (FULL) {
+    if (P->kind == POL_MLP) {
+      for (int i = 0; i < kMlpIn; ++i) s_feat[i] = c->feat[i];
+      return 1;
+    }
   }
   int ex = 0;
-  const int na = decide_scalar(P, s_next, k, &ex);
-  apply_decision(a, na, ex, false);
+  const int na = decide_scalar<FULL>(P, s_next, k, &ex);
+  apply_decision<FULL>(a, na, ex, false);
   return 0;
 }
 
 // Block-level wrappers: thread 0 runs the scalar step; the block joins for an
 // MLP decision.
-__device__ void finish_block(const Sx &a, bool completed, bool broke, bool converged, bool stagnated) {
+template <bool FULL>
+__device__ __forceinline__ void finish_block(const Sx &a, bool completed, bool broke, bool converged, bool stagnated) {
   __shared__ int s_need;
   __shared__ float s_feat[kMlpIn], s_logits[kNAct];
-  if (threadIdx.x == 0) s_need = finish_t0(a, completed, broke, converged, stagnated, s_feat);
+  if (threadIdx.x == 0) s_need = finish_t0<FULL>(a, completed, broke, converged, stagnated, s_feat);
   __syncthreads();
-  if (s_need) {
-    mlp_logits_block(a.pol, s_feat, s_logits);
-    if (threadIdx.x == 0) apply_decision(a, argmax64f(s_logits), 0, false);
+  if constexpr (FULL) {
+    if (s_need) {
+      mlp_logits_block(a.pol, s_feat, s_logits);
+      if (threadIdx.x == 0) apply_decision<FULL>(a, argmax64f(s_logits), 0, false);
+    }
   }
 }
 
-__device__ void init_block(const Sx &a, double s64) {
+template <bool FULL>
+__device__ __forceinline__ void init_block(const Sx &a, double s64) {
   __shared__ int s_need;
   __shared__ float s_feat[kMlpIn], s_logits[kNAct];
-  if (threadIdx.x == 0) s_need = init_t0(a, s64, s_feat);
+  if (threadIdx.x == 0) s_need = init_t0<FULL>(a, s64, s_feat);
   __syncthreads();
-  if (s_need) {
-    mlp_logits_block(a.pol, s_feat, s_logits);
-    if (threadIdx.x == 0) apply_decision(a, argmax64f(s_logits), 0, true);
+  if constexpr (FULL) {
+    if (s_need) {
+      mlp_logits_block(a.pol, s_feat, s_logits);
+      if (threadIdx.x == 0) apply_decision<FULL>(a, argmax64f(s_logits), 0, true);
+    }
   }
 }
 
-__device__ void replace_block(const Sx &a, double s64) {
+template <bool FULL>
+__device__ __forceinline__ void replace_block(const Sx &a, double s64) {
   __shared__ int s_f[3];
   if (threadIdx.x == 0) {
     Ctl *c = a.ctl;
     const int k = c->k;
     const double rt = sqrt(s64) / c->bnorm;
-    if (c->nrep < a.h.cap_rep) {
+    if (c->nrep < a.h.cap_rep && a.writer) {
       a.h.rep_k[c->nrep] = k;
       a.h.rep_rho[c->nrep] = rt;
     }
     c->nrep++;
-    a.h.flag[k - 1] |= FL_REPLACED;
+    if (a.writer) a.h.flag[k - 1] |= FL_REPLACED;
     c->last_true = rt;
     c->rho_new = rt;
     int conv = 0, broke = 0, stag = 0;
@@ -614,23 +659,126 @@ __device__ void replace_block(const Sx &a, double s64) {
     s_f[0] = conv; s_f[1] = broke; s_f[2] = stag;
   }
   __syncthreads();
-  finish_block(a, true, s_f[1] != 0, s_f[0] != 0, s_f[2] != 0);
+  finish_block<FULL>(a, true, s_f[1] != 0, s_f[0] != 0, s_f[2] != 0);
 }
 
 // ---------------------------------------------------------------------------
-// K1: SpMV (or fp64 residual) over a group of kGroupRows rows; one partial per
-// group = the pairwise sum of its eight 256-row subtrees.
+// Scalar steps.  Called by every thread of a workgroup (block-uniform control
+// flow); thread 0 does the scalar work on the LDS copy of the control block.
+// ---------------------------------------------------------------------------
+// Before KX: the end of an iteration (KB's sigma'): replacement test, then
+// beta, policy update and next action.
+template <bool FULL>
+__device__ __forceinline__ void step_x(const Sx &x, const KArgs &a) {
+  Ctl *c = x.ctl;
+  if (c->mode == M_DONE || !c->pend_sigma) return;
+  const int fd = (c->action >> 2) & 3;
+  const double sig = reduce_partials_rt(fd, a.part2, a.P2);
+  __shared__ int s_fin;
+  if (threadIdx.x == 0) {
+    c->pend_sigma = 0;
+    c->sig_new = sig;
+    c->k += 1;
+    const int k = c->k;
+    const double rho = sqrt(sig) / c->bnorm;
+    c->rho_new = rho;
+    const bool rep = (c->R > 0 && k % c->R == 0) || rho <= c->tol || !isfinite(sig);
+    if (rep) {
+      c->mode = M_REPLACE;
+      c->k3op = c->fold_done ? K3_NONE : K3_FOLD;
+      s_fin = 0;
+    } else {
+      s_fin = 1;
+    }
+    c->fold_done = 0;
+  }
+  __syncthreads();
+  if (s_fin) finish_block<FULL>(x, true, false, false, false);
+  __syncthreads();
+}
+
+// Before KB: KA's partials -- nu (alpha, breakdown) after an iteration, the
+// residual norm after a start, replacement or final check.
+template <bool FULL>
+__device__ __forceinline__ void step_b(const Sx &x, const KArgs &a) {
+  Ctl *c = x.ctl;
+  const int la = c->mode;   // what KA has just executed
+  if (la == M_ITER) {
+    const int fd = (c->action >> 2) & 3;
+    const double nu = reduce_partials_rt(fd, a.part1, a.P2);
+    const double alpha = c->sigma / nu;
+    if (!(nu > 0.0 && isfinite(nu)) || !isfinite(alpha)) {
+      finish_block<FULL>(x, false, true, false, false);
+      __syncthreads();
+      if (threadIdx.x == 0) c->b_op = B_EXEC;
+    } else if (threadIdx.x == 0) {
+      c->alpha = alpha;
+      c->b_op = B_AXPY;
+    }
+  } else if (la == M_INIT || la == M_REPLACE || la == M_FINAL) {
+    if (la == M_INIT && !c->bnorm_ready) {   // first start: ||b|| from the start kernel
+      const double bb = partials_total<double>(a.part0, a.P2);
+      if (threadIdx.x == 0) {
+        c->bnorm = sqrt(bb);
+        c->bnorm_ready = 1;
+      }
+      __syncthreads();
+      if (c->bnorm == 0.0) {
+        if (threadIdx.x == 0) {
+          c->zero_solution = 1;
+          if (x.writer) a.h.rho[0] = 0.0;
+          c->status = 0;
+          c->relres_true = 0.0;
+          set_done(c);
+          c->b_op = B_NONE;
+        }
+        __syncthreads();
+        return;
+      }
+    }
+    const double s64 = partials_total<double>(a.part1, a.P2);
+    if (la == M_INIT) {
+      init_block<FULL>(x, s64);
+    } else if (la == M_REPLACE) {
+      replace_block<FULL>(x, s64);
+    } else if (threadIdx.x == 0) {
+      c->relres_true = sqrt(s64) / c->bnorm;
+      set_done(c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) c->b_op = B_EXEC;
+  } else if (threadIdx.x == 0) {
+    c->b_op = B_NONE;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void copy_words(void *dst, const void *src, int bytes) {
+  uint64_t *d = (uint64_t *)dst;
+  const uint64_t *s = (const uint64_t *)src;
+  for (int i = threadIdx.x; i < bytes / 8; i += kBlock) d[i] = s[i];
+}
+
+__device__ __forceinline__ void fold1(double *xhi, int i, double xl) {
+  const double s = xhi[i] + xl;
+  if (isfinite(s)) xhi[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// KA: SpMV of an iteration over a group of 2048 rows (one partial per group =
+// the pairwise sum of its eight 256-row subtrees).
 // ---------------------------------------------------------------------------
 constexpr int kGroupBlocks = kVecBlock / kRowsPerBlock;   // 8 row blocks = 2048 rows
 
 template <int FS, int TIER>
-__device__ __forceinline__ void k1_iter(const KArgs &a, int g, void *lds) {
+__device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, void *lds) {
   using V = typename TierT<TIER>::type;
   const V *p;
   V *q;
   if constexpr (TIER) { p = a.v.p64; q = a.v.q64; } else { p = a.v.p32; q = a.v.q32; }
-  const int fd = (a.ctl->action >> 2) & 3;
+  const int fd = (S.action >> 2) & 3;
   const int n = a.A.n;
+  const GatherPlain<V> gp{p};
   double sub[8];
 #pragma unroll 1
   for (int sb = 0; sb < kGroupBlocks / kRPT; ++sb) {
@@ -642,19 +790,20 @@ __device__ __forceinline__ void k1_iter(const KArgs &a, int g, void *lds) {
     }
     const int nrows = min(kRPT * kRowsPerBlock, n - r0);
     typename AccT<FS>::type acc[kRPT];
-    spmv_rows<FS, kRPT>(a.A, p, r0, nrows, lds, acc);
+    spmv_rows<FS, kRPT>(a.A, gp, r0, nrows, lds, acc);
     V qi[kRPT], pi[kRPT];
     bool valid[kRPT];
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
       const int lr = threadIdx.x + j * kRowsPerBlock;
+      const int i = r0 + lr;
       valid[j] = lr < nrows;
       qi[j] = (V)0;
       pi[j] = (V)0;
       if (valid[j]) {
-        qi[j] = spmv_out<FS, V>(a.A, r0 + lr, acc[j]);
-        q[r0 + lr] = qi[j];
-        pi[j] = p[r0 + lr];
+        qi[j] = spmv_out<FS, V>(a.A, i, acc[j]);
+        q[i] = qi[j];
+        pi[j] = p[i];
       }
     }
     double s2[kRPT];
@@ -666,9 +815,11 @@ __device__ __forceinline__ void k1_iter(const KArgs &a, int g, void *lds) {
 }
 
 // fp64 residual r = b - A x_hi with the partial of its squared norm (start,
-// replacement, final check); a replacement also stores r in the current tier.
-__device__ __forceinline__ void k1_residual(const KArgs &a, int g, int mode, void *lds) {
+// replacement, final check); a start stores r in the fp64 container, a
+// replacement in the current tier.
+__device__ __forceinline__ void ka_residual(const KArgs &a, const Ctl &S, int g, int mode, void *lds) {
   const int n = a.A.n;
+  const GatherPlain<double> gx{a.v.xhi};
   double sub[8];
 #pragma unroll 1
   for (int sb = 0; sb < kGroupBlocks / kRPT; ++sb) {
@@ -680,7 +831,7 @@ __device__ __forceinline__ void k1_residual(const KArgs &a, int g, int mode, voi
     }
     const int nrows = min(kRPT * kRowsPerBlock, n - r0);
     double acc[kRPT];
-    spmv_rows<FP64, kRPT>(a.A, (const double *)a.v.xhi, r0, nrows, lds, acc);
+    spmv_rows<FP64, kRPT>(a.A, gx, r0, nrows, lds, acc);
     double leaf[kRPT];
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
@@ -693,7 +844,7 @@ __device__ __forceinline__ void k1_residual(const KArgs &a, int g, int mode, voi
         if (mode == M_INIT) {
           a.v.r64[i] = r;
         } else if (mode == M_REPLACE) {
-          if (a.ctl->tier) a.v.r64[i] = r; else a.v.r32[i] = (float)r;
+          if (S.tier) a.v.r64[i] = r; else a.v.r32[i] = (float)r;
         }
       }
     }
@@ -705,36 +856,50 @@ __device__ __forceinline__ void k1_residual(const KArgs &a, int g, int mode, voi
   if (threadIdx.x == 0) a.part1[g] = tree8(sub);
 }
 
-__global__ __launch_bounds__(kBlock) void k_slot1(KArgs a) {
-  const int mode = a.ctl->mode;
-  if (a.slot_log && blockIdx.x == 0 && threadIdx.x == 0) a.slot_log[a.slot] = (int8_t)mode;
-  if (mode == M_DONE) return;
+// x_hi += x_lo, x_lo = 0 over one 2048-element group (current tier).
+__device__ __forceinline__ void fold_group(const KArgs &a, int tier, int g) {
+  const int n = a.A.n;
+  const int base = g * kVecBlock + threadIdx.x * kVecPer;
+  for (int j = 0; j < 8; ++j) {
+    const int i = base + j;
+    if (i >= n) break;
+    if (tier) { fold1(a.v.xhi, i, a.v.xlo64[i]); a.v.xlo64[i] = 0.0; }
+    else { fold1(a.v.xhi, i, (double)a.v.xlo32[i]); a.v.xlo32[i] = 0.0f; }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_a(KArgs a) {
   const int g = xcd_group(a.G1);
   if (g >= a.P2) return;
   __shared__ double lds[kLdsDoubles];
+  const Ctl &S = a.ctl[0];
+  const int mode = S.mode;
+  if (a.slot_log && g == 0 && threadIdx.x == 0) a.slot_log[a.slot] = (int8_t)mode;
   if (mode == M_ITER) {
-    const int fs = (a.ctl->action >> 4) & 3, tier = a.ctl->tier;
-    switch (fs * 2 + tier) {
-    case 0: k1_iter<FP16, 0>(a, g, lds); break;
-    case 1: k1_iter<FP16, 1>(a, g, lds); break;
-    case 2: k1_iter<BF16, 0>(a, g, lds); break;
-    case 3: k1_iter<BF16, 1>(a, g, lds); break;
-    case 4: k1_iter<FP32, 0>(a, g, lds); break;
-    case 5: k1_iter<FP32, 1>(a, g, lds); break;
-    case 6: k1_iter<FP64, 0>(a, g, lds); break;
-    default: k1_iter<FP64, 1>(a, g, lds); break;
+    const int fs = (S.action >> 4) & 3;
+    switch (fs * 2 + S.tier) {
+    case 0: ka_iter<FP16, 0>(a, S, g, lds); break;
+    case 1: ka_iter<FP16, 1>(a, S, g, lds); break;
+    case 2: ka_iter<BF16, 0>(a, S, g, lds); break;
+    case 3: ka_iter<BF16, 1>(a, S, g, lds); break;
+    case 4: ka_iter<FP32, 0>(a, S, g, lds); break;
+    case 5: ka_iter<FP32, 1>(a, S, g, lds); break;
+    case 6: ka_iter<FP64, 0>(a, S, g, lds); break;
+    default: ka_iter<FP64, 1>(a, S, g, lds); break;
     }
-  } else {
-    k1_residual(a, g, mode, lds);
+  } else if (mode == M_INIT || mode == M_REPLACE || mode == M_FINAL) {
+    ka_residual(a, S, g, mode, lds);
   }
 }
 
 // ---------------------------------------------------------------------------
-// K2: nu (redundantly per block), alpha, x_lo = axpy(alpha, p, x_lo),
-// r = axpy(-alpha, q, r), partial of sigma' = dot(r, r).
+// KB: x_lo = axpy(alpha, p, x_lo), r = axpy(-alpha, q, r), partial of
+// sigma' = dot(r, r); when the next iteration number is a multiple of the
+// replacement period, x_lo is also folded into x_hi here (the replacement that
+// follows begins with that fold).
 // ---------------------------------------------------------------------------
 template <int FA, int FD>
-__device__ __forceinline__ void k2_body(const KArgs &a) {
+__device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_now) {
   constexpr int TIER = (FA == FP64);
   using V = typename TierT<TIER>::type;
   using Acc = typename AccT<FD>::type;
@@ -742,14 +907,13 @@ __device__ __forceinline__ void k2_body(const KArgs &a) {
   const V *p, *q;
   if constexpr (TIER) { xlo = a.v.xlo64; r = a.v.r64; p = a.v.p64; q = a.v.q64; }
   else { xlo = a.v.xlo32; r = a.v.r32; p = a.v.p32; q = a.v.q32; }
+  const double alpha = S.alpha;
   const int n = a.A.n;
   const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
   const bool full = base + 8 <= n;
-  double nu = 0.0;
-  if constexpr (TIER) nu = partials_total<Acc>(a.part1, a.P2);   // fp64 tier: registers first
   V pv[8], qv[8], rv[8], xv[8];
-  if (full) {                       // fp32 tier: streaming loads first, they stay
-    load8(p + base, pv);            // in flight while the wave reduces nu
+  if (full) {
+    load8(p + base, pv);
     load8(q + base, qv);
     load8(r + base, rv);
     load8(xlo + base, xv);
@@ -763,15 +927,20 @@ __device__ __forceinline__ void k2_body(const KArgs &a) {
       xv[j] = i < n ? xlo[i] : (V)0;
     }
   }
-  if constexpr (!TIER) nu = partials_total<Acc>(a.part1, a.P2);
-  const double alpha = a.ctl->sigma / nu;
-  if (!(nu > 0.0 && isfinite(nu)) || !isfinite(alpha)) return;   // breakdown: KS handles it
   Acc l[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     xv[j] = axpy1<FA>(alpha, pv[j], xv[j]);
     rv[j] = axpy1<FA>(-alpha, qv[j], rv[j]);
     l[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], rv[j]) : (Acc)0;
+  }
+  if (fold_now) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      if (i < n) fold1(a.v.xhi, i, (double)xv[j]);
+      xv[j] = (V)0;
+    }
   }
   if (full) {
     store8(xlo + base, xv);
@@ -790,199 +959,164 @@ __device__ __forceinline__ void k2_body(const KArgs &a) {
   if (threadIdx.x == 0) a.part2[blockIdx.x] = (double)t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_slot2(KArgs a) {
-  const Ctl *c = a.ctl;
-  if (c->mode != M_ITER) return;
-  const int act = c->action;
-  switch (((act & 3) << 2) | ((act >> 2) & 3)) {
-  case 0: k2_body<FP16, FP16>(a); break;
-  case 1: k2_body<FP16, BF16>(a); break;
-  case 2: k2_body<FP16, FP32>(a); break;
-  case 3: k2_body<FP16, FP64>(a); break;
-  case 4: k2_body<BF16, FP16>(a); break;
-  case 5: k2_body<BF16, BF16>(a); break;
-  case 6: k2_body<BF16, FP32>(a); break;
-  case 7: k2_body<BF16, FP64>(a); break;
-  case 8: k2_body<FP32, FP16>(a); break;
-  case 9: k2_body<FP32, BF16>(a); break;
-  case 10: k2_body<FP32, FP32>(a); break;
-  case 11: k2_body<FP32, FP64>(a); break;
-  case 12: k2_body<FP64, FP16>(a); break;
-  case 13: k2_body<FP64, BF16>(a); break;
-  case 14: k2_body<FP64, FP32>(a); break;
-  default: k2_body<FP64, FP64>(a); break;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// KS: one block; final reductions and the scalar / policy step.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void copy_words(void *dst, const void *src, int bytes) {
-  uint64_t *d = (uint64_t *)dst;
-  const uint64_t *s = (const uint64_t *)src;
-  for (int i = threadIdx.x; i < bytes / 8; i += kBlock) d[i] = s[i];
-}
-
-__global__ __launch_bounds__(kBlock) void k_scalar(KArgs a) {
-  __shared__ Ctl sc;
-  __shared__ PolicyDev sp;
-  static_assert(sizeof(Ctl) % 8 == 0 && sizeof(PolicyDev) % 8 == 0, "word copies");
-  copy_words(&sc, a.ctl, sizeof(Ctl));
-  copy_words(&sp, a.pol, sizeof(PolicyDev));
-  __syncthreads();
-  const int mode = sc.mode;
-  if (mode == M_DONE) return;
-  const Sx x{&sc, &sp, a.h};
-  Ctl *c = &sc;
-  if (mode == M_ITER) {
-    const int fd = (c->action >> 2) & 3;
-    const double nu = reduce_partials_rt(fd, a.part1, a.P2);
-    const double sig = reduce_partials_rt(fd, a.part2, a.P2);
-    const double alpha = c->sigma / nu;
-    if (!(nu > 0.0 && isfinite(nu)) || !isfinite(alpha)) {
-      finish_block(x, false, true, false, false);
-    } else {
-      __shared__ int s_fin;
-      if (threadIdx.x == 0) {
-        c->alpha = alpha;
-        c->sig_new = sig;
-        c->k += 1;
-        const int k = c->k;
-        const double rho = sqrt(sig) / c->bnorm;
-        c->rho_new = rho;
-        const bool rep = (c->R > 0 && k % c->R == 0) || rho <= c->tol || !isfinite(sig);
-        if (rep) {
-          c->mode = M_REPLACE;
-          c->k2op = K2_NONE;
-          c->k3op = K3_FOLD;
-          s_fin = 0;
-        } else {
-          s_fin = 1;
-        }
-      }
-      __syncthreads();
-      if (s_fin) finish_block(x, true, false, false, false);
-    }
-  } else {
-    bool skip = false;
-    if (mode == M_INIT && c->bnorm_ready == 0) {
-      const double bb = partials_total<double>(a.part0, a.P2);
-      __shared__ int s_zero;
-      if (threadIdx.x == 0) {
-        c->bnorm = sqrt(bb);
-        c->bnorm_ready = 1;
-        s_zero = 0;
-        if (c->bnorm == 0.0) {
-          c->zero_solution = 1;
-          a.h.rho[0] = 0.0;
-          c->status = 0;
-          c->relres_true = 0.0;
-          set_done(c);
-          s_zero = 1;
-        }
-      }
-      __syncthreads();
-      skip = s_zero != 0;
-    }
-    if (!skip) {
-      const double s64 = partials_total<double>(a.part1, a.P2);
-      if (mode == M_INIT) {
-        init_block(x, s64);
-      } else if (mode == M_REPLACE) {
-        replace_block(x, s64);
-      } else if (threadIdx.x == 0) {   // M_FINAL
-        c->relres_true = sqrt(s64) / c->bnorm;
-        set_done(c);
-      }
-    }
-  }
-  __syncthreads();
-  copy_words(a.ctl, &sc, sizeof(Ctl));
-}
-
-// ---------------------------------------------------------------------------
-// K3: p = rd_fa(fma(beta, p, r)) [+ tier switch], fold, or p = r after a start
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void fold1(double *xhi, int i, double xl) {
-  const double s = xhi[i] + xl;
-  if (isfinite(s)) xhi[i] = s;
-}
-
-template <int FA>
-__device__ __forceinline__ void k3_xpay(const KArgs &a, bool sw) {
-  constexpr int TIER = (FA == FP64);
-  using V = typename TierT<TIER>::type;
-  V *p, *r, *xlo;
-  if constexpr (TIER) { p = a.v.p64; r = a.v.r64; xlo = a.v.xlo64; }
-  else { p = a.v.p32; r = a.v.r32; xlo = a.v.xlo32; }
-  const double beta = a.ctl->beta;
-  const int n = a.A.n;
-  const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
-  if (!sw) {
-    if (base + 8 <= n) {
-      V pv[8], rv[8];
-      load8(p + base, pv);
-      load8(r + base, rv);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) pv[j] = axpy1<FA>(beta, pv[j], rv[j]);
-      store8(p + base, pv);
-    } else {
-      for (int j = 0; j < 8; ++j) {
-        const int i = base + j;
-        if (i < n) p[i] = axpy1<FA>(beta, p[i], r[i]);
-      }
-    }
-    return;
-  }
-  for (int j = 0; j < 8; ++j) {
-    const int i = base + j;
-    if (i >= n) break;
-    const V pn = axpy1<FA>(beta, p[i], r[i]);
-    fold1(a.v.xhi, i, (double)xlo[i]);
-    if constexpr (TIER) {   // fp64 -> fp32
-      a.v.p32[i] = (float)pn;
-      a.v.r32[i] = (float)r[i];
-      a.v.xlo32[i] = 0.0f;
-    } else {                // fp32 -> fp64
-      a.v.p64[i] = (double)pn;
-      a.v.r64[i] = (double)r[i];
-      a.v.xlo64[i] = 0.0;
-    }
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_slot3(KArgs a) {
-  const Ctl *c = a.ctl;
-  const int op = c->k3op;
-  if (op == K3_NONE) return;
+// Elementwise steps (KB or KX): p = r = rd_tier(r64) after a start; the
+// direction update, with a tier change when the next action needs one; the
+// fold of x_lo into x_hi before a replacement or a restart.
+__device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S) {
+  const int op = S.k3op;
   const int n = a.A.n;
   const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
   if (op == K3_FOLD) {
-    const int tier = c->tier;
-    for (int j = 0; j < 8; ++j) {
-      const int i = base + j;
-      if (i >= n) break;
-      if (tier) { fold1(a.v.xhi, i, a.v.xlo64[i]); a.v.xlo64[i] = 0.0; }
-      else { fold1(a.v.xhi, i, (double)a.v.xlo32[i]); a.v.xlo32[i] = 0.0f; }
-    }
+    fold_group(a, S.tier, blockIdx.x);
   } else if (op == K3_COPY) {
-    const int tier = c->tier;
     for (int j = 0; j < 8; ++j) {
       const int i = base + j;
       if (i >= n) break;
       const double r = a.v.r64[i];
-      if (tier) { a.v.p64[i] = r; a.v.xlo64[i] = 0.0; }
+      if (S.tier) { a.v.p64[i] = r; a.v.xlo64[i] = 0.0; }
       else { const float f = (float)r; a.v.r32[i] = f; a.v.p32[i] = f; a.v.xlo32[i] = 0.0f; }
     }
-  } else {
-    const bool sw = c->k3switch != 0;
-    switch (c->k3_fa) {
-    case FP16: k3_xpay<FP16>(a, sw); break;
-    case BF16: k3_xpay<BF16>(a, sw); break;
-    case FP32: k3_xpay<FP32>(a, sw); break;
-    default: k3_xpay<FP64>(a, sw); break;
+  } else if (op == K3_XPAY && !S.k3switch && base + 8 <= n) {   // the common case, vectorised
+    if (S.tier_old) {
+      double pv[8], rv[8];
+      load8(a.v.p64 + base, pv);
+      load8(a.v.r64 + base, rv);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) pv[j] = xpay_rt<double>(S.k3_fa, S.beta, pv[j], rv[j]);
+      store8(a.v.p64 + base, pv);
+    } else {
+      float pv[8], rv[8];
+      load8(a.v.p32 + base, pv);
+      load8(a.v.r32 + base, rv);
+      const int fa = S.k3_fa;
+      const float bf = (float)S.beta;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float t = __builtin_fmaf(bf, pv[j], rv[j]);
+        pv[j] = fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
+      }
+      store8(a.v.p32 + base, pv);
+    }
+  } else if (op == K3_XPAY) {
+    const int told = S.tier_old;
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      if (i >= n) break;
+      if (told) {
+        const double pn = xpay_rt<double>(S.k3_fa, S.beta, a.v.p64[i], a.v.r64[i]);
+        if (S.k3switch) {
+          fold1(a.v.xhi, i, a.v.xlo64[i]);
+          a.v.p32[i] = (float)pn;
+          a.v.r32[i] = (float)a.v.r64[i];
+          a.v.xlo32[i] = 0.0f;
+        } else {
+          a.v.p64[i] = pn;
+        }
+      } else {
+        const float pn = xpay_rt<float>(S.k3_fa, S.beta, a.v.p32[i], a.v.r32[i]);
+        if (S.k3switch) {
+          fold1(a.v.xhi, i, (double)a.v.xlo32[i]);
+          a.v.p64[i] = (double)pn;
+          a.v.r64[i] = (double)a.v.r32[i];
+          a.v.xlo64[i] = 0.0;
+        } else {
+          a.v.p32[i] = pn;
+        }
+      }
     }
   }
+}
+
+#define MPCG_KB_CASE(FA, FD) \
+  case (FA) * 4 + (FD): kb_axpy<FA, FD>(a, S, fold_now); break;
+
+__global__ __launch_bounds__(kBlock) void k_b(KArgs a) {
+  __shared__ Ctl S;
+  __shared__ PolicyDev SP;
+  copy_words(&S, &a.ctl[0], sizeof(Ctl));
+  copy_words(&SP, a.pol, sizeof(PolicyDev));
+  __syncthreads();
+  const Sx x{&S, &SP, a.h, blockIdx.x == 0};
+  if (!S.step_done) step_b<false>(x, a);
+  const int bop = S.b_op;
+  const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
+  if (bop == B_AXPY) {
+    const int act = S.action;
+    switch ((act & 3) * 4 + ((act >> 2) & 3)) {
+      MPCG_KB_CASE(FP16, FP16) MPCG_KB_CASE(FP16, BF16) MPCG_KB_CASE(FP16, FP32) MPCG_KB_CASE(FP16, FP64)
+      MPCG_KB_CASE(BF16, FP16) MPCG_KB_CASE(BF16, BF16) MPCG_KB_CASE(BF16, FP32) MPCG_KB_CASE(BF16, FP64)
+      MPCG_KB_CASE(FP32, FP16) MPCG_KB_CASE(FP32, BF16) MPCG_KB_CASE(FP32, FP32) MPCG_KB_CASE(FP32, FP64)
+      MPCG_KB_CASE(FP64, FP16) MPCG_KB_CASE(FP64, BF16) MPCG_KB_CASE(FP64, FP32) MPCG_KB_CASE(FP64, FP64)
+    default: break;
+    }
+  } else if (bop == B_EXEC) {
+    exec_elementwise(a, S);
+  }
+  if (blockIdx.x == 0) {   // commit the state after this kernel for KX
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (bop == B_AXPY) {
+        S.pend_sigma = 1;
+        S.fold_done = fold_now ? 1 : 0;
+      } else if (bop == B_EXEC) {
+        S.k3op = K3_NONE;
+      }
+      S.b_op = B_NONE;
+      S.step_done = 0;
+    }
+    __syncthreads();
+    copy_words(&a.ctl[1], &S, sizeof(Ctl));
+  }
+}
+
+// KX: end-of-iteration step, then the pending elementwise operation.
+__global__ __launch_bounds__(kBlock) void k_x(KArgs a) {
+  __shared__ Ctl S;
+  __shared__ PolicyDev SP;
+  copy_words(&S, &a.ctl[1], sizeof(Ctl));
+  copy_words(&SP, a.pol, sizeof(PolicyDev));
+  __syncthreads();
+  const Sx x{&S, &SP, a.h, blockIdx.x == 0};
+  if (!S.step_done) step_x<false>(x, a);
+  exec_elementwise(a, S);
+  if (blockIdx.x == 0) {   // commit the state after this kernel for the next KA and KB
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      S.k3op = K3_NONE;
+      S.step_done = 0;
+    }
+    __syncthreads();
+    copy_words(&a.ctl[0], &S, sizeof(Ctl));
+  }
+}
+#undef MPCG_KB_CASE
+
+// One-block step kernels for policies whose step writes shared state or
+// evaluates the network: the step runs once, then KA / KB skip theirs.
+__global__ __launch_bounds__(kBlock) void k_step_b(KArgs a) {
+  __shared__ Ctl S;
+  __shared__ PolicyDev SP;
+  copy_words(&S, &a.ctl[0], sizeof(Ctl));
+  copy_words(&SP, a.pol, sizeof(PolicyDev));
+  __syncthreads();
+  const Sx x{&S, &SP, a.h, true};
+  step_b<true>(x, a);
+  if (threadIdx.x == 0) S.step_done = 1;
+  __syncthreads();
+  copy_words(&a.ctl[0], &S, sizeof(Ctl));
+}
+
+__global__ __launch_bounds__(kBlock) void k_step_x(KArgs a) {
+  __shared__ Ctl S;
+  __shared__ PolicyDev SP;
+  copy_words(&S, &a.ctl[1], sizeof(Ctl));
+  copy_words(&SP, a.pol, sizeof(PolicyDev));
+  __syncthreads();
+  const Sx x{&S, &SP, a.h, true};
+  step_x<true>(x, a);
+  if (threadIdx.x == 0) S.step_done = 1;
+  __syncthreads();
+  copy_words(&a.ctl[1], &S, sizeof(Ctl));
 }
 
 // ---------------------------------------------------------------------------
@@ -1012,7 +1146,7 @@ __global__ __launch_bounds__(kBlock) void k_start(KArgs a) {
 // x = x_hi + x_lo; requests the final true-residual check after a budget stop
 // or a breakdown.
 __global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
-  const Ctl *c = a.ctl;
+  const Ctl *c = &a.ctl[0];
   const int n = a.A.n;
   const int tier = c->tier;
   const int zero = c->zero_solution;
@@ -1024,7 +1158,12 @@ __global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
     else { fold1(a.v.xhi, i, (double)a.v.xlo32[i]); a.v.xlo32[i] = 0.0f; }
     a.v.xout[i] = zero ? 0.0 : a.v.xhi[i];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && (c->status == 1 || c->status == 3)) a.ctl->mode = M_FINAL;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (c->status == 1 || c->status == 3)) {
+    a.ctl[0].mode = M_FINAL;
+    a.ctl[0].k3op = K3_NONE;
+    a.ctl[0].pend_sigma = 0;
+    a.ctl[0].step_done = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1077,7 +1216,8 @@ __global__ __launch_bounds__(kBlock) void k_op_spmv(Mat A, const void *pv, void 
   const int r0 = blk * kRowsPerBlock;
   const int rows = min(kRowsPerBlock, A.n - r0);
   typename AccT<FS>::type acc[1];
-  spmv_rows<FS, 1>(A, (const V *)pv, r0, rows, lds, acc);
+  const GatherPlain<V> gp{(const V *)pv};
+  spmv_rows<FS, 1>(A, gp, r0, rows, lds, acc);
   if (threadIdx.x < rows) ((V *)qv)[r0 + threadIdx.x] = spmv_out<FS, V>(A, r0 + threadIdx.x, acc[0]);
 }
 
@@ -1089,7 +1229,8 @@ __global__ __launch_bounds__(kBlock) void k_op_residual(Mat A, const double *b, 
   const int r0 = blk * kRowsPerBlock;
   const int rows = min(kRowsPerBlock, A.n - r0);
   double acc[1];
-  spmv_rows<FP64, 1>(A, x, r0, rows, lds, acc);
+  const GatherPlain<double> gp{x};
+  spmv_rows<FP64, 1>(A, gp, r0, rows, lds, acc);
   if (threadIdx.x < rows) r[r0 + threadIdx.x] = b[r0 + threadIdx.x] - acc[0];
 }
 
@@ -1139,7 +1280,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_decide(const PolicyDev *P, in
     } else if (threadIdx.x == 0) {
       int ex = 0;
       state[idx] = s;
-      action[idx] = P->kind == POL_QTRAIN ? q_argmax(&P->q[s * kNAct]) : decide_scalar(P, s, (int)k[idx], &ex);
+      action[idx] = P->kind == POL_QTRAIN ? q_argmax(&P->q[s * kNAct]) : decide_scalar<true>(P, s, (int)k[idx], &ex);
     }
   }
 }
@@ -1148,23 +1289,25 @@ __global__ __launch_bounds__(kBlock) void k_policy_decide(const PolicyDev *P, in
 // launchers
 // ---------------------------------------------------------------------------
 void launch_start(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_start, dim3(a.P2), dim3(kBlock), 0, s, a); }
-
-void launch_k1(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_slot1, dim3(a.G1), dim3(kBlock), 0, s, a); }
-void launch_k2(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_slot2, dim3(a.P2), dim3(kBlock), 0, s, a); }
-void launch_ks(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, a); }
-void launch_k3(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_slot3, dim3(a.P2), dim3(kBlock), 0, s, a); }
+void launch_ka(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_a, dim3(a.G1), dim3(kBlock), 0, s, a); }
+void launch_kb(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_b, dim3(a.P2), dim3(kBlock), 0, s, a); }
+void launch_kx(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_x, dim3(a.P2), dim3(kBlock), 0, s, a); }
+void launch_step_b(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_step_b, dim3(1), dim3(kBlock), 0, s, a); }
+void launch_step_x(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_step_x, dim3(1), dim3(kBlock), 0, s, a); }
 
 void launch_slot(const KArgs &a, hipStream_t s) {
-  launch_k1(a, s);
-  launch_k2(a, s);
-  launch_ks(a, s);
-  launch_k3(a, s);
+  launch_ka(a, s);
+  if (a.slow) launch_step_b(a, s);
+  launch_kb(a, s);
+  if (a.slow) launch_step_x(a, s);
+  launch_kx(a, s);
 }
 
 void launch_finish(const KArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(a.P2), dim3(kBlock), 0, s, a);
-  launch_k1(a, s);
-  launch_ks(a, s);
+  launch_ka(a, s);
+  if (a.slow) launch_step_b(a, s);
+  launch_kb(a, s);
 }
 
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,

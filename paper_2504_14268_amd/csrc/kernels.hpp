@@ -25,8 +25,10 @@ struct Vecs {
   const double *b;
   double *xout;   // caller's x: initial guess in, solution out
   double *xhi;    // fp64 accumulator of the solution
-  float *r32, *p32, *q32, *xlo32;
-  double *r64, *p64, *q64, *xlo64;
+  float *r32, *q32, *xlo32;
+  double *r64, *q64, *xlo64;
+  float *p32;     // direction
+  double *p64;
 };
 
 struct Hist {
@@ -59,20 +61,24 @@ struct PolicyDev {
   int32_t *roll_n;
 };
 
-// What the next kernel of each slot position does.
+// Phase of the next KA (mode), what KB executes (b_op), and the pending
+// elementwise operation (k3op) that KB (after a start or a replacement) or KX
+// (after an iteration) applies.
 enum { M_INIT = 0, M_ITER = 1, M_REPLACE = 2, M_FINAL = 3, M_DONE = 4 };
-enum { K2_NONE = 0, K2_AXPY = 1 };
 enum { K3_NONE = 0, K3_XPAY = 1, K3_COPY = 2, K3_FOLD = 3 };
+enum { B_NONE = 0, B_AXPY = 1, B_EXEC = 2 };
 enum { FL_REPLACED = 1, FL_EXPLORED = 2, FL_FALLBACK = 4, FL_SWITCH = 8 };
 
-// Device-resident solver state, written only by "last blocks" (one thread).
+// Device-resident solver state.  Every workgroup of a kernel holds the same
+// copy in LDS; workgroup 0 commits it to the other half of the double buffer.
 struct Ctl {
-  int32_t mode, k2op, k3op, k3switch;
-  int32_t tier, tier_old, action, k;
-  int32_t maxit, status, fell_back, fallback_at;
-  int32_t nrep, nrep_since, s, explored;
-  int32_t prev_action, R, fallback_enabled, k3_fa;
-  int32_t zero_solution, bnorm_ready, pad1, pad2;
+  int32_t mode, k3op, k3switch, tier;
+  int32_t tier_old, action, k, maxit;
+  int32_t status, fell_back, fallback_at, nrep;
+  int32_t nrep_since, s, explored, prev_action;
+  int32_t R, fallback_enabled, k3_fa, zero_solution;
+  int32_t bnorm_ready, pend_sigma, b_op, step_done;
+  int32_t fold_done, pad_;
   double tol, bnorm, sigma, sig_new, alpha, beta, rho_new, last_true, cost_sum, relres_true;
   double rep_hist[3];
   float feat[kMlpIn];
@@ -82,15 +88,16 @@ struct Ctl {
 struct KArgs {
   Mat A;
   Vecs v;
-  Ctl *ctl;
+  Ctl *ctl;            // ctl[0]: read by KA and KB, written by KX; ctl[1]: written by KB, read by KX
+  int slow;            // 1: the scalar steps run in one-block kernels (KS)
   const PolicyDev *pol;
   Hist h;
   double *part0;       // partials of b.b (start)
-  double *part1;       // K1 partials (nu or ||r64||^2), one per 2048-row group
-  double *part2;       // K2 partials (sigma'), one per 2048-element block
-  int P2;              // 2048-element groups = K1 groups = vector blocks
-  int G1;              // K1 workgroups launched (P2 rounded up to 8)
-  int8_t *slot_log;    // optional: K1 records the mode of each slot (profiling)
+  double *part1;       // KA partials (nu or ||r64||^2), one per 2048-row group
+  double *part2;       // KB partials (sigma'), one per 2048-element block
+  int P2;              // 2048-element groups = KA groups = vector blocks
+  int G1;              // KA workgroups launched (P2 rounded up to 8)
+  int8_t *slot_log;    // optional: KA records the mode of each slot (profiling)
   int slot;            // index of this slot (with slot_log)
 };
 

@@ -5,10 +5,11 @@
 namespace mpcg {
 void launch_start(const KArgs &a, hipStream_t s);
 void launch_slot(const KArgs &a, hipStream_t s);
-void launch_k1(const KArgs &a, hipStream_t s);
-void launch_k2(const KArgs &a, hipStream_t s);
-void launch_ks(const KArgs &a, hipStream_t s);
-void launch_k3(const KArgs &a, hipStream_t s);
+void launch_ka(const KArgs &a, hipStream_t s);
+void launch_kb(const KArgs &a, hipStream_t s);
+void launch_kx(const KArgs &a, hipStream_t s);
+void launch_step_x(const KArgs &a, hipStream_t s);
+void launch_step_b(const KArgs &a, hipStream_t s);
 void launch_finish(const KArgs &a, hipStream_t s);
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,
                     int8_t *rexp, hipStream_t s);
