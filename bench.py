@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time to true relres 1e-8 + SpMV HBM GB/s: mixed/learned vs fp64 CG, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_traffic_lap3d_128.json")
 KERNEL_SOURCES = ["paper_2504_14268_amd/csrc/kernels.hip", "paper_2504_14268_amd/csrc/dev.hpp",
                   "paper_2504_14268_amd/csrc/kernels.hpp"]
@@ -66,6 +67,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-rspd", action="store_true", help="skip the random SPD workload")
     ap.add_argument("--N", type=int, default=128, help="3D Laplacian grid size")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for HBM counter collection: one plain copy of 256 MiB (the scale "
+                         "reference for FETCH_SIZE / WRITE_SIZE), then one mixed solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
@@ -96,6 +100,21 @@ def main():
     xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     pol_mixed = M.Policy(kind=M.POLICY_FIXED, fixed_action=act_mixed)
     pol_fp64 = M.Policy(kind=M.POLICY_FIXED, fixed_action=act_fp64)
+
+    if args.counters:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        m.set_policy(pol_mixed)
+        m.set_options(replace_period=50, fallback=False)
+        r = m.solve(bd, xd, tol=tol, maxit=5000)
+        print(json.dumps({"counters_run": True, "copy_bytes": COPY_BYTES, "iters": r["iters"],
+                          "relres_true": r["relres_true"], "kernel_hash": kernel_hash(),
+                          "bytes_per_launch_ka": ka_bytes(A.n, A.nnz, M.BF16, 4)}), flush=True)
+        return
 
     def solve(pol, R, maxit=5000, profile=False):
         m.set_policy(pol)

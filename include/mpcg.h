@@ -109,6 +109,10 @@ typedef struct {
     int32_t profile;           /* 1: time every kernel launch of the solve with
                                   HIP events on the handle's stream (see
                                   mpcg_get_profile); adds event overhead        */
+    int32_t spmv_rows;         /* rows per SpMV workgroup: 512, 1024 or 2048
+                                  (0: chosen from n); results do not depend
+                                  on it                                          */
+    int32_t reserved;
 } mpcg_solve_opts;
 
 /* Per-kernel timing of the last solve made with opts.profile = 1.  One CG

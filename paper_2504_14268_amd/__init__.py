@@ -45,7 +45,8 @@ class PolicyDesc(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("replace_period", C.c_int32), ("fallback", C.c_int32),
-                ("chunk", C.c_int32), ("profile", C.c_int32)]
+                ("chunk", C.c_int32), ("profile", C.c_int32),
+                ("spmv_rows", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -261,8 +262,8 @@ class Matrix:
         _check(lib().mpcg_set_policy(self.h, policy.h if policy is not None else None), "set_policy")
         self.policy = policy
 
-    def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False):
-        o = SolveOpts(replace_period, int(fallback), chunk, int(profile))
+    def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False, spmv_rows=0):
+        o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, 0)
         _check(lib().mpcg_set_options(self.h, C.byref(o)), "set_options")
 
     def solve(self, b, x, tol=1e-8, maxit=1000) -> dict:

@@ -155,9 +155,9 @@ struct mpcg_matrix {
   // policy
   mpcg_policy *pol = nullptr;
   mpcg_policy *defpol = nullptr;
-  mpcg_solve_opts opts{50, 0, 32, 0};
+  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0};
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_chunk[2] = {nullptr, nullptr};
-  int G1 = 0, P2 = 0;
+  int P2 = 0;
 
   Mat mat() const {
     Mat m;
@@ -251,14 +251,15 @@ static int ensure_hist(mpcg_matrix *A, int maxit) {
   return MPCG_OK;
 }
 
-// Elapsed times of the launches of each slot of a completed chunk: KA, KB and
-// (policies with one-block steps) the two step kernels.
+// Kernel durations of each slot of a completed chunk (a start and a stop event
+// per launch): KA, KB, KX and, for policies with one-block steps, the two step
+// kernels.
 static int collect_chunk(mpcg_matrix *A, int pool_idx, int chunk, int per_slot, int64_t first, int m) {
   for (int s = 0; s < m; ++s) {
     hipEvent_t *e = &A->pev[((size_t)pool_idx * chunk + s) * per_slot];
     float t[5] = {0, 0, 0, 0, 0};
-    for (int j = 0; j + 1 < per_slot; ++j) HIP_TRY(hipEventElapsedTime(&t[j], e[j], e[j + 1]));
-    if (per_slot == 4) {          // KA, KB, KX
+    for (int j = 0; 2 * j + 1 < per_slot; ++j) HIP_TRY(hipEventElapsedTime(&t[j], e[2 * j], e[2 * j + 1]));
+    if (per_slot == 6) {          // KA, KB, KX
       A->ta[first + s] = t[0];
       A->tb[first + s] = t[1];
       A->tx[first + s] = t[2];
@@ -271,6 +272,15 @@ static int collect_chunk(mpcg_matrix *A, int pool_idx, int chunk, int per_slot, 
     }
   }
   return MPCG_OK;
+}
+
+// Rows per SpMV workgroup: the largest group size that still gives about four
+// workgroups per compute unit (256 CUs), at least 512.
+static int spmv_group_rows(int n, int requested) {
+  if (requested == 512 || requested == 1024 || requested == 2048) return requested;
+  for (int g = 2048; g > 512; g >>= 1)
+    if ((n + g - 1) / g >= 1024) return g;
+  return 512;
 }
 
 static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
@@ -295,7 +305,9 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
   a.part0 = A->d_part0;
   a.part1 = A->d_part1;
   a.part2 = A->d_part2;
-  a.G1 = A->G1;
+  a.grows = spmv_group_rows(A->n, A->opts.spmv_rows);
+  a.P1 = (A->n + a.grows - 1) / a.grows;
+  a.G1 = round_up(a.P1, 8);
   a.P2 = A->P2;
   return a;
 }
@@ -374,8 +386,8 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   A->nnz_pad = round_up((int)nnz, 8) + 8;
   A->stream = (hipStream_t)stream;
   A->P2 = (A->n + kVecBlock - 1) / kVecBlock;
-  A->G1 = round_up(A->P2, 8);
-  if (A->P2 > 64 * kVecBlock) return bail(fail(MPCG_ERR_INVALID, "n too large for the partial reduction"));
+  if ((A->n + kKaRows - 1) / kKaRows > 64 * kVecBlock)
+    return bail(fail(MPCG_ERR_INVALID, "n too large for the partial reduction"));
   const size_t np = (size_t)A->nnz_pad;
   TRY_A(dmalloc(&A->d_rp, (size_t)n + 1));
   TRY_A(dmalloc(&A->d_ci, np));
@@ -396,7 +408,7 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   launch_shadows(A->n, A->d_rp, A->d_v64, A->d_v32, A->d_vbf, A->d_vh, A->d_rexp, A->stream);
   TRY_A(hipGetLastError());
   TRY_A(dmalloc(&A->d_part0, (size_t)A->P2 + 64));
-  TRY_A(dmalloc(&A->d_part1, (size_t)A->P2 + 64));
+  TRY_A(dmalloc(&A->d_part1, (size_t)(A->n + kKaRows - 1) / kKaRows + 64));
   TRY_A(dmalloc(&A->d_part2, (size_t)A->P2 + 64));
   TRY_A(dmalloc(&A->d_scalar, 8));
   TRY_A(dmalloc(&A->d_ctl, 2));
@@ -601,6 +613,8 @@ int mpcg_set_policy(mpcg_matrix *A, mpcg_policy *P) {
 int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
   if (!A || !o) return fail(MPCG_ERR_INVALID, "NULL argument");
   if (o->replace_period < 0 || o->chunk < 0) return fail(MPCG_ERR_INVALID, "negative option");
+  if (o->spmv_rows != 0 && o->spmv_rows != 512 && o->spmv_rows != 1024 && o->spmv_rows != 2048)
+    return fail(MPCG_ERR_INVALID, "spmv_rows must be 0, 512, 1024 or 2048");
   A->opts = *o;
   return MPCG_OK;
 }
@@ -637,7 +651,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
 
   KArgs a = make_args(A, b, x);
   a.slow = (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->desc.kind == MPCG_POLICY_MLP || P->roll_cap > 0) ? 1 : 0;
-  const int per_slot = a.slow ? 6 : 4;
+  const int per_slot = a.slow ? 10 : 6;   // a start and a stop event per launch
   const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
   const bool prof = A->opts.profile != 0;
   std::memset(&A->prof, 0, sizeof(A->prof));
@@ -673,22 +687,19 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
       if (prof) {
         hipEvent_t *e = &A->pev[((size_t)idx * chunk + s) * per_slot];
         a.slot = (int)(slots + s);
-        int ei = 0;
-        HIP_TRY(hipEventRecord(e[ei++], st));
-        launch_ka(a, st);
-        HIP_TRY(hipEventRecord(e[ei++], st));
+        launch_ka(a, st, e[0], e[1]);
+        int ei = 2;
         if (a.slow) {
-          launch_step_b(a, st);
-          HIP_TRY(hipEventRecord(e[ei++], st));
+          launch_step_b(a, st, e[ei], e[ei + 1]);
+          ei += 2;
         }
-        launch_kb(a, st);
-        HIP_TRY(hipEventRecord(e[ei++], st));
+        launch_kb(a, st, e[ei], e[ei + 1]);
+        ei += 2;
         if (a.slow) {
-          launch_step_x(a, st);
-          HIP_TRY(hipEventRecord(e[ei++], st));
+          launch_step_x(a, st, e[ei], e[ei + 1]);
+          ei += 2;
         }
-        launch_kx(a, st);
-        HIP_TRY(hipEventRecord(e[ei++], st));
+        launch_kx(a, st, e[ei], e[ei + 1]);
       } else {
         launch_slot(a, st);
       }

@@ -21,6 +21,7 @@
 // order every hand-off.  Policies whose step writes shared state (Q-learning
 // updates, rollout logs) or evaluates the MLP run each step once, in a
 // one-block kernel (KS) before KB and before KX.  The host only enqueues launches.
+#include <hip/hip_ext.h>
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -94,7 +95,6 @@ __device__ __forceinline__ void load_vals8(const Mat &A, int c, typename AccT<FS
 // LDS capacity (entries) of one staging window per 256 rows: 8 KiB of values
 // (accumulation type) and their column indices.
 template <typename Acc> struct Cap { static constexpr int value = 8192 / sizeof(Acc); };
-constexpr int kRPT = 2;                                  // rows per thread in K1
 constexpr int kLdsDoubles = kRPT * 2 * 8192 / 8;
 
 template <typename A>
@@ -705,7 +705,7 @@ __device__ __forceinline__ void step_b(const Sx &x, const KArgs &a) {
   const int la = c->mode;   // what KA has just executed
   if (la == M_ITER) {
     const int fd = (c->action >> 2) & 3;
-    const double nu = reduce_partials_rt(fd, a.part1, a.P2);
+    const double nu = reduce_partials_rt(fd, a.part1, a.P1);
     const double alpha = c->sigma / nu;
     if (!(nu > 0.0 && isfinite(nu)) || !isfinite(alpha)) {
       finish_block<FULL>(x, false, true, false, false);
@@ -736,7 +736,7 @@ __device__ __forceinline__ void step_b(const Sx &x, const KArgs &a) {
         return;
       }
     }
-    const double s64 = partials_total<double>(a.part1, a.P2);
+    const double s64 = partials_total<double>(a.part1, a.P1);
     if (la == M_INIT) {
       init_block<FULL>(x, s64);
     } else if (la == M_REPLACE) {
@@ -764,54 +764,299 @@ __device__ __forceinline__ void fold1(double *xhi, int i, double xl) {
   if (isfinite(s)) xhi[i] = s;
 }
 
+template <int RPT>
+__device__ __forceinline__ double subtrees_rt(int fd, const double (&s)[RPT]) {
+  if constexpr (RPT == 1) {
+    return s[0];
+  } else {
+    static_assert(RPT == 2, "pairwise combination written for two subtrees");
+    if (fd == FP64) return s[0] + s[1];
+    return (double)((float)s[0] + (float)s[1]);
+  }
+}
+
 // ---------------------------------------------------------------------------
-// KA: SpMV of an iteration over a group of 2048 rows (one partial per group =
-// the pairwise sum of its eight 256-row subtrees).
+// KA: SpMV over a group of consecutive rows per workgroup (a.grows rows, a
+// power of two from 512 to 2048), software-pipelined: the group's row pointers
+// are staged in LDS once, and while the rows of one window of CSR entries run
+// their gathers and fma chains, the next window's values and column indices
+// are already in flight into registers.  Each 512-row sub-block ends with an
+// epilogue (output, partials); the group partial is the pairwise sum of its
+// sub-block partials, i.e. an aligned subtree of the whole vector's tree.
 // ---------------------------------------------------------------------------
-constexpr int kGroupBlocks = kVecBlock / kRowsPerBlock;   // 8 row blocks = 2048 rows
+constexpr int kMaxGroupRows = 2048;
+
+// LDS window of the group SpMV: values kept in their storage format (16-bit
+// formats as raw bits, widened when read), 4096 entries for 16-bit formats,
+// 2048 otherwise; 24 KiB of values and indices in every case.
+template <int FS> struct LdsWin { using type = float; static constexpr int cap = 2048; };
+template <> struct LdsWin<FP64> { using type = double; static constexpr int cap = 2048; };
+template <> struct LdsWin<BF16> { using type = uint16_t; static constexpr int cap = 4096; };
+template <> struct LdsWin<FP16> { using type = uint16_t; static constexpr int cap = 4096; };
+constexpr int kLdsWinBytes = 24576;
+constexpr int kLdsKa = (kLdsWinBytes + (kMaxGroupRows + 4) * 4) / 8;   // doubles
+
+template <int FS> struct RawVals { float v[8]; };
+template <> struct RawVals<FP64> { double v[8]; };
+template <> struct RawVals<FP16> { uint4 w; };
+template <> struct RawVals<BF16> { uint4 w; };
+
+template <int FS>
+__device__ __forceinline__ void raw_load(const Mat &A, int c, RawVals<FS> &r) {
+  if constexpr (FS == FP64) load8(A.v64 + c, r.v);
+  else if constexpr (FS == FP32) load8(A.v32 + c, r.v);
+  else r.w = *(const uint4 *)((FS == BF16 ? A.vbf : A.vh) + c);
+}
+
+template <int FS>
+__device__ __forceinline__ void raw_to_lds(const RawVals<FS> &r, typename LdsWin<FS>::type *p) {
+  if constexpr (FS == FP64 || FS == FP32) lds_store8(p, r.v);
+  else *(uint4 *)p = r.w;
+}
+
+// One stored value, widened to the accumulation type (exact).
+template <int FS>
+__device__ __forceinline__ typename AccT<FS>::type lds_widen(typename LdsWin<FS>::type x) {
+  if constexpr (FS == BF16) return bf16_bits_to_f32(x);
+  else if constexpr (FS == FP16) return f16_bits_to_f32(x);
+  else return x;
+}
+
+__device__ __forceinline__ double add_rt(int fd, double x, double y) {
+  if (fd == FP64) return x + y;
+  return (double)((float)x + (float)y);
+}
+
+// Pairwise sum of the sub-block partials t[0..3] of a group of `grows` rows.
+__device__ __forceinline__ double group_tree(int fd, int grows, const double (&t)[4]) {
+  if (grows <= 512) return t[0];
+  if (grows <= 1024) return add_rt(fd, t[0], t[1]);
+  return add_rt(fd, add_rt(fd, t[0], t[1]), add_rt(fd, t[2], t[3]));
+}
+
+// Prefetch of one window: up to two 8-entry chunks per thread, held in
+// registers (values in their storage format, column indices).
+template <int FS, int NCH>
+__device__ __forceinline__ void win_load(const Mat &A, int wb, int we, RawVals<FS> &v0, RawVals<FS> &v1,
+                                         int4 &c0a, int4 &c0b, int4 &c1a, int4 &c1b) {
+  const int c0 = wb + threadIdx.x * 8;
+  if (c0 < we) {
+    raw_load<FS>(A, c0, v0);
+    c0a = *(const int4 *)(A.ci + c0);
+    c0b = *(const int4 *)(A.ci + c0 + 4);
+  }
+  if constexpr (NCH == 2) {
+    const int c1 = c0 + kVecBlock;
+    if (c1 < we) {
+      raw_load<FS>(A, c1, v1);
+      c1a = *(const int4 *)(A.ci + c1);
+      c1b = *(const int4 *)(A.ci + c1 + 4);
+    }
+  }
+}
+
+template <int FS, int NCH>
+__device__ __forceinline__ void win_store(int wb, int we, const RawVals<FS> &v0, const RawVals<FS> &v1,
+                                          int4 c0a, int4 c0b, int4 c1a, int4 c1b,
+                                          typename LdsWin<FS>::type *lv, int *lc) {
+  const int o0 = threadIdx.x * 8;
+  if (wb + o0 < we) {
+    raw_to_lds<FS>(v0, lv + o0);
+    *(int4 *)(lc + o0) = c0a;
+    *(int4 *)(lc + o0 + 4) = c0b;
+  }
+  if constexpr (NCH == 2) {
+    const int o1 = o0 + kVecBlock;
+    if (wb + o1 < we) {
+      raw_to_lds<FS>(v1, lv + o1);
+      *(int4 *)(lc + o1) = c1a;
+      *(int4 *)(lc + o1 + 4) = c1b;
+    }
+  }
+}
+
+// pre(sb) runs when sub-block sb starts (own-row loads), epi(sb, acc) when its
+// rows are complete.  Both are called by every thread (block-uniform).
+template <int FS, typename G, typename Pre, typename Epi>
+__device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0, int grows, void *lds_raw,
+                                           Pre &&pre, Epi &&epi) {
+  using Acc = typename AccT<FS>::type;
+  using L = typename LdsWin<FS>::type;
+  constexpr int CAP = LdsWin<FS>::cap;
+  constexpr int NCH = CAP / kVecBlock;
+  static_assert(NCH == 1 || NCH == 2, "window of one or two chunks per thread");
+  static_assert(CAP * (sizeof(L) + 4) <= kLdsWinBytes, "window fits its LDS");
+  L *lv = (L *)lds_raw;
+  int *lc = (int *)(lv + CAP);
+  int *lrp = (int *)((char *)lds_raw + kLdsWinBytes);
+  const int tid = threadIdx.x;
+  for (int i = tid; i <= grows; i += kBlock) lrp[i] = A.rp[g0 + i];
+  __syncthreads();
+  const int nsb = (grows + kKaRows - 1) / kKaRows;
+  RawVals<FS> v0, v1;
+  int4 c0a, c0b, c1a, c1b;
+  int sb = 0;
+  int ke = lrp[min(kKaRows, grows)];
+  int wb = lrp[0] & ~7;
+  win_load<FS, NCH>(A, wb, min(wb + CAP, ke), v0, v1, c0a, c0b, c1a, c1b);
+  Acc acc[kRPT];
+  int my_s[kRPT], my_e[kRPT];
+  auto rows_of = [&](int s) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = s * kKaRows + tid + j * kRowsPerBlock;
+      acc[j] = (Acc)0;
+      my_s[j] = 0;
+      my_e[j] = 0;
+      if (lr < grows) {
+        my_s[j] = lrp[lr];
+        my_e[j] = lrp[lr + 1];
+      }
+    }
+  };
+  rows_of(0);
+  pre(0);
+  while (true) {
+    const int we = min(wb + CAP, ke);
+    win_store<FS, NCH>(wb, we, v0, v1, c0a, c0b, c1a, c1b, lv, lc);
+    __syncthreads();
+    // the next window: the rest of this sub-block, or the start of the next one
+    int nsb_ = sb, nwb = wb + CAP, nke = ke;
+    if (we >= ke) {
+      nsb_ = sb + 1;
+      if (nsb_ < nsb) {
+        nwb = lrp[nsb_ * kKaRows] & ~7;
+        nke = lrp[min((nsb_ + 1) * kKaRows, grows)];
+      }
+    }
+    // The next window's loads are issued right after this window's first
+    // gathers: waiting for those gathers (in-order counters) then does not
+    // wait for the prefetch, which stays in flight through the fma chains.
+    bool pf = nsb_ < nsb;
+    if constexpr (sizeof(Acc) == 4) {
+      // the thread's rows advance together, eight entries each per step, so
+      // the gathers of all its rows are in flight at once
+      int lo[kRPT], hi[kRPT], steps = 0;
+#pragma unroll
+      for (int j = 0; j < kRPT; ++j) {
+        lo[j] = max(my_s[j], wb);
+        hi[j] = min(my_e[j], we);
+        steps = max(steps, (hi[j] - lo[j] + 7) >> 3);
+      }
+      for (int st = 0; st < steps; ++st) {
+        Acc xv[kRPT][8], vv[kRPT][8];
+        int cnt[kRPT];
+#pragma unroll
+        for (int j = 0; j < kRPT; ++j) {
+          const int kk = lo[j] + st * 8;
+          cnt[j] = hi[j] - kk;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (u < cnt[j]) {
+              vv[j][u] = lds_widen<FS>(lv[kk - wb + u]);
+              xv[j][u] = gather.template get<Acc>(lc[kk - wb + u]);
+            }
+          }
+        }
+        if (pf) {
+          win_load<FS, NCH>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+          pf = false;
+        }
+#pragma unroll
+        for (int j = 0; j < kRPT; ++j)
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (u < cnt[j]) acc[j] = fma_acc(vv[j][u], xv[j][u], acc[j]);
+      }
+    } else {
+      // fp64: one row at a time (register budget)
+#pragma unroll
+      for (int j = 0; j < kRPT; ++j) {
+        const int lo = max(my_s[j], wb), hi = min(my_e[j], we);
+        for (int kk = lo; kk < hi; kk += 8) {
+          const int cnt = hi - kk;
+          Acc xv[8], vv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (u < cnt) {
+              vv[u] = lds_widen<FS>(lv[kk - wb + u]);
+              xv[u] = gather.template get<Acc>(lc[kk - wb + u]);
+            }
+          }
+          if (pf) {
+            win_load<FS, NCH>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+            pf = false;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (u < cnt) acc[j] = fma_acc(vv[u], xv[u], acc[j]);
+        }
+      }
+    }
+    if (pf) win_load<FS, NCH>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+    if (we >= ke) {
+      epi(sb, acc);
+      if (nsb_ >= nsb) break;
+      rows_of(nsb_);
+      pre(nsb_);
+    }
+    __syncthreads();   // the LDS window is refilled next
+    sb = nsb_;
+    wb = nwb;
+    ke = nke;
+  }
+}
 
 template <int FS, int TIER>
 __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, void *lds) {
   using V = typename TierT<TIER>::type;
+  using Acc = typename AccT<FS>::type;
   const V *p;
   V *q;
   if constexpr (TIER) { p = a.v.p64; q = a.v.q64; } else { p = a.v.p32; q = a.v.q32; }
   const int fd = (S.action >> 2) & 3;
   const int n = a.A.n;
-  const GatherPlain<V> gp{p};
-  double sub[8];
-#pragma unroll 1
-  for (int sb = 0; sb < kGroupBlocks / kRPT; ++sb) {
-    const int r0 = (g * kGroupBlocks + sb * kRPT) * kRowsPerBlock;
-    if (r0 >= n) {            // zero-padded subtrees
+  const int g0 = g * a.grows;
+  const int grows = min(a.grows, n - g0);
+  V pi[kRPT];
+  int8_t ex[kRPT];
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  auto pre = [&](int sb) {
 #pragma unroll
-      for (int j = 0; j < kRPT; ++j) sub[sb * kRPT + j] = 0.0;
-      continue;
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      pi[j] = (V)0;
+      ex[j] = 0;
+      if (lr < grows) {
+        pi[j] = p[g0 + lr];
+        if constexpr (FS == FP16) ex[j] = a.A.rexp[g0 + lr];
+      }
     }
-    const int nrows = min(kRPT * kRowsPerBlock, n - r0);
-    typename AccT<FS>::type acc[kRPT];
-    spmv_rows<FS, kRPT>(a.A, gp, r0, nrows, lds, acc);
-    V qi[kRPT], pi[kRPT];
+  };
+  auto epi = [&](int sb, Acc (&acc)[kRPT]) {
+    V qi[kRPT];
     bool valid[kRPT];
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
-      const int lr = threadIdx.x + j * kRowsPerBlock;
-      const int i = r0 + lr;
-      valid[j] = lr < nrows;
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      valid[j] = lr < grows;
       qi[j] = (V)0;
-      pi[j] = (V)0;
       if (valid[j]) {
-        qi[j] = spmv_out<FS, V>(a.A, i, acc[j]);
-        q[i] = qi[j];
-        pi[j] = p[i];
+        if constexpr (FS == FP16) qi[j] = (V)ldexp((double)acc[j], (int)ex[j]);
+        else qi[j] = (V)acc[j];
+        q[g0 + lr] = qi[j];
       }
     }
     double s2[kRPT];
     dot_leaf_multi_rt<kRPT>(fd, pi, qi, valid, s2);
-#pragma unroll
-    for (int j = 0; j < kRPT; ++j) sub[sb * kRPT + j] = s2[j];
-  }
-  if (threadIdx.x == 0) a.part1[g] = tree8_rt(fd, sub);
+    const double s = subtrees_rt<kRPT>(fd, s2);
+    t[0] = sb == 0 ? s : t[0];
+    t[1] = sb == 1 ? s : t[1];
+    t[2] = sb == 2 ? s : t[2];
+    t[3] = sb == 3 ? s : t[3];
+  };
+  spmv_group<FS>(a.A, GatherPlain<V>{p}, g0, grows, lds, pre, epi);
+  if (threadIdx.x == 0) a.part1[g] = group_tree(fd, a.grows, t);
 }
 
 // fp64 residual r = b - A x_hi with the partial of its squared norm (start,
@@ -819,27 +1064,26 @@ __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, voi
 // replacement in the current tier.
 __device__ __forceinline__ void ka_residual(const KArgs &a, const Ctl &S, int g, int mode, void *lds) {
   const int n = a.A.n;
-  const GatherPlain<double> gx{a.v.xhi};
-  double sub[8];
-#pragma unroll 1
-  for (int sb = 0; sb < kGroupBlocks / kRPT; ++sb) {
-    const int r0 = (g * kGroupBlocks + sb * kRPT) * kRowsPerBlock;
-    if (r0 >= n) {
+  const int g0 = g * a.grows;
+  const int grows = min(a.grows, n - g0);
+  double bi[kRPT];
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  auto pre = [&](int sb) {
 #pragma unroll
-      for (int j = 0; j < kRPT; ++j) sub[sb * kRPT + j] = 0.0;
-      continue;
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      bi[j] = lr < grows ? a.v.b[g0 + lr] : 0.0;
     }
-    const int nrows = min(kRPT * kRowsPerBlock, n - r0);
-    double acc[kRPT];
-    spmv_rows<FP64, kRPT>(a.A, gx, r0, nrows, lds, acc);
+  };
+  auto epi = [&](int sb, double (&acc)[kRPT]) {
     double leaf[kRPT];
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
-      const int lr = threadIdx.x + j * kRowsPerBlock;
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
       leaf[j] = 0.0;
-      if (lr < nrows) {
-        const int i = r0 + lr;
-        const double r = a.v.b[i] - acc[j];
+      if (lr < grows) {
+        const int i = g0 + lr;
+        const double r = bi[j] - acc[j];
         leaf[j] = r * r;
         if (mode == M_INIT) {
           a.v.r64[i] = r;
@@ -850,10 +1094,14 @@ __device__ __forceinline__ void ka_residual(const KArgs &a, const Ctl &S, int g,
     }
     double s2[kRPT];
     block_tree_multi<kRPT>(leaf, s2);
-#pragma unroll
-    for (int j = 0; j < kRPT; ++j) sub[sb * kRPT + j] = s2[j];
-  }
-  if (threadIdx.x == 0) a.part1[g] = tree8(sub);
+    const double s = subtrees_rt<kRPT>(FP64, s2);
+    t[0] = sb == 0 ? s : t[0];
+    t[1] = sb == 1 ? s : t[1];
+    t[2] = sb == 2 ? s : t[2];
+    t[3] = sb == 3 ? s : t[3];
+  };
+  spmv_group<FP64>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pre, epi);
+  if (threadIdx.x == 0) a.part1[g] = group_tree(FP64, a.grows, t);
 }
 
 // x_hi += x_lo, x_lo = 0 over one 2048-element group (current tier).
@@ -870,8 +1118,8 @@ __device__ __forceinline__ void fold_group(const KArgs &a, int tier, int g) {
 
 __global__ __launch_bounds__(kBlock) void k_a(KArgs a) {
   const int g = xcd_group(a.G1);
-  if (g >= a.P2) return;
-  __shared__ double lds[kLdsDoubles];
+  if (g >= a.P1) return;
+  __shared__ double lds[kLdsKa];
   const Ctl &S = a.ctl[0];
   const int mode = S.mode;
   if (a.slot_log && g == 0 && threadIdx.x == 0) a.slot_log[a.slot] = (int8_t)mode;
@@ -898,6 +1146,16 @@ __global__ __launch_bounds__(kBlock) void k_a(KArgs a) {
 // replacement period, x_lo is also folded into x_hi here (the replacement that
 // follows begins with that fold).
 // ---------------------------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ void load8_tail(const V *p, int base, int n, bool full, V (&v)[8]) {
+  if (full) {
+    load8(p + base, v);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = base + j < n ? p[base + j] : (V)0;
+  }
+}
+
 template <int FA, int FD>
 __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_now) {
   constexpr int TIER = (FA == FP64);
@@ -912,21 +1170,10 @@ __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_
   const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
   const bool full = base + 8 <= n;
   V pv[8], qv[8], rv[8], xv[8];
-  if (full) {
-    load8(p + base, pv);
-    load8(q + base, qv);
-    load8(r + base, rv);
-    load8(xlo + base, xv);
-  } else {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int i = base + j;
-      pv[j] = i < n ? p[i] : (V)0;
-      qv[j] = i < n ? q[i] : (V)0;
-      rv[j] = i < n ? r[i] : (V)0;
-      xv[j] = i < n ? xlo[i] : (V)0;
-    }
-  }
+  load8_tail(p, base, n, full, pv);
+  load8_tail(q, base, n, full, qv);
+  load8_tail(r, base, n, full, rv);
+  load8_tail(xlo, base, n, full, xv);
   Acc l[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -1289,11 +1536,17 @@ __global__ __launch_bounds__(kBlock) void k_policy_decide(const PolicyDev *P, in
 // launchers
 // ---------------------------------------------------------------------------
 void launch_start(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_start, dim3(a.P2), dim3(kBlock), 0, s, a); }
-void launch_ka(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_a, dim3(a.G1), dim3(kBlock), 0, s, a); }
-void launch_kb(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_b, dim3(a.P2), dim3(kBlock), 0, s, a); }
-void launch_kx(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_x, dim3(a.P2), dim3(kBlock), 0, s, a); }
-void launch_step_b(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_step_b, dim3(1), dim3(kBlock), 0, s, a); }
-void launch_step_x(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_step_x, dim3(1), dim3(kBlock), 0, s, a); }
+// Optional events (e0, e1) take the kernel's own start and stop times.
+template <typename K>
+static void launch_timed(K kern, int grid, const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0, a);
+  else hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
+}
+void launch_ka(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_a, a.G1, a, s, e0, e1); }
+void launch_kb(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_b, a.P2, a, s, e0, e1); }
+void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_x, a.P2, a, s, e0, e1); }
+void launch_step_b(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_step_b, 1, a, s, e0, e1); }
+void launch_step_x(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_step_x, 1, a, s, e0, e1); }
 
 void launch_slot(const KArgs &a, hipStream_t s) {
   launch_ka(a, s);

@@ -5,6 +5,8 @@
 namespace mpcg {
 
 constexpr int kMaxEdges = 16;
+constexpr int kRPT = 2;                          // rows per thread in KA
+constexpr int kKaRows = kRPT * kRowsPerBlock;    // rows per KA workgroup
 constexpr int kMlpIn = 16, kMlpH = 128, kNAct = 64;
 
 // Matrix in HBM: CSR int32 indices, fp64 values and three shadows.  Value and
@@ -93,10 +95,12 @@ struct KArgs {
   const PolicyDev *pol;
   Hist h;
   double *part0;       // partials of b.b (start)
-  double *part1;       // KA partials (nu or ||r64||^2), one per 2048-row group
+  double *part1;       // KA partials (nu or ||r64||^2), one per KA workgroup
   double *part2;       // KB partials (sigma'), one per 2048-element block
-  int P2;              // 2048-element groups = KA groups = vector blocks
-  int G1;              // KA workgroups launched (P2 rounded up to 8)
+  int P1;              // KA row groups (grows rows each)
+  int grows;           // rows per KA group: 512, 1024 or 2048
+  int P2;              // 2048-element vector blocks
+  int G1;              // KA workgroups launched (P1 rounded up to 8)
   int8_t *slot_log;    // optional: KA records the mode of each slot (profiling)
   int slot;            // index of this slot (with slot_log)
 };

@@ -5,11 +5,12 @@
 namespace mpcg {
 void launch_start(const KArgs &a, hipStream_t s);
 void launch_slot(const KArgs &a, hipStream_t s);
-void launch_ka(const KArgs &a, hipStream_t s);
-void launch_kb(const KArgs &a, hipStream_t s);
-void launch_kx(const KArgs &a, hipStream_t s);
-void launch_step_x(const KArgs &a, hipStream_t s);
-void launch_step_b(const KArgs &a, hipStream_t s);
+// With events e0/e1 the launch records the kernel's own start and stop times.
+void launch_ka(const KArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_kb(const KArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_step_x(const KArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_step_b(const KArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_finish(const KArgs &a, hipStream_t s);
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,
                     int8_t *rexp, hipStream_t s);
