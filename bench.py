@@ -59,6 +59,119 @@ def ka_bytes(n: int, nnz: int, fs: int, vec_bytes: int) -> int:
     return b
 
 
+def mix_of(M, actions) -> dict:
+    """Share of each format per operation over a solve's actions."""
+    a = np.asarray(actions, dtype=np.int64)
+    if a.size == 0:
+        return {}
+    names = ("fp16", "bf16", "fp32", "fp64")
+    out = {}
+    for op, shift in (("spmv", 4), ("dot", 2), ("axpy", 0)):
+        f = (a >> shift) & 3
+        out[op] = {names[i]: round(float(np.mean(f == i)), 3) for i in range(4) if np.any(f == i)}
+    return out
+
+
+def build_systems(M, W, torch, seeds, n_hi=5e5, kappa_hi=1e8):
+    """Device systems (Matrix, b, x) of family_system(seed), b ~ U[-1,1] (seed + 10000)."""
+    systems = []
+    for sd in seeds:
+        A = W.family_system(sd, n_hi=n_hi, kappa_hi=kappa_hi)
+        mm = M.Matrix(A)
+        mm.set_options(replace_period=50, fallback=True)
+        b = torch.from_numpy(W.rhs(A.n, sd + 10000)).cuda()
+        systems.append((mm, b, torch.empty(A.n, dtype=torch.float64, device="cuda")))
+    return systems
+
+
+def train_qtable(M, systems, episodes, maxit, cost, seed=12345, rollouts=0):
+    """Trains a device Q-table (Algorithm 1) over the systems, episode sweeps."""
+    P = M.Policy(kind=M.POLICY_QTABLE_TRAIN, cost=cost, seed=seed)
+    if rollouts:
+        P.rollouts_enable(rollouts)
+    res = M.train_qlearning(P, systems, episodes=episodes, maxit=maxit, tol=1e-8, eps_start=1.0,
+                            eps_end=0.1, order=1)
+    return P, res
+
+
+def qlearning_experiment(args, M, W, torch) -> dict:
+    """Tabular Q-learning on seeded systems (2D/3D Laplacians and random SPD,
+    n log-uniform in [1e4, 5e5], cond up to 1e8), then greedy inference on
+    held-out seeds against the fixed mixed action and fp64 CG."""
+    train_seeds = range(100, 100 + args.train_systems)
+    held = range(300, 300 + args.heldout_systems)
+    out = {"experiment": "tabular Q-learning precision policy", "train_seeds": [train_seeds[0], train_seeds[-1]],
+           "heldout_seeds": [held[0], held[-1]], "episodes_per_system": args.episodes,
+           "train_maxit": 1000, "eval_maxit": args.eval_maxit}
+    policies = {}
+    t0 = time.time()
+    systems = build_systems(M, W, torch, train_seeds)
+    out["train_setup_s"] = round(time.time() - t0, 1)
+    log(f"[qlearning] {len(systems)} training systems built in {out['train_setup_s']} s")
+    for cost in ("C1", "C2"):
+        t0 = time.time()
+        P, res = train_qtable(M, systems, args.episodes, 1000, cost)
+        dt = time.time() - t0
+        it = np.array([r["iters"] for r in res])
+        conv = np.array([r["status"] in (0, 2) for r in res])
+        sweeps = np.array_split(np.arange(len(res)), args.episodes)
+        out[f"train_{cost}"] = {"wall_s": round(dt, 1), "episodes": len(res),
+                                "iterations": int(it.sum()),
+                                "converged_share_per_sweep": [round(float(conv[s].mean()), 3) for s in sweeps],
+                                "mean_cost_per_iteration_per_sweep": [
+                                    round(float(sum(res[j]["cost_sum"] for j in s) / max(1, sum(res[j]["iters"] for j in s))), 3)
+                                    for s in sweeps]}
+        log(f"[qlearning] {cost}: {out[f'train_{cost}']}")
+        policies[cost] = P
+    for mm, _, _ in systems:
+        mm.close()
+    del systems
+    fixed = M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.BF16, M.FP32, M.FP32))
+    fp64 = M.Policy(kind=M.POLICY_FIXED, fixed_action=63)
+    greedy = {}
+    for cost, P in policies.items():
+        g = M.Policy(kind=M.POLICY_QTABLE, cost=cost)
+        g.set_qtable(P.qtable())
+        greedy[cost] = g
+    rows = []
+    for sd in held:
+        A = W.family_system(sd)
+        mm = M.Matrix(A)
+        b = torch.from_numpy(W.rhs(A.n, sd + 10000)).cuda()
+        x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        row = {"seed": sd, "name": A.name, "n": A.n, "nnz": A.nnz}
+        for lab, pol in (("fp64", fp64), ("fixed_mixed", fixed), ("learned_C1", greedy["C1"]),
+                         ("learned_C2", greedy["C2"])):
+            mm.set_policy(pol)
+            mm.set_options(replace_period=50, fallback=True)
+            x.zero_()
+            r = mm.solve(b, x, tol=1e-8, maxit=args.eval_maxit)
+            row[lab] = {"status": r["status"], "iters": r["iters"], "ms": round(r["time_ms"], 3),
+                        "relres_true": r["relres_true"], "cost_sum": r["cost_sum"],
+                        "fallback_at": r["fallback_at"]}
+            if lab.startswith("learned"):
+                row[lab]["mix"] = mix_of(M, mm.history()["actions"])
+        rows.append(row)
+        log(f"[qlearning] held-out {sd} {A.name}: " +
+            ", ".join(f"{k} {row[k]['status']}/{row[k]['iters']}/{row[k]['ms']}ms" for k in
+                      ("fp64", "fixed_mixed", "learned_C1", "learned_C2")))
+        mm.close()
+    summ = {}
+    for lab in ("fp64", "fixed_mixed", "learned_C1", "learned_C2"):
+        ok = [r for r in rows if r[lab]["status"] in (0, 2)]
+        both = [r for r in rows if r[lab]["status"] in (0, 2) and r["fp64"]["status"] in (0, 2)]
+        summ[lab] = {"success": f"{len(ok)}/{len(rows)}",
+                     "fallbacks": sum(1 for r in rows if r[lab]["fallback_at"] >= 0),
+                     "median_time_ratio_vs_fp64": round(float(np.median([r[lab]["ms"] / r["fp64"]["ms"] for r in both])), 3)
+                     if both else None,
+                     "median_iter_ratio_vs_fp64": round(float(np.median([r[lab]["iters"] / r["fp64"]["iters"] for r in both])), 3)
+                     if both else None,
+                     "total_ms": round(sum(r[lab]["ms"] for r in rows), 1)}
+    out["heldout_summary"] = summ
+    out["heldout"] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +180,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-rspd", action="store_true", help="skip the random SPD workload")
     ap.add_argument("--N", type=int, default=128, help="3D Laplacian grid size")
+    ap.add_argument("--qlearning", action="store_true",
+                    help="tabular Q-learning experiment: train on seeded systems, evaluate on held-out ones")
+    ap.add_argument("--train-systems", type=int, default=200)
+    ap.add_argument("--heldout-systems", type=int, default=50)
+    ap.add_argument("--episodes", type=int, default=5)
+    ap.add_argument("--eval-maxit", type=int, default=20000)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-policy leg")
     ap.add_argument("--counters", action="store_true",
                     help="short run for HBM counter collection: one plain copy of 256 MiB (the scale "
                          "reference for FETCH_SIZE / WRITE_SIZE), then one mixed solve")
@@ -100,6 +220,10 @@ def main():
     xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     pol_mixed = M.Policy(kind=M.POLICY_FIXED, fixed_action=act_mixed)
     pol_fp64 = M.Policy(kind=M.POLICY_FIXED, fixed_action=act_fp64)
+
+    if args.qlearning:
+        print(json.dumps(qlearning_experiment(args, M, W, torch)), flush=True)
+        return
 
     if args.counters:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -221,6 +345,31 @@ def main():
             "profiled_solve_ms": round(rp["time_ms"], 3),
         },
     }
+
+    if not args.no_learned:
+        # Q-table trained on the device (Algorithm 1) over small seeded systems of the
+        # training family, then used greedily on this workload.
+        t0 = time.time()
+        P_l, tr = train_qtable(M, build_systems(M, W, torch, range(100, 112), n_hi=1e5), episodes=3,
+                               maxit=1000, cost="C1")
+        t_train = time.time() - t0
+        m.set_policy(P_l)
+        m.set_options(replace_period=50, fallback=True)
+        lr_runs = []
+        for _ in range(max(1, args.steps // 2) + 1):
+            xd.zero_()
+            lr_runs.append(m.solve(bd, xd, tol=tol, maxit=5000))
+        rl = lr_runs[-1]
+        h = m.history()
+        out["learned"] = {"policy": "Q-table, C1 costs, trained on 12 seeded systems x 3 episodes "
+                                    "(2D/3D Laplacians, random SPD, n <= 1e5)",
+                          "ms": round(float(np.median([r["time_ms"] for r in lr_runs[1:]])), 3),
+                          "iters": rl["iters"], "status": rl["status"], "relres_true": rl["relres_true"],
+                          "train_s": round(t_train, 1), "train_episodes": len(tr),
+                          "action_mix": mix_of(M, h["actions"]),
+                          "speedup_vs_fp64": round(fp64_ms / float(np.median([r["time_ms"] for r in lr_runs[1:]])), 3)}
+        log(f"[bench] learned: {out['learned']}")
+        m.set_policy(pol_mixed)
 
     if not args.no_rspd:
         t0 = time.time()

@@ -218,6 +218,46 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *opts);
 int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t maxit,
                mpcg_result *res);
 
+/* ---------------------------------------------------------------- training
+ * Tabular Q-learning over many systems (section 4.1, Algorithm 1): episodes run
+ * one after the other, each a full solve from x0 = 0 (section 4.2's start) with
+ * the epsilon-greedy training policy P, which updates its device Q-table (and
+ * logs rollouts if enabled) inside the solve.  Episode j (0-based, in the order
+ * below) has the number e = first_episode + j, which seeds its exploration
+ * draws, and epsilon_e = eps_start + (eps_end - eps_start) (e - 1) / (E_total - 1)
+ * (E_total = 1: eps_start), a linear schedule from eps_start to eps_end.
+ */
+typedef struct {
+    int32_t episodes;          /* E >= 1 episodes per system                     */
+    int32_t maxit;             /* iteration budget of an episode (T_max)         */
+    double tol;                /* convergence threshold of an episode (> 0)      */
+    double eps_start, eps_end; /* epsilon schedule, both in [0, 1]               */
+    int32_t order;             /* 0: all episodes of system 0, then system 1 ...
+                                  1: sweeps: episode 1 of every system, then 2 ... */
+    int32_t first_episode;     /* number of the first episode (>= 1)             */
+    int32_t total_episodes;    /* E_total of the schedule (0: first_episode - 1 +
+                                  m * episodes, i.e. this call's last episode)   */
+    int32_t reserved;
+} mpcg_train_desc;
+
+typedef struct {
+    int32_t system;            /* index into A[]                                  */
+    int32_t episode;           /* episode number e                                */
+    double epsilon;            /* epsilon_e                                       */
+    mpcg_result res;           /* the episode's solve                             */
+} mpcg_episode_result;
+
+/*
+ * Trains P (kind MPCG_POLICY_QTABLE_TRAIN) on m systems: A[i] with device
+ * right-hand side b[i] and device solution buffer x[i] (double[n_i], zeroed by
+ * the call before each episode of system i).  Each system keeps its own solve
+ * options (replacement period, fallback); its attached policy is restored
+ * afterwards.  out (host, may be NULL) receives m * episodes records in episode
+ * order.  Errors as mpcg_solve; invalid descriptors give MPCG_ERR_INVALID.
+ */
+int mpcg_train_qlearning(mpcg_policy *P, int32_t m, mpcg_matrix *const *A, const double *const *b,
+                         double *const *x, const mpcg_train_desc *desc, mpcg_episode_result *out);
+
 /*
  * History of the last solve, host arrays (any may be NULL):
  *   rho[cap]     relative residual rho_k, k = 0..iters (the true one where replaced)

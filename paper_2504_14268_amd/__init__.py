@@ -69,6 +69,19 @@ class Result(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class TrainDesc(C.Structure):
+    _fields_ = [("episodes", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double),
+                ("eps_start", C.c_double), ("eps_end", C.c_double), ("order", C.c_int32),
+                ("first_episode", C.c_int32), ("total_episodes", C.c_int32), ("reserved", C.c_int32)]
+
+
+class EpisodeResult(C.Structure):
+    _fields_ = [("system", C.c_int32), ("episode", C.c_int32), ("epsilon", C.c_double), ("res", Result)]
+
+    def as_dict(self):
+        return {"system": self.system, "episode": self.episode, "epsilon": self.epsilon, **self.res.as_dict()}
+
+
 _lib = None
 
 
@@ -105,6 +118,7 @@ def lib():
             "mpcg_op_axpy": [vp, C.c_int, d, vp, vp],
             "mpcg_op_residual": [vp, vp, vp, vp],
             "mpcg_get_profile": [vp, C.POINTER(Profile)],
+            "mpcg_train_qlearning": [vp, i32, vp, vp, vp, C.POINTER(TrainDesc), vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -230,6 +244,22 @@ class Policy:
         _check(lib().mpcg_policy_decide(self.h, m, _np_ptr(k), _np_ptr(rho), _np_ptr(stag), fp,
                                         _np_ptr(st), _np_ptr(ac)), "policy_decide")
         return st, ac
+
+
+def train_qlearning(policy: "Policy", systems, episodes=5, maxit=1000, tol=1e-8, eps_start=1.0, eps_end=0.1,
+                    order=0, first_episode=1, total_episodes=0):
+    """Tabular Q-learning over `systems` = [(Matrix, b, x), ...] (b, x float64 device
+    tensors; x is overwritten).  Returns one dict per episode (mpcg_train_qlearning)."""
+    m = len(systems)
+    hs = (C.c_void_p * max(m, 1))(*[s[0].h for s in systems])
+    bs = (C.c_void_p * max(m, 1))(*[s[1].data_ptr() for s in systems])
+    xs = (C.c_void_p * max(m, 1))(*[s[2].data_ptr() for s in systems])
+    for s in systems:
+        assert s[1].is_cuda and s[2].is_cuda and s[1].numel() == s[0].n and s[2].numel() == s[0].n
+    d = TrainDesc(episodes, maxit, tol, eps_start, eps_end, order, first_episode, total_episodes, 0)
+    out = (EpisodeResult * max(m * episodes, 1))()
+    _check(lib().mpcg_train_qlearning(policy.h, m, hs, bs, xs, C.byref(d), out), "mpcg_train_qlearning")
+    return [out[j].as_dict() for j in range(m * episodes)]
 
 
 class Matrix:

@@ -781,6 +781,45 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   return MPCG_OK;
 }
 
+// ---------------------------------------------------------------- training
+int mpcg_train_qlearning(mpcg_policy *P, int32_t m, mpcg_matrix *const *A, const double *const *b,
+                         double *const *x, const mpcg_train_desc *d, mpcg_episode_result *out) {
+  if (!P || !A || !b || !x || !d || m < 0) return fail(MPCG_ERR_INVALID, "NULL or negative argument");
+  if (P->desc.kind != MPCG_POLICY_QTABLE_TRAIN) return fail(MPCG_ERR_INVALID, "policy is not a training policy");
+  if (d->episodes < 1 || d->maxit < 0 || !(d->tol > 0.0) || !std::isfinite(d->tol) || d->first_episode < 1 ||
+      !(d->eps_start >= 0.0 && d->eps_start <= 1.0) || !(d->eps_end >= 0.0 && d->eps_end <= 1.0) ||
+      (d->order != 0 && d->order != 1) || d->total_episodes < 0)
+    return fail(MPCG_ERR_INVALID, "bad training descriptor");
+  for (int i = 0; i < m; ++i)
+    if (!A[i] || !b[i] || !x[i]) return fail(MPCG_ERR_INVALID, "NULL system");
+  const int64_t total = d->total_episodes > 0 ? d->total_episodes
+                                              : (int64_t)d->first_episode - 1 + (int64_t)m * d->episodes;
+  const int64_t njobs = (int64_t)m * d->episodes;
+  for (int64_t j = 0; j < njobs; ++j) {
+    const int sys = d->order == 0 ? (int)(j / d->episodes) : (int)(j % m);
+    const int64_t e = d->first_episode + j;
+    const double eps = total > 1 ? d->eps_start + (d->eps_end - d->eps_start) * (double)(e - 1) / (double)(total - 1)
+                                 : d->eps_start;
+    mpcg_matrix *M = A[sys];
+    P->episode = e;
+    P->epsilon = std::min(1.0, std::max(0.0, eps));
+    mpcg_policy *saved = M->pol;
+    M->pol = P;
+    HIP_TRY(hipMemsetAsync(x[sys], 0, sizeof(double) * (size_t)M->n, M->stream));
+    mpcg_result r;
+    const int rc = mpcg_solve(M, b[sys], x[sys], d->tol, d->maxit, &r);
+    M->pol = saved;
+    if (rc) return rc;
+    if (out) {
+      out[j].system = sys;
+      out[j].episode = (int32_t)e;
+      out[j].epsilon = P->epsilon;
+      out[j].res = r;
+    }
+  }
+  return MPCG_OK;
+}
+
 int mpcg_get_profile(mpcg_matrix *A, mpcg_profile *out) {
   if (!A || !out) return fail(MPCG_ERR_INVALID, "NULL argument");
   *out = A->prof;
