@@ -218,6 +218,46 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *opts);
 int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t maxit,
                mpcg_result *res);
 
+/* ---------------------------------------------------------------- batched
+ * Many independent systems in one persistent launch.  Each workgroup takes
+ * whole systems from a queue and runs the solve of section 3 with the policy
+ * attached to that system (fixed, Q-table or MLP; not training policies or
+ * rollout logs, whose state is shared), its own options (replacement period,
+ * fallback) and its own tol / maxit.  Every system's result -- iterations,
+ * history, x -- is bit-identical to mpcg_solve on that system alone, for every
+ * configuration.
+ */
+typedef struct {
+    int32_t workgroups;        /* persistent workgroups (0: autotuned)          */
+    int32_t spmv_rows;         /* rows per SpMV group, 512/1024/2048 (0: autotuned) */
+    int32_t order;             /* 0: largest systems (nnz) first; 1: as given   */
+    int32_t autotune_iters;    /* iterations per system in each autotuning trial
+                                  (0: 16)                                        */
+} mpcg_batch_opts;
+
+typedef struct {
+    double time_ms;            /* device time of the batched launch             */
+    double tune_ms;            /* device time of the autotuning trials          */
+    int32_t workgroups;        /* configuration used                            */
+    int32_t spmv_rows;
+    int32_t tuned;             /* 0: given, 1: autotuned now, 2: autotuner cache */
+    int32_t reserved;
+} mpcg_batch_info;
+
+/*
+ * Solves A[i] x[i] = b[i] for i < nsys.  A[i] are distinct handles on one
+ * device; b[i], x[i] are device double[n_i] (x[i]: initial guess in, solution
+ * out); tol[i], maxit[i] host arrays as in mpcg_solve; res[i] (host) receives
+ * each system's summary (time_ms: the whole launch).  Runs on A[0]'s stream
+ * after synchronising every A[i]'s stream.  The autotuner (options 0) times
+ * short trials of candidate configurations on copies of x0 and remembers the
+ * choice for the batch shape (count, total rows, total nonzeros).  info (host,
+ * may be NULL) receives the configuration and times.
+ */
+int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const *b, double *const *x,
+                       const double *tol, const int32_t *maxit, const mpcg_batch_opts *opts,
+                       mpcg_result *res, mpcg_batch_info *info);
+
 /* ---------------------------------------------------------------- training
  * Tabular Q-learning over many systems (section 4.1, Algorithm 1): episodes run
  * one after the other, each a full solve from x0 = 0 (section 4.2's start) with

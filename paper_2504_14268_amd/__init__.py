@@ -69,6 +69,19 @@ class Result(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("workgroups", C.c_int32), ("spmv_rows", C.c_int32), ("order", C.c_int32),
+                ("autotune_iters", C.c_int32)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("time_ms", C.c_double), ("tune_ms", C.c_double), ("workgroups", C.c_int32),
+                ("spmv_rows", C.c_int32), ("tuned", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 class TrainDesc(C.Structure):
     _fields_ = [("episodes", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double),
                 ("eps_start", C.c_double), ("eps_end", C.c_double), ("order", C.c_int32),
@@ -119,6 +132,7 @@ def lib():
             "mpcg_op_residual": [vp, vp, vp, vp],
             "mpcg_get_profile": [vp, C.POINTER(Profile)],
             "mpcg_train_qlearning": [vp, i32, vp, vp, vp, C.POINTER(TrainDesc), vp],
+            "mpcg_solve_batched": [i32, vp, vp, vp, vp, vp, C.POINTER(BatchOpts), vp, C.POINTER(BatchInfo)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -244,6 +258,27 @@ class Policy:
         _check(lib().mpcg_policy_decide(self.h, m, _np_ptr(k), _np_ptr(rho), _np_ptr(stag), fp,
                                         _np_ptr(st), _np_ptr(ac)), "policy_decide")
         return st, ac
+
+
+def solve_batched(systems, tol=1e-8, maxit=1000, workgroups=0, spmv_rows=0, order=0, autotune_iters=0):
+    """One persistent launch over systems = [(Matrix, b, x), ...] (device float64
+    tensors; x holds x0 and receives the solution).  tol / maxit: scalars or
+    per-system lists.  Returns (list of result dicts, batch info dict)."""
+    m = len(systems)
+    tols = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, dtype=np.float64), (m,)))
+    mits = np.ascontiguousarray(np.broadcast_to(np.asarray(maxit, dtype=np.int32), (m,)))
+    for s in systems:
+        assert s[1].is_cuda and s[2].is_cuda and s[1].numel() == s[0].n and s[2].numel() == s[0].n
+        assert s[1].dtype == s[2].dtype and s[1].element_size() == 8 and s[1].is_contiguous() and s[2].is_contiguous()
+    hs = (C.c_void_p * max(m, 1))(*[s[0].h for s in systems])
+    bs = (C.c_void_p * max(m, 1))(*[s[1].data_ptr() for s in systems])
+    xs = (C.c_void_p * max(m, 1))(*[s[2].data_ptr() for s in systems])
+    res = (Result * max(m, 1))()
+    info = BatchInfo()
+    o = BatchOpts(workgroups, spmv_rows, order, autotune_iters)
+    _check(lib().mpcg_solve_batched(m, hs, bs, xs, _np_ptr(tols), _np_ptr(mits), C.byref(o), res, C.byref(info)),
+           "mpcg_solve_batched")
+    return [res[i].as_dict() for i in range(m)], info.as_dict()
 
 
 def train_qlearning(policy: "Policy", systems, episodes=5, maxit=1000, tol=1e-8, eps_start=1.0, eps_end=0.1,

@@ -12,6 +12,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -620,19 +623,9 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
 }
 
 // ---------------------------------------------------------------- solve
-int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t maxit, mpcg_result *res) {
-  if (!A || !b || !x || !res) return fail(MPCG_ERR_INVALID, "NULL argument");
-  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MPCG_ERR_INVALID, "tol must be positive and finite");
-  if (maxit < 0 || maxit > (1 << 29)) return fail(MPCG_ERR_INVALID, "maxit out of range");
-  int rc = ensure_ws(A);
-  if (rc) return rc;
-  rc = ensure_hist(A, maxit);
-  if (rc) return rc;
-  mpcg_policy *P = A->pol ? A->pol : A->defpol;
-  if (P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
-  hipStream_t st = A->stream;
-  HIP_TRY(hipStreamSynchronize(st));   // staging buffers below are reused
-
+// Policy descriptor and initial control block of a solve (start: fp64 action,
+// residual of x0), staged through the handle's pinned buffers.
+static int upload_start(mpcg_matrix *A, mpcg_policy *P, double tol, int32_t maxit, hipStream_t st) {
   *A->h_pol = P->device_struct();
   HIP_TRY(hipMemcpyAsync(A->d_pol, A->h_pol, sizeof(PolicyDev), hipMemcpyHostToDevice, st));
   Ctl &c = *A->h_ctl;
@@ -648,6 +641,34 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   c.fallback_enabled = A->opts.fallback ? 1 : 0;
   c.tol = tol;
   HIP_TRY(hipMemcpyAsync(A->d_ctl, A->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  return MPCG_OK;
+}
+
+static void fill_result(const Ctl &r, mpcg_result *res) {
+  std::memset(res, 0, sizeof(*res));
+  res->status = r.status;
+  res->iters = r.k;
+  res->n_replace = r.nrep;
+  res->fallback_at = r.fell_back ? r.fallback_at : -1;
+  res->relres_true = r.relres_true;
+  res->cost_sum = r.cost_sum;
+}
+
+int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t maxit, mpcg_result *res) {
+  if (!A || !b || !x || !res) return fail(MPCG_ERR_INVALID, "NULL argument");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MPCG_ERR_INVALID, "tol must be positive and finite");
+  if (maxit < 0 || maxit > (1 << 29)) return fail(MPCG_ERR_INVALID, "maxit out of range");
+  int rc = ensure_ws(A);
+  if (rc) return rc;
+  rc = ensure_hist(A, maxit);
+  if (rc) return rc;
+  mpcg_policy *P = A->pol ? A->pol : A->defpol;
+  if (P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
+  hipStream_t st = A->stream;
+  HIP_TRY(hipStreamSynchronize(st));   // staging buffers below are reused
+
+  rc = upload_start(A, P, tol, maxit, st);
+  if (rc) return rc;
 
   KArgs a = make_args(A, b, x);
   a.slow = (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->desc.kind == MPCG_POLICY_MLP || P->roll_cap > 0) ? 1 : 0;
@@ -746,13 +767,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, A->ev_start, A->ev_end));
   const Ctl &r = *A->h_ctl;
-  std::memset(res, 0, sizeof(*res));
-  res->status = r.status;
-  res->iters = r.k;
-  res->n_replace = r.nrep;
-  res->fallback_at = r.fell_back ? r.fallback_at : -1;
-  res->relres_true = r.relres_true;
-  res->cost_sum = r.cost_sum;
+  fill_result(r, res);
   res->time_ms = ms;
   res->slots = (int32_t)slots;
   A->last_iters = r.k;
@@ -777,6 +792,202 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
         pr.resid_ms += all;
       }
     }
+  }
+  return MPCG_OK;
+}
+
+// ---------------------------------------------------------------- batched
+namespace {
+
+struct BatchCfg {
+  int workgroups, spmv_rows;
+};
+
+// Autotuner memory: the configuration chosen for a batch shape.
+struct BatchKey {
+  int nsys;
+  int64_t sum_n, sum_nnz;
+  bool operator<(const BatchKey &o) const {
+    return std::tie(nsys, sum_n, sum_nnz) < std::tie(o.nsys, o.sum_n, o.sum_nnz);
+  }
+};
+std::map<BatchKey, BatchCfg> g_batch_tuned;
+std::mutex g_batch_mu;
+
+}  // namespace
+
+// One batched launch over the prepared systems with configuration cfg; x[i]
+// receives the solutions (the caller's buffers or the autotuner's copies).
+static int batch_run(int nsys, mpcg_matrix *const *A, const double *const *b, double *const *x, const double *tol,
+                     const int32_t *maxit, const std::vector<mpcg_policy *> &pols, const std::vector<int32_t> &order,
+                     const BatchCfg &cfg, hipStream_t st, float *ms_out) {
+  std::vector<BatchSys> hs((size_t)nsys);
+  for (int i = 0; i < nsys; ++i) {
+    int rc = upload_start(A[i], pols[i], tol[i], maxit[i], st);
+    if (rc) return rc;
+    KArgs a = make_args(A[i], b[i], x[i]);
+    a.grows = cfg.spmv_rows;
+    a.P1 = (A[i]->n + a.grows - 1) / a.grows;
+    a.G1 = round_up(a.P1, 8);
+    hs[i].a = a;
+    hs[i].max_slots = 2 * maxit[i] + 16;
+  }
+  BatchSys *d_sys = nullptr;
+  int32_t *d_order = nullptr, *d_queue = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = MPCG_OK;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    dfree(d_sys);
+    dfree(d_order);
+    dfree(d_queue);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  hipError_t e = dmalloc(&d_sys, (size_t)nsys);
+  if (e == hipSuccess) e = dmalloc(&d_order, (size_t)nsys);
+  if (e == hipSuccess) e = dmalloc(&d_queue, 1);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_sys, hs.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(d_queue, 0, sizeof(int32_t), st);
+  if (e == hipSuccess) {
+    launch_batched(d_sys, d_order, nsys, d_queue, cfg.workgroups, st, e0, e1);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && ms_out) e = hipEventElapsedTime(ms_out, e0, e1);
+  if (e != hipSuccess)
+    rc = fail(e == hipErrorOutOfMemory ? MPCG_ERR_NOMEM : MPCG_ERR_DEVICE,
+              std::string("batched launch: ") + hipGetErrorString(e));
+  cleanup();
+  return rc;
+}
+
+int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const *b, double *const *x,
+                       const double *tol, const int32_t *maxit, const mpcg_batch_opts *opts, mpcg_result *res,
+                       mpcg_batch_info *info) {
+  if (nsys < 0 || (nsys > 0 && (!A || !b || !x || !tol || !maxit || !res)))
+    return fail(MPCG_ERR_INVALID, "NULL or negative argument");
+  mpcg_batch_opts o{0, 0, 0, 0};
+  if (opts) o = *opts;
+  if (o.workgroups < 0 || (o.spmv_rows != 0 && o.spmv_rows != 512 && o.spmv_rows != 1024 && o.spmv_rows != 2048) ||
+      (o.order != 0 && o.order != 1) || o.autotune_iters < 0)
+    return fail(MPCG_ERR_INVALID, "bad batch options");
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (nsys == 0) return MPCG_OK;
+  std::vector<mpcg_policy *> pols((size_t)nsys);
+  int64_t sum_n = 0, sum_nnz = 0;
+  for (int i = 0; i < nsys; ++i) {
+    if (!A[i] || !b[i] || !x[i]) return fail(MPCG_ERR_INVALID, "NULL system");
+    if (!(tol[i] > 0.0) || !std::isfinite(tol[i])) return fail(MPCG_ERR_INVALID, "tol must be positive and finite");
+    if (maxit[i] < 0 || maxit[i] > (1 << 29)) return fail(MPCG_ERR_INVALID, "maxit out of range");
+    mpcg_policy *P = A[i]->pol ? A[i]->pol : A[i]->defpol;
+    if (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->roll_cap > 0)
+      return fail(MPCG_ERR_INVALID, "training policies and rollout logs are not batched (shared state)");
+    if (P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
+    pols[i] = P;
+    int rc = ensure_ws(A[i]);
+    if (rc) return rc;
+    rc = ensure_hist(A[i], maxit[i]);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(A[i]->stream));
+    sum_n += A[i]->n;
+    sum_nnz += A[i]->nnz;
+  }
+  {
+    std::vector<mpcg_matrix *> u(A, A + nsys);
+    std::sort(u.begin(), u.end());
+    if (std::adjacent_find(u.begin(), u.end()) != u.end())
+      return fail(MPCG_ERR_INVALID, "a matrix handle appears twice in the batch");
+  }
+  hipStream_t st = A[0]->stream;
+  std::vector<int32_t> order((size_t)nsys);
+  for (int i = 0; i < nsys; ++i) order[i] = i;
+  if (o.order == 0)
+    std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) { return A[p]->nnz > A[q]->nnz; });
+
+  BatchCfg cfg{o.workgroups, o.spmv_rows};
+  int tuned = 0;
+  double tune_ms = 0.0;
+  if (cfg.workgroups == 0 || cfg.spmv_rows == 0) {
+    const BatchKey key{nsys, sum_n, sum_nnz};
+    bool have = false;
+    {
+      std::lock_guard<std::mutex> lk(g_batch_mu);
+      auto it = g_batch_tuned.find(key);
+      if (it != g_batch_tuned.end()) {
+        if (cfg.workgroups == 0) cfg.workgroups = it->second.workgroups;
+        if (cfg.spmv_rows == 0) cfg.spmv_rows = it->second.spmv_rows;
+        have = true;
+        tuned = 2;
+      }
+    }
+    if (!have) {
+      // Timed trials of a few iterations per system on copies of x0; every
+      // candidate gives the same results, only the time differs.
+      std::vector<int> wgs, rows;
+      if (cfg.workgroups) wgs = {cfg.workgroups};
+      else wgs = {256, 512, std::max(1, std::min(nsys, 1024))};
+      if (cfg.spmv_rows) rows = {cfg.spmv_rows};
+      else rows = {512, 2048};
+      std::vector<double *> xt((size_t)nsys, nullptr);
+      std::vector<int32_t> mt((size_t)nsys);
+      const int ti = o.autotune_iters > 0 ? o.autotune_iters : 16;
+      int rc = MPCG_OK;
+      for (int i = 0; i < nsys && rc == MPCG_OK; ++i) {
+        hipError_t e = dmalloc(&xt[i], (size_t)A[i]->n);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(xt[i], x[i], sizeof(double) * A[i]->n, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) rc = fail(MPCG_ERR_NOMEM, "autotuner scratch");
+        mt[i] = std::min(maxit[i], ti);
+      }
+      BatchCfg best{0, 0};
+      float best_ms = 0.0f;
+      for (int w : wgs) {
+        for (int r : rows) {
+          if (rc) break;
+          float ms = 0.0f;
+          rc = batch_run(nsys, A, b, xt.data(), tol, mt.data(), pols, order, BatchCfg{w, r}, st, &ms);
+          tune_ms += ms;
+          if (!rc && (best.workgroups == 0 || ms < best_ms)) {
+            best = BatchCfg{w, r};
+            best_ms = ms;
+          }
+          // the trial overwrote x: restore the copies of x0 for the next one
+          for (int i = 0; i < nsys && !rc; ++i)
+            if (hipMemcpyAsync(xt[i], x[i], sizeof(double) * A[i]->n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+              rc = fail(MPCG_ERR_DEVICE, "autotuner copy");
+        }
+      }
+      (void)hipStreamSynchronize(st);
+      for (double *p : xt) dfree(p);
+      if (rc) return rc;
+      cfg = best;
+      tuned = 1;
+      std::lock_guard<std::mutex> lk(g_batch_mu);
+      g_batch_tuned[key] = best;
+    }
+  }
+  float ms = 0.0f;
+  int rc = batch_run(nsys, A, b, x, tol, maxit, pols, order, cfg, st, &ms);
+  if (rc) return rc;
+  for (int i = 0; i < nsys; ++i) {
+    Ctl r;
+    HIP_TRY(hipMemcpy(&r, A[i]->d_ctl + 1, sizeof(Ctl), hipMemcpyDeviceToHost));
+    if (r.status < 0) return fail(MPCG_ERR_DEVICE, "batched solve did not reach a final state");
+    fill_result(r, &res[i]);
+    res[i].time_ms = ms;
+    A[i]->last_iters = r.k;
+    A[i]->last_nrep = r.nrep;
+  }
+  if (info) {
+    info->time_ms = ms;
+    info->tune_ms = tune_ms;
+    info->workgroups = cfg.workgroups;
+    info->spmv_rows = cfg.spmv_rows;
+    info->tuned = tuned;
   }
   return MPCG_OK;
 }

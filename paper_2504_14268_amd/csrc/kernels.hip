@@ -1157,7 +1157,7 @@ __device__ __forceinline__ void load8_tail(const V *p, int base, int n, bool ful
 }
 
 template <int FA, int FD>
-__device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_now) {
+__device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_now, int blk) {
   constexpr int TIER = (FA == FP64);
   using V = typename TierT<TIER>::type;
   using Acc = typename AccT<FD>::type;
@@ -1167,7 +1167,7 @@ __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_
   else { xlo = a.v.xlo32; r = a.v.r32; p = a.v.p32; q = a.v.q32; }
   const double alpha = S.alpha;
   const int n = a.A.n;
-  const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   const bool full = base + 8 <= n;
   V pv[8], qv[8], rv[8], xv[8];
   load8_tail(p, base, n, full, pv);
@@ -1203,18 +1203,18 @@ __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_
     }
   }
   const Acc t = block_tree(tree8(l));
-  if (threadIdx.x == 0) a.part2[blockIdx.x] = (double)t;
+  if (threadIdx.x == 0) a.part2[blk] = (double)t;
 }
 
 // Elementwise steps (KB or KX): p = r = rd_tier(r64) after a start; the
 // direction update, with a tier change when the next action needs one; the
 // fold of x_lo into x_hi before a replacement or a restart.
-__device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S) {
+__device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, int blk) {
   const int op = S.k3op;
   const int n = a.A.n;
-  const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   if (op == K3_FOLD) {
-    fold_group(a, S.tier, blockIdx.x);
+    fold_group(a, S.tier, blk);
   } else if (op == K3_COPY) {
     for (int j = 0; j < 8; ++j) {
       const int i = base + j;
@@ -1275,7 +1275,35 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S) {
 }
 
 #define MPCG_KB_CASE(FA, FD) \
-  case (FA) * 4 + (FD): kb_axpy<FA, FD>(a, S, fold_now); break;
+  case (FA) * 4 + (FD): kb_axpy<FA, FD>(a, S, fold_now, blk); break;
+
+// KB's vector work for 2048-element block blk.
+__device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, bool fold_now, int blk) {
+  if (bop == B_AXPY) {
+    const int act = S.action;
+    switch ((act & 3) * 4 + ((act >> 2) & 3)) {
+      MPCG_KB_CASE(FP16, FP16) MPCG_KB_CASE(FP16, BF16) MPCG_KB_CASE(FP16, FP32) MPCG_KB_CASE(FP16, FP64)
+      MPCG_KB_CASE(BF16, FP16) MPCG_KB_CASE(BF16, BF16) MPCG_KB_CASE(BF16, FP32) MPCG_KB_CASE(BF16, FP64)
+      MPCG_KB_CASE(FP32, FP16) MPCG_KB_CASE(FP32, BF16) MPCG_KB_CASE(FP32, FP32) MPCG_KB_CASE(FP32, FP64)
+      MPCG_KB_CASE(FP64, FP16) MPCG_KB_CASE(FP64, BF16) MPCG_KB_CASE(FP64, FP32) MPCG_KB_CASE(FP64, FP64)
+    default: break;
+    }
+  } else if (bop == B_EXEC) {
+    exec_elementwise(a, S, blk);
+  }
+}
+
+// Control-block bookkeeping at the end of KB's work.
+__device__ __forceinline__ void kb_commit(Ctl &S, int bop, bool fold_now) {
+  if (bop == B_AXPY) {
+    S.pend_sigma = 1;
+    S.fold_done = fold_now ? 1 : 0;
+  } else if (bop == B_EXEC) {
+    S.k3op = K3_NONE;
+  }
+  S.b_op = B_NONE;
+  S.step_done = 0;
+}
 
 __global__ __launch_bounds__(kBlock) void k_b(KArgs a) {
   __shared__ Ctl S;
@@ -1287,30 +1315,10 @@ __global__ __launch_bounds__(kBlock) void k_b(KArgs a) {
   if (!S.step_done) step_b<false>(x, a);
   const int bop = S.b_op;
   const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
-  if (bop == B_AXPY) {
-    const int act = S.action;
-    switch ((act & 3) * 4 + ((act >> 2) & 3)) {
-      MPCG_KB_CASE(FP16, FP16) MPCG_KB_CASE(FP16, BF16) MPCG_KB_CASE(FP16, FP32) MPCG_KB_CASE(FP16, FP64)
-      MPCG_KB_CASE(BF16, FP16) MPCG_KB_CASE(BF16, BF16) MPCG_KB_CASE(BF16, FP32) MPCG_KB_CASE(BF16, FP64)
-      MPCG_KB_CASE(FP32, FP16) MPCG_KB_CASE(FP32, BF16) MPCG_KB_CASE(FP32, FP32) MPCG_KB_CASE(FP32, FP64)
-      MPCG_KB_CASE(FP64, FP16) MPCG_KB_CASE(FP64, BF16) MPCG_KB_CASE(FP64, FP32) MPCG_KB_CASE(FP64, FP64)
-    default: break;
-    }
-  } else if (bop == B_EXEC) {
-    exec_elementwise(a, S);
-  }
+  kb_work(a, S, bop, fold_now, blockIdx.x);
   if (blockIdx.x == 0) {   // commit the state after this kernel for KX
     __syncthreads();
-    if (threadIdx.x == 0) {
-      if (bop == B_AXPY) {
-        S.pend_sigma = 1;
-        S.fold_done = fold_now ? 1 : 0;
-      } else if (bop == B_EXEC) {
-        S.k3op = K3_NONE;
-      }
-      S.b_op = B_NONE;
-      S.step_done = 0;
-    }
+    if (threadIdx.x == 0) kb_commit(S, bop, fold_now);
     __syncthreads();
     copy_words(&a.ctl[1], &S, sizeof(Ctl));
   }
@@ -1325,7 +1333,7 @@ __global__ __launch_bounds__(kBlock) void k_x(KArgs a) {
   __syncthreads();
   const Sx x{&S, &SP, a.h, blockIdx.x == 0};
   if (!S.step_done) step_x<false>(x, a);
-  exec_elementwise(a, S);
+  exec_elementwise(a, S, blockIdx.x);
   if (blockIdx.x == 0) {   // commit the state after this kernel for the next KA and KB
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1369,10 +1377,10 @@ __global__ __launch_bounds__(kBlock) void k_step_x(KArgs a) {
 // ---------------------------------------------------------------------------
 // start / finish
 // ---------------------------------------------------------------------------
-// x_hi = x0, x_lo = 0, partials of b.b (pairwise fp64) for ||b||.
-__global__ __launch_bounds__(kBlock) void k_start(KArgs a) {
+// x_hi = x0, x_lo = 0, partials of b.b (pairwise fp64) for ||b|| (block blk).
+__device__ __forceinline__ void start_block(const KArgs &a, int blk) {
   const int n = a.A.n;
-  const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   double l[8];
   for (int j = 0; j < 8; ++j) {
     const int i = base + j;
@@ -1387,17 +1395,15 @@ __global__ __launch_bounds__(kBlock) void k_start(KArgs a) {
     }
   }
   const double t = block_tree(tree8(l));
-  if (threadIdx.x == 0) a.part0[blockIdx.x] = t;
+  if (threadIdx.x == 0) a.part0[blk] = t;
 }
 
-// x = x_hi + x_lo; requests the final true-residual check after a budget stop
-// or a breakdown.
-__global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
-  const Ctl *c = &a.ctl[0];
+__global__ __launch_bounds__(kBlock) void k_start(KArgs a) { start_block(a, blockIdx.x); }
+
+// x = x_hi + x_lo over block blk (tier and zero-solution flag of the final state).
+__device__ __forceinline__ void finish_block_x(const KArgs &a, int tier, int zero, int blk) {
   const int n = a.A.n;
-  const int tier = c->tier;
-  const int zero = c->zero_solution;
-  const int base = blockIdx.x * kVecBlock + threadIdx.x * kVecPer;
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   for (int j = 0; j < 8; ++j) {
     const int i = base + j;
     if (i >= n) break;
@@ -1405,11 +1411,146 @@ __global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
     else { fold1(a.v.xhi, i, (double)a.v.xlo32[i]); a.v.xlo32[i] = 0.0f; }
     a.v.xout[i] = zero ? 0.0 : a.v.xhi[i];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && (c->status == 1 || c->status == 3)) {
-    a.ctl[0].mode = M_FINAL;
-    a.ctl[0].k3op = K3_NONE;
-    a.ctl[0].pend_sigma = 0;
-    a.ctl[0].step_done = 0;
+}
+
+// Requests the final true-residual check after a budget stop or a breakdown.
+__device__ __forceinline__ void request_final(Ctl *c) {
+  if (c->status == 1 || c->status == 3) {
+    c->mode = M_FINAL;
+    c->k3op = K3_NONE;
+    c->pend_sigma = 0;
+    c->step_done = 0;
+  }
+}
+
+// x = x_hi + x_lo; requests the final true-residual check after a budget stop
+// or a breakdown.
+__global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
+  const Ctl *c = &a.ctl[0];
+  finish_block_x(a, c->tier, c->zero_solution, blockIdx.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) request_final(&a.ctl[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent solve: each workgroup takes whole systems from a queue
+// (an atomic counter over a host-given order) and runs the same slot program as
+// the three-kernel path -- SpMV pass, alpha step and axpy pass, beta/policy step
+// and direction-update pass -- over all of the system's row groups and vector
+// blocks, with workgroup barriers in place of kernel boundaries.  Every
+// operation, reduction tree and step is the one of the single-system path, so
+// each system's result is bit-identical to its own mpcg_solve.  The slot loop
+// of a system is bounded (max_slots), and a workgroup leaves when the queue is
+// empty, so every wave exits.
+// ---------------------------------------------------------------------------
+template <int FS, int TIER>
+__device__ __forceinline__ void ka_iter_all(const KArgs &a, const Ctl &S, void *lds) {
+  for (int g = 0; g < a.P1; ++g) {
+    ka_iter<FS, TIER>(a, S, g, lds);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void ka_pass(const KArgs &a, const Ctl &S, void *lds) {
+  const int mode = S.mode;
+  if (mode == M_ITER) {
+    const int fs = (S.action >> 4) & 3;
+    switch (fs * 2 + S.tier) {
+    case 0: ka_iter_all<FP16, 0>(a, S, lds); break;
+    case 1: ka_iter_all<FP16, 1>(a, S, lds); break;
+    case 2: ka_iter_all<BF16, 0>(a, S, lds); break;
+    case 3: ka_iter_all<BF16, 1>(a, S, lds); break;
+    case 4: ka_iter_all<FP32, 0>(a, S, lds); break;
+    case 5: ka_iter_all<FP32, 1>(a, S, lds); break;
+    case 6: ka_iter_all<FP64, 0>(a, S, lds); break;
+    default: ka_iter_all<FP64, 1>(a, S, lds); break;
+    }
+  } else if (mode == M_INIT || mode == M_REPLACE || mode == M_FINAL) {
+    for (int g = 0; g < a.P1; ++g) {
+      ka_residual(a, S, g, mode, lds);
+      __syncthreads();
+    }
+  }
+}
+
+template <int FA, int FD>
+__device__ __forceinline__ void kb_axpy_all(const KArgs &a, const Ctl &S, bool fold_now) {
+  for (int blk = 0; blk < a.P2; ++blk) kb_axpy<FA, FD>(a, S, fold_now, blk);
+}
+
+#define MPCG_KB_ALL(FA, FD) \
+  case (FA) * 4 + (FD): kb_axpy_all<FA, FD>(a, S, fold_now); break;
+
+__device__ __forceinline__ void kb_pass(const KArgs &a, const Ctl &S, int bop, bool fold_now) {
+  if (bop == B_AXPY) {
+    const int act = S.action;
+    switch ((act & 3) * 4 + ((act >> 2) & 3)) {
+      MPCG_KB_ALL(FP16, FP16) MPCG_KB_ALL(FP16, BF16) MPCG_KB_ALL(FP16, FP32) MPCG_KB_ALL(FP16, FP64)
+      MPCG_KB_ALL(BF16, FP16) MPCG_KB_ALL(BF16, BF16) MPCG_KB_ALL(BF16, FP32) MPCG_KB_ALL(BF16, FP64)
+      MPCG_KB_ALL(FP32, FP16) MPCG_KB_ALL(FP32, BF16) MPCG_KB_ALL(FP32, FP32) MPCG_KB_ALL(FP32, FP64)
+      MPCG_KB_ALL(FP64, FP16) MPCG_KB_ALL(FP64, BF16) MPCG_KB_ALL(FP64, FP32) MPCG_KB_ALL(FP64, FP64)
+    default: break;
+    }
+  } else if (bop == B_EXEC) {
+    for (int blk = 0; blk < a.P2; ++blk) exec_elementwise(a, S, blk);
+  }
+}
+#undef MPCG_KB_ALL
+
+__global__ __launch_bounds__(kBlock, 2) void k_batched(const BatchSys *sys, const int32_t *order, int nsys,
+                                                     int32_t *queue) {
+  __shared__ Ctl S;
+  __shared__ PolicyDev SP;
+  __shared__ double lds[kLdsKa];
+  __shared__ int s_idx;
+  while (true) {
+    if (threadIdx.x == 0) s_idx = __hip_atomic_fetch_add(queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int qi = __builtin_amdgcn_readfirstlane(s_idx);
+    __syncthreads();
+    if (qi >= nsys) break;
+    const int si = __builtin_amdgcn_readfirstlane(order[qi]);
+    const KArgs &a = sys[si].a;
+    const int max_slots = sys[si].max_slots;
+    copy_words(&SP, a.pol, sizeof(PolicyDev));
+    copy_words(&S, &a.ctl[0], sizeof(Ctl));
+    __syncthreads();
+    const Sx x{&S, &SP, a.h, true};
+    for (int blk = 0; blk < a.P2; ++blk) start_block(a, blk);
+    __syncthreads();
+    int slots = 0;
+    while (S.mode != M_DONE && slots < max_slots) {
+      ++slots;
+      ka_pass(a, S, lds);
+      step_b<true>(x, a);
+      const int bop = S.b_op;
+      const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
+      kb_pass(a, S, bop, fold_now);
+      __syncthreads();
+      if (threadIdx.x == 0) kb_commit(S, bop, fold_now);
+      __syncthreads();
+      step_x<true>(x, a);
+      for (int blk = 0; blk < a.P2; ++blk) exec_elementwise(a, S, blk);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        S.k3op = K3_NONE;
+        S.step_done = 0;
+      }
+      __syncthreads();
+    }
+    const bool finished = S.mode == M_DONE;
+    for (int blk = 0; blk < a.P2; ++blk) finish_block_x(a, S.tier, S.zero_solution, blk);
+    __syncthreads();
+    if (threadIdx.x == 0 && finished) request_final(&S);
+    __syncthreads();
+    if (S.mode == M_FINAL) {
+      ka_pass(a, S, lds);
+      step_b<true>(x, a);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && !finished) S.status = -1;   // slot budget exhausted (not expected)
+    __syncthreads();
+    copy_words(&a.ctl[1], &S, sizeof(Ctl));
+    __syncthreads();
   }
 }
 
@@ -1561,6 +1702,12 @@ void launch_finish(const KArgs &a, hipStream_t s) {
   launch_ka(a, s);
   if (a.slow) launch_step_b(a, s);
   launch_kb(a, s);
+}
+
+void launch_batched(const BatchSys *sys, const int32_t *order, int nsys, int32_t *queue, int grid,
+                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (e0) hipExtLaunchKernelGGL(k_batched, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0, sys, order, nsys, queue);
+  else hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBlock), 0, s, sys, order, nsys, queue);
 }
 
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,

@@ -105,4 +105,12 @@ struct KArgs {
   int slot;            // index of this slot (with slot_log)
 };
 
+// One system of a batched solve: its kernel arguments (its own control block,
+// policy, vectors, histories) and its slot budget.
+struct BatchSys {
+  KArgs a;
+  int32_t max_slots;
+  int32_t pad_[3];
+};
+
 }  // namespace mpcg

@@ -12,6 +12,8 @@ void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_
 void launch_step_x(const KArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_step_b(const KArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_finish(const KArgs &a, hipStream_t s);
+void launch_batched(const BatchSys *sys, const int32_t *order, int nsys, int32_t *queue, int grid,
+                    hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,
                     int8_t *rexp, hipStream_t s);
 void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipStream_t s);
