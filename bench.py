@@ -116,7 +116,7 @@ def batched_experiment(args, M, W, torch) -> dict:
         A = W.batch_system(sd)
         m = M.Matrix(A)
         m.set_policy(pol)
-        m.set_options(replace_period=50, fallback=False)
+        m.set_options(replace_period=50, fallback=True)
         mats.append(m)
         bs.append(torch.from_numpy(W.rhs(A.n, sd + 5000)).cuda())
         xs.append(torch.zeros(A.n, dtype=torch.float64, device="cuda"))
@@ -136,6 +136,7 @@ def batched_experiment(args, M, W, torch) -> dict:
     zero()
     res_t, info_t = M.solve_batched(systems, tol=1e-8, maxit=maxit)        # autotunes, then solves
     log(f"[batched] autotuned: {info_t}")
+    assert all(r["status"] in (0, 2) for r in res_t), "a batched system did not converge"
     runs = []
     for _ in range(2):
         zero()
@@ -164,8 +165,11 @@ def batched_experiment(args, M, W, torch) -> dict:
     alg = sum(r["iters"] * iteration_bytes(n, z, M.BF16, 4) for r, (n, z) in zip(res_b, shapes))
     alg64 = sum(r["iters"] * iteration_bytes(n, z, M.FP64, 8) for r, (n, z) in zip(res_64, shapes))
     out = {"experiment": "batched persistent solve", "systems": len(mats), "sum_n": sum_n, "sum_nnz": sum_nnz,
-           "setup_s": round(setup_s, 1), "action": "bf16 SpMV, fp32 dot, fp32 axpy, R=50",
-           "config": {k: info_b[k] for k in ("workgroups", "spmv_rows")}, "autotune_ms": round(info_t["tune_ms"], 1),
+           "setup_s": round(setup_s, 1), "action": "bf16 SpMV, fp32 dot, fp32 axpy, R=50, fp64 fallback on stagnation",
+           "config": {k: info_b[k] for k in ("strategy", "workgroups", "spmv_rows", "split_rows", "n_split")},
+           "persistent_ms": round(info_b["persistent_ms"], 2), "split_ms": round(info_b["split_ms"], 2),
+           "fallbacks": int(sum(1 for r in res_b if r["fallback_at"] >= 0)),
+           "autotune_ms": round(info_t["tune_ms"], 1),
            "batched_ms": round(info_b["time_ms"], 2), "batched_wall_ms": round(wall_b * 1e3, 2),
            "sequential_wall_ms": round(wall_s * 1e3, 2),
            "speedup_vs_sequential": round(wall_s / wall_b, 2),

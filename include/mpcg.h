@@ -219,8 +219,10 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
                mpcg_result *res);
 
 /* ---------------------------------------------------------------- batched
- * Many independent systems in one persistent launch.  Each workgroup takes
- * whole systems from a queue and runs the solve of section 3 with the policy
+ * Many independent systems, either in one persistent launch (each workgroup
+ * takes whole systems from a queue) or in lockstep (each iteration's three
+ * kernels cover every running system).  Each system runs the solve of
+ * section 3 with the policy
  * attached to that system (fixed, Q-table or MLP; not training policies or
  * rollout logs, whose state is shared), its own options (replacement period,
  * fallback) and its own tol / maxit.  Every system's result -- iterations,
@@ -233,6 +235,13 @@ typedef struct {
     int32_t order;             /* 0: largest systems (nnz) first; 1: as given   */
     int32_t autotune_iters;    /* iterations per system in each autotuning trial
                                   (0: 16)                                        */
+    int32_t split_rows;        /* systems with more rows than this run through
+                                  the full-device path (mpcg_solve) after the
+                                  persistent launch; 0: autotuned, -1: none    */
+    int32_t strategy;          /* 1: one persistent launch (workgroups take
+                                  whole systems); 2: lockstep -- three launches
+                                  per iteration over the row groups and blocks
+                                  of all running systems; 0: autotuned          */
 } mpcg_batch_opts;
 
 typedef struct {
@@ -241,18 +250,23 @@ typedef struct {
     int32_t workgroups;        /* configuration used                            */
     int32_t spmv_rows;
     int32_t tuned;             /* 0: given, 1: autotuned now, 2: autotuner cache */
-    int32_t reserved;
+    int32_t split_rows;        /* -1: every system in the persistent launch     */
+    int32_t n_split;           /* systems solved through the full-device path   */
+    int32_t strategy;          /* strategy used (1 or 2)                        */
+    double persistent_ms;      /* device time of the persistent launch          */
+    double split_ms;           /* device time of the full-device solves         */
 } mpcg_batch_info;
 
 /*
  * Solves A[i] x[i] = b[i] for i < nsys.  A[i] are distinct handles on one
  * device; b[i], x[i] are device double[n_i] (x[i]: initial guess in, solution
  * out); tol[i], maxit[i] host arrays as in mpcg_solve; res[i] (host) receives
- * each system's summary (time_ms: the whole launch).  Runs on A[0]'s stream
+ * each system's summary (time_ms: the whole batch).  Runs on A[0]'s stream
  * after synchronising every A[i]'s stream.  The autotuner (options 0) times
- * short trials of candidate configurations on copies of x0 and remembers the
- * choice for the batch shape (count, total rows, total nonzeros).  info (host,
- * may be NULL) receives the configuration and times.
+ * short trials of candidate configurations (workgroups, SpMV group rows, size
+ * split) on copies of x0 and remembers the choice for the batch shape (count,
+ * total rows, total nonzeros).  info (host, may be NULL) receives the
+ * configuration and times.
  */
 int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const *b, double *const *x,
                        const double *tol, const int32_t *maxit, const mpcg_batch_opts *opts,

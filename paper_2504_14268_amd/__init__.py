@@ -71,12 +71,14 @@ class Result(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("workgroups", C.c_int32), ("spmv_rows", C.c_int32), ("order", C.c_int32),
-                ("autotune_iters", C.c_int32)]
+                ("autotune_iters", C.c_int32), ("split_rows", C.c_int32), ("strategy", C.c_int32)]
 
 
 class BatchInfo(C.Structure):
     _fields_ = [("time_ms", C.c_double), ("tune_ms", C.c_double), ("workgroups", C.c_int32),
-                ("spmv_rows", C.c_int32), ("tuned", C.c_int32), ("reserved", C.c_int32)]
+                ("spmv_rows", C.c_int32), ("tuned", C.c_int32), ("split_rows", C.c_int32),
+                ("n_split", C.c_int32), ("strategy", C.c_int32), ("persistent_ms", C.c_double),
+                ("split_ms", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -260,7 +262,8 @@ class Policy:
         return st, ac
 
 
-def solve_batched(systems, tol=1e-8, maxit=1000, workgroups=0, spmv_rows=0, order=0, autotune_iters=0):
+def solve_batched(systems, tol=1e-8, maxit=1000, workgroups=0, spmv_rows=0, order=0, autotune_iters=0,
+                  split_rows=0, strategy=0):
     """One persistent launch over systems = [(Matrix, b, x), ...] (device float64
     tensors; x holds x0 and receives the solution).  tol / maxit: scalars or
     per-system lists.  Returns (list of result dicts, batch info dict)."""
@@ -275,7 +278,7 @@ def solve_batched(systems, tol=1e-8, maxit=1000, workgroups=0, spmv_rows=0, orde
     xs = (C.c_void_p * max(m, 1))(*[s[2].data_ptr() for s in systems])
     res = (Result * max(m, 1))()
     info = BatchInfo()
-    o = BatchOpts(workgroups, spmv_rows, order, autotune_iters)
+    o = BatchOpts(workgroups, spmv_rows, order, autotune_iters, split_rows, strategy)
     _check(lib().mpcg_solve_batched(m, hs, bs, xs, _np_ptr(tols), _np_ptr(mits), C.byref(o), res, C.byref(info)),
            "mpcg_solve_batched")
     return [res[i].as_dict() for i in range(m)], info.as_dict()

@@ -800,7 +800,8 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
 namespace {
 
 struct BatchCfg {
-  int workgroups, spmv_rows;
+  int workgroups, spmv_rows, split_rows;   // split_rows < 0: no split
+  int lockstep;                            // 1: lockstep kernels instead of the persistent launch
 };
 
 // Autotuner memory: the configuration chosen for a batch shape.
@@ -822,7 +823,7 @@ static int batch_run(int nsys, mpcg_matrix *const *A, const double *const *b, do
                      const int32_t *maxit, const std::vector<mpcg_policy *> &pols, const std::vector<int32_t> &order,
                      const BatchCfg &cfg, hipStream_t st, float *ms_out) {
   std::vector<BatchSys> hs((size_t)nsys);
-  for (int i = 0; i < nsys; ++i) {
+  for (int32_t i : order) {
     int rc = upload_start(A[i], pols[i], tol[i], maxit[i], st);
     if (rc) return rc;
     KArgs a = make_args(A[i], b[i], x[i]);
@@ -850,10 +851,11 @@ static int batch_run(int nsys, mpcg_matrix *const *A, const double *const *b, do
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e == hipSuccess) e = hipMemcpyAsync(d_sys, hs.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st);
+  const int nq = (int)order.size();
+  if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * nq, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemsetAsync(d_queue, 0, sizeof(int32_t), st);
   if (e == hipSuccess) {
-    launch_batched(d_sys, d_order, nsys, d_queue, cfg.workgroups, st, e0, e1);
+    launch_batched(d_sys, d_order, nq, d_queue, cfg.workgroups, st, e0, e1);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -865,15 +867,192 @@ static int batch_run(int nsys, mpcg_matrix *const *A, const double *const *b, do
   return rc;
 }
 
+// Lockstep strategy: each iteration is three launches over the row groups /
+// vector blocks of every system still running.  The host enqueues chunks of
+// iterations, gathers the systems' modes after each chunk and, one chunk
+// behind, rebuilds the tables without the finished systems (double-buffered,
+// so a table is rewritten only after the chunk that read it has completed).
+static int batch_lockstep(int nsys, mpcg_matrix *const *A, const double *const *b, double *const *x,
+                          const double *tol, const int32_t *maxit, const std::vector<mpcg_policy *> &pols,
+                          const std::vector<int32_t> &order, const BatchCfg &cfg, hipStream_t st, float *ms_out) {
+  std::vector<BatchSys> hs((size_t)nsys);
+  int slow = 0, max_slots = 16;
+  for (int32_t i : order) {
+    int rc = upload_start(A[i], pols[i], tol[i], maxit[i], st);
+    if (rc) return rc;
+    KArgs a = make_args(A[i], b[i], x[i]);
+    a.grows = cfg.spmv_rows;
+    a.P1 = (A[i]->n + a.grows - 1) / a.grows;
+    a.G1 = round_up(a.P1, 8);
+    hs[i].a = a;
+    hs[i].max_slots = 2 * maxit[i] + 16;
+    max_slots = std::max(max_slots, hs[i].max_slots);
+    if (pols[i]->desc.kind == MPCG_POLICY_MLP) slow = 1;
+  }
+  size_t cap_ka = 0, cap_vb = 0;
+  for (int32_t i : order) {
+    cap_ka += (size_t)hs[i].a.P1;
+    cap_vb += (size_t)hs[i].a.P2;
+  }
+  const size_t nq = order.size();
+  BatchSys *d_sys = nullptr;
+  SysBlk *d_ka[2] = {nullptr, nullptr}, *d_vb[2] = {nullptr, nullptr};
+  int32_t *d_act[2] = {nullptr, nullptr}, *d_modes = nullptr, *h_modes = nullptr;
+  SysBlk *h_tab = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr, ev[2] = {nullptr, nullptr};
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    dfree(d_sys);
+    for (int j = 0; j < 2; ++j) { dfree(d_ka[j]); dfree(d_vb[j]); dfree(d_act[j]); }
+    dfree(d_modes);
+    if (h_modes) (void)hipHostFree(h_modes);
+    if (h_tab) (void)hipHostFree(h_tab);
+    for (hipEvent_t *p : {&e0, &e1, &ev[0], &ev[1]})
+      if (*p) (void)hipEventDestroy(*p);
+  };
+#define LS_TRY(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) {                                                                       \
+      cleanup();                                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? MPCG_ERR_NOMEM : MPCG_ERR_DEVICE,                   \
+                  std::string("lockstep: ") + #expr + ": " + hipGetErrorString(e_));             \
+    }                                                                                             \
+  } while (0)
+  LS_TRY(dmalloc(&d_sys, (size_t)nsys));
+  for (int j = 0; j < 2; ++j) {
+    LS_TRY(dmalloc(&d_ka[j], cap_ka));
+    LS_TRY(dmalloc(&d_vb[j], cap_vb));
+    LS_TRY(dmalloc(&d_act[j], nq));
+  }
+  LS_TRY(dmalloc(&d_modes, nq));
+  // pinned staging: modes of the two chunks in flight, and the tables of the
+  // two buffers (ka, vb, act each)
+  LS_TRY(hipHostMalloc((void **)&h_modes, sizeof(int32_t) * 2 * nq, hipHostMallocDefault));
+  const size_t tab_words = cap_ka + cap_vb + (nq + 1) / 2 + 1;
+  LS_TRY(hipHostMalloc((void **)&h_tab, sizeof(SysBlk) * 2 * tab_words, hipHostMallocDefault));
+  LS_TRY(hipEventCreate(&e0));
+  LS_TRY(hipEventCreate(&e1));
+  LS_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  LS_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  LS_TRY(hipMemcpyAsync(d_sys, hs.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
+  int nka[2] = {0, 0}, nvb[2] = {0, 0}, nact[2] = {0, 0};
+  std::vector<int32_t> act_list[2];
+  // writes the tables of `active` into buffer j (pinned staging, then device)
+  auto build = [&](int j, const std::vector<int32_t> &active) -> hipError_t {
+    SysBlk *ka = h_tab + (size_t)j * tab_words, *vb = ka + cap_ka;
+    int32_t *ac = (int32_t *)(vb + cap_vb);
+    int a1 = 0, a2 = 0;
+    for (int32_t s : active) {
+      for (int g = 0; g < hs[s].a.P1; ++g) ka[a1++] = SysBlk{s, g};
+      for (int q = 0; q < hs[s].a.P2; ++q) vb[a2++] = SysBlk{s, q};
+    }
+    for (size_t t = 0; t < active.size(); ++t) ac[t] = active[t];
+    nka[j] = a1;
+    nvb[j] = a2;
+    nact[j] = (int)active.size();
+    act_list[j] = active;
+    hipError_t e = hipSuccess;
+    if (a1) e = hipMemcpyAsync(d_ka[j], ka, sizeof(SysBlk) * a1, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && a2) e = hipMemcpyAsync(d_vb[j], vb, sizeof(SysBlk) * a2, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && nact[j])
+      e = hipMemcpyAsync(d_act[j], ac, sizeof(int32_t) * nact[j], hipMemcpyHostToDevice, st);
+    return e;
+  };
+  std::vector<int32_t> all(order.begin(), order.end());
+  LS_TRY(build(0, all));
+  LS_TRY(build(1, all));
+  LS_TRY(hipEventRecord(e0, st));
+  launch_lock_start(d_sys, d_vb[0], nvb[0], st);
+  LS_TRY(hipGetLastError());
+  const int chunk = 16;
+  int64_t slots = 0;
+  int ci = 0;
+  bool done = false;
+  while (slots < max_slots && !done) {
+    const int j = ci & 1;
+    const int m = (int)std::min<int64_t>(chunk, max_slots - slots);
+    for (int s = 0; s < m; ++s)
+      launch_lock_slot(d_sys, d_ka[j], nka[j], d_vb[j], nvb[j], d_act[j], nact[j], slow, st);
+    launch_lock_modes(d_sys, d_act[j], nact[j], d_modes, st);
+    LS_TRY(hipGetLastError());
+    if (nact[j]) LS_TRY(hipMemcpyAsync(h_modes + (size_t)j * nq, d_modes, sizeof(int32_t) * nact[j],
+                                       hipMemcpyDeviceToHost, st));
+    LS_TRY(hipEventRecord(ev[j], st));
+    slots += m;
+    // one chunk behind: the modes after chunk ci-1 give the active set of chunk ci+1
+    if (ci > 0) {
+      const int pj = (ci - 1) & 1;
+      LS_TRY(hipEventSynchronize(ev[pj]));
+      std::vector<int32_t> next;
+      for (int t = 0; t < nact[pj]; ++t)
+        if (h_modes[(size_t)pj * nq + t] != M_DONE) next.push_back(act_list[pj][t]);
+      if (next.empty()) {
+        done = true;
+        break;
+      }
+      LS_TRY(build(pj, next));   // buffer pj is next used by chunk ci+1
+    }
+    ci++;
+  }
+  LS_TRY(hipStreamSynchronize(st));
+  // the final state of every system: fold and x; a final true residual after a
+  // budget stop or a breakdown
+  LS_TRY(build(0, all));
+  launch_lock_finish(d_sys, d_ka[0], nka[0], d_vb[0], nvb[0], d_act[0], nact[0], slow, st);
+  LS_TRY(hipGetLastError());
+  LS_TRY(hipEventRecord(e1, st));
+  LS_TRY(hipStreamSynchronize(st));
+  if (ms_out) LS_TRY(hipEventElapsedTime(ms_out, e0, e1));
+#undef LS_TRY
+  cleanup();
+  return MPCG_OK;
+}
+
+// The whole batch under cfg: systems above the split through mpcg_solve (one
+// after the other, after the persistent launch), the others in the launch.
+// res may be NULL (trials).  Device times of both parts in ms_p / ms_s.
+static int batch_all(int nsys, mpcg_matrix *const *A, const double *const *b, double *const *x, const double *tol,
+                     const int32_t *maxit, const std::vector<mpcg_policy *> &pols, const std::vector<int32_t> &order,
+                     const BatchCfg &cfg, hipStream_t st, mpcg_result *res, float *ms_p, float *ms_s, int *n_split) {
+  std::vector<int32_t> small_order, large;
+  for (int32_t i : order) {
+    if (cfg.split_rows >= 0 && A[i]->n > cfg.split_rows) large.push_back(i);
+    else small_order.push_back(i);
+  }
+  *ms_p = 0.0f;
+  *ms_s = 0.0f;
+  *n_split = (int)large.size();
+  if (!small_order.empty()) {
+    // the persistent kernel (or the lockstep kernels) over small_order
+    int rc = cfg.lockstep ? batch_lockstep(nsys, A, b, x, tol, maxit, pols, small_order, cfg, st, ms_p)
+                          : batch_run(nsys, A, b, x, tol, maxit, pols, small_order, cfg, st, ms_p);
+    if (rc) return rc;
+  }
+  for (int32_t i : large) {
+    mpcg_matrix *M = A[i];
+    mpcg_policy *saved = M->pol;
+    M->pol = pols[i];
+    mpcg_result r;
+    const int rc = mpcg_solve(M, b[i], x[i], tol[i], maxit[i], &r);
+    M->pol = saved;
+    if (rc) return rc;
+    *ms_s += (float)r.time_ms;
+    if (res) res[i] = r;
+  }
+  return MPCG_OK;
+}
+
 int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const *b, double *const *x,
                        const double *tol, const int32_t *maxit, const mpcg_batch_opts *opts, mpcg_result *res,
                        mpcg_batch_info *info) {
   if (nsys < 0 || (nsys > 0 && (!A || !b || !x || !tol || !maxit || !res)))
     return fail(MPCG_ERR_INVALID, "NULL or negative argument");
-  mpcg_batch_opts o{0, 0, 0, 0};
+  mpcg_batch_opts o{0, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (o.workgroups < 0 || (o.spmv_rows != 0 && o.spmv_rows != 512 && o.spmv_rows != 1024 && o.spmv_rows != 2048) ||
-      (o.order != 0 && o.order != 1) || o.autotune_iters < 0)
+      (o.order != 0 && o.order != 1) || o.autotune_iters < 0 || o.split_rows < -1 || o.strategy < 0 ||
+      o.strategy > 2)
     return fail(MPCG_ERR_INVALID, "bad batch options");
   if (info) std::memset(info, 0, sizeof(*info));
   if (nsys == 0) return MPCG_OK;
@@ -908,18 +1087,26 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
   if (o.order == 0)
     std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) { return A[p]->nnz > A[q]->nnz; });
 
-  BatchCfg cfg{o.workgroups, o.spmv_rows};
+  // strategy 1: persistent launch; 2: lockstep kernels (workgroups and split
+  // do not apply); 0: the autotuner chooses.
+  BatchCfg cfg{o.workgroups, o.spmv_rows, o.split_rows, o.strategy == 2 ? 1 : 0};
+  if (o.strategy == 2) {
+    cfg.workgroups = 1;
+    cfg.split_rows = -1;
+  }
   int tuned = 0;
   double tune_ms = 0.0;
-  if (cfg.workgroups == 0 || cfg.spmv_rows == 0) {
+  if (o.strategy == 0 || cfg.workgroups == 0 || cfg.spmv_rows == 0 || cfg.split_rows == 0) {
     const BatchKey key{nsys, sum_n, sum_nnz};
     bool have = false;
     {
       std::lock_guard<std::mutex> lk(g_batch_mu);
       auto it = g_batch_tuned.find(key);
       if (it != g_batch_tuned.end()) {
+        if (o.strategy == 0) cfg = it->second;
         if (cfg.workgroups == 0) cfg.workgroups = it->second.workgroups;
         if (cfg.spmv_rows == 0) cfg.spmv_rows = it->second.spmv_rows;
+        if (cfg.split_rows == 0) cfg.split_rows = it->second.split_rows;
         have = true;
         tuned = 2;
       }
@@ -927,11 +1114,13 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
     if (!have) {
       // Timed trials of a few iterations per system on copies of x0; every
       // candidate gives the same results, only the time differs.
-      std::vector<int> wgs, rows;
+      std::vector<int> wgs, rows, splits;
       if (cfg.workgroups) wgs = {cfg.workgroups};
-      else wgs = {256, 512, std::max(1, std::min(nsys, 1024))};
+      else wgs = {256, 512};
       if (cfg.spmv_rows) rows = {cfg.spmv_rows};
       else rows = {512, 2048};
+      if (cfg.split_rows) splits = {cfg.split_rows};
+      else splits = {-1, 100000, 30000, 10000};
       std::vector<double *> xt((size_t)nsys, nullptr);
       std::vector<int32_t> mt((size_t)nsys);
       const int ti = o.autotune_iters > 0 ? o.autotune_iters : 16;
@@ -943,23 +1132,30 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
         if (e != hipSuccess) rc = fail(MPCG_ERR_NOMEM, "autotuner scratch");
         mt[i] = std::min(maxit[i], ti);
       }
-      BatchCfg best{0, 0};
+      std::vector<BatchCfg> cands;
+      if (o.strategy != 2)
+        for (int w : wgs)
+          for (int r : rows)
+            for (int sp : splits) cands.push_back(BatchCfg{w, r, sp, 0});
+      if (o.strategy != 1)
+        for (int r : rows) cands.push_back(BatchCfg{1, r, -1, 1});
+      BatchCfg best{0, 0, 0, 0};
       float best_ms = 0.0f;
-      for (int w : wgs) {
-        for (int r : rows) {
-          if (rc) break;
-          float ms = 0.0f;
-          rc = batch_run(nsys, A, b, xt.data(), tol, mt.data(), pols, order, BatchCfg{w, r}, st, &ms);
-          tune_ms += ms;
-          if (!rc && (best.workgroups == 0 || ms < best_ms)) {
-            best = BatchCfg{w, r};
-            best_ms = ms;
-          }
-          // the trial overwrote x: restore the copies of x0 for the next one
-          for (int i = 0; i < nsys && !rc; ++i)
-            if (hipMemcpyAsync(xt[i], x[i], sizeof(double) * A[i]->n, hipMemcpyDeviceToDevice, st) != hipSuccess)
-              rc = fail(MPCG_ERR_DEVICE, "autotuner copy");
+      for (const BatchCfg &cand : cands) {
+        if (rc) break;
+        float mp = 0.0f, ms_ = 0.0f;
+        int ns = 0;
+        rc = batch_all(nsys, A, b, xt.data(), tol, mt.data(), pols, order, cand, st, nullptr, &mp, &ms_, &ns);
+        const float t = mp + ms_;
+        tune_ms += t;
+        if (!rc && (best.workgroups == 0 || t < best_ms)) {
+          best = cand;
+          best_ms = t;
         }
+        // the trial overwrote x: restore the copies of x0 for the next one
+        for (int i = 0; i < nsys && !rc; ++i)
+          if (hipMemcpyAsync(xt[i], x[i], sizeof(double) * A[i]->n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            rc = fail(MPCG_ERR_DEVICE, "autotuner copy");
       }
       (void)hipStreamSynchronize(st);
       for (double *p : xt) dfree(p);
@@ -970,10 +1166,16 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
       g_batch_tuned[key] = best;
     }
   }
-  float ms = 0.0f;
-  int rc = batch_run(nsys, A, b, x, tol, maxit, pols, order, cfg, st, &ms);
+  float ms_p = 0.0f, ms_s = 0.0f;
+  int n_split = 0;
+  int rc = batch_all(nsys, A, b, x, tol, maxit, pols, order, cfg, st, res, &ms_p, &ms_s, &n_split);
   if (rc) return rc;
+  const float ms = ms_p + ms_s;
   for (int i = 0; i < nsys; ++i) {
+    if (cfg.split_rows >= 0 && A[i]->n > cfg.split_rows) {
+      res[i].time_ms = ms;
+      continue;
+    }
     Ctl r;
     HIP_TRY(hipMemcpy(&r, A[i]->d_ctl + 1, sizeof(Ctl), hipMemcpyDeviceToHost));
     if (r.status < 0) return fail(MPCG_ERR_DEVICE, "batched solve did not reach a final state");
@@ -988,6 +1190,11 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
     info->workgroups = cfg.workgroups;
     info->spmv_rows = cfg.spmv_rows;
     info->tuned = tuned;
+    info->split_rows = cfg.split_rows;
+    info->n_split = n_split;
+    info->persistent_ms = ms_p;
+    info->split_ms = ms_s;
+    info->strategy = cfg.lockstep ? 2 : 1;
   }
   return MPCG_OK;
 }

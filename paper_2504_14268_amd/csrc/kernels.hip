@@ -1116,10 +1116,8 @@ __device__ __forceinline__ void fold_group(const KArgs &a, int tier, int g) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_a(KArgs a) {
-  const int g = xcd_group(a.G1);
-  if (g >= a.P1) return;
-  __shared__ double lds[kLdsKa];
+// KA's work on row group g of one system.
+__device__ __forceinline__ void ka_body(const KArgs &a, int g, double *lds) {
   const Ctl &S = a.ctl[0];
   const int mode = S.mode;
   if (a.slot_log && g == 0 && threadIdx.x == 0) a.slot_log[a.slot] = (int8_t)mode;
@@ -1138,6 +1136,13 @@ __global__ __launch_bounds__(kBlock) void k_a(KArgs a) {
   } else if (mode == M_INIT || mode == M_REPLACE || mode == M_FINAL) {
     ka_residual(a, S, g, mode, lds);
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_a(KArgs a) {
+  const int g = xcd_group(a.G1);
+  if (g >= a.P1) return;
+  __shared__ double lds[kLdsKa];
+  ka_body(a, g, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1305,18 +1310,19 @@ __device__ __forceinline__ void kb_commit(Ctl &S, int bop, bool fold_now) {
   S.step_done = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_b(KArgs a) {
+// KB's work on vector block blk of one system; block 0 commits the state.
+__device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
   copy_words(&S, &a.ctl[0], sizeof(Ctl));
   copy_words(&SP, a.pol, sizeof(PolicyDev));
   __syncthreads();
-  const Sx x{&S, &SP, a.h, blockIdx.x == 0};
+  const Sx x{&S, &SP, a.h, blk == 0};
   if (!S.step_done) step_b<false>(x, a);
   const int bop = S.b_op;
   const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
-  kb_work(a, S, bop, fold_now, blockIdx.x);
-  if (blockIdx.x == 0) {   // commit the state after this kernel for KX
+  kb_work(a, S, bop, fold_now, blk);
+  if (blk == 0) {   // commit the state after this kernel for KX
     __syncthreads();
     if (threadIdx.x == 0) kb_commit(S, bop, fold_now);
     __syncthreads();
@@ -1324,17 +1330,18 @@ __global__ __launch_bounds__(kBlock) void k_b(KArgs a) {
   }
 }
 
-// KX: end-of-iteration step, then the pending elementwise operation.
-__global__ __launch_bounds__(kBlock) void k_x(KArgs a) {
+// KX's work on vector block blk: end-of-iteration step, then the pending
+// elementwise operation; block 0 commits the state.
+__device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
   copy_words(&S, &a.ctl[1], sizeof(Ctl));
   copy_words(&SP, a.pol, sizeof(PolicyDev));
   __syncthreads();
-  const Sx x{&S, &SP, a.h, blockIdx.x == 0};
+  const Sx x{&S, &SP, a.h, blk == 0};
   if (!S.step_done) step_x<false>(x, a);
-  exec_elementwise(a, S, blockIdx.x);
-  if (blockIdx.x == 0) {   // commit the state after this kernel for the next KA and KB
+  exec_elementwise(a, S, blk);
+  if (blk == 0) {   // commit the state after this kernel for the next KA and KB
     __syncthreads();
     if (threadIdx.x == 0) {
       S.k3op = K3_NONE;
@@ -1344,11 +1351,15 @@ __global__ __launch_bounds__(kBlock) void k_x(KArgs a) {
     copy_words(&a.ctl[0], &S, sizeof(Ctl));
   }
 }
+
+__global__ __launch_bounds__(kBlock) void k_b(KArgs a) { kb_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(kBlock) void k_x(KArgs a) { kx_body(a, blockIdx.x); }
 #undef MPCG_KB_CASE
 
 // One-block step kernels for policies whose step writes shared state or
 // evaluates the network: the step runs once, then KA / KB skip theirs.
-__global__ __launch_bounds__(kBlock) void k_step_b(KArgs a) {
+__device__ __forceinline__ void step_b_body(const KArgs &a) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
   copy_words(&S, &a.ctl[0], sizeof(Ctl));
@@ -1361,7 +1372,7 @@ __global__ __launch_bounds__(kBlock) void k_step_b(KArgs a) {
   copy_words(&a.ctl[0], &S, sizeof(Ctl));
 }
 
-__global__ __launch_bounds__(kBlock) void k_step_x(KArgs a) {
+__device__ __forceinline__ void step_x_body(const KArgs &a) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
   copy_words(&S, &a.ctl[1], sizeof(Ctl));
@@ -1373,6 +1384,10 @@ __global__ __launch_bounds__(kBlock) void k_step_x(KArgs a) {
   __syncthreads();
   copy_words(&a.ctl[1], &S, sizeof(Ctl));
 }
+
+__global__ __launch_bounds__(kBlock) void k_step_b(KArgs a) { step_b_body(a); }
+
+__global__ __launch_bounds__(kBlock) void k_step_x(KArgs a) { step_x_body(a); }
 
 // ---------------------------------------------------------------------------
 // start / finish
@@ -1555,6 +1570,63 @@ __global__ __launch_bounds__(kBlock, 2) void k_batched(const BatchSys *sys, cons
 }
 
 // ---------------------------------------------------------------------------
+// Batched lockstep: the three kernels of an iteration over the row groups or
+// vector blocks of many systems at once.  Entry t of a table names (system,
+// group or block); each workgroup runs the single-system body on it, so every
+// system computes exactly what its own solve computes.  Systems that are done
+// return at once; the host drops them from the tables as it learns of them.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_a_lock(const BatchSys *sys, const SysBlk *tab, int ntab, int nround) {
+  const int t = xcd_group(nround);
+  if (t >= ntab) return;
+  const int si = __builtin_amdgcn_readfirstlane(tab[t].sys);
+  const int g = __builtin_amdgcn_readfirstlane(tab[t].idx);
+  __shared__ double lds[kLdsKa];
+  ka_body(sys[si].a, g, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_lock(const BatchSys *sys, const SysBlk *tab, int ntab) {
+  const int si = __builtin_amdgcn_readfirstlane(tab[blockIdx.x].sys);
+  const int blk = __builtin_amdgcn_readfirstlane(tab[blockIdx.x].idx);
+  kb_body(sys[si].a, blk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_x_lock(const BatchSys *sys, const SysBlk *tab, int ntab) {
+  const int si = __builtin_amdgcn_readfirstlane(tab[blockIdx.x].sys);
+  const int blk = __builtin_amdgcn_readfirstlane(tab[blockIdx.x].idx);
+  kx_body(sys[si].a, blk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_step_b_lock(const BatchSys *sys, const int32_t *act) {
+  step_b_body(sys[__builtin_amdgcn_readfirstlane(act[blockIdx.x])].a);
+}
+
+__global__ __launch_bounds__(kBlock) void k_step_x_lock(const BatchSys *sys, const int32_t *act) {
+  step_x_body(sys[__builtin_amdgcn_readfirstlane(act[blockIdx.x])].a);
+}
+
+__global__ __launch_bounds__(kBlock) void k_start_lock(const BatchSys *sys, const SysBlk *tab) {
+  const int si = __builtin_amdgcn_readfirstlane(tab[blockIdx.x].sys);
+  start_block(sys[si].a, __builtin_amdgcn_readfirstlane(tab[blockIdx.x].idx));
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_lock(const BatchSys *sys, const SysBlk *tab) {
+  const int si = __builtin_amdgcn_readfirstlane(tab[blockIdx.x].sys);
+  const int blk = __builtin_amdgcn_readfirstlane(tab[blockIdx.x].idx);
+  const KArgs &a = sys[si].a;
+  const Ctl *c = &a.ctl[0];
+  finish_block_x(a, c->tier, c->zero_solution, blk);
+  if (blk == 0 && threadIdx.x == 0) request_final(&a.ctl[0]);
+}
+
+// modes[i] = mode of system act[i] after the last iteration kernel.
+__global__ __launch_bounds__(kBlock) void k_modes_lock(const BatchSys *sys, const int32_t *act, int nact,
+                                                        int32_t *modes) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < nact) modes[i] = sys[act[i]].a.ctl[0].mode;
+}
+
+// ---------------------------------------------------------------------------
 // setup: shadows
 // ---------------------------------------------------------------------------
 // Thread per row: fp16 row exponent e (largest magnitude scaled into
@@ -1708,6 +1780,34 @@ void launch_batched(const BatchSys *sys, const int32_t *order, int nsys, int32_t
                     hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (e0) hipExtLaunchKernelGGL(k_batched, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0, sys, order, nsys, queue);
   else hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBlock), 0, s, sys, order, nsys, queue);
+}
+
+void launch_lock_slot(const BatchSys *sys, const SysBlk *tka, int nka, const SysBlk *tvb, int nvb,
+                      const int32_t *act, int nact, int slow, hipStream_t s) {
+  const int nr = (nka + 7) / 8 * 8;
+  if (nka > 0) hipLaunchKernelGGL(k_a_lock, dim3(nr), dim3(kBlock), 0, s, sys, tka, nka, nr);
+  if (slow && nact > 0) hipLaunchKernelGGL(k_step_b_lock, dim3(nact), dim3(kBlock), 0, s, sys, act);
+  if (nvb > 0) hipLaunchKernelGGL(k_b_lock, dim3(nvb), dim3(kBlock), 0, s, sys, tvb, nvb);
+  if (slow && nact > 0) hipLaunchKernelGGL(k_step_x_lock, dim3(nact), dim3(kBlock), 0, s, sys, act);
+  if (nvb > 0) hipLaunchKernelGGL(k_x_lock, dim3(nvb), dim3(kBlock), 0, s, sys, tvb, nvb);
+}
+
+void launch_lock_start(const BatchSys *sys, const SysBlk *tvb, int nvb, hipStream_t s) {
+  if (nvb > 0) hipLaunchKernelGGL(k_start_lock, dim3(nvb), dim3(kBlock), 0, s, sys, tvb);
+}
+
+void launch_lock_finish(const BatchSys *sys, const SysBlk *tka, int nka, const SysBlk *tvb, int nvb,
+                        const int32_t *act, int nact, int slow, hipStream_t s) {
+  if (nvb > 0) hipLaunchKernelGGL(k_finish_lock, dim3(nvb), dim3(kBlock), 0, s, sys, tvb);
+  const int nr = (nka + 7) / 8 * 8;
+  if (nka > 0) hipLaunchKernelGGL(k_a_lock, dim3(nr), dim3(kBlock), 0, s, sys, tka, nka, nr);
+  if (slow && nact > 0) hipLaunchKernelGGL(k_step_b_lock, dim3(nact), dim3(kBlock), 0, s, sys, act);
+  if (nvb > 0) hipLaunchKernelGGL(k_b_lock, dim3(nvb), dim3(kBlock), 0, s, sys, tvb, nvb);
+}
+
+void launch_lock_modes(const BatchSys *sys, const int32_t *act, int nact, int32_t *modes, hipStream_t s) {
+  if (nact > 0) hipLaunchKernelGGL(k_modes_lock, dim3((nact + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sys, act,
+                                   nact, modes);
 }
 
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,

@@ -113,4 +113,10 @@ struct BatchSys {
   int32_t pad_[3];
 };
 
+// Entry of a lockstep table: a system and one of its row groups (KA) or vector
+// blocks (KB, KX).
+struct SysBlk {
+  int32_t sys, idx;
+};
+
 }  // namespace mpcg

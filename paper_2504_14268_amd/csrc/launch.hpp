@@ -14,6 +14,12 @@ void launch_step_b(const KArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEv
 void launch_finish(const KArgs &a, hipStream_t s);
 void launch_batched(const BatchSys *sys, const int32_t *order, int nsys, int32_t *queue, int grid,
                     hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_lock_slot(const BatchSys *sys, const SysBlk *tka, int nka, const SysBlk *tvb, int nvb,
+                      const int32_t *act, int nact, int slow, hipStream_t s);
+void launch_lock_start(const BatchSys *sys, const SysBlk *tvb, int nvb, hipStream_t s);
+void launch_lock_finish(const BatchSys *sys, const SysBlk *tka, int nka, const SysBlk *tvb, int nvb,
+                        const int32_t *act, int nact, int slow, hipStream_t s);
+void launch_lock_modes(const BatchSys *sys, const int32_t *act, int nact, int32_t *modes, hipStream_t s);
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,
                     int8_t *rexp, hipStream_t s);
 void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipStream_t s);

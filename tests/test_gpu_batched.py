@@ -105,13 +105,19 @@ def same(r1, x1, h1, r2, x2, h2):
 def test_batched_equals_single_and_oracle(M):
     sysl = batch_systems()
     gp, op = policies(M, len(sysl))
-    cfgs = [dict(workgroups=3, spmv_rows=512), dict(workgroups=64, spmv_rows=2048, order=1), dict()]
+    cfgs = [dict(workgroups=3, spmv_rows=512, split_rows=-1, strategy=1),
+            dict(workgroups=64, spmv_rows=2048, order=1, split_rows=-1, strategy=1),
+            dict(workgroups=16, spmv_rows=1024, split_rows=3000, strategy=1),
+            dict(spmv_rows=512, strategy=2), dict(spmv_rows=2048, strategy=2, order=1), dict()]
     outs, single = run_batch(M, sysl, gp, cfgs)
-    for res, info, xs, hist in outs:
+    for (res, info, xs, hist), cfg in zip(outs, cfgs):
         assert info["workgroups"] > 0 and info["spmv_rows"] in (512, 1024, 2048)
+        if cfg.get("strategy"):
+            assert info["strategy"] == cfg["strategy"]
         for i in range(len(sysl)):
             same(res[i], xs[i], hist[i], *single[i])
-    assert outs[2][1]["tuned"] in (1, 2)
+    assert outs[2][1]["n_split"] == sum(1 for A, _ in sysl if A.n > 3000) > 0
+    assert outs[5][1]["tuned"] in (1, 2)
     for i, ((A, b), P) in enumerate(zip(sysl, op)):
         xo, info = O.cg(A, b, tol=1e-8, maxit=600, policy=P, replace_period=50, fallback=True)
         r, x, h = single[i]
@@ -124,10 +130,11 @@ def test_batched_fallback_and_budget(M):
     b = W.rhs(A.n, 32) * 1e6
     sysl = [(A, b), (W.laplacian_2d(30), W.rhs(900, 3))]
     gp = [M.Policy(kind=M.POLICY_FIXED, fixed_action=0), M.Policy(kind=M.POLICY_FIXED, fixed_action=21)]
-    outs, single = run_batch(M, sysl, gp, [dict(workgroups=2, spmv_rows=1024)], maxit=40)
-    res, info, xs, hist = outs[0]
-    for i in range(2):
-        same(res[i], xs[i], hist[i], *single[i])
+    outs, single = run_batch(M, sysl, gp, [dict(workgroups=2, spmv_rows=1024, split_rows=-1, strategy=1),
+                                           dict(spmv_rows=1024, strategy=2)], maxit=40)
+    for res, info, xs, hist in outs:
+        for i in range(2):
+            same(res[i], xs[i], hist[i], *single[i])
 
 
 def test_batched_rejects(M):
