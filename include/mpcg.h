@@ -312,6 +312,53 @@ typedef struct {
 int mpcg_train_qlearning(mpcg_policy *P, int32_t m, mpcg_matrix *const *A, const double *const *b,
                          double *const *x, const mpcg_train_desc *desc, mpcg_episode_result *out);
 
+/* ---------------------------------------------------------------- MLP trainer
+ * The MLP policy's network (16 features -> 128 -> 128 -> 64 action values,
+ * GELU) trained by fitted Q-iteration, the function-approximation form of the
+ * Q-learning update of section 4.1: per epoch the targets
+ *   y_t = r_t + gamma (1 - done_t) max_a Q_frozen(s_{t+1}, a)
+ * come from the weights frozen at the epoch's start; each batch then takes one
+ * Adam step (fp32 master weights) on mean 1/2 (Q(s_t, a_t) - y_t)^2.  The
+ * products run on bfloat16 matrix cores with fp32 accumulation.  Parameters
+ * are float[26944] in the order W1[128][16] | b1[128] | W2[128][128] | b2[128]
+ * | W3[64][128] | b3[64] (W[out][in], row-major).  Data arrays are device
+ * pointers: feat, next float[n][16], act int32[n] (0..63), rew float[n],
+ * done uint8[n].
+ */
+typedef struct mpcg_mlp mpcg_mlp;
+
+typedef struct {
+    int32_t batch;             /* samples per Adam step, a multiple of 64       */
+    int32_t epochs;            /* passes over the floor(n / batch) batches, in
+                                  the order given                                */
+    double lr, beta1, beta2, eps;   /* Adam (1e-3, 0.9, 0.999, 1e-8)            */
+    double gamma;              /* discount of the targets (section 4.1: 0.9)    */
+} mpcg_mlp_train_desc;
+
+/* Creates a network with the given initial parameters (host array), its Adam
+ * state zeroed; runs on `stream` (hipStream_t, NULL: default stream). */
+int mpcg_mlp_create(const float *params, void *stream, mpcg_mlp **out);
+int mpcg_mlp_destroy(mpcg_mlp *net);
+/* Replaces the parameters (host array) and zeroes the Adam state. */
+int mpcg_mlp_set_params(mpcg_mlp *net, const float *params);
+/* Copies the fp32 master parameters to host memory. */
+int mpcg_mlp_get_params(mpcg_mlp *net, float *params_out);
+/* logits[n][64] (device) = the training forward pass (bfloat16 matrix cores)
+ * of feat[n][16] (device) with the current weights. */
+int mpcg_mlp_forward(mpcg_mlp *net, const float *feat, int32_t n, float *logits);
+/* Gradient of the loss over one batch of B samples (B a multiple of 64;
+ * device feat, act, target float[B]) for the current weights, no update: grad
+ * (host float[26944]) and *loss (host). */
+int mpcg_mlp_grad(mpcg_mlp *net, const float *feat, const int32_t *act, const float *target, int32_t B,
+                  float *grad, float *loss);
+/* Trains on n rollouts; epoch_loss (host float[epochs], may be NULL) receives
+ * each epoch's mean batch loss. */
+int mpcg_mlp_train(mpcg_mlp *net, const float *feat, const float *next, const int32_t *act, const float *rew,
+                   const uint8_t *done, int32_t n, const mpcg_mlp_train_desc *desc, float *epoch_loss);
+/* Gives P (kind MPCG_POLICY_MLP) the network's weights for the decision path:
+ * weights rounded to bfloat16, biases fp32. */
+int mpcg_policy_set_mlp_from(mpcg_policy *P, mpcg_mlp *net);
+
 /*
  * History of the last solve, host arrays (any may be NULL):
  *   rho[cap]     relative residual rho_k, k = 0..iters (the true one where replaced)

@@ -84,6 +84,11 @@ class BatchInfo(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class MlpTrainDesc(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("gamma", C.c_double)]
+
+
 class TrainDesc(C.Structure):
     _fields_ = [("episodes", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double),
                 ("eps_start", C.c_double), ("eps_end", C.c_double), ("order", C.c_int32),
@@ -135,6 +140,14 @@ def lib():
             "mpcg_get_profile": [vp, C.POINTER(Profile)],
             "mpcg_train_qlearning": [vp, i32, vp, vp, vp, C.POINTER(TrainDesc), vp],
             "mpcg_solve_batched": [i32, vp, vp, vp, vp, vp, C.POINTER(BatchOpts), vp, C.POINTER(BatchInfo)],
+            "mpcg_mlp_create": [vp, vp, C.POINTER(vp)],
+            "mpcg_mlp_destroy": [vp],
+            "mpcg_mlp_set_params": [vp, vp],
+            "mpcg_mlp_get_params": [vp, vp],
+            "mpcg_mlp_forward": [vp, vp, i32, vp],
+            "mpcg_mlp_grad": [vp, vp, vp, vp, i32, vp, C.POINTER(C.c_float)],
+            "mpcg_mlp_train": [vp, vp, vp, vp, vp, vp, i32, C.POINTER(MlpTrainDesc), vp],
+            "mpcg_policy_set_mlp_from": [vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -260,6 +273,86 @@ class Policy:
         _check(lib().mpcg_policy_decide(self.h, m, _np_ptr(k), _np_ptr(rho), _np_ptr(stag), fp,
                                         _np_ptr(st), _np_ptr(ac)), "policy_decide")
         return st, ac
+
+
+MLP_PARAMS = 128 * 16 + 128 + 128 * 128 + 128 + 64 * 128 + 64
+MLP_SHAPES = (("W1", (128, 16)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)), ("W3", (64, 128)), ("b3", (64,)))
+
+
+def mlp_pack(w: dict) -> np.ndarray:
+    """Parameter dict -> float32[26944] in the order W1 | b1 | W2 | b2 | W3 | b3."""
+    return np.concatenate([np.asarray(w[k], dtype=np.float32).reshape(-1) for k, _ in MLP_SHAPES])
+
+
+def mlp_unpack(v) -> dict:
+    out, o = {}, 0
+    for k, shp in MLP_SHAPES:
+        size = int(np.prod(shp))
+        out[k] = np.asarray(v[o:o + size], dtype=np.float32).reshape(shp)
+        o += size
+    return out
+
+
+class Mlp:
+    """The MLP policy network with its Adam trainer (mpcg_mlp_*)."""
+
+    def __init__(self, params: dict, stream=None):
+        v = np.ascontiguousarray(mlp_pack(params))
+        h = C.c_void_p()
+        _check(lib().mpcg_mlp_create(_np_ptr(v), _stream_handle(stream), C.byref(h)), "mpcg_mlp_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            lib().mpcg_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: dict):
+        v = np.ascontiguousarray(mlp_pack(params))
+        _check(lib().mpcg_mlp_set_params(self.h, _np_ptr(v)), "mlp_set_params")
+
+    def params(self) -> dict:
+        v = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(lib().mpcg_mlp_get_params(self.h, _np_ptr(v)), "mlp_get_params")
+        return mlp_unpack(v)
+
+    def forward(self, feat):
+        """feat: float32 device tensor [n, 16] -> logits float32 device tensor [n, 64]."""
+        import torch
+
+        assert feat.is_cuda and feat.dtype == torch.float32 and feat.is_contiguous() and feat.shape[1] == 16
+        out = torch.empty((feat.shape[0], 64), dtype=torch.float32, device=feat.device)
+        _check(lib().mpcg_mlp_forward(self.h, _t_ptr(feat), feat.shape[0], _t_ptr(out)), "mlp_forward")
+        return out
+
+    def grad(self, feat, act, target):
+        """One batch's gradient (device tensors) -> (dict of float32 arrays, loss)."""
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().mpcg_mlp_grad(self.h, _t_ptr(feat), _t_ptr(act), _t_ptr(target), feat.shape[0], _np_ptr(g),
+                                   C.byref(loss)), "mlp_grad")
+        return mlp_unpack(g), loss.value
+
+    def train(self, data: dict, batch=256, epochs=1, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, gamma=0.9):
+        """data: device tensors feat, next (float32 [n,16]), act (int32), rew (float32), done (uint8)."""
+        n = int(data["act"].shape[0])
+        for k in ("feat", "next", "act", "rew", "done"):
+            assert data[k].is_cuda and data[k].is_contiguous() and data[k].shape[0] == n
+        d = MlpTrainDesc(batch, epochs, lr, beta1, beta2, eps, gamma)
+        out = np.zeros(max(epochs, 1), dtype=np.float32)
+        _check(lib().mpcg_mlp_train(self.h, _t_ptr(data["feat"]), _t_ptr(data["next"]), _t_ptr(data["act"]),
+                                    _t_ptr(data["rew"]), _t_ptr(data["done"]), n, C.byref(d), _np_ptr(out)),
+               "mlp_train")
+        return out[:epochs]
+
+    def to_policy(self, policy: "Policy"):
+        _check(lib().mpcg_policy_set_mlp_from(policy.h, self.h), "policy_set_mlp_from")
 
 
 def solve_batched(systems, tol=1e-8, maxit=1000, workgroups=0, spmv_rows=0, order=0, autotune_iters=0,

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpcg.so")
-SOURCES = ["kernels.hip", "api.hip"]
+SOURCES = ["kernels.hip", "mlp.hip", "api.hip"]
 ARCH = os.environ.get("MPCG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "launch.hpp"
+#include "mlp.hpp"
 #include "mpcg.h"
 
 using namespace mpcg;
@@ -123,7 +124,6 @@ struct mpcg_policy {
   }
 };
 
-static const int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kNAct * kMlpH + kNAct;
 
 struct mpcg_matrix {
   int n = 0, nnz = 0, nnz_pad = 0;
@@ -1236,6 +1236,214 @@ int mpcg_train_qlearning(mpcg_policy *P, int32_t m, mpcg_matrix *const *A, const
     }
   }
   return MPCG_OK;
+}
+
+// ---------------------------------------------------------------- MLP trainer
+struct mpcg_mlp {
+  hipStream_t stream = nullptr;
+  float *d_master = nullptr, *d_m = nullptr, *d_v = nullptr;
+  uint16_t *d_wb = nullptr;     // bf16 copies: current and frozen
+  float *d_bias = nullptr;      // biases: current and frozen
+  MlpWeights cur{}, frozen{};
+  float *d_part = nullptr, *d_ploss = nullptr;
+  int part_cap = 0;             // workgroups the partial buffers hold
+  float *d_target = nullptr, *d_ymax = nullptr;
+  int64_t tcap = 0;
+  float *d_grad = nullptr, *d_loss = nullptr;
+  int64_t loss_cap = 0;
+  int64_t steps = 0;            // Adam steps taken
+
+  void release() {
+    dfree(d_master); dfree(d_m); dfree(d_v); dfree(d_wb); dfree(d_bias);
+    dfree(d_part); dfree(d_ploss); dfree(d_target); dfree(d_ymax); dfree(d_grad); dfree(d_loss);
+  }
+};
+
+static void mlp_views(mpcg_mlp *N) {
+  const int nw = kMlpH * kMlpIn + kMlpH * kMlpH + kNAct * kMlpH + kMlpH * kMlpH + kNAct * kMlpH;
+  auto carve = [&](uint16_t *base, float *bias, MlpWeights &w) {
+    w.w1b = base;
+    w.w2b = w.w1b + kMlpH * kMlpIn;
+    w.w3b = w.w2b + kMlpH * kMlpH;
+    w.w2t = w.w3b + kNAct * kMlpH;
+    w.w3t = w.w2t + kMlpH * kMlpH;
+    w.b1 = bias;
+    w.b2 = w.b1 + kMlpH;
+    w.b3 = w.b2 + kMlpH;
+  };
+  carve(N->d_wb, N->d_bias, N->cur);
+  carve(N->d_wb + nw, N->d_bias + 2 * kMlpH + kNAct, N->frozen);
+}
+
+static int mlp_ensure_part(mpcg_mlp *N, int nwg) {
+  if (N->part_cap >= nwg) return MPCG_OK;
+  dfree(N->d_part);
+  dfree(N->d_ploss);
+  HIP_TRY(dmalloc(&N->d_part, (size_t)nwg * kMlpParams));
+  HIP_TRY(dmalloc(&N->d_ploss, (size_t)nwg));
+  N->part_cap = nwg;
+  return MPCG_OK;
+}
+
+int mpcg_mlp_create(const float *params, void *stream, mpcg_mlp **out) {
+  if (!params || !out) return fail(MPCG_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  mpcg_mlp *N = new (std::nothrow) mpcg_mlp();
+  if (!N) return fail(MPCG_ERR_NOMEM, "host allocation failed");
+  N->stream = (hipStream_t)stream;
+  const int nw = kMlpH * kMlpIn + kMlpH * kMlpH + kNAct * kMlpH + kMlpH * kMlpH + kNAct * kMlpH;
+  hipError_t e = dmalloc(&N->d_master, (size_t)kMlpParams);
+  if (e == hipSuccess) e = dmalloc(&N->d_m, (size_t)kMlpParams);
+  if (e == hipSuccess) e = dmalloc(&N->d_v, (size_t)kMlpParams);
+  if (e == hipSuccess) e = dmalloc(&N->d_wb, (size_t)2 * nw);
+  if (e == hipSuccess) e = dmalloc(&N->d_bias, (size_t)2 * (2 * kMlpH + kNAct));
+  if (e == hipSuccess) e = dmalloc(&N->d_grad, (size_t)kMlpParams);
+  if (e != hipSuccess) {
+    N->release();
+    delete N;
+    return fail(MPCG_ERR_NOMEM, "MLP allocation failed");
+  }
+  mlp_views(N);
+  *out = N;
+  const int rc = mpcg_mlp_set_params(N, params);
+  if (rc) {
+    N->release();
+    delete N;
+    *out = nullptr;
+  }
+  return rc;
+}
+
+int mpcg_mlp_destroy(mpcg_mlp *N) {
+  if (!N) return MPCG_OK;
+  (void)hipStreamSynchronize(N->stream);
+  N->release();
+  delete N;
+  return MPCG_OK;
+}
+
+int mpcg_mlp_set_params(mpcg_mlp *N, const float *params) {
+  if (!N || !params) return fail(MPCG_ERR_INVALID, "NULL argument");
+  for (int p = 0; p < kMlpParams; ++p)
+    if (!std::isfinite(params[p])) return fail(MPCG_ERR_INVALID, "non-finite parameter");
+  HIP_TRY(hipMemcpyAsync(N->d_master, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, N->stream));
+  HIP_TRY(hipMemsetAsync(N->d_m, 0, sizeof(float) * kMlpParams, N->stream));
+  HIP_TRY(hipMemsetAsync(N->d_v, 0, sizeof(float) * kMlpParams, N->stream));
+  launch_mlp_copies(N->cur, N->d_master, N->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(N->stream));
+  N->steps = 0;
+  return MPCG_OK;
+}
+
+int mpcg_mlp_get_params(mpcg_mlp *N, float *params) {
+  if (!N || !params) return fail(MPCG_ERR_INVALID, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(N->stream));
+  HIP_TRY(hipMemcpy(params, N->d_master, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+  return MPCG_OK;
+}
+
+int mpcg_mlp_forward(mpcg_mlp *N, const float *feat, int32_t n, float *logits) {
+  if (!N || n < 0 || (n > 0 && (!feat || !logits))) return fail(MPCG_ERR_INVALID, "bad argument");
+  launch_mlp_forward(N->cur, feat, n, logits, nullptr, nullptr, 0.0f, nullptr, nullptr, N->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(N->stream));
+  return MPCG_OK;
+}
+
+int mpcg_mlp_grad(mpcg_mlp *N, const float *feat, const int32_t *act, const float *target, int32_t B, float *grad,
+                  float *loss) {
+  if (!N || !feat || !act || !target || !grad || B <= 0 || B % 64) return fail(MPCG_ERR_INVALID, "bad argument");
+  int rc = mlp_ensure_part(N, B / 64);
+  if (rc) return rc;
+  if (!N->d_loss) {
+    HIP_TRY(dmalloc(&N->d_loss, 1));
+    N->loss_cap = 1;
+  }
+  launch_mlp_grad(N->cur, feat, act, target, 0, B, N->d_part, N->d_ploss, N->stream);
+  launch_mlp_update(MlpState{N->d_master, N->d_m, N->d_v, N->cur}, N->d_part, N->d_ploss, B / 64, 0, 0, 0.f, 0.f, 0.f,
+                    0.f, N->d_grad, N->d_loss, N->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(grad, N->d_grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, N->stream));
+  float l = 0.0f;
+  HIP_TRY(hipMemcpyAsync(&l, N->d_loss, sizeof(float), hipMemcpyDeviceToHost, N->stream));
+  HIP_TRY(hipStreamSynchronize(N->stream));
+  if (loss) *loss = l;
+  return MPCG_OK;
+}
+
+int mpcg_mlp_train(mpcg_mlp *N, const float *feat, const float *next, const int32_t *act, const float *rew,
+                   const uint8_t *done, int32_t n, const mpcg_mlp_train_desc *d, float *epoch_loss) {
+  if (!N || !d || n < 0 || (n > 0 && (!feat || !next || !act || !rew || !done)))
+    return fail(MPCG_ERR_INVALID, "bad argument");
+  if (d->batch <= 0 || d->batch % 64 || d->epochs < 0 || !(d->lr > 0.0) || !(d->beta1 >= 0.0 && d->beta1 < 1.0) ||
+      !(d->beta2 >= 0.0 && d->beta2 < 1.0) || !(d->eps > 0.0) || !(d->gamma >= 0.0 && d->gamma <= 1.0))
+    return fail(MPCG_ERR_INVALID, "bad training descriptor");
+  const int nb = n / d->batch;   // whole batches, in order
+  int rc = mlp_ensure_part(N, d->batch / 64);
+  if (rc) return rc;
+  if (N->tcap < n) {
+    dfree(N->d_target);
+    dfree(N->d_ymax);
+    HIP_TRY(dmalloc(&N->d_target, (size_t)std::max(n, 1)));
+    HIP_TRY(dmalloc(&N->d_ymax, (size_t)std::max(n, 1)));
+    N->tcap = n;
+  }
+  const int64_t nsteps = (int64_t)nb * d->epochs;
+  if (N->loss_cap < nsteps) {
+    dfree(N->d_loss);
+    HIP_TRY(dmalloc(&N->d_loss, (size_t)std::max<int64_t>(nsteps, 1)));
+    N->loss_cap = std::max<int64_t>(nsteps, 1);
+  }
+  const MlpState st{N->d_master, N->d_m, N->d_v, N->cur};
+  int64_t k = 0;
+  for (int ep = 0; ep < d->epochs; ++ep) {
+    launch_mlp_copies(N->frozen, N->d_master, N->stream);   // weights frozen for this epoch's targets
+    launch_mlp_forward(N->frozen, next, n, nullptr, rew, done, (float)d->gamma, N->d_target, N->d_ymax, N->stream);
+    for (int j = 0; j < nb; ++j, ++k) {
+      launch_mlp_grad(N->cur, feat, act, N->d_target, j * d->batch, d->batch, N->d_part, N->d_ploss, N->stream);
+      N->steps++;
+      launch_mlp_update(st, N->d_part, N->d_ploss, d->batch / 64, 1, (int)N->steps, (float)d->lr, (float)d->beta1,
+                        (float)d->beta2, (float)d->eps, nullptr, N->d_loss + k, N->stream);
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  std::vector<float> losses((size_t)std::max<int64_t>(nsteps, 1));
+  if (nsteps > 0)
+    HIP_TRY(hipMemcpyAsync(losses.data(), N->d_loss, sizeof(float) * nsteps, hipMemcpyDeviceToHost, N->stream));
+  HIP_TRY(hipStreamSynchronize(N->stream));
+  if (epoch_loss)
+    for (int ep = 0; ep < d->epochs; ++ep) {
+      double s = 0.0;
+      for (int j = 0; j < nb; ++j) s += losses[(size_t)ep * nb + j];
+      epoch_loss[ep] = nb ? (float)(s / nb) : 0.0f;
+    }
+  return MPCG_OK;
+}
+
+// Round-to-nearest-even to bfloat16 of an fp32 value (inf/nan kept).
+static float host_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) != 0x7f800000u) {
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+  }
+  float y;
+  std::memcpy(&y, &u, 4);
+  return y;
+}
+
+int mpcg_policy_set_mlp_from(mpcg_policy *P, mpcg_mlp *N) {
+  if (!P || !N) return fail(MPCG_ERR_INVALID, "NULL argument");
+  std::vector<float> p(kMlpParams);
+  int rc = mpcg_mlp_get_params(N, p.data());
+  if (rc) return rc;
+  const int o1 = kMlpH * kMlpIn, o2 = o1 + kMlpH, o3 = o2 + kMlpH * kMlpH, o4 = o3 + kMlpH, o5 = o4 + kNAct * kMlpH;
+  for (int i = 0; i < kMlpParams; ++i)
+    if (i < o1 || (i >= o2 && i < o3) || (i >= o4 && i < o5)) p[i] = host_bf16(p[i]);
+  const float *w = p.data();
+  return mpcg_policy_set_mlp(P, w, w + o1, w + o2, w + o3, w + o4, w + o5);
 }
 
 int mpcg_get_profile(mpcg_matrix *A, mpcg_profile *out) {
