@@ -185,6 +185,100 @@ def batched_experiment(args, M, W, torch) -> dict:
     return out
 
 
+MLP_FLOPS_PER_SAMPLE_EPOCH = 2 * (16 * 128 + 128 * 128 + 128 * 64) * 2 + 2 * (128 * 64 + 128 * 128 + 16 * 128 +
+                                                                             128 * 128 + 128 * 64)
+
+
+def evaluate_policies(M, W, torch, seeds, policies: dict, maxit: int, family=None) -> tuple:
+    """Solves each held-out system with every policy (fallback on); per-system rows and a summary."""
+    family = family or W.family_system
+    rows = []
+    for sd in seeds:
+        A = family(sd)
+        mm = M.Matrix(A)
+        b = torch.from_numpy(W.rhs(A.n, sd + 10000)).cuda()
+        x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        row = {"seed": sd, "name": A.name, "n": A.n, "nnz": A.nnz}
+        for lab, pol in policies.items():
+            mm.set_policy(pol)
+            mm.set_options(replace_period=50, fallback=True, profile=False)
+            x.zero_()
+            r = mm.solve(b, x, tol=1e-8, maxit=maxit)
+            row[lab] = {"status": r["status"], "iters": r["iters"], "ms": round(r["time_ms"], 3),
+                        "relres_true": r["relres_true"], "cost_sum": r["cost_sum"], "fallback_at": r["fallback_at"]}
+            if lab not in ("fp64",):
+                row[lab]["mix"] = mix_of(M, mm.history()["actions"])
+        rows.append(row)
+        log(f"[eval] {sd} {A.name}: " + ", ".join(f"{k} {row[k]['status']}/{row[k]['iters']}/{row[k]['ms']}ms"
+                                                   for k in policies))
+        mm.close()
+    summ = {}
+    for lab in policies:
+        ok = [r for r in rows if r[lab]["status"] in (0, 2)]
+        both = [r for r in ok if r["fp64"]["status"] in (0, 2)] if "fp64" in policies else []
+        summ[lab] = {"success": f"{len(ok)}/{len(rows)}",
+                     "fallbacks": sum(1 for r in rows if r[lab]["fallback_at"] >= 0),
+                     "total_ms": round(sum(r[lab]["ms"] for r in rows), 1),
+                     "total_iters": int(sum(r[lab]["iters"] for r in rows)),
+                     "total_cost": round(sum(r[lab]["cost_sum"] for r in rows), 1),
+                     "median_time_ratio_vs_fp64": round(float(np.median([r[lab]["ms"] / r["fp64"]["ms"] for r in both])), 3)
+                     if both else None}
+    return rows, summ
+
+
+def mlp_experiment(args, M, W, torch) -> dict:
+    """Learned MLP policy: rollouts logged by the solver during tabular Q-learning
+    (section 4.1) on seeded training systems, the network trained on them by
+    fitted Q-iteration on the matrix cores, then compared on held-out systems
+    with the Q-table it came from, the untrained network, fixed mixed precision
+    and fp64 CG (every policy with the fp64 fallback)."""
+    out = {"experiment": "MLP precision policy"}
+    t0 = time.time()
+    systems = build_systems(M, W, torch, range(100, 100 + args.train_systems))
+    out["train_systems"] = len(systems)
+    log(f"[mlp] {len(systems)} training systems built in {time.time() - t0:.1f} s")
+    t0 = time.time()
+    P, res = train_qtable(M, systems, args.episodes, 1000, "C1", rollouts=1_000_000)
+    roll = P.rollouts()
+    n = len(roll["act"])
+    out["qlearning"] = {"episodes": len(res), "wall_s": round(time.time() - t0, 1), "rollouts": n}
+    log(f"[mlp] Q-learning: {out['qlearning']}")
+    for mm, _, _ in systems:
+        mm.close()
+    del systems
+    perm = np.random.default_rng(2024).permutation(n)
+    data = {"feat": roll["feat"][perm], "next": roll["next"][perm], "act": roll["act"][perm].astype(np.int32),
+            "rew": roll["rew"][perm].astype(np.float32), "done": roll["done"][perm].astype(np.uint8)}
+    dd = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in data.items()}
+    p0 = M.mlp_init_params(77)
+    net = M.Mlp(p0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(dd, batch=512, epochs=args.mlp_epochs, lr=1e-3, gamma=0.9)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    used = (n // 512) * 512
+    flops = MLP_FLOPS_PER_SAMPLE_EPOCH * used * args.mlp_epochs
+    out["training"] = {"samples": used, "epochs": args.mlp_epochs, "batch": 512, "wall_s": round(dt, 3),
+                       "samples_per_s": round(used * args.mlp_epochs / dt, 0),
+                       "TFLOPs": round(flops / dt / 1e12, 3), "bf16_peak_TFLOPs": 2500.0,
+                       "epoch_loss": [round(float(l), 5) for l in losses]}
+    log(f"[mlp] training: {out['training']}")
+    mlp_pol = M.Policy(kind=M.POLICY_MLP)
+    net.to_policy(mlp_pol)
+    untrained = M.Policy(kind=M.POLICY_MLP)
+    M.Mlp(p0).to_policy(untrained)
+    greedy = M.Policy(kind=M.POLICY_QTABLE, cost="C1")
+    greedy.set_qtable(P.qtable())
+    pols = {"fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=63),
+            "fixed_mixed": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.BF16, M.FP32, M.FP32)),
+            "qtable": greedy, "mlp_untrained": untrained, "mlp": mlp_pol}
+    rows, summ = evaluate_policies(M, W, torch, range(2000, 2000 + args.heldout_systems), pols, args.eval_maxit)
+    out["heldout_summary"] = summ
+    out["heldout"] = rows
+    return out
+
+
 def qlearning_experiment(args, M, W, torch) -> dict:
     """Tabular Q-learning on seeded systems (2D/3D Laplacians and random SPD,
     n log-uniform in [1e4, 5e5], cond up to 1e8), then greedy inference on
@@ -281,6 +375,9 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="batched experiment: 512 uneven systems in one persistent launch vs sequential solves")
     ap.add_argument("--batch-systems", type=int, default=512)
+    ap.add_argument("--mlp", action="store_true",
+                    help="MLP policy experiment: rollouts from Q-learning runs, matrix-core training, held-out comparison")
+    ap.add_argument("--mlp-epochs", type=int, default=30)
     ap.add_argument("--counters", action="store_true",
                     help="short run for HBM counter collection: one plain copy of 256 MiB (the scale "
                          "reference for FETCH_SIZE / WRITE_SIZE), then one mixed solve")
@@ -314,6 +411,10 @@ def main():
     xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     pol_mixed = M.Policy(kind=M.POLICY_FIXED, fixed_action=act_mixed)
     pol_fp64 = M.Policy(kind=M.POLICY_FIXED, fixed_action=act_fp64)
+
+    if args.mlp:
+        print(json.dumps(mlp_experiment(args, M, W, torch)), flush=True)
+        return
 
     if args.batched:
         print(json.dumps(batched_experiment(args, M, W, torch)), flush=True)

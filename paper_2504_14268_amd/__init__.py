@@ -293,6 +293,17 @@ def mlp_unpack(v) -> dict:
     return out
 
 
+def mlp_init_params(seed: int) -> dict:
+    """Seeded He-normal weights (float32), zero biases."""
+    rng = np.random.default_rng(seed)
+    return dict(W1=(rng.standard_normal((128, 16)) * np.sqrt(2.0 / 16)).astype(np.float32),
+                b1=np.zeros(128, np.float32),
+                W2=(rng.standard_normal((128, 128)) * np.sqrt(2.0 / 128)).astype(np.float32),
+                b2=np.zeros(128, np.float32),
+                W3=(rng.standard_normal((64, 128)) * np.sqrt(1.0 / 128)).astype(np.float32),
+                b3=np.zeros(64, np.float32))
+
+
 class Mlp:
     """The MLP policy network with its Adam trainer (mpcg_mlp_*)."""
 
