@@ -48,12 +48,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def ka_bytes(n: int, nnz: int, fs: int, vec_bytes: int) -> int:
+def ka_bytes(n: int, nnz: int, fs: int, vec_bytes: int, idx_bytes: int = 4) -> int:
     """Algorithmic bytes of one iteration launch of KA (SpMV q = A p with the
-    p.q partial): each CSR entry once (value + int32 index), the row pointers,
-    p read once and q written once; fp16 adds the one-byte row exponents."""
+    p.q partial): each CSR entry once (value + column index: int32, or the
+    16-bit delta col - row where the matrix has them), the row pointers, p read
+    once and q written once; fp16 adds the one-byte row exponents."""
     val = {0: 2, 1: 2, 2: 4, 3: 8}[fs]
-    b = nnz * (val + 4) + 4 * (n + 1) + 2 * n * vec_bytes
+    b = nnz * (val + idx_bytes) + 4 * (n + 1) + 2 * n * vec_bytes
     if fs == 0:
         b += n
     return b
@@ -436,7 +437,8 @@ def main():
         r = m.solve(bd, xd, tol=tol, maxit=5000)
         print(json.dumps({"counters_run": True, "copy_bytes": COPY_BYTES, "iters": r["iters"],
                           "relres_true": r["relres_true"], "kernel_hash": kernel_hash(),
-                          "bytes_per_launch_ka": ka_bytes(A.n, A.nnz, M.BF16, 4)}), flush=True)
+                          "bytes_per_launch_ka": ka_bytes(A.n, A.nnz, M.BF16, 4, 2 if m.info()["index16"] else 4)}),
+              flush=True)
         return
 
     def solve(pol, R, maxit=5000, profile=False):
@@ -481,8 +483,9 @@ def main():
     k1_64_us = prof64["ka_iter_ms"] / prof64["n_iter_slots"] * 1e3
     k2_64_us = prof64["kb_iter_ms"] / prof64["n_iter_slots"] * 1e3
     k3_64_us = prof64["kx_iter_ms"] / prof64["n_iter_slots"] * 1e3
-    bytes_k1 = ka_bytes(A.n, A.nnz, M.BF16, 4)
-    bytes_k1_64 = ka_bytes(A.n, A.nnz, M.FP64, 8)
+    idx_bytes = 2 if m.info()["index16"] else 4
+    bytes_k1 = ka_bytes(A.n, A.nnz, M.BF16, 4, idx_bytes)
+    bytes_k1_64 = ka_bytes(A.n, A.nnz, M.FP64, 8, idx_bytes)
     bytes_k2 = 6 * A.n * 4      # p, q, r, x_lo read; r, x_lo written
     bytes_k2_64 = 6 * A.n * 8
     bytes_k3 = 3 * A.n * 4      # p, r read; p written
@@ -525,7 +528,8 @@ def main():
         "setup_ms": round(setup_ms, 1),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_a: CSR SpMV (bf16 values, fp32 accumulation) with the fused p.q partial",
+            "kernel": "k_a: CSR SpMV (bf16 values, " + ("16-bit column deltas" if idx_bytes == 2 else "int32 columns")
+                      + ", fp32 accumulation) with the fused p.q partial",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -112,7 +112,10 @@ typedef struct {
     int32_t spmv_rows;         /* rows per SpMV workgroup: 512, 1024 or 2048
                                   (0: chosen from n); results do not depend
                                   on it                                          */
-    int32_t reserved;
+    int32_t index16;           /* 0: the SpMV reads 16-bit column deltas
+                                  (col - row) when every one fits, which
+                                  mpcg_create_csr detects; -1: always the
+                                  32-bit indices; results do not depend on it */
 } mpcg_solve_opts;
 
 /* Per-kernel timing of the last solve made with opts.profile = 1.  One CG
@@ -165,6 +168,16 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
 
 /* Frees the handle and everything it owns.  NULL is a no-op. */
 int mpcg_destroy(mpcg_matrix *A);
+
+typedef struct {
+    int64_t n, nnz;
+    int32_t index16;           /* 1: 16-bit column deltas are stored (every
+                                  |col - row| <= 32767)                          */
+    int32_t reserved;
+} mpcg_matrix_info;
+
+/* Sizes and storage choices of a matrix handle (host struct). */
+int mpcg_get_info(mpcg_matrix *A, mpcg_matrix_info *info);
 
 /* Copies the shadows to host arrays: float[nnz], uint16 bf16 bits[nnz],
  * uint16 fp16 bits[nnz] (row-scaled values), int8 row exponents[n]. */

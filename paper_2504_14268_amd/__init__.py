@@ -46,7 +46,7 @@ class PolicyDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("replace_period", C.c_int32), ("fallback", C.c_int32),
                 ("chunk", C.c_int32), ("profile", C.c_int32),
-                ("spmv_rows", C.c_int32), ("reserved", C.c_int32)]
+                ("spmv_rows", C.c_int32), ("index16", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -58,6 +58,10 @@ class Profile(C.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class MatrixInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("index16", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -117,6 +121,7 @@ def lib():
         sig = {
             "mpcg_create_csr": [i64, i64, vp, vp, vp, C.c_int, vp, C.POINTER(vp)],
             "mpcg_destroy": [vp],
+            "mpcg_get_info": [vp, C.POINTER(MatrixInfo)],
             "mpcg_get_shadows": [vp, vp, vp, vp, vp],
             "mpcg_policy_create": [C.POINTER(PolicyDesc), C.POINTER(vp)],
             "mpcg_policy_destroy": [vp],
@@ -430,12 +435,17 @@ class Matrix:
         except Exception:
             pass
 
+    def info(self) -> dict:
+        i = MatrixInfo()
+        _check(lib().mpcg_get_info(self.h, C.byref(i)), "get_info")
+        return {"n": i.n, "nnz": i.nnz, "index16": bool(i.index16)}
+
     def set_policy(self, policy: Policy | None):
         _check(lib().mpcg_set_policy(self.h, policy.h if policy is not None else None), "set_policy")
         self.policy = policy
 
-    def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False, spmv_rows=0):
-        o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, 0)
+    def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False, spmv_rows=0, index16=0):
+        o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, index16)
         _check(lib().mpcg_set_options(self.h, C.byref(o)), "set_options")
 
     def solve(self, b, x, tol=1e-8, maxit=1000) -> dict:

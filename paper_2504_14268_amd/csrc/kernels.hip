@@ -835,49 +835,73 @@ __device__ __forceinline__ double group_tree(int fd, int grows, const double (&t
 }
 
 // Prefetch of one window: up to two 8-entry chunks per thread, held in
-// registers (values in their storage format, column indices).
-template <int FS, int NCH>
+// registers (values in their storage format; column indices as int32, or as
+// 16-bit deltas col - row when DC, one int4 per chunk).
+template <int FS, int NCH, bool DC>
 __device__ __forceinline__ void win_load(const Mat &A, int wb, int we, RawVals<FS> &v0, RawVals<FS> &v1,
                                          int4 &c0a, int4 &c0b, int4 &c1a, int4 &c1b) {
   const int c0 = wb + threadIdx.x * 8;
   if (c0 < we) {
     raw_load<FS>(A, c0, v0);
-    c0a = *(const int4 *)(A.ci + c0);
-    c0b = *(const int4 *)(A.ci + c0 + 4);
+    if constexpr (DC) {
+      c0a = *(const int4 *)(A.dc + c0);
+    } else {
+      c0a = *(const int4 *)(A.ci + c0);
+      c0b = *(const int4 *)(A.ci + c0 + 4);
+    }
   }
   if constexpr (NCH == 2) {
     const int c1 = c0 + kVecBlock;
     if (c1 < we) {
       raw_load<FS>(A, c1, v1);
-      c1a = *(const int4 *)(A.ci + c1);
-      c1b = *(const int4 *)(A.ci + c1 + 4);
+      if constexpr (DC) {
+        c1a = *(const int4 *)(A.dc + c1);
+      } else {
+        c1a = *(const int4 *)(A.ci + c1);
+        c1b = *(const int4 *)(A.ci + c1 + 4);
+      }
     }
   }
 }
 
-template <int FS, int NCH>
+template <int FS, int NCH, bool DC>
 __device__ __forceinline__ void win_store(int wb, int we, const RawVals<FS> &v0, const RawVals<FS> &v1,
                                           int4 c0a, int4 c0b, int4 c1a, int4 c1b,
-                                          typename LdsWin<FS>::type *lv, int *lc) {
+                                          typename LdsWin<FS>::type *lv, void *lc) {
   const int o0 = threadIdx.x * 8;
   if (wb + o0 < we) {
     raw_to_lds<FS>(v0, lv + o0);
-    *(int4 *)(lc + o0) = c0a;
-    *(int4 *)(lc + o0 + 4) = c0b;
+    if constexpr (DC) {
+      *(int4 *)((int16_t *)lc + o0) = c0a;
+    } else {
+      *(int4 *)((int *)lc + o0) = c0a;
+      *(int4 *)((int *)lc + o0 + 4) = c0b;
+    }
   }
   if constexpr (NCH == 2) {
     const int o1 = o0 + kVecBlock;
     if (wb + o1 < we) {
       raw_to_lds<FS>(v1, lv + o1);
-      *(int4 *)(lc + o1) = c1a;
-      *(int4 *)(lc + o1 + 4) = c1b;
+      if constexpr (DC) {
+        *(int4 *)((int16_t *)lc + o1) = c1a;
+      } else {
+        *(int4 *)((int *)lc + o1) = c1a;
+        *(int4 *)((int *)lc + o1 + 4) = c1b;
+      }
     }
   }
 }
 
+// Column of window entry e of a row `row`: the stored index, or row + delta.
+template <bool DC>
+__device__ __forceinline__ int win_col(const void *lc, int e, int row) {
+  if constexpr (DC) return row + (int)((const int16_t *)lc)[e];
+  else return ((const int *)lc)[e];
+}
+
 // pre(sb) runs when sub-block sb starts (own-row loads), epi(sb, acc) when its
 // rows are complete.  Both are called by every thread (block-uniform).
-template <int FS, typename G, typename Pre, typename Epi>
+template <int FS, bool DC, typename G, typename Pre, typename Epi>
 __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0, int grows, void *lds_raw,
                                            Pre &&pre, Epi &&epi) {
   using Acc = typename AccT<FS>::type;
@@ -887,7 +911,7 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
   static_assert(NCH == 1 || NCH == 2, "window of one or two chunks per thread");
   static_assert(CAP * (sizeof(L) + 4) <= kLdsWinBytes, "window fits its LDS");
   L *lv = (L *)lds_raw;
-  int *lc = (int *)(lv + CAP);
+  void *lc = (void *)(lv + CAP);
   int *lrp = (int *)((char *)lds_raw + kLdsWinBytes);
   const int tid = threadIdx.x;
   for (int i = tid; i <= grows; i += kBlock) lrp[i] = A.rp[g0 + i];
@@ -898,9 +922,9 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
   int sb = 0;
   int ke = lrp[min(kKaRows, grows)];
   int wb = lrp[0] & ~7;
-  win_load<FS, NCH>(A, wb, min(wb + CAP, ke), v0, v1, c0a, c0b, c1a, c1b);
+  win_load<FS, NCH, DC>(A, wb, min(wb + CAP, ke), v0, v1, c0a, c0b, c1a, c1b);
   Acc acc[kRPT];
-  int my_s[kRPT], my_e[kRPT];
+  int my_s[kRPT], my_e[kRPT], my_row[kRPT];
   auto rows_of = [&](int s) {
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
@@ -908,6 +932,7 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
       acc[j] = (Acc)0;
       my_s[j] = 0;
       my_e[j] = 0;
+      my_row[j] = g0 + lr;
       if (lr < grows) {
         my_s[j] = lrp[lr];
         my_e[j] = lrp[lr + 1];
@@ -918,7 +943,7 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
   pre(0);
   while (true) {
     const int we = min(wb + CAP, ke);
-    win_store<FS, NCH>(wb, we, v0, v1, c0a, c0b, c1a, c1b, lv, lc);
+    win_store<FS, NCH, DC>(wb, we, v0, v1, c0a, c0b, c1a, c1b, lv, lc);
     __syncthreads();
     // the next window: the rest of this sub-block, or the start of the next one
     int nsb_ = sb, nwb = wb + CAP, nke = ke;
@@ -954,12 +979,12 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
           for (int u = 0; u < 8; ++u) {
             if (u < cnt[j]) {
               vv[j][u] = lds_widen<FS>(lv[kk - wb + u]);
-              xv[j][u] = gather.template get<Acc>(lc[kk - wb + u]);
+              xv[j][u] = gather.template get<Acc>(win_col<DC>(lc, kk - wb + u, my_row[j]));
             }
           }
         }
         if (pf) {
-          win_load<FS, NCH>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+          win_load<FS, NCH, DC>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
           pf = false;
         }
 #pragma unroll
@@ -980,11 +1005,11 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
           for (int u = 0; u < 8; ++u) {
             if (u < cnt) {
               vv[u] = lds_widen<FS>(lv[kk - wb + u]);
-              xv[u] = gather.template get<Acc>(lc[kk - wb + u]);
+              xv[u] = gather.template get<Acc>(win_col<DC>(lc, kk - wb + u, my_row[j]));
             }
           }
           if (pf) {
-            win_load<FS, NCH>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+            win_load<FS, NCH, DC>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
             pf = false;
           }
 #pragma unroll
@@ -993,7 +1018,7 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
         }
       }
     }
-    if (pf) win_load<FS, NCH>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+    if (pf) win_load<FS, NCH, DC>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
     if (we >= ke) {
       epi(sb, acc);
       if (nsb_ >= nsb) break;
@@ -1055,7 +1080,8 @@ __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, voi
     t[2] = sb == 2 ? s : t[2];
     t[3] = sb == 3 ? s : t[3];
   };
-  spmv_group<FS>(a.A, GatherPlain<V>{p}, g0, grows, lds, pre, epi);
+  if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{p}, g0, grows, lds, pre, epi);
+  else spmv_group<FS, false>(a.A, GatherPlain<V>{p}, g0, grows, lds, pre, epi);
   if (threadIdx.x == 0) a.part1[g] = group_tree(fd, a.grows, t);
 }
 
@@ -1100,7 +1126,8 @@ __device__ __forceinline__ void ka_residual(const KArgs &a, const Ctl &S, int g,
     t[2] = sb == 2 ? s : t[2];
     t[3] = sb == 3 ? s : t[3];
   };
-  spmv_group<FP64>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pre, epi);
+  if (a.A.dc) spmv_group<FP64, true>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pre, epi);
+  else spmv_group<FP64, false>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pre, epi);
   if (threadIdx.x == 0) a.part1[g] = group_tree(FP64, a.grows, t);
 }
 
@@ -1624,6 +1651,28 @@ __global__ __launch_bounds__(kBlock) void k_modes_lock(const BatchSys *sys, cons
                                                         int32_t *modes) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < nact) modes[i] = sys[act[i]].a.ctl[0].mode;
+}
+
+// ---------------------------------------------------------------------------
+// setup: 16-bit column deltas dc[k] = col[k] - row, thread per row; *bad = 1
+// when a delta leaves the int16 range (the caller then drops the array).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_dcol(int n, const int *rp, const int *ci, int16_t *dc, int *bad) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int d = ci[k] - i;
+    if (d < -32768 || d > 32767) {
+      *bad = 1;
+      dc[k] = 0;
+    } else {
+      dc[k] = (int16_t)d;
+    }
+  }
+}
+
+void launch_dcol(int n, const int *rp, const int *ci, int16_t *dc, int *bad, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_dcol, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, rp, ci, dc, bad);
 }
 
 // ---------------------------------------------------------------------------

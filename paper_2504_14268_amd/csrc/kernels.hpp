@@ -15,6 +15,7 @@ constexpr int kMlpIn = 16, kMlpH = 128, kNAct = 64;
 struct Mat {
   int n, nnz;
   const int *rp, *ci;
+  const int16_t *dc;          // col - row as int16 when every row fits, else NULL
   const double *v64;
   const float *v32;
   const uint16_t *vbf, *vh;   // bf16 bits, fp16 bits (row-scaled)

@@ -197,3 +197,26 @@ def test_run_twice_identical(M):
     assert np.array_equal(x1, x2) and np.array_equal(h1["rho"], h2["rho"])
     r1.pop("time_ms"); r2.pop("time_ms")
     assert r1 == r2
+
+
+def test_index16_equals_index32(M):
+    """16-bit column deltas change only the bytes read: same history and x."""
+    import torch
+
+    A = W.laplacian_3d(24)
+    b = W.rhs(A.n, 8)
+    m = M.Matrix(A)
+    assert m.info()["index16"]
+    assert not M.Matrix(W.random_spd(70000, 3, 1.0)).info()["index16"]
+    out = []
+    for idx in (0, -1):
+        m.set_policy(M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.FP16, M.FP32, M.FP32)))
+        m.set_options(replace_period=50, fallback=False, index16=idx)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        r = m.solve(torch.from_numpy(b).cuda(), x, tol=1e-8, maxit=500)
+        out.append((r, x.cpu().numpy(), m.history()))
+    (r1, x1, h1), (r2, x2, h2) = out
+    assert r1["iters"] == r2["iters"] and np.array_equal(x1, x2) and np.array_equal(h1["rho"], h2["rho"])
+    xo, info = O.cg(A, b, tol=1e-8, maxit=500, policy=O.OraclePolicy(fixed_action=M.action(M.FP16, M.FP32, M.FP32)),
+                    replace_period=50)
+    assert_same(x1, r1, h1, xo, info)
