@@ -268,6 +268,28 @@ __device__ __forceinline__ double reduce_partials_rt(int fd, const double *part,
   return fd == FP64 ? partials_total<double>(part, P) : partials_total<float>(part, P);
 }
 
+// Pairwise total of at most kVecBlock partials already loaded by the block
+// (thread t holds partials 8t .. 8t+7, zero past the end): the same tree as
+// reduce_partials for one segment.
+template <typename A>
+__device__ __forceinline__ double tree_preloaded(const double (&pv)[8]) {
+  A l[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) l[j] = (A)pv[j];
+  return (double)block_tree(tree8(l));
+}
+
+__device__ __forceinline__ double tree_preloaded_rt(int fd, const double (&pv)[8]) {
+  return fd == FP64 ? tree_preloaded<double>(pv) : tree_preloaded<float>(pv);
+}
+
+// Thread t's 8 partials of part[0..P) (P <= kVecBlock), zero past the end.
+__device__ __forceinline__ void preload_partials(const double *part, int P, double (&pv)[8]) {
+  const int base = threadIdx.x * 8;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) pv[j] = base + j < P ? part[base + j] : 0.0;
+}
+
 // Sum of eight consecutive sibling subtrees in the accumulation format of fd.
 __device__ __forceinline__ double tree8_rt(int fd, const double (&s)[8]) {
   if (fd == FP64) return tree8(s);
@@ -488,8 +510,11 @@ __device__ __forceinline__ int init_t0(const Sx &a, double s64, float *s_feat) {
     return 0;
   }
   c->sigma = s64;
-  const int stag = (k >= P->w_stag) && (rt >= a.h.rho[k - P->w_stag]);
-  const int s = policy_state(P, k, rt, stag);
+  // the state (and its stagnation flag, a history read) feeds only learned
+  // policies and rollouts
+  const bool need_state = FULL || P->kind != POL_FIXED;
+  const int stag = need_state && (k >= P->w_stag) && (rt >= a.h.rho[k - P->w_stag]);
+  const int s = need_state ? policy_state(P, k, rt, stag) : 0;
   c->s = s;
   if constexpr (FULL)
     if (P->kind == POL_MLP || P->roll_cap > 0) mlp_features(P, k, a.h.rho, stag, rt, c->prev_action, c->feat);
@@ -529,7 +554,8 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
     if (!isfinite(beta)) broke = true;
   }
   int stag = 0, s_next = s;
-  if (!broke) {
+  const bool need_state = FULL || P->kind != POL_FIXED;
+  if (!broke && need_state) {
     stag = (k >= P->w_stag) && (rho >= a.h.rho[k - P->w_stag]);
     s_next = policy_state(P, k, rho, stag);
     if (want_feat) mlp_features(P, k, a.h.rho, stag, c->last_true, act, c->feat_next);
@@ -669,11 +695,11 @@ __device__ __forceinline__ void replace_block(const Sx &a, double s64) {
 // Before KX: the end of an iteration (KB's sigma'): replacement test, then
 // beta, policy update and next action.
 template <bool FULL>
-__device__ __forceinline__ void step_x(const Sx &x, const KArgs &a) {
+__device__ __forceinline__ void step_x(const Sx &x, const KArgs &a, const double (&pre)[8], bool have_pre) {
   Ctl *c = x.ctl;
   if (c->mode == M_DONE || !c->pend_sigma) return;
   const int fd = (c->action >> 2) & 3;
-  const double sig = reduce_partials_rt(fd, a.part2, a.P2);
+  const double sig = have_pre ? tree_preloaded_rt(fd, pre) : reduce_partials_rt(fd, a.part2, a.P2);
   __shared__ int s_fin;
   if (threadIdx.x == 0) {
     c->pend_sigma = 0;
@@ -697,15 +723,21 @@ __device__ __forceinline__ void step_x(const Sx &x, const KArgs &a) {
   __syncthreads();
 }
 
+template <bool FULL>
+__device__ __forceinline__ void step_x(const Sx &x, const KArgs &a) {
+  const double none[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  step_x<FULL>(x, a, none, false);
+}
+
 // Before KB: KA's partials -- nu (alpha, breakdown) after an iteration, the
 // residual norm after a start, replacement or final check.
 template <bool FULL>
-__device__ __forceinline__ void step_b(const Sx &x, const KArgs &a) {
+__device__ __forceinline__ void step_b(const Sx &x, const KArgs &a, const double (&pre)[8], bool have_pre) {
   Ctl *c = x.ctl;
   const int la = c->mode;   // what KA has just executed
   if (la == M_ITER) {
     const int fd = (c->action >> 2) & 3;
-    const double nu = reduce_partials_rt(fd, a.part1, a.P1);
+    const double nu = have_pre ? tree_preloaded_rt(fd, pre) : reduce_partials_rt(fd, a.part1, a.P1);
     const double alpha = c->sigma / nu;
     if (!(nu > 0.0 && isfinite(nu)) || !isfinite(alpha)) {
       finish_block<FULL>(x, false, true, false, false);
@@ -736,7 +768,7 @@ __device__ __forceinline__ void step_b(const Sx &x, const KArgs &a) {
         return;
       }
     }
-    const double s64 = partials_total<double>(a.part1, a.P1);
+    const double s64 = have_pre ? tree_preloaded<double>(pre) : partials_total<double>(a.part1, a.P1);
     if (la == M_INIT) {
       init_block<FULL>(x, s64);
     } else if (la == M_REPLACE) {
@@ -751,6 +783,12 @@ __device__ __forceinline__ void step_b(const Sx &x, const KArgs &a) {
     c->b_op = B_NONE;
   }
   __syncthreads();
+}
+
+template <bool FULL>
+__device__ __forceinline__ void step_b(const Sx &x, const KArgs &a) {
+  const double none[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  step_b<FULL>(x, a, none, false);
 }
 
 __device__ __forceinline__ void copy_words(void *dst, const void *src, int bytes) {
@@ -1338,14 +1376,18 @@ __device__ __forceinline__ void kb_commit(Ctl &S, int bop, bool fold_now) {
 }
 
 // KB's work on vector block blk of one system; block 0 commits the state.
+// The step's partials are loaded together with the control block.
 __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
+  double pre[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bool fast = a.P1 <= kVecBlock;
+  if (fast) preload_partials(a.part1, a.P1, pre);
   copy_words(&S, &a.ctl[0], sizeof(Ctl));
   copy_words(&SP, a.pol, sizeof(PolicyDev));
   __syncthreads();
   const Sx x{&S, &SP, a.h, blk == 0};
-  if (!S.step_done) step_b<false>(x, a);
+  if (!S.step_done) step_b<false>(x, a, pre, fast);
   const int bop = S.b_op;
   const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
   kb_work(a, S, bop, fold_now, blk);
@@ -1358,16 +1400,62 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
 }
 
 // KX's work on vector block blk: end-of-iteration step, then the pending
-// elementwise operation; block 0 commits the state.
+// elementwise operation; block 0 commits the state.  The partials come with
+// the control block, and the direction update's operands are issued before
+// the step's arithmetic, so the step's latency overlaps the vector loads.
+template <int TIER>
+__device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S, int blk, const double (&pre)[8],
+                                            bool have_pre) {
+  using V = typename TierT<TIER>::type;
+  const int n = a.A.n;
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
+  const bool full = base + 8 <= n;
+  V pv[8], rv[8];
+  __builtin_amdgcn_sched_barrier(0);
+  if (full) {
+    if constexpr (TIER) { load8(a.v.p64 + base, pv); load8(a.v.r64 + base, rv); }
+    else { load8(a.v.p32 + base, pv); load8(a.v.r32 + base, rv); }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  step_x<false>(x, a, pre, have_pre);
+  if (S.k3op == K3_XPAY && !S.k3switch && full) {
+    if constexpr (TIER) {
+      const double beta = S.beta;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) pv[j] = __builtin_fma(beta, pv[j], rv[j]);
+      store8(a.v.p64 + base, pv);
+    } else {
+      const int fa = S.k3_fa;
+      const float bf = (float)S.beta;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float t = __builtin_fmaf(bf, pv[j], rv[j]);
+        pv[j] = fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
+      }
+      store8(a.v.p32 + base, pv);
+    }
+  } else {
+    exec_elementwise(a, S, blk);
+  }
+}
+
 __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
+  double pre[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bool fast = a.P2 <= kVecBlock;
+  if (fast) preload_partials(a.part2, a.P2, pre);
   copy_words(&S, &a.ctl[1], sizeof(Ctl));
   copy_words(&SP, a.pol, sizeof(PolicyDev));
   __syncthreads();
   const Sx x{&S, &SP, a.h, blk == 0};
-  if (!S.step_done) step_x<false>(x, a);
-  exec_elementwise(a, S, blk);
+  if (!S.step_done && S.pend_sigma) {
+    if (S.tier) kx_iter_pre<1>(a, x, S, blk, pre, fast);
+    else kx_iter_pre<0>(a, x, S, blk, pre, fast);
+  } else {
+    if (!S.step_done) step_x<false>(x, a, pre, fast);
+    exec_elementwise(a, S, blk);
+  }
   if (blk == 0) {   // commit the state after this kernel for the next KA and KB
     __syncthreads();
     if (threadIdx.x == 0) {
