@@ -220,3 +220,26 @@ def test_index16_equals_index32(M):
     xo, info = O.cg(A, b, tol=1e-8, maxit=500, policy=O.OraclePolicy(fixed_action=M.action(M.FP16, M.FP32, M.FP32)),
                     replace_period=50)
     assert_same(x1, r1, h1, xo, info)
+
+
+@pytest.mark.parametrize("which", ["lap3d_128", "rspd_1M"])
+def test_full_size_first_iterations(M, which):
+    """At the benchmark's full sizes and launch configuration: the first
+    iterations (start, three CG steps, final true residual) equal the oracle's
+    bit for bit, and a full SpMV in the benchmark's format matches too."""
+    import torch
+
+    if which == "lap3d_128":
+        A, b = W.laplacian_3d(128), W.rhs(128 ** 3, 2)
+    else:
+        A = W.random_spd(1_000_000, 3, W.spread_for_kappa(1e6))
+        b = W.rhs(A.n, 4)
+    act = M.action(M.BF16, M.FP32, M.FP32)
+    x, res, h = gpu_solve(M, A, b, maxit=3, policy=M.Policy(kind=M.POLICY_FIXED, fixed_action=act), R=50)
+    xo, info = O.cg(A, b, tol=1e-8, maxit=3, policy=O.OraclePolicy(fixed_action=act), replace_period=50)
+    assert_same(x, res, h, xo, info)
+    m = M.Matrix(A)
+    p = np.random.default_rng(5).standard_normal(A.n).astype(np.float32)
+    q = torch.empty(A.n, dtype=torch.float32, device="cuda")
+    m.op_spmv(M.BF16, 0, torch.from_numpy(p).cuda(), q)
+    assert np.array_equal(q.cpu().numpy(), O.spmv(A, p.astype(np.float64), O.BF16, False).astype(np.float32))
