@@ -130,6 +130,7 @@ struct mpcg_matrix {
   hipStream_t stream = nullptr;
   int *d_rp = nullptr, *d_ci = nullptr;
   int16_t *d_dc = nullptr;     // 16-bit column deltas, when every row fits
+  uint32_t *d_pbf = nullptr, *d_ph = nullptr;   // with d_dc: interleaved 16-bit value | delta
   double *d_v64 = nullptr;
   float *d_v32 = nullptr;
   uint16_t *d_vbf = nullptr, *d_vh = nullptr;
@@ -170,6 +171,8 @@ struct mpcg_matrix {
     m.rp = d_rp;
     m.ci = d_ci;
     m.dc = d_dc;
+    m.pbf = d_pbf;
+    m.ph = d_ph;
     m.v64 = d_v64;
     m.v32 = d_v32;
     m.vbf = d_vbf;
@@ -179,7 +182,7 @@ struct mpcg_matrix {
   }
 
   void release() {
-    dfree(d_rp); dfree(d_ci); dfree(d_dc); dfree(d_v64); dfree(d_v32); dfree(d_vbf); dfree(d_vh); dfree(d_rexp);
+    dfree(d_rp); dfree(d_ci); dfree(d_dc); dfree(d_pbf); dfree(d_ph); dfree(d_v64); dfree(d_v32); dfree(d_vbf); dfree(d_vh); dfree(d_rexp);
     dfree(d_xhi); dfree(d_r32); dfree(d_p32); dfree(d_q32); dfree(d_xlo32);
     dfree(d_r64); dfree(d_p64); dfree(d_q64); dfree(d_xlo64);
     dfree(d_part0); dfree(d_part1); dfree(d_part2); dfree(d_scalar); dfree(d_ctl); dfree(d_pol);
@@ -310,7 +313,11 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
   a.part0 = A->d_part0;
   a.part1 = A->d_part1;
   a.part2 = A->d_part2;
-  if (A->opts.index16 < 0) a.A.dc = nullptr;   // 32-bit indices requested
+  if (A->opts.index16 < 0) {   // 32-bit indices requested
+    a.A.dc = nullptr;
+    a.A.pbf = nullptr;
+    a.A.ph = nullptr;
+  }
   a.grows = spmv_group_rows(A->n, A->opts.spmv_rows);
   a.P1 = (A->n + a.grows - 1) / a.grows;
   a.G1 = round_up(a.P1, 8);
@@ -429,6 +436,13 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
     TRY_A(hipMemcpyAsync(&bad, A->d_scalar, sizeof(int), hipMemcpyDeviceToHost, A->stream));
     TRY_A(hipStreamSynchronize(A->stream));
     if (bad) dfree(A->d_dc);
+  }
+  if (A->d_dc) {
+    TRY_A(dmalloc(&A->d_pbf, np));
+    TRY_A(dmalloc(&A->d_ph, np));
+    launch_pack16((int)np, A->d_vbf, A->d_dc, A->d_pbf, A->stream);
+    launch_pack16((int)np, A->d_vh, A->d_dc, A->d_ph, A->stream);
+    TRY_A(hipGetLastError());
   }
   TRY_A(dmalloc(&A->d_ctl, 2));
   TRY_A(dmalloc(&A->d_pol, 1));

@@ -879,6 +879,22 @@ template <int FS, int NCH, bool DC>
 __device__ __forceinline__ void win_load(const Mat &A, int wb, int we, RawVals<FS> &v0, RawVals<FS> &v1,
                                          int4 &c0a, int4 &c0b, int4 &c1a, int4 &c1b) {
   const int c0 = wb + threadIdx.x * 8;
+  if constexpr (DC && (FS == BF16 || FS == FP16)) {
+    // interleaved value | delta words: 32 bytes per 8 entries, one stream
+    const uint32_t *pk = FS == BF16 ? A.pbf : A.ph;
+    if (c0 < we) {
+      c0a = *(const int4 *)(pk + c0);
+      c0b = *(const int4 *)(pk + c0 + 4);
+    }
+    if constexpr (NCH == 2) {
+      const int c1 = c0 + kVecBlock;
+      if (c1 < we) {
+        c1a = *(const int4 *)(pk + c1);
+        c1b = *(const int4 *)(pk + c1 + 4);
+      }
+    }
+    return;
+  }
   if (c0 < we) {
     raw_load<FS>(A, c0, v0);
     if constexpr (DC) {
@@ -907,6 +923,21 @@ __device__ __forceinline__ void win_store(int wb, int we, const RawVals<FS> &v0,
                                           int4 c0a, int4 c0b, int4 c1a, int4 c1b,
                                           typename LdsWin<FS>::type *lv, void *lc) {
   const int o0 = threadIdx.x * 8;
+  if constexpr (DC && (FS == BF16 || FS == FP16)) {
+    uint32_t *lp = (uint32_t *)lv;   // the interleaved words as they are
+    if (wb + o0 < we) {
+      *(int4 *)(lp + o0) = c0a;
+      *(int4 *)(lp + o0 + 4) = c0b;
+    }
+    if constexpr (NCH == 2) {
+      const int o1 = o0 + kVecBlock;
+      if (wb + o1 < we) {
+        *(int4 *)(lp + o1) = c1a;
+        *(int4 *)(lp + o1 + 4) = c1b;
+      }
+    }
+    return;
+  }
   if (wb + o0 < we) {
     raw_to_lds<FS>(v0, lv + o0);
     if constexpr (DC) {
@@ -946,10 +977,12 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
   using L = typename LdsWin<FS>::type;
   constexpr int CAP = LdsWin<FS>::cap;
   constexpr int NCH = CAP / kVecBlock;
+  constexpr bool PACK = DC && (FS == BF16 || FS == FP16);   // value | delta << 16 words
   static_assert(NCH == 1 || NCH == 2, "window of one or two chunks per thread");
   static_assert(CAP * (sizeof(L) + 4) <= kLdsWinBytes, "window fits its LDS");
   L *lv = (L *)lds_raw;
   void *lc = (void *)(lv + CAP);
+  const uint32_t *lp = (const uint32_t *)lds_raw;
   int *lrp = (int *)((char *)lds_raw + kLdsWinBytes);
   const int tid = threadIdx.x;
   for (int i = tid; i <= grows; i += kBlock) lrp[i] = A.rp[g0 + i];
@@ -1016,8 +1049,14 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             if (u < cnt[j]) {
-              vv[j][u] = lds_widen<FS>(lv[kk - wb + u]);
-              xv[j][u] = gather.template get<Acc>(win_col<DC>(lc, kk - wb + u, my_row[j]));
+              if constexpr (PACK) {
+                const uint32_t e = lp[kk - wb + u];
+                vv[j][u] = lds_widen<FS>((L)(e & 0xffffu));
+                xv[j][u] = gather.template get<Acc>(my_row[j] + (int)(int16_t)(e >> 16));
+              } else {
+                vv[j][u] = lds_widen<FS>(lv[kk - wb + u]);
+                xv[j][u] = gather.template get<Acc>(win_col<DC>(lc, kk - wb + u, my_row[j]));
+              }
             }
           }
         }
@@ -1757,6 +1796,16 @@ __global__ __launch_bounds__(kBlock) void k_dcol(int n, const int *rp, const int
       dc[k] = (int16_t)d;
     }
   }
+}
+
+// Interleaved value | delta << 16 words of a 16-bit shadow (entries in [0, np)).
+__global__ __launch_bounds__(kBlock) void k_pack16(int np, const uint16_t *v, const int16_t *dc, uint32_t *out) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < np) out[k] = (uint32_t)v[k] | ((uint32_t)(uint16_t)dc[k] << 16);
+}
+
+void launch_pack16(int np, const uint16_t *v, const int16_t *dc, uint32_t *out, hipStream_t s) {
+  if (np > 0) hipLaunchKernelGGL(k_pack16, dim3((np + kBlock - 1) / kBlock), dim3(kBlock), 0, s, np, v, dc, out);
 }
 
 void launch_dcol(int n, const int *rp, const int *ci, int16_t *dc, int *bad, hipStream_t s) {

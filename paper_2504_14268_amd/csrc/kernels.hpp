@@ -16,6 +16,7 @@ struct Mat {
   int n, nnz;
   const int *rp, *ci;
   const int16_t *dc;          // col - row as int16 when every row fits, else NULL
+  const uint32_t *pbf, *ph;   // with dc: bf16 / fp16 value | delta << 16 per entry
   const double *v64;
   const float *v32;
   const uint16_t *vbf, *vh;   // bf16 bits, fp16 bits (row-scaled)

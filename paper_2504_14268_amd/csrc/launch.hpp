@@ -20,6 +20,7 @@ void launch_lock_start(const BatchSys *sys, const SysBlk *tvb, int nvb, hipStrea
 void launch_lock_finish(const BatchSys *sys, const SysBlk *tka, int nka, const SysBlk *tvb, int nvb,
                         const int32_t *act, int nact, int slow, hipStream_t s);
 void launch_lock_modes(const BatchSys *sys, const int32_t *act, int nact, int32_t *modes, hipStream_t s);
+void launch_pack16(int np, const uint16_t *v, const int16_t *dc, uint32_t *out, hipStream_t s);
 void launch_dcol(int n, const int *rp, const int *ci, int16_t *dc, int *bad, hipStream_t s);
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,
                     int8_t *rexp, hipStream_t s);
