@@ -60,6 +60,17 @@ def ka_bytes(n: int, nnz: int, fs: int, vec_bytes: int, idx_bytes: int = 4) -> i
     return b
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def mix_of(M, actions) -> dict:
     """Share of each format per operation over a solve's actions."""
     a = np.asarray(actions, dtype=np.int64)
@@ -617,6 +628,7 @@ def main():
         _, it_p, _ = O.cg_plain(A, b, tol=1e-30, maxit=sample_it)
         t_p = time.perf_counter() - t0
         out["cpu_baseline"]["plain_fp64_cg_ms_scaled"] = round(t_p / sample_it * r64["iters"] * 1e3, 1)
+        out["cpu_baseline"]["host"] = {"cpu_model": cpu_model(), "cores_available": len(os.sched_getaffinity(0))}
         log(f"[bench] oracle: {per_it * 1e3:.1f} ms/it emulated, {t_p / sample_it * 1e3:.1f} ms/it plain fp64")
 
     print(json.dumps(out), flush=True)
