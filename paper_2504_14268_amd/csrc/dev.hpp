@@ -128,20 +128,49 @@ __device__ __forceinline__ typename AccT<FD>::type dot_leaf(V u, V v) {
 // ---------------------------------------------------------------------------
 // Pairwise reductions.  The whole vector is one recursive-halving tree over
 // its zero-padded power-of-two length; any aligned power-of-two block of it is
-// a subtree.  A thread holding an aligned chunk, a 64-lane butterfly (lane
-// pairs (t, t^m) are sibling subtrees; x + y = y + x bit for bit) and a fixed
-// combination of the block's waves reproduce that tree exactly.
+// a subtree.  A thread holding an aligned chunk, a 64-lane tree that adds
+// sibling subtrees (x + y = y + x bit for bit) and a fixed combination of the
+// block's waves reproduce that tree exactly.
 // ---------------------------------------------------------------------------
 template <typename A>
 __device__ __forceinline__ A tree8(const A (&l)[8]) {
   return ((l[0] + l[1]) + (l[2] + l[3])) + ((l[4] + l[5]) + (l[6] + l[7]));
 }
 
+// A DPP lane permutation (every source lane exists, so every lane is written).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Tree over the 64 lanes, total in every lane.  Lane pairs, then pairs of
+// pairs, are combined by quad permutations; quads within each 8-lane half-row
+// by the half-row mirror (lane i <-> 7 - i); halves of each 16-lane row by the
+// row mirror (i <-> 15 - i).  After each step every lane of a subtree holds its
+// sum; the four row sums then combine as (r0 + r1) + (r2 + r3).
 template <typename A>
 __device__ __forceinline__ A wave_tree(A v) {
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) v = v + __shfl_xor(v, m, 64);
-  return v;
+  v = v + dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]: lanes t, t ^ 1
+  v = v + dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]: lanes t, t ^ 2
+  v = v + dpp_move<0x141>(v);   // row_half_mirror
+  v = v + dpp_move<0x140>(v);   // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // Block of kBlock threads, each holding the sum of an aligned subtree of equal
