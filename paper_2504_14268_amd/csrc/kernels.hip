@@ -968,11 +968,14 @@ __device__ __forceinline__ int win_col(const void *lc, int e, int row) {
   else return ((const int *)lc)[e];
 }
 
-// pre(sb) runs when sub-block sb starts (own-row loads), epi(sb, acc) when its
-// rows are complete.  Both are called by every thread (block-uniform).
-template <int FS, bool DC, typename G, typename Pre, typename Epi>
+// pref(sb) issues sub-block sb's own-row loads ahead of time: for sb = 0
+// before the row pointers are staged, for later sub-blocks together with the
+// prefetch of their first window.  pre(sb) runs when sub-block sb starts,
+// epi(sb, acc) when its rows are complete.  All three are called by every
+// thread (block-uniform).
+template <int FS, bool DC, typename G, typename Pref, typename Pre, typename Epi>
 __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0, int grows, void *lds_raw,
-                                           Pre &&pre, Epi &&epi) {
+                                           Pref &&pref, Pre &&pre, Epi &&epi) {
   using Acc = typename AccT<FS>::type;
   using L = typename LdsWin<FS>::type;
   constexpr int CAP = LdsWin<FS>::cap;
@@ -985,6 +988,7 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
   const uint32_t *lp = (const uint32_t *)lds_raw;
   int *lrp = (int *)((char *)lds_raw + kLdsWinBytes);
   const int tid = threadIdx.x;
+  pref(0);
   for (int i = tid; i <= grows; i += kBlock) lrp[i] = A.rp[g0 + i];
   __syncthreads();
   const int nsb = (grows + kKaRows - 1) / kKaRows;
@@ -1062,6 +1066,7 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
         }
         if (pf) {
           win_load<FS, NCH, DC>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+          if (nsb_ != sb) pref(nsb_);
           pf = false;
         }
 #pragma unroll
@@ -1087,6 +1092,7 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
           }
           if (pf) {
             win_load<FS, NCH, DC>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+            if (nsb_ != sb) pref(nsb_);
             pf = false;
           }
 #pragma unroll
@@ -1095,7 +1101,10 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
         }
       }
     }
-    if (pf) win_load<FS, NCH, DC>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+    if (pf) {
+      win_load<FS, NCH, DC>(A, nwb, min(nwb + CAP, nke), v0, v1, c0a, c0b, c1a, c1b);
+      if (nsb_ != sb) pref(nsb_);
+    }
     if (we >= ke) {
       epi(sb, acc);
       if (nsb_ >= nsb) break;
@@ -1120,18 +1129,24 @@ __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, voi
   const int n = a.A.n;
   const int g0 = g * a.grows;
   const int grows = min(a.grows, n - g0);
-  V pi[kRPT];
+  V pi[kRPT], pn[kRPT];   // own elements of p: current sub-block, next sub-block
   int8_t ex[kRPT];
   double t[4] = {0.0, 0.0, 0.0, 0.0};
+  auto pref = [&](int sb) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      pn[j] = lr < grows ? p[g0 + lr] : (V)0;
+    }
+  };
   auto pre = [&](int sb) {
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
       const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
-      pi[j] = (V)0;
+      pi[j] = pn[j];
       ex[j] = 0;
-      if (lr < grows) {
-        pi[j] = p[g0 + lr];
-        if constexpr (FS == FP16) ex[j] = a.A.rexp[g0 + lr];
+      if constexpr (FS == FP16) {
+        if (lr < grows) ex[j] = a.A.rexp[g0 + lr];
       }
     }
   };
@@ -1157,8 +1172,8 @@ __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, voi
     t[2] = sb == 2 ? s : t[2];
     t[3] = sb == 3 ? s : t[3];
   };
-  if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{p}, g0, grows, lds, pre, epi);
-  else spmv_group<FS, false>(a.A, GatherPlain<V>{p}, g0, grows, lds, pre, epi);
+  if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref, pre, epi);
+  else spmv_group<FS, false>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref, pre, epi);
   if (threadIdx.x == 0) a.part1[g] = group_tree(fd, a.grows, t);
 }
 
@@ -1203,8 +1218,9 @@ __device__ __forceinline__ void ka_residual(const KArgs &a, const Ctl &S, int g,
     t[2] = sb == 2 ? s : t[2];
     t[3] = sb == 3 ? s : t[3];
   };
-  if (a.A.dc) spmv_group<FP64, true>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pre, epi);
-  else spmv_group<FP64, false>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pre, epi);
+  auto pref = [](int) {};
+  if (a.A.dc) spmv_group<FP64, true>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pref, pre, epi);
+  else spmv_group<FP64, false>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pref, pre, epi);
   if (threadIdx.x == 0) a.part1[g] = group_tree(FP64, a.grows, t);
 }
 
