@@ -1281,24 +1281,20 @@ __device__ __forceinline__ void load8_tail(const V *p, int base, int n, bool ful
   }
 }
 
-template <int FA, int FD>
-__device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_now, int blk) {
+// x_lo and r updates and the sigma' partial on operands already loaded.
+template <int FA, int FD, typename V>
+__device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool fold_now, int blk, const V (&pv)[8],
+                                             const V (&qv)[8], V (&rv)[8], V (&xv)[8]) {
   constexpr int TIER = (FA == FP64);
-  using V = typename TierT<TIER>::type;
+  static_assert(sizeof(V) == sizeof(typename TierT<TIER>::type), "operands in the tier of fa");
   using Acc = typename AccT<FD>::type;
   V *xlo, *r;
-  const V *p, *q;
-  if constexpr (TIER) { xlo = a.v.xlo64; r = a.v.r64; p = a.v.p64; q = a.v.q64; }
-  else { xlo = a.v.xlo32; r = a.v.r32; p = a.v.p32; q = a.v.q32; }
+  if constexpr (TIER) { xlo = a.v.xlo64; r = a.v.r64; }
+  else { xlo = a.v.xlo32; r = a.v.r32; }
   const double alpha = S.alpha;
   const int n = a.A.n;
   const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   const bool full = base + 8 <= n;
-  V pv[8], qv[8], rv[8], xv[8];
-  load8_tail(p, base, n, full, pv);
-  load8_tail(q, base, n, full, qv);
-  load8_tail(r, base, n, full, rv);
-  load8_tail(xlo, base, n, full, xv);
   Acc l[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -1329,6 +1325,24 @@ __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_
   }
   const Acc t = block_tree(tree8(l));
   if (threadIdx.x == 0) a.part2[blk] = (double)t;
+}
+
+template <int FA, int FD>
+__device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_now, int blk) {
+  constexpr int TIER = (FA == FP64);
+  using V = typename TierT<TIER>::type;
+  const V *p, *q, *r, *xlo;
+  if constexpr (TIER) { xlo = a.v.xlo64; r = a.v.r64; p = a.v.p64; q = a.v.q64; }
+  else { xlo = a.v.xlo32; r = a.v.r32; p = a.v.p32; q = a.v.q32; }
+  const int n = a.A.n;
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
+  const bool full = base + 8 <= n;
+  V pv[8], qv[8], rv[8], xv[8];
+  load8_tail(p, base, n, full, pv);
+  load8_tail(q, base, n, full, qv);
+  load8_tail(r, base, n, full, rv);
+  load8_tail(xlo, base, n, full, xv);
+  kb_axpy_vals<FA, FD>(a, S, fold_now, blk, pv, qv, rv, xv);
 }
 
 // Elementwise steps (KB or KX): p = r = rd_tier(r64) after a start; the
@@ -1401,6 +1415,8 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
 
 #define MPCG_KB_CASE(FA, FD) \
   case (FA) * 4 + (FD): kb_axpy<FA, FD>(a, S, fold_now, blk); break;
+#define MPCG_KB_VALS(FA, FD) \
+  case (FA) * 4 + (FD): kb_axpy_vals<FA, FD>(a, S, fold_now, blk, pv, qv, rv, xv); break;
 
 // KB's vector work for 2048-element block blk.
 __device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, bool fold_now, int blk) {
@@ -1442,6 +1458,40 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   copy_words(&SP, a.pol, sizeof(PolicyDev));
   __syncthreads();
   const Sx x{&S, &SP, a.h, blk == 0};
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
+  const bool blk_full = (blk + 1) * kVecBlock <= a.A.n;   // block-uniform
+  if (!S.step_done && S.mode == M_ITER && (S.action & 3) != FP64 && blk_full) {
+    // an iteration in the fp32 containers on a whole block: the four operands
+    // are in flight while the alpha step runs
+    float pv[8], qv[8], rv[8], xv[8];
+    __builtin_amdgcn_sched_barrier(0);
+    load8(a.v.p32 + base, pv);
+    load8(a.v.q32 + base, qv);
+    load8(a.v.r32 + base, rv);
+    load8(a.v.xlo32 + base, xv);
+    __builtin_amdgcn_sched_barrier(0);
+    step_b<false>(x, a, pre, fast);
+    const int bop = S.b_op;
+    const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
+    if (bop == B_AXPY) {
+      const int act = S.action;
+      switch ((act & 3) * 4 + ((act >> 2) & 3)) {
+        MPCG_KB_VALS(FP16, FP16) MPCG_KB_VALS(FP16, BF16) MPCG_KB_VALS(FP16, FP32) MPCG_KB_VALS(FP16, FP64)
+        MPCG_KB_VALS(BF16, FP16) MPCG_KB_VALS(BF16, BF16) MPCG_KB_VALS(BF16, FP32) MPCG_KB_VALS(BF16, FP64)
+        MPCG_KB_VALS(FP32, FP16) MPCG_KB_VALS(FP32, BF16) MPCG_KB_VALS(FP32, FP32) MPCG_KB_VALS(FP32, FP64)
+      default: break;
+      }
+    } else {
+      kb_work(a, S, bop, fold_now, blk);
+    }
+    if (blk == 0) {
+      __syncthreads();
+      if (threadIdx.x == 0) kb_commit(S, bop, fold_now);
+      __syncthreads();
+      copy_words(&a.ctl[1], &S, sizeof(Ctl));
+    }
+    return;
+  }
   if (!S.step_done) step_b<false>(x, a, pre, fast);
   const int bop = S.b_op;
   const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
@@ -1526,6 +1576,7 @@ __global__ __launch_bounds__(kBlock) void k_b(KArgs a) { kb_body(a, blockIdx.x);
 
 __global__ __launch_bounds__(kBlock) void k_x(KArgs a) { kx_body(a, blockIdx.x); }
 #undef MPCG_KB_CASE
+#undef MPCG_KB_VALS
 
 // One-block step kernels for policies whose step writes shared state or
 // evaluates the network: the step runs once, then KA / KB skip theirs.
