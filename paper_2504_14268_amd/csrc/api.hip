@@ -262,22 +262,21 @@ static int ensure_hist(mpcg_matrix *A, int maxit) {
 // Kernel durations of each slot of a completed chunk (a start and a stop event
 // per launch): KA, KB, KX and, for policies with one-block steps, the two step
 // kernels.
-static int collect_chunk(mpcg_matrix *A, int pool_idx, int chunk, int per_slot, int64_t first, int m) {
+// Launch durations of a chunk's slots: KA, [step before KB], KB, [step before
+// KX], KX, in launch order.
+static int collect_chunk(mpcg_matrix *A, int pool_idx, int chunk, int per_slot, bool step_b, bool step_x,
+                         int64_t first, int m) {
   for (int s = 0; s < m; ++s) {
     hipEvent_t *e = &A->pev[((size_t)pool_idx * chunk + s) * per_slot];
     float t[5] = {0, 0, 0, 0, 0};
     for (int j = 0; 2 * j + 1 < per_slot; ++j) HIP_TRY(hipEventElapsedTime(&t[j], e[2 * j], e[2 * j + 1]));
-    if (per_slot == 6) {          // KA, KB, KX
-      A->ta[first + s] = t[0];
-      A->tb[first + s] = t[1];
-      A->tx[first + s] = t[2];
-      A->ts[first + s] = 0.0f;
-    } else {                      // KA, step, KB, step, KX
-      A->ta[first + s] = t[0];
-      A->tb[first + s] = t[2];
-      A->tx[first + s] = t[4];
-      A->ts[first + s] = t[1] + t[3];
-    }
+    int j = 0;
+    A->ta[first + s] = t[j++];
+    A->ts[first + s] = 0.0f;
+    if (step_b) A->ts[first + s] += t[j++];
+    A->tb[first + s] = t[j++];
+    if (step_x) A->ts[first + s] += t[j++];
+    A->tx[first + s] = t[j++];
   }
   return MPCG_OK;
 }
@@ -711,8 +710,14 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   if (rc) return rc;
 
   KArgs a = make_args(A, b, x);
-  a.slow = (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->desc.kind == MPCG_POLICY_MLP || P->roll_cap > 0) ? 1 : 0;
-  const int per_slot = a.slow ? 10 : 6;   // a start and a stop event per launch
+  // Q-learning writes the table during the solve: one-block steps.  The
+  // network and rollout logging only read shared state: every KB workgroup
+  // runs the full step (workgroup 0 writing the logs), and the per-iteration
+  // decision runs once, in the one-block step kernel before KX.
+  a.slow = P->desc.kind == MPCG_POLICY_QTABLE_TRAIN ? 1 : 0;
+  a.full = !a.slow && (P->desc.kind == MPCG_POLICY_MLP || P->roll_cap > 0) ? 1 : 0;
+  const bool step_x = a.slow || a.full;
+  const int per_slot = 6 + (a.slow ? 2 : 0) + (step_x ? 2 : 0);   // a start and a stop event per launch
   const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
   const bool prof = A->opts.profile != 0;
   std::memset(&A->prof, 0, sizeof(A->prof));
@@ -756,7 +761,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
         }
         launch_kb(a, st, e[ei], e[ei + 1]);
         ei += 2;
-        if (a.slow) {
+        if (step_x) {
           launch_step_x(a, st, e[ei], e[ei + 1]);
           ei += 2;
         }
@@ -774,7 +779,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
       const int pidx = (ci - 1) & 1;
       HIP_TRY(hipEventSynchronize(A->ev_chunk[pidx]));
       if (prof && pending[pidx]) {
-        int rc2 = collect_chunk(A, pidx, chunk, per_slot, chunk_first[pidx], chunk_m[pidx]);
+        int rc2 = collect_chunk(A, pidx, chunk, per_slot, a.slow, step_x, chunk_first[pidx], chunk_m[pidx]);
         if (rc2) return rc2;
       }
       pending[pidx] = false;
@@ -789,7 +794,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   if (prof) {
     for (int i = 0; i < 2; ++i)
       if (pending[i]) {
-        int rc2 = collect_chunk(A, i, chunk, per_slot, chunk_first[i], chunk_m[i]);
+        int rc2 = collect_chunk(A, i, chunk, per_slot, a.slow, step_x, chunk_first[i], chunk_m[i]);
         if (rc2) return rc2;
       }
   }

@@ -348,13 +348,15 @@ __device__ double lg_clamped(const PolicyDev *P, double r) {
   return (r <= P->eps_min) ? log10_policy(P->eps_min) : log10_policy(r);
 }
 
-__device__ void mlp_features(const PolicyDev *P, int k, const double *hr, int stag, double last_true,
+// rho_k itself is passed as cur (the history entry k is written by the same
+// step, by one workgroup only); the older lags come from the history.
+__device__ void mlp_features(const PolicyDev *P, int k, const double *hr, double cur, int stag, double last_true,
                              int prev, float *f) {
   double lg[8];
   for (int i = 0; i < 8; ++i) {
     int idx = k - i;
     if (idx < 0) idx = 0;
-    lg[i] = lg_clamped(P, hr[idx]);
+    lg[i] = lg_clamped(P, idx == k ? cur : hr[idx]);
   }
   for (int i = 0; i < 8; ++i) f[i] = (float)lg[i];
   f[8] = (float)(lg[0] - lg[1]);
@@ -517,7 +519,7 @@ __device__ __forceinline__ int init_t0(const Sx &a, double s64, float *s_feat) {
   const int s = need_state ? policy_state(P, k, rt, stag) : 0;
   c->s = s;
   if constexpr (FULL)
-    if (P->kind == POL_MLP || P->roll_cap > 0) mlp_features(P, k, a.h.rho, stag, rt, c->prev_action, c->feat);
+    if (P->kind == POL_MLP || P->roll_cap > 0) mlp_features(P, k, a.h.rho, rt, stag, rt, c->prev_action, c->feat);
   if (c->fell_back) {
     apply_decision<FULL>(a, 63, 0, true);
     return 0;
@@ -558,7 +560,7 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
   if (!broke && need_state) {
     stag = (k >= P->w_stag) && (rho >= a.h.rho[k - P->w_stag]);
     s_next = policy_state(P, k, rho, stag);
-    if (want_feat) mlp_features(P, k, a.h.rho, stag, c->last_true, act, c->feat_next);
+    if (want_feat) mlp_features(P, k, a.h.rho, rho, stag, c->last_true, act, c->feat_next);
   } else if (want_feat) {
     for (int i = 0; i < kMlpIn; ++i) c->feat_next[i] = c->feat[i];
   }
@@ -1448,6 +1450,7 @@ __device__ __forceinline__ void kb_commit(Ctl &S, int bop, bool fold_now) {
 
 // KB's work on vector block blk of one system; block 0 commits the state.
 // The step's partials are loaded together with the control block.
+template <bool FULL = false>
 __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
@@ -1470,7 +1473,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
     load8(a.v.r32 + base, rv);
     load8(a.v.xlo32 + base, xv);
     __builtin_amdgcn_sched_barrier(0);
-    step_b<false>(x, a, pre, fast);
+    step_b<FULL>(x, a, pre, fast);
     const int bop = S.b_op;
     const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
     if (bop == B_AXPY) {
@@ -1492,7 +1495,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
     }
     return;
   }
-  if (!S.step_done) step_b<false>(x, a, pre, fast);
+  if (!S.step_done) step_b<FULL>(x, a, pre, fast);
   const int bop = S.b_op;
   const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
   kb_work(a, S, bop, fold_now, blk);
@@ -1575,6 +1578,12 @@ __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
 __global__ __launch_bounds__(kBlock) void k_b(KArgs a) { kb_body(a, blockIdx.x); }
 
 __global__ __launch_bounds__(kBlock) void k_x(KArgs a) { kx_body(a, blockIdx.x); }
+
+// KB whose replicated step is the full one (state features, the network's
+// decision at a start or a stop, rollout log by workgroup 0): for policies
+// that read but never write shared policy state during a solve.  Their
+// end-of-iteration decision runs once, in the one-block step kernel before KX.
+__global__ __launch_bounds__(kBlock) void k_b_full(KArgs a) { kb_body<true>(a, blockIdx.x); }
 #undef MPCG_KB_CASE
 #undef MPCG_KB_VALS
 
@@ -2009,7 +2018,9 @@ static void launch_timed(K kern, int grid, const KArgs &a, hipStream_t s, hipEve
   else hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
 }
 void launch_ka(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_a, a.G1, a, s, e0, e1); }
-void launch_kb(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_b, a.P2, a, s, e0, e1); }
+void launch_kb(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_timed(a.full ? k_b_full : k_b, a.P2, a, s, e0, e1);
+}
 void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_x, a.P2, a, s, e0, e1); }
 void launch_step_b(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_step_b, 1, a, s, e0, e1); }
 void launch_step_x(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_step_x, 1, a, s, e0, e1); }
@@ -2018,7 +2029,7 @@ void launch_slot(const KArgs &a, hipStream_t s) {
   launch_ka(a, s);
   if (a.slow) launch_step_b(a, s);
   launch_kb(a, s);
-  if (a.slow) launch_step_x(a, s);
+  if (a.slow || a.full) launch_step_x(a, s);
   launch_kx(a, s);
 }
 

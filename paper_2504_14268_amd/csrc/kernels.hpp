@@ -94,6 +94,7 @@ struct KArgs {
   Vecs v;
   Ctl *ctl;            // ctl[0]: read by KA and KB, written by KX; ctl[1]: written by KB, read by KX
   int slow;            // 1: the scalar steps run in one-block kernels (KS)
+  int full;            // 1: KB runs the full replicated step, the end-of-iteration step runs in KS
   const PolicyDev *pol;
   Hist h;
   double *part0;       // partials of b.b (start)
