@@ -352,12 +352,14 @@ __device__ double lg_clamped(const PolicyDev *P, double r) {
 // step, by one workgroup only); the older lags come from the history.
 __device__ void mlp_features(const PolicyDev *P, int k, const double *hr, double cur, int stag, double last_true,
                              int prev, float *f) {
-  double lg[8];
-  for (int i = 0; i < 8; ++i) {
+  double hv[8], lg[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {   // every history load in flight before the logarithms
     int idx = k - i;
     if (idx < 0) idx = 0;
-    lg[i] = lg_clamped(P, idx == k ? cur : hr[idx]);
+    hv[i] = idx == k ? cur : hr[idx];
   }
+  for (int i = 0; i < 8; ++i) lg[i] = lg_clamped(P, hv[i]);
   for (int i = 0; i < 8; ++i) f[i] = (float)lg[i];
   f[8] = (float)(lg[0] - lg[1]);
   f[9] = (float)((double)k / (double)P->t_bin);
@@ -590,7 +592,7 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
         c->k3op = K3_FOLD;
     return 0;
   }
-  {
+  if (training || (FULL && active && a.writer && P->roll_cap > 0)) {   // the reward has a reader
     const double rw = policy_reward(P, act, rho, false);
     if (training && a.writer) {
       const double *row = &P->q[s_next * kNAct];
