@@ -348,17 +348,29 @@ __device__ double lg_clamped(const PolicyDev *P, double r) {
   return (r <= P->eps_min) ? log10_policy(P->eps_min) : log10_policy(r);
 }
 
-// rho_k itself is passed as cur (the history entry k is written by the same
-// step, by one workgroup only); the older lags come from the history.
-__device__ void mlp_features(const PolicyDev *P, int k, const double *hr, double cur, int stag, double last_true,
-                             int prev, float *f) {
-  double hv[8], lg[8];
+// The residual history a step reads: rho_{k-i}, i = 0..7 (index clamped at
+// 0) for the network features, and rho_{k - w_stag} for the stagnation flag.
+// rho_k itself is the step's own value (the history entry k is written by the
+// same step, by one workgroup only).  All loads are issued together.
+struct HistVals {
+  double lag[8];
+  double stag_ref;
+};
+
+__device__ __forceinline__ void load_hist(const PolicyDev *P, const double *hr, int k, double cur, bool lags,
+                                          HistVals &h) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {   // every history load in flight before the logarithms
+  for (int i = 0; i < 8; ++i) {
     int idx = k - i;
     if (idx < 0) idx = 0;
-    hv[i] = idx == k ? cur : hr[idx];
+    h.lag[i] = !lags ? 0.0 : idx == k ? cur : hr[idx];
   }
+  h.stag_ref = k >= P->w_stag ? hr[k - P->w_stag] : 0.0;
+}
+
+__device__ void mlp_features(const PolicyDev *P, int k, const double (&hv)[8], int stag, double last_true,
+                             int prev, float *f) {
+  double lg[8];
   for (int i = 0; i < 8; ++i) lg[i] = lg_clamped(P, hv[i]);
   for (int i = 0; i < 8; ++i) f[i] = (float)lg[i];
   f[8] = (float)(lg[0] - lg[1]);
@@ -517,11 +529,13 @@ __device__ __forceinline__ int init_t0(const Sx &a, double s64, float *s_feat) {
   // the state (and its stagnation flag, a history read) feeds only learned
   // policies and rollouts
   const bool need_state = FULL || P->kind != POL_FIXED;
-  const int stag = need_state && (k >= P->w_stag) && (rt >= a.h.rho[k - P->w_stag]);
+  const bool lags = FULL && (P->kind == POL_MLP || P->roll_cap > 0);
+  HistVals hv;
+  if (need_state) load_hist(P, a.h.rho, k, rt, lags, hv);
+  const int stag = need_state && (k >= P->w_stag) && (rt >= hv.stag_ref);
   const int s = need_state ? policy_state(P, k, rt, stag) : 0;
   c->s = s;
-  if constexpr (FULL)
-    if (P->kind == POL_MLP || P->roll_cap > 0) mlp_features(P, k, a.h.rho, rt, stag, rt, c->prev_action, c->feat);
+  if (lags) mlp_features(P, k, hv.lag, stag, rt, c->prev_action, c->feat);
   if (c->fell_back) {
     apply_decision<FULL>(a, 63, 0, true);
     return 0;
@@ -560,9 +574,11 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
   int stag = 0, s_next = s;
   const bool need_state = FULL || P->kind != POL_FIXED;
   if (!broke && need_state) {
-    stag = (k >= P->w_stag) && (rho >= a.h.rho[k - P->w_stag]);
+    HistVals hv;
+    load_hist(P, a.h.rho, k, rho, want_feat, hv);
+    stag = (k >= P->w_stag) && (rho >= hv.stag_ref);
     s_next = policy_state(P, k, rho, stag);
-    if (want_feat) mlp_features(P, k, a.h.rho, rho, stag, c->last_true, act, c->feat_next);
+    if (want_feat) mlp_features(P, k, hv.lag, stag, c->last_true, act, c->feat_next);
   } else if (want_feat) {
     for (int i = 0; i < kMlpIn; ++i) c->feat_next[i] = c->feat[i];
   }
@@ -1594,11 +1610,14 @@ __global__ __launch_bounds__(kBlock) void k_b_full(KArgs a) { kb_body<true>(a, b
 __device__ __forceinline__ void step_b_body(const KArgs &a) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
+  double pre[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bool fast = a.P1 <= kVecBlock;
+  if (fast) preload_partials(a.part1, a.P1, pre);
   copy_words(&S, &a.ctl[0], sizeof(Ctl));
   copy_words(&SP, a.pol, sizeof(PolicyDev));
   __syncthreads();
   const Sx x{&S, &SP, a.h, true};
-  step_b<true>(x, a);
+  step_b<true>(x, a, pre, fast);
   if (threadIdx.x == 0) S.step_done = 1;
   __syncthreads();
   copy_words(&a.ctl[0], &S, sizeof(Ctl));
@@ -1607,11 +1626,14 @@ __device__ __forceinline__ void step_b_body(const KArgs &a) {
 __device__ __forceinline__ void step_x_body(const KArgs &a) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
+  double pre[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bool fast = a.P2 <= kVecBlock;
+  if (fast) preload_partials(a.part2, a.P2, pre);
   copy_words(&S, &a.ctl[1], sizeof(Ctl));
   copy_words(&SP, a.pol, sizeof(PolicyDev));
   __syncthreads();
   const Sx x{&S, &SP, a.h, true};
-  step_x<true>(x, a);
+  step_x<true>(x, a, pre, fast);
   if (threadIdx.x == 0) S.step_done = 1;
   __syncthreads();
   copy_words(&a.ctl[1], &S, sizeof(Ctl));
