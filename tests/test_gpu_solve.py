@@ -134,6 +134,38 @@ def test_qlearning_training_episodes(M, cost):
         assert np.array_equal(g[key], np.concatenate([r[key] for r in all_roll]))
 
 
+@pytest.mark.parametrize("kind", ["qtable", "mlp"])
+def test_logging_policies_full_step(M, kind):
+    """Policies that only read shared state (a fixed Q-table, the network) with
+    rollout logging run the full step in every KB workgroup and log from
+    workgroup 0: 20,000 rows (10 vector blocks, a ragged tail); both policies
+    stagnate, fall back to fp64 and converge, which logs a terminal row.
+    The solve and the logged rollouts equal the oracle's bit for bit."""
+    from test_oracle_policy import mlp_weights
+
+    A = W.random_spd(20000, 31, 0.5)
+    b = W.rhs(A.n, 32)
+    if kind == "qtable":
+        q = np.random.default_rng(6).standard_normal((100, 64))
+        P = M.Policy(kind=M.POLICY_QTABLE)
+        P.set_qtable(q)
+        op = O.OraclePolicy(kind=O.POL_QTABLE, q=q)
+    else:
+        w = mlp_weights(7)
+        P = M.Policy(kind=M.POLICY_MLP)
+        P.set_mlp(w)
+        op = O.OraclePolicy(kind=O.POL_MLP, mlp=w)
+    P.rollouts_enable(5000)
+    x, res, h = gpu_solve(M, A, b, maxit=700, policy=P, R=50, fallback=True)
+    xo, info = O.cg(A, b, tol=1e-8, maxit=700, policy=op, replace_period=50, fallback=True, roll_cap=5000)
+    assert_same(x, res, h, xo, info)
+    assert res["status"] == 2
+    g = P.rollouts()
+    assert len(g["act"]) == len(info["rollouts"]["act"]) > 10
+    for key in ("feat", "next", "act", "rew", "done"):
+        assert np.array_equal(g[key], info["rollouts"][key]), key
+
+
 def test_mlp_policy_solve(M):
     from test_oracle_policy import mlp_weights
 
