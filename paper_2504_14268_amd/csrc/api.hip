@@ -717,6 +717,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   a.slow = P->desc.kind == MPCG_POLICY_QTABLE_TRAIN ? 1 : 0;
   a.full = !a.slow && (P->desc.kind == MPCG_POLICY_MLP || P->roll_cap > 0) ? 1 : 0;
   const bool step_x = a.slow || a.full;
+  a.net = (P->desc.kind == MPCG_POLICY_MLP && P->has_mlp) ? P->d_mlp : nullptr;
   const int per_slot = 6 + (a.slow ? 2 : 0) + (step_x ? 2 : 0);   // a start and a stop event per launch
   const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
   const bool prof = A->opts.profile != 0;

@@ -418,30 +418,108 @@ __device__ int decide_scalar(const PolicyDev *P, int s, int k, int *explored) {
   return 63;
 }
 
+// Network weights staged in LDS by the one-block step kernel: each matrix
+// input-major with its rows padded by one word (W1^T [16][129], W2^T
+// [128][129], W3^T [128][65]), then b1, b2, b3.  At each step of the output
+// chains a wave reads consecutive words, and the transposing copy writes
+// words 129 (or 65) apart, both free of bank conflicts.
+constexpr int kW1s = kMlpH + 1, kW2s = kMlpH + 1, kW3s = kNAct + 1;
+constexpr int kNetW2 = kMlpIn * kW1s, kNetW3 = kNetW2 + kMlpH * kW2s, kNetB1 = kNetW3 + kMlpH * kW3s;
+constexpr int kNetB2 = kNetB1 + kMlpH, kNetB3 = kNetB2 + kMlpH, kNetLds = kNetB3 + kNAct;
+
+// Copy of the packed weights W1 | b1 | W2 | b2 | W3 | b3 (row-major [out][in])
+// into the LDS layout above, by the whole block, in two halves: net_load
+// issues every load of a thread (into registers), net_store writes them to
+// LDS, so other loads issued in between share the same round trip.
+struct NetRegs {
+  static constexpr int n1 = kMlpH * kMlpIn / kBlock, n2 = kMlpH * kMlpH / kBlock, n3 = kNAct * kMlpH / kBlock;
+  float r1[n1], r2[n2], r3[n3], rb[3];
+};
+static_assert(NetRegs::n1 * kBlock == kMlpH * kMlpIn && NetRegs::n2 * kBlock == kMlpH * kMlpH &&
+                  NetRegs::n3 * kBlock == kNAct * kMlpH,
+              "whole rounds of the block");
+
+__device__ __forceinline__ void net_load(const float *__restrict__ g, NetRegs &r) {
+  const float *W1 = g, *b1 = W1 + kMlpH * kMlpIn, *W2 = b1 + kMlpH, *b2 = W2 + kMlpH * kMlpH, *W3 = b2 + kMlpH,
+              *b3 = W3 + kNAct * kMlpH;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < NetRegs::n1; ++j) r.r1[j] = W1[t + j * kBlock];
+#pragma unroll
+  for (int j = 0; j < NetRegs::n2; ++j) r.r2[j] = W2[t + j * kBlock];
+#pragma unroll
+  for (int j = 0; j < NetRegs::n3; ++j) r.r3[j] = W3[t + j * kBlock];
+  r.rb[0] = t < kMlpH ? b1[t] : 0.0f;
+  r.rb[1] = t < kMlpH ? b2[t] : 0.0f;
+  r.rb[2] = t < kNAct ? b3[t] : 0.0f;
+}
+
+__device__ __forceinline__ void net_store(const NetRegs &r, float *wl) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < NetRegs::n1; ++j) {
+    const int e = t + j * kBlock;
+    wl[(e % kMlpIn) * kW1s + e / kMlpIn] = r.r1[j];
+  }
+#pragma unroll
+  for (int j = 0; j < NetRegs::n2; ++j) {
+    const int e = t + j * kBlock;
+    wl[kNetW2 + (e % kMlpH) * kW2s + e / kMlpH] = r.r2[j];
+  }
+#pragma unroll
+  for (int j = 0; j < NetRegs::n3; ++j) {
+    const int e = t + j * kBlock;
+    wl[kNetW3 + (e % kMlpH) * kW3s + e / kMlpH] = r.r3[j];
+  }
+  if (t < kMlpH) {
+    wl[kNetB1 + t] = r.rb[0];
+    wl[kNetB2 + t] = r.rb[1];
+  }
+  if (t < kNAct) wl[kNetB3 + t] = r.rb[2];
+}
+
 // MLP logits by one block: x = bf16(feat); h1 = bf16(gelu(W1 x + b1));
 // h2 = bf16(gelu(W2 h1 + b2)); y = W3 h2 + b3.  Each output is one thread's fp32
-// fma chain over its inputs in ascending order.
-__device__ void mlp_logits_block(const PolicyDev *P, const float *feat, float *logits) {
+// fma chain over its inputs in ascending order.  Weights from the policy
+// (global, row-major) or, when wl is not NULL, from the staged LDS copy.
+__device__ void mlp_logits_block(const PolicyDev *P, const float *feat, float *logits, const float *wl) {
   __shared__ float x[kMlpIn], h1[kMlpH], h2[kMlpH];
   const int t = threadIdx.x;
   if (t < kMlpIn) x[t] = rd_bf16_from_f32(feat[t]);
   __syncthreads();
   if (t < kMlpH) {
     float acc = 0.0f;
-    for (int i = 0; i < kMlpIn; ++i) acc = __builtin_fmaf(P->W1[t * kMlpIn + i], x[i], acc);
-    h1[t] = rd_bf16_from_f32(gelu_as(acc + P->b1[t]));
+    if (wl) {
+      for (int i = 0; i < kMlpIn; ++i) acc = __builtin_fmaf(wl[i * kW1s + t], x[i], acc);
+      acc = acc + wl[kNetB1 + t];
+    } else {
+      for (int i = 0; i < kMlpIn; ++i) acc = __builtin_fmaf(P->W1[t * kMlpIn + i], x[i], acc);
+      acc = acc + P->b1[t];
+    }
+    h1[t] = rd_bf16_from_f32(gelu_as(acc));
   }
   __syncthreads();
   if (t < kMlpH) {
     float acc = 0.0f;
-    for (int i = 0; i < kMlpH; ++i) acc = __builtin_fmaf(P->W2[t * kMlpH + i], h1[i], acc);
-    h2[t] = rd_bf16_from_f32(gelu_as(acc + P->b2[t]));
+    if (wl) {
+      for (int i = 0; i < kMlpH; ++i) acc = __builtin_fmaf(wl[kNetW2 + i * kW2s + t], h1[i], acc);
+      acc = acc + wl[kNetB2 + t];
+    } else {
+      for (int i = 0; i < kMlpH; ++i) acc = __builtin_fmaf(P->W2[t * kMlpH + i], h1[i], acc);
+      acc = acc + P->b2[t];
+    }
+    h2[t] = rd_bf16_from_f32(gelu_as(acc));
   }
   __syncthreads();
   if (t < kNAct) {
     float acc = 0.0f;
-    for (int i = 0; i < kMlpH; ++i) acc = __builtin_fmaf(P->W3[t * kMlpH + i], h2[i], acc);
-    logits[t] = acc + P->b3[t];
+    if (wl) {
+      for (int i = 0; i < kMlpH; ++i) acc = __builtin_fmaf(wl[kNetW3 + i * kW3s + t], h2[i], acc);
+      logits[t] = acc + wl[kNetB3 + t];
+    } else {
+      for (int i = 0; i < kMlpH; ++i) acc = __builtin_fmaf(P->W3[t * kMlpH + i], h2[i], acc);
+      logits[t] = acc + P->b3[t];
+    }
   }
   __syncthreads();
 }
@@ -461,7 +539,8 @@ struct Sx {
   Ctl *ctl;
   const PolicyDev *pol;
   Hist h;
-  bool writer;   // commits histories, Q updates and rollouts
+  bool writer;        // commits histories, Q updates and rollouts
+  const float *wl;    // network weights staged in LDS, or NULL (read from the policy)
 };
 __device__ void set_done(Ctl *c) {
   c->mode = M_DONE;
@@ -654,7 +733,7 @@ __device__ __forceinline__ void finish_block(const Sx &a, bool completed, bool b
   __syncthreads();
   if constexpr (FULL) {
     if (s_need) {
-      mlp_logits_block(a.pol, s_feat, s_logits);
+      mlp_logits_block(a.pol, s_feat, s_logits, a.wl);
       if (threadIdx.x == 0) apply_decision<FULL>(a, argmax64f(s_logits), 0, false);
     }
   }
@@ -668,7 +747,7 @@ __device__ __forceinline__ void init_block(const Sx &a, double s64) {
   __syncthreads();
   if constexpr (FULL) {
     if (s_need) {
-      mlp_logits_block(a.pol, s_feat, s_logits);
+      mlp_logits_block(a.pol, s_feat, s_logits, a.wl);
       if (threadIdx.x == 0) apply_decision<FULL>(a, argmax64f(s_logits), 0, true);
     }
   }
@@ -1574,7 +1653,7 @@ __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   copy_words(&S, &a.ctl[1], sizeof(Ctl));
   copy_words(&SP, a.pol, sizeof(PolicyDev));
   __syncthreads();
-  const Sx x{&S, &SP, a.h, blk == 0};
+  const Sx x{&S, &SP, a.h, blk == 0, nullptr};
   if (!S.step_done && S.pend_sigma) {
     if (S.tier) kx_iter_pre<1>(a, x, S, blk, pre, fast);
     else kx_iter_pre<0>(a, x, S, blk, pre, fast);
@@ -1616,23 +1695,28 @@ __device__ __forceinline__ void step_b_body(const KArgs &a) {
   copy_words(&S, &a.ctl[0], sizeof(Ctl));
   copy_words(&SP, a.pol, sizeof(PolicyDev));
   __syncthreads();
-  const Sx x{&S, &SP, a.h, true};
+  const Sx x{&S, &SP, a.h, true, nullptr};
   step_b<true>(x, a, pre, fast);
   if (threadIdx.x == 0) S.step_done = 1;
   __syncthreads();
   copy_words(&a.ctl[0], &S, sizeof(Ctl));
 }
 
-__device__ __forceinline__ void step_x_body(const KArgs &a) {
+// wl: LDS for the network weights (staged here, in the same round trip as the
+// control block and the partials), or NULL.
+__device__ __forceinline__ void step_x_body(const KArgs &a, float *wl = nullptr) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
+  NetRegs nr;
+  if (wl) net_load(a.net, nr);
   double pre[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const bool fast = a.P2 <= kVecBlock;
   if (fast) preload_partials(a.part2, a.P2, pre);
   copy_words(&S, &a.ctl[1], sizeof(Ctl));
   copy_words(&SP, a.pol, sizeof(PolicyDev));
+  if (wl) net_store(nr, wl);
   __syncthreads();
-  const Sx x{&S, &SP, a.h, true};
+  const Sx x{&S, &SP, a.h, true, wl};
   step_x<true>(x, a, pre, fast);
   if (threadIdx.x == 0) S.step_done = 1;
   __syncthreads();
@@ -1642,6 +1726,12 @@ __device__ __forceinline__ void step_x_body(const KArgs &a) {
 __global__ __launch_bounds__(kBlock) void k_step_b(KArgs a) { step_b_body(a); }
 
 __global__ __launch_bounds__(kBlock) void k_step_x(KArgs a) { step_x_body(a); }
+
+// The one-block step of a network policy, with the weights staged in LDS.
+__global__ __launch_bounds__(kBlock) void k_step_x_net(KArgs a) {
+  __shared__ float wl[kNetLds];
+  step_x_body(a, wl);
+}
 
 // ---------------------------------------------------------------------------
 // start / finish
@@ -1783,7 +1873,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_batched(const BatchSys *sys, cons
     copy_words(&SP, a.pol, sizeof(PolicyDev));
     copy_words(&S, &a.ctl[0], sizeof(Ctl));
     __syncthreads();
-    const Sx x{&S, &SP, a.h, true};
+    const Sx x{&S, &SP, a.h, true, nullptr};
     for (int blk = 0; blk < a.P2; ++blk) start_block(a, blk);
     __syncthreads();
     int slots = 0;
@@ -2020,7 +2110,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_decide(const PolicyDev *P, in
     if (P->kind == POL_MLP) {
       if (threadIdx.x < kMlpIn) s_feat[threadIdx.x] = feat[(size_t)idx * kMlpIn + threadIdx.x];
       __syncthreads();
-      mlp_logits_block(P, s_feat, s_logits);
+      mlp_logits_block(P, s_feat, s_logits, nullptr);
       if (threadIdx.x == 0) { state[idx] = s; action[idx] = argmax64f(s_logits); }
       __syncthreads();
     } else if (threadIdx.x == 0) {
@@ -2047,7 +2137,9 @@ void launch_kb(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
 }
 void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_x, a.P2, a, s, e0, e1); }
 void launch_step_b(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_step_b, 1, a, s, e0, e1); }
-void launch_step_x(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_step_x, 1, a, s, e0, e1); }
+void launch_step_x(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_timed(a.net ? k_step_x_net : k_step_x, 1, a, s, e0, e1);
+}
 
 void launch_slot(const KArgs &a, hipStream_t s) {
   launch_ka(a, s);

@@ -95,6 +95,7 @@ struct KArgs {
   Ctl *ctl;            // ctl[0]: read by KA and KB, written by KX; ctl[1]: written by KB, read by KX
   int slow;            // 1: the scalar steps run in one-block kernels (KS)
   int full;            // 1: KB runs the full replicated step, the end-of-iteration step runs in KS
+  const float *net;    // network weights (W1|b1|W2|b2|W3|b3) for KS to stage in LDS, or NULL
   const PolicyDev *pol;
   Hist h;
   double *part0;       // partials of b.b (start)
