@@ -142,7 +142,7 @@ struct mpcg_matrix {
   double *d_part0 = nullptr, *d_part1 = nullptr, *d_part2 = nullptr, *d_scalar = nullptr;
   Ctl *d_ctl = nullptr;        // [2]
   Ctl *h_ctl = nullptr;        // pinned
-  int32_t *h_flag = nullptr;   // pinned [2]
+  Ctl *h_poll = nullptr;       // pinned [2]: the control block after each chunk
   PolicyDev *d_pol = nullptr;
   PolicyDev *h_pol = nullptr;  // pinned staging
   // history
@@ -190,9 +190,9 @@ struct mpcg_matrix {
     for (hipEvent_t e : pev) (void)hipEventDestroy(e);
     pev.clear();
     if (h_ctl) (void)hipHostFree(h_ctl);
-    if (h_flag) (void)hipHostFree(h_flag);
+    if (h_poll) (void)hipHostFree(h_poll);
     if (h_pol) (void)hipHostFree(h_pol);
-    h_ctl = nullptr; h_flag = nullptr; h_pol = nullptr;
+    h_ctl = nullptr; h_poll = nullptr; h_pol = nullptr;
     for (hipEvent_t *e : {&ev_start, &ev_end, &ev_chunk[0], &ev_chunk[1]})
       if (*e) { (void)hipEventDestroy(*e); *e = nullptr; }
     if (defpol) { defpol->release(); delete defpol; defpol = nullptr; }
@@ -446,7 +446,7 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   TRY_A(dmalloc(&A->d_ctl, 2));
   TRY_A(dmalloc(&A->d_pol, 1));
   TRY_A(hipHostMalloc((void **)&A->h_ctl, sizeof(Ctl), hipHostMallocDefault));
-  TRY_A(hipHostMalloc((void **)&A->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+  TRY_A(hipHostMalloc((void **)&A->h_poll, 2 * sizeof(Ctl), hipHostMallocDefault));
   TRY_A(hipHostMalloc((void **)&A->h_pol, sizeof(PolicyDev), hipHostMallocDefault));
   TRY_A(hipEventCreate(&A->ev_start));
   TRY_A(hipEventCreate(&A->ev_end));
@@ -745,8 +745,26 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   int64_t chunk_first[2] = {0, 0};
   int chunk_m[2] = {0, 0};
   bool pending[2] = {false, false};
+  // Chunk sizes follow the predicted end of the solve: from the last two polls,
+  // the recursive residual's decay per iteration gives the iterations still
+  // needed; once they fit in the chunk already in flight, the next chunks
+  // shrink (to no fewer than 4 slots), so few idle slots run after the stop.
+  int poll_k[2] = {-1, -1};   // last two polled (iteration, residual), newest first
+  double poll_rho[2] = {0.0, 0.0};
+  int in_flight = 0;          // slots of the newest enqueued chunk
+  auto next_chunk = [&]() -> int {
+    if (poll_k[1] < 0 || poll_k[0] <= poll_k[1] || !(poll_rho[0] > 0.0) || !(poll_rho[1] > poll_rho[0]) ||
+        !std::isfinite(poll_rho[1]) || !(tol > 0.0))
+      return chunk;
+    if (poll_rho[0] <= tol) return std::min(chunk, 4);
+    const double rate = std::log(poll_rho[0] / poll_rho[1]) / (double)(poll_k[0] - poll_k[1]);   // < 0
+    const double need = std::log(tol / poll_rho[0]) / rate - (double)in_flight + 4.0;
+    if (!(need < (double)chunk)) return chunk;
+    return std::max(std::min(chunk, 4), (int)std::ceil(need));
+  };
   while (slots < max_slots) {
-    const int m = (int)std::min<int64_t>(chunk, max_slots - slots);
+    const int m = (int)std::min<int64_t>(next_chunk(), max_slots - slots);
+    in_flight = m;
     const int idx = ci & 1;
     chunk_first[idx] = slots;
     chunk_m[idx] = m;
@@ -774,7 +792,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
     HIP_TRY(hipGetLastError());
     slots += m;
     pending[idx] = true;
-    HIP_TRY(hipMemcpyAsync(&A->h_flag[idx], &A->d_ctl->mode, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&A->h_poll[idx], A->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(A->ev_chunk[idx], st));
     if (ci > 0) {
       const int pidx = (ci - 1) & 1;
@@ -784,10 +802,15 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
         if (rc2) return rc2;
       }
       pending[pidx] = false;
-      if (A->h_flag[pidx] == M_DONE) {
+      const Ctl &pc = A->h_poll[pidx];
+      if (pc.mode == M_DONE) {
         done = true;
         break;
       }
+      poll_k[1] = poll_k[0];
+      poll_rho[1] = poll_rho[0];
+      poll_k[0] = pc.k;
+      poll_rho[0] = pc.rho_new;
     }
     ci++;
   }
@@ -800,8 +823,8 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
       }
   }
   if (!done) {
-    HIP_TRY(hipMemcpy(&A->h_flag[0], &A->d_ctl->mode, sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (A->h_flag[0] != M_DONE) return fail(MPCG_ERR_DEVICE, "solver did not reach a final state");
+    HIP_TRY(hipMemcpy(&A->h_poll[0], A->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    if (A->h_poll[0].mode != M_DONE) return fail(MPCG_ERR_DEVICE, "solver did not reach a final state");
   }
   a.slot_log = nullptr;
   launch_finish(a, st);
