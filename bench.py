@@ -567,7 +567,9 @@ def main():
         P_l, tr = train_qtable(M, build_systems(M, W, torch, range(100, 112), n_hi=1e5), episodes=3,
                                maxit=1000, cost="C1")
         t_train = time.time() - t0
-        m.set_policy(P_l)
+        greedy = M.Policy(kind=M.POLICY_QTABLE, cost="C1")   # the trained table, no exploration
+        greedy.set_qtable(P_l.qtable())
+        m.set_policy(greedy)
         m.set_options(replace_period=50, fallback=True)
         lr_runs = []
         for _ in range(max(1, args.steps // 2) + 1):
