@@ -395,8 +395,8 @@ def main():
                          "reference for FETCH_SIZE / WRITE_SIZE), then one mixed solve")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "a multi-GPU decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU only (--gpus {args.gpus} requested); "
+              "a multi-GPU row decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
