@@ -64,6 +64,7 @@ struct mpcg_policy {
   mpcg_policy_desc desc{};
   int n_states = 0;
   double *d_q = nullptr;
+  std::vector<uint8_t> qbest;   // greedy action per state of the table last set from the host
   float *d_mlp = nullptr;   // W1 | b1 | W2 | b2 | W3 | b3
   bool has_mlp = false;
   int32_t roll_cap = 0;
@@ -100,6 +101,11 @@ struct mpcg_policy {
       p.b2 = p.W2 + kMlpH * kMlpH;
       p.W3 = p.b2 + kMlpH;
       p.b3 = p.W3 + kNAct * kMlpH;
+    }
+    p.n_qbest = 0;
+    if (desc.kind == MPCG_POLICY_QTABLE && n_states <= kQbestMax && (int)qbest.size() == n_states) {
+      p.n_qbest = n_states;
+      for (int s = 0; s < n_states; ++s) p.qbest[s] = qbest[s];
     }
     p.replace_period = desc.replace_period;
     p.roll_cap = roll_cap;
@@ -223,6 +229,7 @@ static int policy_alloc(mpcg_policy *P) {
   P->n_states = P->desc.b_res * P->desc.b_it * 2;
   HIP_TRY(dmalloc(&P->d_q, (size_t)P->n_states * kNAct));
   HIP_TRY(hipMemset(P->d_q, 0, sizeof(double) * (size_t)P->n_states * kNAct));
+  P->qbest.assign((size_t)P->n_states, 0);   // all-zero table: action 0 everywhere
   HIP_TRY(dmalloc(&P->d_rcount, 1));
   HIP_TRY(hipMemset(P->d_rcount, 0, sizeof(int32_t)));
   return MPCG_OK;
@@ -522,6 +529,16 @@ int mpcg_policy_destroy(mpcg_policy *P) {
 int mpcg_policy_set_qtable(mpcg_policy *P, const double *q) {
   if (!P || !q) return fail(MPCG_ERR_INVALID, "NULL argument");
   HIP_TRY(hipMemcpy(P->d_q, q, sizeof(double) * (size_t)P->n_states * kNAct, hipMemcpyHostToDevice));
+  // the greedy action per state, by the device's rule (first strict maximum)
+  P->qbest.resize((size_t)P->n_states);
+  for (int s = 0; s < P->n_states; ++s) {
+    const double *row = q + (size_t)s * kNAct;
+    int best = 0;
+    double bv = row[0];
+    for (int a = 1; a < kNAct; ++a)
+      if (row[a] > bv) { best = a; bv = row[a]; }
+    P->qbest[s] = (uint8_t)best;
+  }
   return MPCG_OK;
 }
 

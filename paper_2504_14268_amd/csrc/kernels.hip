@@ -398,13 +398,20 @@ __device__ void roll_log(const PolicyDev *P, const float *f, const float *fn, in
   P->roll_done[i] = (uint8_t)done;
 }
 
+// Greedy action of a fixed table: precomputed with the policy when the table
+// has at most kQbestMax states (the same argmax, lowest index on ties), else
+// from the table.
+__device__ __forceinline__ int q_greedy(const PolicyDev *P, int s) {
+  return s < P->n_qbest ? (int)P->qbest[s] : q_argmax(&P->q[s * kNAct]);
+}
+
 template <bool FULL>
 __device__ int decide_scalar(const PolicyDev *P, int s, int k, int *explored) {
   *explored = 0;
-  if constexpr (!FULL) return P->kind == POL_QTABLE ? q_argmax(&P->q[s * kNAct]) : P->fixed_action;
+  if constexpr (!FULL) return P->kind == POL_QTABLE ? q_greedy(P, s) : P->fixed_action;
   switch (P->kind) {
   case POL_FIXED: return P->fixed_action;
-  case POL_QTABLE: return q_argmax(&P->q[s * kNAct]);
+  case POL_QTABLE: return q_greedy(P, s);
   case POL_QTRAIN: {
     const double u0 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, 0);
     if (u0 < P->epsilon) {

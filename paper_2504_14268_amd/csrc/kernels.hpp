@@ -8,6 +8,7 @@ constexpr int kMaxEdges = 16;
 constexpr int kRPT = 2;                          // rows per thread in KA
 constexpr int kKaRows = kRPT * kRowsPerBlock;    // rows per KA workgroup
 constexpr int kMlpIn = 16, kMlpH = 128, kNAct = 64;
+constexpr int kQbestMax = 256;                   // states whose greedy action travels with the policy
 
 // Matrix in HBM: CSR int32 indices, fp64 values and three shadows.  Value and
 // index arrays are padded to a multiple of 8 entries (+8) so the SpMV can read
@@ -63,6 +64,8 @@ struct PolicyDev {
   float *roll_rew;
   uint8_t *roll_done;
   int32_t *roll_n;
+  int32_t n_qbest;               // greedy table: qbest[s] = argmax_a q[s][a] for s < n_qbest (else 0 states)
+  uint8_t qbest[kQbestMax];
 };
 
 // Phase of the next KA (mode), what KB executes (b_op), and the pending
