@@ -77,7 +77,8 @@ typedef struct mpcg_policy mpcg_policy;
 /*
  * Policy description (section 4.1).  State s = (j*b_it + i)*2 + stag with the
  * iteration bin i = min(k / ceil(t_bin/b_it), b_it-1), the residual bin
- * j = #{ t : rho <= res_edges[t] } over the b_res-1 decreasing thresholds, and
+ * j = #{ t : rho <= T_t } over the b_res-1 decreasing thresholds T_t that the
+ * library derives from b_res and eps_min (mpcg_residual_thresholds), and
  * stag = [k >= w_stag and rho_k >= rho_{k-w_stag}].  Reward (section 4.1):
  * w1*min(-log10 rho', -log10 eps_min) - w2*(c[f_s]+c[f_d]+c[f_a]) + w3 on
  * convergence; a breakdown ends the episode with -w2*cost - w3.  Q update:
@@ -88,12 +89,13 @@ typedef struct {
     int32_t fixed_action;      /* used by MPCG_POLICY_FIXED                      */
     int32_t t_bin;             /* iteration-bin horizon (1000)                   */
     int32_t b_it;              /* iteration bins (5)                             */
-    int32_t b_res;             /* residual bins (10), <= 17                      */
+    int32_t b_res;             /* residual bins (10), in [1, 17]                 */
     int32_t w_stag;            /* stagnation window (10)                         */
-    double res_edges[16];      /* b_res-1 thresholds, strictly decreasing        */
     double lr, gamma;          /* Q-learning rate and discount (0.1, 0.9)        */
     double w1, w2, w3;         /* reward weights (1.0, 0.1, 10.0)                */
-    double eps_min;            /* residual floor of the accuracy term (1e-16)    */
+    double eps_min;            /* residual floor of the accuracy term and of the
+                                  residual bins (1e-16); must be a power of ten
+                                  10^-E (the double nearest to it), 1 <= E <= 300 */
     double cost[4];            /* c(fp16), c(bf16), c(fp32), c(fp64)             */
     uint64_t seed;             /* exploration draws                              */
     int32_t replace_period;    /* R seen by the MLP features                     */
@@ -146,6 +148,10 @@ typedef struct {
     double cost_sum;           /* sum over iterations of the policy's op costs   */
     double time_ms;            /* device time from first enqueue to done         */
     int32_t slots;             /* kernel slots enqueued (diagnostic)             */
+    int32_t spmv_rows;         /* kernel configuration used: rows per SpMV
+                                  workgroup (512, 1024 or 2048)                  */
+    int32_t index16;           /* kernel configuration used: 1 if the SpMV read
+                                  16-bit column deltas                           */
     int32_t reserved;
 } mpcg_result;
 
@@ -160,8 +166,9 @@ typedef struct {
  * stream) on which this handle's work runs.  Validation: 1 <= n, nnz < 2^31,
  * row_ptr[0] = 0, row_ptr[n] = nnz, row_ptr non-decreasing, 0 <= col < n,
  * columns strictly increasing within a row, values finite, every row has a
- * positive diagonal entry (host arrays only; device arrays are checked for
- * sizes).  Error: MPCG_ERR_CSR with a message naming the first bad row.
+ * positive diagonal entry.  Device arrays are copied to the host for this
+ * check first, so both kinds are validated the same way.  Error: MPCG_ERR_CSR
+ * with a message naming the first bad row.
  */
 int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
                     const double *val, int mem_kind, void *stream, mpcg_matrix **out);
@@ -185,7 +192,23 @@ int mpcg_get_shadows(mpcg_matrix *A, float *f32, uint16_t *bf16, uint16_t *f16, 
 
 /* ---------------------------------------------------------------- policies */
 
-/* Creates a policy; Q-table (n_states x 64, zero) and rollout log live on the device. */
+/*
+ * Residual-bin thresholds of section 4.1 (the residual bin j_k with
+ * delta = -log10(eps_min) / b_res): out[j-1] = T_j, the double nearest to
+ * 10^(-delta j) = 10^(-E j / b_res) for j = 1 .. b_res-1, where eps_min is the
+ * double nearest to 10^-E.  Computed exactly on the host (big-integer
+ * comparisons against the neighbouring doubles' midpoints), so
+ * j_k = #{ j : rho_k <= T_j } equals the floor formula away from the real
+ * boundaries and is decided identically everywhere.  out: host double[b_res-1].
+ * Errors: MPCG_ERR_INVALID if b_res is outside [1, 17] or eps_min is not such a
+ * power of ten.  Pure host code: needs no GPU.
+ */
+int mpcg_residual_thresholds(int32_t b_res, double eps_min, double *out);
+
+/* Creates a policy; Q-table (n_states x 64, zero) and rollout log live on the
+ * device.  The residual-bin thresholds are derived from b_res and eps_min as by
+ * mpcg_residual_thresholds.  Errors: MPCG_ERR_INVALID for a bad kind, action,
+ * bin parameter or eps_min. */
 int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out);
 int mpcg_policy_destroy(mpcg_policy *P);
 /* Host double[n_states*64] in/out, n_states = b_res*b_it*2. */

@@ -6,6 +6,7 @@ CPU-baseline leg load this module; the product path never does.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from decimal import Decimal, getcontext
@@ -224,7 +225,8 @@ class OraclePolicy:
         s = self.s
         s.kind, s.fixed_action = kind, fixed_action
         s.t_bin, s.b_it, s.b_res, s.w_stag = t_bin, b_it, b_res, w_stag
-        for i, e in enumerate(residual_edges(b_res)):
+        # section 4.1: delta = -log10(eps_min) / r with eps_min a power of ten
+        for i, e in enumerate(residual_edges(b_res, int(round(-math.log10(eps_min))))):
             s.res_edges[i] = e
         n_states = b_res * b_it * 2
         self.q = _f64(np.zeros((n_states, 64)) if q is None else q).copy()

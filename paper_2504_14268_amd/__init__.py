@@ -8,7 +8,6 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from decimal import Decimal, getcontext
 
 import numpy as np
 
@@ -35,7 +34,6 @@ class PolicyDesc(C.Structure):
     _fields_ = [
         ("kind", C.c_int32), ("fixed_action", C.c_int32), ("t_bin", C.c_int32),
         ("b_it", C.c_int32), ("b_res", C.c_int32), ("w_stag", C.c_int32),
-        ("res_edges", C.c_double * 16),
         ("lr", C.c_double), ("gamma", C.c_double),
         ("w1", C.c_double), ("w2", C.c_double), ("w3", C.c_double), ("eps_min", C.c_double),
         ("cost", C.c_double * 4), ("seed", C.c_uint64),
@@ -67,7 +65,8 @@ class MatrixInfo(C.Structure):
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("n_replace", C.c_int32),
                 ("fallback_at", C.c_int32), ("relres_true", C.c_double), ("cost_sum", C.c_double),
-                ("time_ms", C.c_double), ("slots", C.c_int32), ("reserved", C.c_int32)]
+                ("time_ms", C.c_double), ("slots", C.c_int32), ("spmv_rows", C.c_int32),
+                ("index16", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -123,6 +122,7 @@ def lib():
             "mpcg_destroy": [vp],
             "mpcg_get_info": [vp, C.POINTER(MatrixInfo)],
             "mpcg_get_shadows": [vp, vp, vp, vp, vp],
+            "mpcg_residual_thresholds": [i32, d, vp],
             "mpcg_policy_create": [C.POINTER(PolicyDesc), C.POINTER(vp)],
             "mpcg_policy_destroy": [vp],
             "mpcg_policy_set_qtable": [vp, vp],
@@ -187,10 +187,11 @@ def _stream_handle(stream):
     return C.c_void_p(s.cuda_stream)
 
 
-def residual_edges(b_res: int = 10, eps_min_exp: int = 16):
-    """Nearest doubles to 10^(-j*delta), delta = eps_min_exp / b_res, j = 1..b_res-1."""
-    getcontext().prec = 60
-    return [float(Decimal(10) ** (Decimal(-eps_min_exp * j) / Decimal(b_res))) for j in range(1, b_res)]
+def residual_thresholds(b_res: int = 10, eps_min: float = 1e-16):
+    """The library's residual-bin thresholds T_1..T_{b_res-1} (mpcg_residual_thresholds)."""
+    out = np.zeros(max(b_res - 1, 1))
+    _check(lib().mpcg_residual_thresholds(b_res, eps_min, _np_ptr(out)), "mpcg_residual_thresholds")
+    return out[:b_res - 1]
 
 
 class Policy:
@@ -201,8 +202,6 @@ class Policy:
                  replace_period=50):
         d = PolicyDesc()
         d.kind, d.fixed_action, d.t_bin, d.b_it, d.b_res, d.w_stag = kind, fixed_action, t_bin, b_it, b_res, w_stag
-        for i, e in enumerate(residual_edges(b_res, int(round(-np.log10(eps_min))))):
-            d.res_edges[i] = e
         d.lr, d.gamma = lr, gamma
         d.w1, d.w2, d.w3 = w
         d.eps_min = eps_min

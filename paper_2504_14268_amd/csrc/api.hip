@@ -16,6 +16,7 @@
 #include <mutex>
 #include <tuple>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -57,11 +58,142 @@ void dfree(T *&p) {
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// ---------------------------------------------------------------------------
+// Residual-bin thresholds (section 4.1, the residual bin j_k): with
+// delta = -log10(eps_min) / b_res, the bin boundaries are 10^(-delta j),
+// j = 1 .. b_res-1.  eps_min must be a power of ten, 10^-E (the double nearest
+// to it), so each boundary is 10^(-E j / b_res) exactly, and T_j is the double
+// nearest to that real number.  The comparisons below are exact: a dyadic
+// number M 2^F (M > 0 odd or even integer, F integer) lies below 10^(-N/D)
+// iff M^D 10^N < 2^(-F D), compared as big integers.  10^(-N/D) is never a
+// double's midpoint (it is not dyadic), so "nearest" has no ties.
+// ---------------------------------------------------------------------------
+struct Big {
+  std::vector<uint32_t> w;   // little-endian base-2^32 digits, no leading zeros
+  explicit Big(uint64_t v = 0) {
+    while (v) { w.push_back((uint32_t)v); v >>= 32; }
+  }
+  void mul_small(uint32_t m) {
+    uint64_t carry = 0;
+    for (uint32_t &d : w) {
+      const uint64_t t = (uint64_t)d * m + carry;
+      d = (uint32_t)t;
+      carry = t >> 32;
+    }
+    if (carry) w.push_back((uint32_t)carry);
+  }
+  static Big mul(const Big &a, const Big &b) {
+    Big r;
+    if (a.w.empty() || b.w.empty()) return r;
+    r.w.assign(a.w.size() + b.w.size(), 0);
+    for (size_t i = 0; i < a.w.size(); ++i) {
+      uint64_t carry = 0;
+      for (size_t j = 0; j < b.w.size(); ++j) {
+        const uint64_t t = (uint64_t)a.w[i] * b.w[j] + r.w[i + j] + carry;
+        r.w[i + j] = (uint32_t)t;
+        carry = t >> 32;
+      }
+      size_t k = i + b.w.size();
+      while (carry) {
+        const uint64_t t = (uint64_t)r.w[k] + carry;
+        r.w[k++] = (uint32_t)t;
+        carry = t >> 32;
+      }
+    }
+    while (!r.w.empty() && r.w.back() == 0) r.w.pop_back();
+    return r;
+  }
+  static Big pow2(int64_t e) {   // 2^e, e >= 0
+    Big r;
+    r.w.assign((size_t)(e / 32) + 1, 0);
+    r.w.back() = 1u << (e % 32);
+    return r;
+  }
+  static int cmp(const Big &a, const Big &b) {
+    if (a.w.size() != b.w.size()) return a.w.size() < b.w.size() ? -1 : 1;
+    for (size_t i = a.w.size(); i-- > 0;)
+      if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+    return 0;
+  }
+};
+
+// sign of (M 2^F) - 10^(-N/D) for M >= 1, N >= 0, D >= 1
+int cmp_dyadic_pow10(uint64_t M, int64_t F, int64_t N, int64_t D) {
+  Big lhs(1);
+  const Big m(M);
+  for (int64_t i = 0; i < D; ++i) lhs = Big::mul(lhs, m);   // M^D
+  for (int64_t i = 0; i < N; ++i) lhs.mul_small(10);          // M^D 10^N
+  const int64_t s = F * D;                                    // compare with 2^(-s)
+  if (s >= 0) {
+    // M^D 10^N 2^s >= 1 > 10^0 unless everything is 1
+    Big l2 = Big::mul(lhs, Big::pow2(s));
+    return Big::cmp(l2, Big(1));
+  }
+  return Big::cmp(lhs, Big::pow2(-s));
+}
+
+// sign of x - 10^(-N/D) for a positive finite double x
+int cmp_double_pow10(double x, int64_t N, int64_t D) {
+  int e;
+  const double fr = std::frexp(x, &e);                        // x = fr 2^e, fr in [0.5, 1)
+  const uint64_t M = (uint64_t)std::ldexp(fr, 53);           // exact
+  return cmp_dyadic_pow10(M, (int64_t)e - 53, N, D);
+}
+
+// sign of midpoint(x, nextafter(x, +inf)) - 10^(-N/D), x > 0 finite normal or subnormal
+int cmp_mid_pow10(double x, int64_t N, int64_t D) {
+  // The next double up is x + ulp(x) with ulp(x) = 2^F the spacing of x's
+  // binade (also when it starts the next binade), so the midpoint is
+  // (2 Mx + 1) 2^(F-1) with x = Mx 2^F.
+  int e;
+  const double fr = std::frexp(x, &e);
+  uint64_t Mx = (uint64_t)std::ldexp(fr, 53);
+  int64_t F = (int64_t)e - 53;
+  if (x < std::ldexp(1.0, -1022)) {   // subnormal: spacing 2^-1074
+    Mx = (uint64_t)std::ldexp(x, 1074);
+    F = -1074;
+  }
+  return cmp_dyadic_pow10(2 * Mx + 1, F - 1, N, D);
+}
+
+// Power-of-ten exponent E with eps_min == (double)10^-E, or -1.
+int pow10_exponent(double eps_min) {
+  if (!(eps_min > 0.0 && eps_min < 1.0) || !std::isfinite(eps_min)) return -1;
+  const int E = (int)std::lround(-std::log10(eps_min));
+  if (E < 1 || E > 300) return -1;
+  char buf[16];
+  std::snprintf(buf, sizeof(buf), "1e-%d", E);
+  return std::strtod(buf, nullptr) == eps_min ? E : -1;   // strtod rounds correctly
+}
+
+// T_j, j = 1 .. b_res-1: the double nearest to 10^(-E j / b_res).
+int residual_thresholds(int b_res, double eps_min, double *out) {
+  if (b_res < 1 || b_res > kMaxEdges + 1) return fail(MPCG_ERR_INVALID, "b_res must be in [1, 17]");
+  const int E = pow10_exponent(eps_min);
+  if (E < 0) return fail(MPCG_ERR_INVALID, "eps_min must be a power of ten 10^-E, 1 <= E <= 300");
+  for (int j = 1; j < b_res; ++j) {
+    const int64_t g = std::gcd((int64_t)E * j, (int64_t)b_res);
+    const int64_t N = (int64_t)E * j / g, D = (int64_t)b_res / g;
+    double c = (double)std::pow(10.0L, -(long double)N / (long double)D);
+    // walk to the nearest double: the midpoint above c must lie above the
+    // target and the midpoint below c below it
+    for (int guard = 0; guard < 64 && cmp_mid_pow10(c, N, D) < 0; ++guard) c = std::nextafter(c, INFINITY);
+    for (int guard = 0; guard < 64 && cmp_mid_pow10(std::nextafter(c, 0.0), N, D) > 0; ++guard)
+      c = std::nextafter(c, 0.0);
+    if (!(cmp_mid_pow10(c, N, D) > 0 && cmp_mid_pow10(std::nextafter(c, 0.0), N, D) < 0))
+      return fail(MPCG_ERR_INVALID, "residual threshold search did not settle");
+    out[j - 1] = c;
+  }
+  for (int j = b_res; j <= kMaxEdges; ++j) out[j - 1] = 0.0;
+  return MPCG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 struct mpcg_policy {
   mpcg_policy_desc desc{};
+  double edges[kMaxEdges] = {};   // residual-bin thresholds derived from b_res, eps_min
   int n_states = 0;
   double *d_q = nullptr;
   std::vector<uint8_t> qbest;   // greedy action per state of the table last set from the host
@@ -82,7 +214,7 @@ struct mpcg_policy {
     p.b_it = desc.b_it;
     p.b_res = desc.b_res;
     p.w_stag = desc.w_stag;
-    for (int i = 0; i < kMaxEdges; ++i) p.edges[i] = desc.res_edges[i];
+    for (int i = 0; i < kMaxEdges; ++i) p.edges[i] = edges[i];
     p.q = d_q;
     p.lr = desc.lr;
     p.gamma = desc.gamma;
@@ -213,7 +345,6 @@ static void default_desc(mpcg_policy_desc *d) {
   d->b_it = 5;
   d->b_res = 10;
   d->w_stag = 10;
-  for (int j = 1; j < 10; ++j) d->res_edges[j - 1] = std::pow(10.0, -1.6 * j);
   d->lr = 0.1;
   d->gamma = 0.9;
   d->w1 = 1.0;
@@ -226,6 +357,8 @@ static void default_desc(mpcg_policy_desc *d) {
 }
 
 static int policy_alloc(mpcg_policy *P) {
+  int rc = residual_thresholds(P->desc.b_res, P->desc.eps_min, P->edges);
+  if (rc) return rc;
   P->n_states = P->desc.b_res * P->desc.b_it * 2;
   HIP_TRY(dmalloc(&P->d_q, (size_t)P->n_states * kNAct));
   HIP_TRY(hipMemset(P->d_q, 0, sizeof(double) * (size_t)P->n_states * kNAct));
@@ -337,6 +470,15 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
 extern "C" {
 
 const char *mpcg_last_error(void) { return g_err.c_str(); }
+
+int mpcg_residual_thresholds(int32_t b_res, double eps_min, double *out) {
+  if (!out) return fail(MPCG_ERR_INVALID, "out is NULL");
+  double t[kMaxEdges];
+  const int rc = residual_thresholds(b_res, eps_min, t);
+  if (rc) return rc;
+  for (int j = 0; j + 1 < b_res; ++j) out[j] = t[j];
+  return MPCG_OK;
+}
 
 static int validate_csr(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v) {
   if (rp[0] != 0) return fail(MPCG_ERR_CSR, "row_ptr[0] != 0");
@@ -856,6 +998,8 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   fill_result(r, res);
   res->time_ms = ms;
   res->slots = (int32_t)slots;
+  res->spmv_rows = a.grows;
+  res->index16 = a.A.dc ? 1 : 0;
   A->last_iters = r.k;
   A->last_nrep = r.nrep;
   if (prof) {
@@ -1267,6 +1411,8 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
     if (r.status < 0) return fail(MPCG_ERR_DEVICE, "batched solve did not reach a final state");
     fill_result(r, &res[i]);
     res[i].time_ms = ms;
+    res[i].spmv_rows = cfg.spmv_rows;
+    res[i].index16 = (A[i]->d_dc && A[i]->opts.index16 >= 0) ? 1 : 0;
     A[i]->last_iters = r.k;
     A[i]->last_nrep = r.nrep;
   }

@@ -138,8 +138,9 @@ def test_policy_decisions_bit_exact(M):
     k = rng.integers(0, 3000, m)
     rho = 10.0 ** rng.uniform(-17, 1, m)
     edges = O.residual_edges()
-    rho[:9] = edges                      # exact bin edges
+    rho[:9] = edges                      # exact bin edges, and both neighbouring doubles
     rho[9:18] = np.nextafter(edges, 1.0)
+    rho[18:27] = np.nextafter(edges, 0.0)
     stag = rng.integers(0, 2, m)
     q = rng.standard_normal((100, 64))
     q[:, 5] = q[:, 9] = 10.0             # ties: the lowest index wins
@@ -151,6 +152,19 @@ def test_policy_decisions_bit_exact(M):
     assert np.array_equal(st, want_s)
     assert np.array_equal(ac, np.argmax(q[want_s], axis=1))
     assert np.all(ac[np.max(q[want_s], axis=1) == 10.0] == 5)
+    # another bin layout: the library derives its thresholds from b_res and
+    # eps_min; the oracle from its own decimal computation
+    e6 = O.residual_edges(7, 12)
+    rho2 = rho.copy()
+    rho2[:6], rho2[6:12], rho2[12:18] = e6, np.nextafter(e6, 1.0), np.nextafter(e6, 0.0)
+    q6 = rng.standard_normal((7 * 3 * 2, 64))
+    P6 = M.Policy(kind=M.POLICY_QTABLE, b_res=7, eps_min=1e-12, b_it=3, t_bin=900)
+    P6.set_qtable(q6)
+    st6, ac6 = P6.decide(k, rho2, stag)
+    op6 = O.OraclePolicy(kind=O.POL_QTABLE, q=q6, b_res=7, eps_min=1e-12, b_it=3, t_bin=900)
+    want6 = np.array([op6.state(int(k[i]), float(rho2[i]), int(stag[i])) for i in range(m)])
+    assert np.array_equal(st6, want6)
+    assert np.array_equal(ac6, np.argmax(q6[want6], axis=1))
     # MLP: logits from the fp32 fixed-order decision path
     from test_oracle_policy import mlp_weights
 
