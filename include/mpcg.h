@@ -416,6 +416,19 @@ int mpcg_op_spmv(mpcg_matrix *A, int fmt, int tier64, const void *p, void *q);
 /* *out (host) = dot_f(u, v): operands rounded to f, products in the accumulation
  * format, pairwise sum over the zero-padded power-of-two length. */
 int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out);
+/*
+ * mpcg_op_dot without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same kernels and result as mpcg_op_dot, but the block
+ * partials live in one static device array of the library (512 KiB per device,
+ * held until the process ends) and the result is written to out, a device
+ * double; nothing is synchronised: the result is ready when the handle's
+ * stream reaches it.  Limit: n <= 65536 * 2048 = 134,217,728 elements, else
+ * MPCG_ERR_INVALID before any launch.  Every call on one device shares that
+ * array, so calls that overlap on one device (several streams, several host
+ * threads) race and must be serialised by the caller.
+ */
+int mpcg_op_dot_noalloc(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out);
 /* y = rd_f(fma(alpha, u, y)) (tier of f) */
 int mpcg_op_axpy(mpcg_matrix *A, int fmt, double alpha, const void *u, void *y);
 /* r (double[n], device) = b - A x in fp64 */

@@ -140,6 +140,7 @@ def lib():
             "mpcg_get_history": [vp, vp, vp, vp, i32, vp, vp, i32, C.POINTER(i32)],
             "mpcg_op_spmv": [vp, C.c_int, C.c_int, vp, vp],
             "mpcg_op_dot": [vp, C.c_int, C.c_int, vp, vp, C.POINTER(d)],
+            "mpcg_op_dot_noalloc": [vp, C.c_int, C.c_int, vp, vp, vp],
             "mpcg_op_axpy": [vp, C.c_int, d, vp, vp],
             "mpcg_op_residual": [vp, vp, vp, vp],
             "mpcg_get_profile": [vp, C.POINTER(Profile)],
@@ -489,6 +490,10 @@ class Matrix:
         out = C.c_double(0.0)
         _check(lib().mpcg_op_dot(self.h, fmt, tier64, _t_ptr(u), _t_ptr(v), C.byref(out)), "op_dot")
         return out.value
+
+    def op_dot_noalloc(self, fmt, tier64, u, v, out):
+        """dot_f(u, v) into the device double out[0], with no allocation (mpcg_op_dot_noalloc)."""
+        _check(lib().mpcg_op_dot_noalloc(self.h, fmt, tier64, _t_ptr(u), _t_ptr(v), _t_ptr(out)), "op_dot_noalloc")
 
     def op_axpy(self, fmt, alpha, u, y):
         _check(lib().mpcg_op_axpy(self.h, fmt, alpha, _t_ptr(u), _t_ptr(y)), "op_axpy")

@@ -1728,6 +1728,16 @@ int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *
   return MPCG_OK;
 }
 
+int mpcg_op_dot_noalloc(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out) {
+  if (!A || !u || !v || !out || fmt < 0 || fmt > 3 || (tier64 != 0 && tier64 != 1))
+    return fail(MPCG_ERR_INVALID, "bad argument");
+  if ((int64_t)(A->n + kVecBlock - 1) / kVecBlock > kNoAllocPartials)
+    return fail(MPCG_ERR_INVALID, "n exceeds the allocation-free dot's limit of " +
+                                      std::to_string((int64_t)kNoAllocPartials * kVecBlock) + " elements");
+  HIP_TRY(launch_op_dot_noalloc(A->n, fmt, tier64, u, v, out, A->stream));
+  return MPCG_OK;
+}
+
 int mpcg_op_axpy(mpcg_matrix *A, int fmt, double alpha, const void *u, void *y) {
   if (!A || !u || !y || fmt < 0 || fmt > 3) return fail(MPCG_ERR_INVALID, "bad argument");
   launch_op_axpy(A->n, fmt, alpha, u, y, A->stream);

@@ -22,6 +22,8 @@
 // updates, rollout logs) or evaluates the MLP run each step once, in a
 // one-block kernel (KS) before KB and before KX.  The host only enqueues launches.
 #include <hip/hip_ext.h>
+
+#include <mutex>
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -2241,6 +2243,52 @@ void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double
   }
 #undef MPCG_DOT
   hipLaunchKernelGGL(k_op_dot_final, dim3(1), dim3(kBlock), 0, s, fd, part, P2, out);
+}
+
+// ---------------------------------------------------------------------------
+// The dot product without allocation: the same two kernels as launch_op_dot,
+// with the block partials in a file-scope device array instead of handle
+// memory.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is looked up once per device with
+// hipGetSymbolAddress (with that device current) and only that address is
+// ever passed to kernels.  Every call on one device shares that device's
+// array, so calls that overlap on one device race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this device's scratch array (looked up on first use).
+static hipError_t scratch_address(double **out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_op_dot_noalloc(int n, int fd, int tier, const void *u, const void *v, double *out,
+                                 hipStream_t s) {
+  const int P2 = (n + kVecBlock - 1) / kVecBlock;
+  if (P2 > kNoAllocPartials) return hipErrorInvalidValue;
+  double *part = nullptr;
+  const hipError_t e = scratch_address(&part);
+  if (e != hipSuccess) return e;
+  launch_op_dot(n, fd, tier, u, v, part, P2, out, s);
+  return hipGetLastError();
 }
 
 void launch_op_axpy(int n, int fa, double alpha, const void *u, void *y, hipStream_t s) {

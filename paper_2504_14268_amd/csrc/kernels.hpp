@@ -9,6 +9,7 @@ constexpr int kRPT = 2;                          // rows per thread in KA
 constexpr int kKaRows = kRPT * kRowsPerBlock;    // rows per KA workgroup
 constexpr int kMlpIn = 16, kMlpH = 128, kNAct = 64;
 constexpr int kQbestMax = 256;                   // states whose greedy action travels with the policy
+constexpr int kNoAllocPartials = 65536;          // block partials of the allocation-free dot (512 KiB)
 
 // Matrix in HBM: CSR int32 indices, fp64 values and three shadows.  Value and
 // index arrays are padded to a multiple of 8 entries (+8) so the SpMV can read

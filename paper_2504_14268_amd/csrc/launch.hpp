@@ -28,6 +28,10 @@ void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipS
 void launch_op_residual(const Mat &A, const double *b, const double *x, double *r, hipStream_t s);
 void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double *part, int P2, double *out,
                    hipStream_t s);
+// launch_op_dot with its partials in the library's static device array (at
+// most kNoAllocPartials blocks of kVecBlock elements); no allocation.
+hipError_t launch_op_dot_noalloc(int n, int fd, int tier, const void *u, const void *v, double *out,
+                                 hipStream_t s);
 void launch_op_axpy(int n, int fa, double alpha, const void *u, void *y, hipStream_t s);
 void launch_policy_decide(const PolicyDev *P, int m, const int64_t *k, const double *rho, const int32_t *stag,
                           const float *feat, int32_t *state, int32_t *action, hipStream_t s);
