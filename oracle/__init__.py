@@ -101,6 +101,10 @@ def lib():
         L.orc_uniform.argtypes = [C.c_uint64] * 4
         L.orc_mix64.restype = C.c_uint64
         L.orc_mix64.argtypes = [C.c_uint64]
+        L.orc_stag.restype = C.c_int
+        L.orc_stag.argtypes = [dp, i64, C.c_int]
+        L.orc_stagnated.restype = C.c_int
+        L.orc_stagnated.argtypes = [C.c_int, dp]
         L.orc_state.restype = C.c_int
         L.orc_state.argtypes = [C.POINTER(Policy), i64, d, C.c_int]
         L.orc_reward.restype = d
@@ -187,6 +191,18 @@ def xpay(beta: float, r, p, fa: int):
 
 def log10(x: float) -> float:
     return lib().orc_log10(x)
+
+
+def stag_flag(hist_rho, k: int, W: int) -> int:
+    """The state's stagnation flag stag_k on the history rho_0..rho_k."""
+    h = _f64(hist_rho)
+    return lib().orc_stag(_p(h), k, W)
+
+
+def stagnated(m: int, last3) -> int:
+    """The fallback trigger at the m-th replacement: last3 = true rho at m-2, m-1, m."""
+    t = _f64(last3)
+    return lib().orc_stagnated(m, _p(t))
 
 
 def uniform(seed: int, episode: int, k: int, stream: int) -> float:

@@ -573,6 +573,26 @@ typedef struct {
     double *dump_r;            /* [dump_cap][n] residual r at the start of iteration k, or NULL */
 } orc_hist;
 
+/* Stagnation flag of the state (a reading: the paper's state has no such
+ * component; the flag is set when the residual has not decreased over the
+ * last W iterations): stag_k = [k >= W and rho_k >= rho_{k-W}], on the history
+ * rho_0 .. rho_k. */
+int orc_stag(const double *hist_rho, int64_t k, int W)
+{
+    return (k >= W) && (hist_rho[k] >= hist_rho[k - W]);
+}
+
+/* Stagnation of the true residual, the fallback trigger (a reading: the
+ * paper only says runs stop on numerical instabilities): at the m-th
+ * replacement since the last (re)start, m >= 3, the true relative residual
+ * has not decreased over the last two replacement periods,
+ * rho_true(m) >= rho_true(m-2).  last3 holds rho_true(m-2), rho_true(m-1),
+ * rho_true(m) in that order. */
+int orc_stagnated(int m, const double last3[3])
+{
+    return m >= 3 && last3[2] >= last3[0];
+}
+
 static int decide(const orc_policy *pol, int kind, const float *feat, int s, int64_t k, int *explored)
 {
     *explored = 0;
@@ -658,7 +678,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             if (rt <= prm->tol) { status = fell_back ? 2 : 0; break; }
             if (!isfinite(rt)) { status = 3; break; }
             sigma = s64;
-            int stag = (k >= W) && (rt >= hist_rho[k - W]);
+            int stag = orc_stag(hist_rho, k, W);
             s = orc_state(pol, k, rt, stag);
             orc_mlp_features(pol, k, hist_rho, stag, last_true, prev_a, feat);
             a = fell_back ? 63 : decide(pol, kind, feat, s, k, &explored);
@@ -710,7 +730,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
                     sig_new = s64;
                     rep_hist[0] = rep_hist[1]; rep_hist[1] = rep_hist[2]; rep_hist[2] = rt;
                     nrep_since++;
-                    if (nrep_since >= 3 && rt >= rep_hist[0]) stagnated = 1;
+                    if (orc_stagnated(nrep_since, rep_hist)) stagnated = 1;
                 }
             }
             hist_rho[k] = rho_new;
@@ -722,7 +742,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
 
         int stag = 0, s_next = s;
         if (!broke) {
-            stag = (k >= W) && (rho_new >= hist_rho[k - W]);
+            stag = orc_stag(hist_rho, k, W);
             s_next = orc_state(pol, k, rho_new, stag);
             if (policy_active)
                 orc_mlp_features(pol, k, hist_rho, stag, last_true, a, feat_next);

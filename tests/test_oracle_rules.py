@@ -1,0 +1,184 @@
+"""Pins for the oracle's solver rules that the paper leaves to a reading:
+the state's stagnation flag, the true-residual stagnation rule that triggers
+the fp64 fallback, the tier switch (fold and re-round), the terminal reward of
+a breakdown with its rollout row, and the bootstrapped update at truncation
+(section 4.1's Q update; Algorithm 1).  Every expected value is worked by hand
+from the definitions in the comments, or comes from an independent library
+(numpy's float32 rounding), never from the oracle's own output.  CPU only."""
+import math
+
+import numpy as np
+
+import oracle as O
+import workloads as W
+
+
+# ---------------------------------------------------------------- stag_k
+def test_stag_flag_hand_history():
+    # stag_k = [k >= W and rho_k >= rho_{k-W}]
+    # W = 3 on rho = 1.0 .9 .8 .9 .9 .95 .5 .5:
+    #   k < 3: 0;  k=3: .9 >= 1.0 no;  k=4: .9 >= .9 yes (equality counts);
+    #   k=5: .95 >= .8 yes;  k=6: .5 >= .9 no;  k=7: .5 >= .9 no
+    # (a window of W-1 flags k=3, a window of W+1 misses k=4, a strict
+    #  comparison misses k=4, a reversed one flags k=3)
+    h = [1.0, 0.9, 0.8, 0.9, 0.9, 0.95, 0.5, 0.5]
+    assert [O.stag_flag(h, k, 3) for k in range(8)] == [0, 0, 0, 0, 1, 1, 0, 0]
+    # W = 2 on rho = .5 .6 .7: k=1 has rho_1 >= rho_0 but k < W, so 0; k=2: .7 >= .5
+    assert [O.stag_flag([0.5, 0.6, 0.7], k, 2) for k in range(3)] == [0, 0, 1]
+    # W = 1 on a flat history: every k >= 1 is stagnant
+    assert [O.stag_flag([0.3, 0.3, 0.3], k, 1) for k in range(3)] == [0, 1, 1]
+
+
+# ---------------------------------------------------------------- m-2 stagnation rule
+def first_firing(log):
+    """First replacement m (1-based since the start) where the pinned rule fires."""
+    for m in range(1, len(log) + 1):
+        last3 = [log[m - 3] if m >= 3 else 0.0, log[m - 2] if m >= 2 else 0.0, log[m - 1]]
+        if O.stagnated(m, last3):
+            return m
+    return None
+
+
+def test_stagnation_rule_hand_logs():
+    # fires at replacement m >= 3 when rho_true(m) >= rho_true(m-2)
+    # log 1e-2 5e-3 6e-3 4e-3 7e-3: m=3: 6e-3 >= 1e-2 no; m=4: 4e-3 >= 5e-3 no;
+    # m=5: 7e-3 >= 6e-3 yes  -> 5   (an m-1 rule would fire at m=3)
+    assert first_firing([1e-2, 5e-3, 6e-3, 4e-3, 7e-3]) == 5
+    # equality counts: 1e-2 5e-3 1e-2 -> m=3: 1e-2 >= 1e-2 yes
+    assert first_firing([1e-2, 5e-3, 1e-2]) == 3
+    # a steady decrease never fires
+    assert first_firing([10.0 ** -j for j in range(1, 12)]) is None
+    # m = 2 never fires, even when rho_true(2) exceeds rho_true(1)
+    assert not O.stagnated(2, [0.0, 1e-3, 5e-3])
+    assert not O.stagnated(1, [0.0, 0.0, 5e-3])
+
+
+def test_stagnation_fallback_in_a_solve():
+    """bf16 everywhere on a 32x32 Laplacian: the true residuals at the
+    replacements (every 50 iterations) are about 7.54e-2, 4.11e-2, 3.76e-2,
+    3.54e-2, 3.55e-2, 3.73e-2.  The rule first fires at m = 6 (3.73e-2 >= 3.54e-2),
+    so the solve falls back at k = 300; an m-1 rule would fire at m = 5
+    (3.55e-2 >= 3.54e-2), k = 250."""
+    A = W.laplacian_2d(32)
+    b = W.rhs(A.n, 2)
+    pol = O.OraclePolicy(fixed_action=16 * 1 + 4 * 1 + 1)
+    x, info = O.cg(A, b, tol=1e-8, maxit=3000, policy=pol, replace_period=50, fallback=True)
+    rep = info["rep_rho"]
+    assert info["rep_k"][:6].tolist() == [50, 100, 150, 200, 250, 300]
+    assert first_firing(list(rep[:6])) == 6
+    assert rep[4] >= rep[3]                      # the m-1 reading would have fired at m = 5
+    assert info["fallback_at"] == 300 and info["status"] == 2
+    assert info["flags"][299] & O.FL_FALLBACK
+    assert not np.any(info["flags"][:299] & O.FL_FALLBACK)
+    assert np.all(info["actions"][300:] == 63)   # fp64 CG after the restart
+    assert info["relres_true"] <= 1e-8
+
+
+# ---------------------------------------------------------------- tier switch
+def switching_table(first, then):
+    """Greedy table whose action is `first` in iteration bin 0 (k < 200) and
+    `then` afterwards, whatever the residual bin and flag."""
+    q = np.zeros((100, 64))
+    for s in range(100):
+        i = (s // 2) % 5
+        q[s, first if i == 0 else then] = 1.0
+    return q
+
+
+def test_tier_switch_fp32_to_fp64():
+    """The switch is decided after iteration 199, so iterations 0..199 are the
+    fp32 solve's; widening r and p to fp64 changes no value."""
+    A = W.laplacian_2d(64)
+    b = W.rhs(A.n, 1)
+    kw = dict(tol=1e-13, maxit=202, replace_period=0, dump=202)
+    _, sw = O.cg(A, b, policy=O.OraclePolicy(kind=O.POL_QTABLE, q=switching_table(42, 63)), **kw)
+    _, f32 = O.cg(A, b, policy=O.OraclePolicy(fixed_action=42), **kw)
+    assert sw["actions"][:200].tolist() == [42] * 200 and sw["actions"][200:].tolist() == [63, 63]
+    for key in ("r", "p"):
+        assert np.array_equal(sw["dump"][key][:201], f32["dump"][key][:201])
+    assert np.array_equal(sw["dump"]["r"][200], sw["dump"]["r"][200].astype(np.float32).astype(np.float64))
+    assert [k for k in range(202) if sw["flags"][k] & O.FL_SWITCH] == [199]
+
+
+def test_tier_switch_fp64_to_fp32_rerounds():
+    """Going from fp64 to fp32 vectors, r and p are rounded to fp32 (round to
+    nearest even, here numpy's float32 cast) right after the direction update
+    of iteration 199: iteration 200 starts from the fp64 solve's r_200 and
+    p_200 rounded."""
+    A = W.laplacian_2d(64)
+    b = W.rhs(A.n, 1)
+    kw = dict(tol=1e-13, maxit=202, replace_period=0, dump=202)
+    _, sw = O.cg(A, b, policy=O.OraclePolicy(kind=O.POL_QTABLE, q=switching_table(63, 42)), **kw)
+    _, f64 = O.cg(A, b, policy=O.OraclePolicy(fixed_action=63), **kw)
+    for key in ("r", "p"):
+        assert np.array_equal(sw["dump"][key][:200], f64["dump"][key][:200])
+        want = f64["dump"][key][200].astype(np.float32).astype(np.float64)
+        assert np.array_equal(sw["dump"][key][200], want)
+        assert not np.array_equal(want, f64["dump"][key][200])   # the rounding did something
+    assert [k for k in range(202) if sw["flags"][k] & O.FL_SWITCH] == [199]
+
+
+# ---------------------------------------------------------------- breakdown reward
+def indefinite_2x2():
+    # [[1, 2], [2, 1]]: eigenvalues 3 and -1, positive diagonal
+    return W.CSR(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32),
+                 np.array([1.0, 2.0, 2.0, 1.0]))
+
+
+def test_breakdown_terminal_reward_and_rollout_row():
+    """b = (1, -1): r_0 = p_0 = b, q = A p = (-1, 1), nu = p.q = -2 < 0, so
+    iteration 0 breaks down.  An all-zero table picks action 0 (fp16 x3, cost
+    3 * 0.8 = 2.4 under C1); the breakdown is terminal with reward
+    -0.1 * 2.4 - 10 = -10.24, and Q[s_0, 0] = 0 + 0.1 * (-10.24 - 0) = -1.024.
+    s_0: k = 0, rho_0 = 1 (bin 0), no stagnation -> state 0.  Its features: the
+    eight log10 rho lags of rho_0 = 1 are 0, the difference 0, k / 1000 = 0,
+    stag 0, log10 of the last true rho = 0, (k mod R) / R = 0, and the previous
+    action (fp64 x3 at the start) gives 3/3 three times."""
+    A = indefinite_2x2()
+    b = np.array([1.0, -1.0])
+    pol = O.OraclePolicy(kind=O.POL_QTRAIN, epsilon=0.0, cost="C1")
+    _, info = O.cg(A, b, tol=1e-8, maxit=10, policy=pol, replace_period=50, roll_cap=8)
+    assert info["status"] == 3 and info["iters"] == 0
+    assert abs(pol.q[0, 0] - (-1.024)) < 1e-12
+    assert np.count_nonzero(pol.q) == 1
+    ro = info["rollouts"]
+    assert len(ro["act"]) == 1 and ro["act"][0] == 0 and ro["done"][0] == 1
+    assert ro["rew"][0] == np.float32(-10.24)
+    want_f = np.array([0.0] * 13 + [1.0, 1.0, 1.0], np.float32)
+    assert np.array_equal(ro["feat"][0], want_f) and np.array_equal(ro["next"][0], want_f)
+    # with the fallback: the fp64 restart breaks down the same way; the policy
+    # no longer acts, so nothing more is logged or learned
+    pol2 = O.OraclePolicy(kind=O.POL_QTRAIN, epsilon=0.0, cost="C1")
+    _, info2 = O.cg(A, b, tol=1e-8, maxit=10, policy=pol2, replace_period=50, fallback=True, roll_cap=8)
+    assert info2["status"] == 3 and info2["fallback_at"] == 0
+    assert len(info2["rollouts"]["act"]) == 1 and abs(pol2.q[0, 0] - (-1.024)) < 1e-12
+
+
+# ---------------------------------------------------------------- truncation bootstrap
+def test_truncation_at_maxit_bootstraps():
+    """A = diag(1, 2), b = (1, 1), maxit = 1, a table with Q[0, 42] = 1 (so the
+    greedy action is fp32 x3, cost 3.0 under C1).  One fp32 iteration:
+    q = (1, 2), nu = 3, sigma = 2, alpha = 2/3; with a = fl32(2/3),
+    r_1 = (fl32(1 - a), fl32(1 - 2a)) = (1 - a, 1 - 2a) exactly; sigma' = the
+    fp32 sum of the fp32 squares; rho_1 = sqrt(sigma') / sqrt(2), about 1/3,
+    bin 0, k = 1 < W: state 0 again.  The episode is cut at maxit, which is not
+    terminal (section 4.1's update with the bootstrap term):
+    Q[0, 42] = 1 + 0.1 * (R + 0.9 * max_a Q[0, a] - 1), max = 1 (read before
+    the update), R = -log10 rho_1 - 0.1 * 3.0."""
+    A = W.CSR(2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, 2.0]))
+    b = np.array([1.0, 1.0])
+    q0 = np.zeros((100, 64))
+    q0[0, 42] = 1.0
+    pol = O.OraclePolicy(kind=O.POL_QTRAIN, q=q0, epsilon=0.0, cost="C1")
+    _, info = O.cg(A, b, tol=1e-8, maxit=1, policy=pol, replace_period=50)
+    assert info["status"] == 1 and info["iters"] == 1 and info["actions"].tolist() == [42]
+    a = np.float32(2.0 / 3.0)
+    r1 = np.array([np.float32(1.0) - a, np.float32(1.0) - np.float32(2.0) * a], np.float32)
+    assert r1[0] == np.float32(5592405 / 2 ** 24) and r1[1] == np.float32(-5592406 / 2 ** 24)
+    sig = np.float32(r1[0] * r1[0]) + np.float32(r1[1] * r1[1])
+    rho1 = math.sqrt(float(sig)) / math.sqrt(2.0)
+    assert info["rho"][1] == rho1
+    R = -math.log10(rho1) - 0.1 * 3.0
+    boot = 1.0 + 0.1 * (R + 0.9 * 1.0 - 1.0)
+    assert abs(pol.q[0, 42] - boot) < 1e-12
+    assert abs(pol.q[0, 42] - (1.0 + 0.1 * (R - 1.0))) > 1e-3   # the terminal form differs
