@@ -12,8 +12,12 @@ Workloads (synthetic, seeded):
 A step is one complete solve of the 3D Laplacian in mixed precision, inputs
 resident in HBM.  `value` is its time to solution in ms (lower is better).
 The SpMV roofline figure comes from HIP events around every SpMV launch of a
-profiled solve; the CPU baseline is the oracle on the host, on a bounded number
-of iterations, scaled to the GPU's iteration count.
+profiled solve, on the algorithmic bytes of one launch (each CSR entry once
+with an int32 column index, the row pointers, p read once, q written once);
+the bytes the kernel really streams (16-bit column deltas) are reported beside
+it.  The CPU baseline is the oracle's plain fp64 CG on the host, run to
+convergence on the same system, single-threaded, with an OpenMP variant on
+every host core beside it.
 """
 from __future__ import annotations
 
@@ -53,9 +57,9 @@ def ka_bytes(n: int, nnz: int, fs: int, vec_bytes: int, idx_bytes: int = 4) -> i
     p.q partial): each CSR entry once (value + column index: int32, or the
     16-bit delta col - row where the matrix has them), the row pointers, p read
     once and q written once; fp16 adds the one-byte row exponents."""
-    val = {0: 2, 1: 2, 2: 4, 3: 8}[fs]
+    val = {0: 2, 1: 2, 2: 4, 3: 8, 4: 1}[fs]
     b = nnz * (val + idx_bytes) + 4 * (n + 1) + 2 * n * vec_bytes
-    if fs == 0:
+    if fs in (0, 4):       # fp16 and q52 read the row exponents
         b += n
     return b
 
@@ -76,11 +80,11 @@ def mix_of(M, actions) -> dict:
     a = np.asarray(actions, dtype=np.int64)
     if a.size == 0:
         return {}
-    names = ("fp16", "bf16", "fp32", "fp64")
+    names = ("fp16", "bf16", "fp32", "fp64", "q52")
     out = {}
-    for op, shift in (("spmv", 4), ("dot", 2), ("axpy", 0)):
-        f = (a >> shift) & 3
-        out[op] = {names[i]: round(float(np.mean(f == i)), 3) for i in range(4) if np.any(f == i)}
+    for op, shift, mask in (("spmv", 4, 7), ("dot", 2, 3), ("axpy", 0, 3)):
+        f = (a >> shift) & mask
+        out[op] = {names[i]: round(float(np.mean(f == i)), 3) for i in range(5) if np.any(f == i)}
     return out
 
 
@@ -393,6 +397,11 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="short run for HBM counter collection: one plain copy of 256 MiB (the scale "
                          "reference for FETCH_SIZE / WRITE_SIZE), then one mixed solve")
+    ap.add_argument("--counters-system", choices=["lap3d", "rspd"], default="lap3d",
+                    help="system of the counter run: the 3D Laplacian or the random SPD (n = 1e6)")
+    ap.add_argument("--counters-maxit", type=int, default=5000,
+                    help="iteration budget of the counter run's solve")
+    ap.add_argument("--counters-fp64", action="store_true", help="counter run with the fp64 action")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU only (--gpus {args.gpus} requested); "
@@ -437,18 +446,28 @@ def main():
         return
 
     if args.counters:
+        if args.counters_system == "rspd":
+            A = W.random_spd(1_000_000, 3, W.spread_for_kappa(1e6))
+            m = M.Matrix(A)
+            bd = torch.from_numpy(W.rhs(A.n, 4)).cuda()
+            xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        m.set_policy(pol_mixed)
-        m.set_options(replace_period=50, fallback=False)
-        r = m.solve(bd, xd, tol=tol, maxit=5000)
-        print(json.dumps({"counters_run": True, "copy_bytes": COPY_BYTES, "iters": r["iters"],
-                          "relres_true": r["relres_true"], "kernel_hash": kernel_hash(),
-                          "bytes_per_launch_ka": ka_bytes(A.n, A.nnz, M.BF16, 4, 2 if m.info()["index16"] else 4)}),
+        pol = pol_fp64 if args.counters_fp64 else pol_mixed
+        fs, vb = (M.FP64, 8) if args.counters_fp64 else (M.BF16, 4)
+        m.set_policy(pol)
+        m.set_options(replace_period=0 if args.counters_fp64 else 50, fallback=False)
+        r = m.solve(bd, xd, tol=tol, maxit=args.counters_maxit)
+        print(json.dumps({"counters_run": True, "system": A.name, "n": A.n, "nnz": A.nnz,
+                          "action": "fp64" if args.counters_fp64 else "mixed", "copy_bytes": COPY_BYTES,
+                          "iters": r["iters"], "relres_true": r["relres_true"], "kernel_hash": kernel_hash(),
+                          "algorithmic_bytes_per_launch_ka": ka_bytes(A.n, A.nnz, fs, vb, 4),
+                          "moved_bytes_per_launch_ka": ka_bytes(A.n, A.nnz, fs, vb,
+                                                                2 if m.info()["index16"] else 4)}),
               flush=True)
         return
 
@@ -477,6 +496,16 @@ def main():
     log(f"[bench] mixed: {res['iters']} it, relres {res['relres_true']:.3e}, device {dev_ms:.2f} ms, "
         f"wall {wall_ms:.2f} ms")
 
+    # q52 (Table 1's quarter precision) matrix storage, same dot and update formats
+    act_q52 = M.action(M.Q52, M.FP32, M.FP32)
+    pol_q52 = M.Policy(kind=M.POLICY_FIXED, fixed_action=act_q52)
+    solve(pol_q52, 50)
+    q52_runs = [solve(pol_q52, 50) for _ in range(max(1, args.steps // 2))]
+    rq = q52_runs[-1]
+    assert rq["status"] == 0 and rq["relres_true"] <= tol, rq
+    q52_ms = float(np.median([r["time_ms"] for r in q52_runs]))
+    log(f"[bench] q52: {rq['iters']} it, relres {rq['relres_true']:.3e}, device {q52_ms:.2f} ms")
+
     fp64_runs = [solve(pol_fp64, 0) for _ in range(max(1, args.steps // 2))]
     r64 = fp64_runs[-1]
     assert r64["status"] == 0, r64
@@ -488,6 +517,9 @@ def main():
     prof = m.profile()
     rp64 = solve(pol_fp64, 0, profile=True)
     prof64 = m.profile()
+    solve(pol_q52, 50, profile=True)
+    profq = m.profile()
+    k1_q_us = profq["ka_iter_ms"] / profq["n_iter_slots"] * 1e3
     k1_us = prof["ka_iter_ms"] / prof["n_iter_slots"] * 1e3
     k2_us = prof["kb_iter_ms"] / prof["n_iter_slots"] * 1e3
     k3_us = prof["kx_iter_ms"] / prof["n_iter_slots"] * 1e3
@@ -495,8 +527,9 @@ def main():
     k2_64_us = prof64["kb_iter_ms"] / prof64["n_iter_slots"] * 1e3
     k3_64_us = prof64["kx_iter_ms"] / prof64["n_iter_slots"] * 1e3
     idx_bytes = 2 if m.info()["index16"] else 4
-    bytes_k1 = ka_bytes(A.n, A.nnz, M.BF16, 4, idx_bytes)
-    bytes_k1_64 = ka_bytes(A.n, A.nnz, M.FP64, 8, idx_bytes)
+    bytes_k1 = ka_bytes(A.n, A.nnz, M.BF16, 4, 4)            # algorithmic: int32 column indices
+    bytes_k1_moved = ka_bytes(A.n, A.nnz, M.BF16, 4, idx_bytes)   # what the kernel streams
+    bytes_k1_64 = ka_bytes(A.n, A.nnz, M.FP64, 8, 4)
     bytes_k2 = 6 * A.n * 4      # p, q, r, x_lo read; r, x_lo written
     bytes_k2_64 = 6 * A.n * 8
     bytes_k3 = 3 * A.n * 4      # p, r read; p written
@@ -549,6 +582,9 @@ def main():
             "bytes_per_launch": bytes_k1,
             "avg_launch_us": round(k1_us, 3),
             "launches": prof["n_iter_slots"],
+            "moved_bytes_per_launch": bytes_k1_moved,
+            "achieved_on_moved_bytes": round(bytes_k1_moved / (k1_us * 1e-6) / 1e9, 1),
+            "frac_on_moved_bytes": round(bytes_k1_moved / (k1_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
         },
         "kernels": {
             "kb_axpy_dot": {"avg_us": round(k2_us, 3), "GB/s": round(bytes_k2 / (k2_us * 1e-6) / 1e9, 1)},
@@ -557,6 +593,14 @@ def main():
             "kb_fp64": {"avg_us": round(k2_64_us, 3), "GB/s": round(bytes_k2_64 / (k2_64_us * 1e-6) / 1e9, 1)},
             "kx_fp64": {"avg_us": round(k3_64_us, 3), "GB/s": round(bytes_k3_64 / (k3_64_us * 1e-6) / 1e9, 1)},
             "profiled_solve_ms": round(rp["time_ms"], 3),
+        },
+        "q52_storage": {
+            "action": "SpMV in q52 storage (row-scaled, fp32 accumulation), dot fp32, axpy fp32, R=50",
+            "ms": round(q52_ms, 3), "iters": rq["iters"], "relres_true": rq["relres_true"],
+            "speedup_vs_fp64": round(fp64_ms / q52_ms, 3),
+            "ka_avg_us": round(k1_q_us, 3),
+            "ka_GB/s_algorithmic": round(ka_bytes(A.n, A.nnz, 4, 4, 4) / (k1_q_us * 1e-6) / 1e9, 1),
+            "ka_GB/s_moved": round(ka_bytes(A.n, A.nnz, 4, 4, idx_bytes) / (k1_q_us * 1e-6) / 1e9, 1),
         },
     }
 
@@ -610,28 +654,48 @@ def main():
     if not args.no_cpu:
         import oracle as O
 
-        cores = 1
-        sample_it = 40
+        host = {"cpu_model": cpu_model(), "cores_available": len(os.sched_getaffinity(0)),
+                "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+        # the oracle's plain fp64 CG (native double, no emulation), single-threaded,
+        # on the whole workload, run to the same tolerance
         t0 = time.perf_counter()
-        O.cg(A, b, tol=1e-30, maxit=sample_it, policy=O.OraclePolicy(fixed_action=act_mixed),
-             replace_period=50)
-        t_or = time.perf_counter() - t0
-        per_it = t_or / sample_it
-        out["cpu_baseline"] = {
-            "value": round(per_it * res["iters"] * 1e3, 1),
-            "unit": "ms",
-            "cores": cores,
-            "kind": "oracle",
-            "sample": f"{sample_it} iterations of the oracle's emulated mixed CG (same action, same "
-                      f"3D Laplacian {args.N}^3) took {t_or:.2f} s single-threaded including its shadow "
-                      f"setup; scaled to the GPU's {res['iters']} iterations",
-        }
-        t0 = time.perf_counter()
-        _, it_p, _ = O.cg_plain(A, b, tol=1e-30, maxit=sample_it)
+        _, it_p, rr_p = O.cg_plain(A, b, tol=tol, maxit=5000)
         t_p = time.perf_counter() - t0
-        out["cpu_baseline"]["plain_fp64_cg_ms_scaled"] = round(t_p / sample_it * r64["iters"] * 1e3, 1)
-        out["cpu_baseline"]["host"] = {"cpu_model": cpu_model(), "cores_available": len(os.sched_getaffinity(0))}
-        log(f"[bench] oracle: {per_it * 1e3:.1f} ms/it emulated, {t_p / sample_it * 1e3:.1f} ms/it plain fp64")
+        log(f"[bench] oracle plain fp64 CG: {it_p} it in {t_p:.2f} s (1 thread)")
+        # the same method on every host core (fixed-chunk, in-order reductions)
+        t0 = time.perf_counter()
+        _, it_o, rr_o, th = O.cg_openmp(A, b, tol=tol, maxit=5000)
+        t_o = time.perf_counter() - t0
+        log(f"[bench] OpenMP fp64 CG: {it_o} it in {t_o:.2f} s ({th} threads)")
+        # the emulated mixed oracle: its shadow setup (a solve with maxit 0) is
+        # subtracted; this is a parity tool, not a speed baseline
+        sample_it = 20
+        t0 = time.perf_counter()
+        O.cg(A, b, tol=1e-30, maxit=0, policy=O.OraclePolicy(fixed_action=act_mixed), replace_period=50)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.cg(A, b, tol=1e-30, maxit=sample_it, policy=O.OraclePolicy(fixed_action=act_mixed), replace_period=50)
+        t_em = time.perf_counter() - t0 - t_setup
+        out["cpu_baseline"] = {
+            "value": round(t_p * 1e3, 1),
+            "unit": "ms",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"the whole workload: the oracle's plain fp64 CG (native double, no emulation) on the "
+                      f"3D Laplacian {args.N}^3 from x0 = 0, run to convergence ({it_p} iterations, recursive "
+                      f"relres {rr_p:.2e}), single-threaded; the GPU's fp64 CG takes {r64['iters']} iterations",
+            "vs_gpu_fp64": round(t_p * 1e3 / fp64_ms, 1),
+            "vs_gpu_mixed": round(t_p * 1e3 / dev_ms, 1),
+            "openmp": {"value": round(t_o * 1e3, 1), "unit": "ms", "cores": th, "iters": it_o,
+                       "relres": rr_o, "kind": "fp64 CG, OpenMP row-parallel SpMV and updates, "
+                                                "fixed 8192-row chunk sums added in chunk order"},
+            "emulated_mixed": {"label": "emulation: not a speed baseline",
+                               "ms_per_iteration": round(t_em / sample_it * 1e3, 2),
+                               "sample": f"{sample_it} iterations of the oracle's emulated mixed CG (same "
+                                         f"action), shadow setup ({t_setup:.2f} s) excluded"},
+            "host": host,
+        }
+        log(f"[bench] oracle emulated mixed: {t_em / sample_it * 1e3:.1f} ms/it (setup {t_setup:.2f} s excluded)")
 
     print(json.dumps(out), flush=True)
 

@@ -22,8 +22,12 @@
  *     the stream given at creation, in order; entry points that return host data
  *     synchronise that stream before returning.
  *   - The library never frees caller memory; handles own what they allocate.
- *   - Formats: MPCG_FP16 = 0, MPCG_BF16 = 1, MPCG_FP32 = 2, MPCG_FP64 = 3.
- *     An action is a = 16*f_spmv + 4*f_dot + f_axpy  (0..63).
+ *   - Formats: MPCG_FP16 = 0, MPCG_BF16 = 1, MPCG_FP32 = 2, MPCG_FP64 = 3, and
+ *     MPCG_Q52 = 4 (Table 1's quarter precision: 1 sign, 5 exponent, 2 fraction
+ *     bits; matrix storage of the SpMV only).
+ *     An action is a = 16*f_spmv + 4*f_dot + f_axpy: 0..63 for the four
+ *     arithmetic formats (the learned policies' action set), 64..79 for q52
+ *     SpMV storage with f_dot, f_axpy in 0..3 (fixed policies).
  *   - Vector "tier": vectors of an iteration whose axpy format is fp64 are stored
  *     as double, otherwise as float (tier64 = 1 / 0).
  */
@@ -52,6 +56,7 @@ extern "C" {
 #define MPCG_BF16 1
 #define MPCG_FP32 2
 #define MPCG_FP64 3
+#define MPCG_Q52 4
 
 #define MPCG_MEM_HOST 0
 #define MPCG_MEM_DEVICE 1
@@ -86,7 +91,7 @@ typedef struct mpcg_policy mpcg_policy;
  */
 typedef struct {
     int32_t kind;              /* MPCG_POLICY_*                                  */
-    int32_t fixed_action;      /* used by MPCG_POLICY_FIXED                      */
+    int32_t fixed_action;      /* used by MPCG_POLICY_FIXED (0..79)              */
     int32_t t_bin;             /* iteration-bin horizon (1000)                   */
     int32_t b_it;              /* iteration bins (5)                             */
     int32_t b_res;             /* residual bins (10), in [1, 17]                 */
@@ -96,7 +101,8 @@ typedef struct {
     double eps_min;            /* residual floor of the accuracy term and of the
                                   residual bins (1e-16); must be a power of ten
                                   10^-E (the double nearest to it), 1 <= E <= 300 */
-    double cost[4];            /* c(fp16), c(bf16), c(fp32), c(fp64)             */
+    double cost[4];            /* c(fp16), c(bf16), c(fp32), c(fp64); a q52 SpMV
+                                  is charged c(fp16)                             */
     uint64_t seed;             /* exploration draws                              */
     int32_t replace_period;    /* R seen by the MLP features                     */
     int32_t reserved;
@@ -189,6 +195,10 @@ int mpcg_get_info(mpcg_matrix *A, mpcg_matrix_info *info);
 /* Copies the shadows to host arrays: float[nnz], uint16 bf16 bits[nnz],
  * uint16 fp16 bits[nnz] (row-scaled values), int8 row exponents[n]. */
 int mpcg_get_shadows(mpcg_matrix *A, float *f32, uint16_t *bf16, uint16_t *f16, int8_t *rexp);
+/* Copies the q52 shadow (Table 1's quarter precision, round to nearest even
+ * from fp64, after the same exact per-row power-of-two scale as fp16) to a
+ * host uint8 array[nnz] of its bit patterns. */
+int mpcg_get_shadow_q52(mpcg_matrix *A, uint8_t *q52);
 
 /* ---------------------------------------------------------------- policies */
 
@@ -410,8 +420,8 @@ int mpcg_get_history(mpcg_matrix *A, double *rho, uint8_t *act, uint8_t *flags, 
  * The hot-path kernels one at a time, on the handle's stream (device pointers).
  * p, q, u, v, y are float[n] (tier64 = 0) or double[n] (tier64 = 1).
  */
-/* q = SpMV_f(A, p): row fma chain in CSR order, accumulated in fp32 (f <= 2) or
- * fp64 (f = 3), output rounded to the tier. */
+/* q = SpMV_f(A, p): row fma chain in CSR order, accumulated in fp32 (f != 3) or
+ * fp64 (f = 3), output rounded to the tier; f = MPCG_Q52 reads the q52 shadow. */
 int mpcg_op_spmv(mpcg_matrix *A, int fmt, int tier64, const void *p, void *q);
 /* *out (host) = dot_f(u, v): operands rounded to f, products in the accumulation
  * format, pairwise sum over the zero-padded power-of-two length. */

@@ -17,19 +17,50 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mpcg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-F16, BF16, F32, F64 = 0, 1, 2, 3
+F16, BF16, F32, F64, Q52 = 0, 1, 2, 3, 4
 ORDER_PAIRWISE, ORDER_SEQ = 0, 1
 POL_FIXED, POL_QTABLE, POL_QTRAIN, POL_MLP = 0, 1, 2, 3
 FL_REPLACED, FL_EXPLORED, FL_FALLBACK, FL_SWITCH = 1, 2, 4, 8
 
 
+OMP_SRC = os.path.join(HERE, "cg_openmp.c")
+OMP_LIB = os.path.join(HERE, "libcgomp.so")
+
+
 def build() -> str:
-    """Compile the oracle with gcc (ISO C, no contraction, no fast math)."""
+    """Compile the oracle with gcc (ISO C, no contraction, no fast math), and the
+    multi-core fp64 CG speed baseline beside it (OpenMP)."""
     cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", "-o", LIB + ".tmp", SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-o", OMP_LIB + ".tmp", OMP_SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(OMP_LIB + ".tmp", OMP_LIB)
     return LIB
+
+
+_omp = None
+
+
+def cg_openmp(A, b, tol=1e-8, maxit=1000):
+    """Plain fp64 CG on every host core (speed baseline).  Returns (x, iters, relres, threads)."""
+    global _omp
+    if _omp is None:
+        if not os.path.exists(OMP_LIB) or os.path.getmtime(OMP_LIB) < os.path.getmtime(OMP_SRC):
+            build()
+        L = C.CDLL(OMP_LIB)
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        L.cgomp_solve.restype = C.c_int
+        L.cgomp_solve.argtypes = [C.c_int64, ip, ip, dp, dp, dp, C.c_double, C.c_int32, ip, dp]
+        _omp = L
+    x = np.zeros(A.n)
+    it = C.c_int32(0)
+    rr = C.c_double(0.0)
+    th = _omp.cgomp_solve(A.n, _p(_i32(A.row_ptr), C.c_int32), _p(_i32(A.col), C.c_int32), _p(_f64(A.val)),
+                          _p(_f64(b)), _p(x), tol, maxit, C.byref(it), C.byref(rr))
+    return x, it.value, rr.value, th
 
 
 class Policy(C.Structure):
@@ -90,6 +121,7 @@ def lib():
         L.orc_row_exp.argtypes = [dp, i64]
         L.orc_shadows.argtypes = [i64, ip, ip, dp, dp, dp, dp, ip]
         L.orc_spmv.argtypes = [i64, ip, ip, dp, C.c_int, C.c_int, dp, dp]
+        L.orc_shadow_q52.argtypes = [i64, ip, ip, dp, dp, ip]
         L.orc_residual.argtypes = [i64, ip, ip, dp, dp, dp, dp]
         L.orc_dot.restype = d
         L.orc_dot.argtypes = [i64, dp, dp, C.c_int, C.c_int]
@@ -155,6 +187,15 @@ def shadows(A):
     lib().orc_shadows(A.n, _p(_i32(A.row_ptr), C.c_int32), _p(_i32(A.col), C.c_int32),
                       _p(_f64(A.val)), _p(s32), _p(sb), _p(sh), _p(e, C.c_int32))
     return s32, sb, sh, e
+
+
+def shadow_q52(A):
+    """(q52 shadow values as float64, row exponents) of the CSR matrix A."""
+    v = np.empty(A.nnz)
+    e = np.empty(A.n, dtype=np.int32)
+    lib().orc_shadow_q52(A.n, _p(_i32(A.row_ptr), C.c_int32), _p(_i32(A.col), C.c_int32), _p(_f64(A.val)),
+                         _p(v), _p(e, C.c_int32))
+    return v, e
 
 
 def spmv(A, p, fs: int, tier64: int):

@@ -70,11 +70,15 @@
 #define BF16 1
 #define F32 2
 #define F64 3
+#define Q52 4   /* Table 1's quarter precision: 5 exponent bits, t = 3 (the printed
+                   t is garbled; u = 2^-3 = 0.125 as printed fixes it); used
+                   only as the SpMV's matrix storage */
+#define NFMT 5
 
 /* Table 1: significand bits t (with the implicit bit), e_min, e_max. */
-static const int FMT_T[4] = {11, 8, 24, 53};
-static const int FMT_EMIN[4] = {-14, -126, -126, -1022};
-static const int FMT_EMAX[4] = {15, 127, 127, 1023};
+static const int FMT_T[NFMT] = {11, 8, 24, 53, 3};
+static const int FMT_EMIN[NFMT] = {-14, -126, -126, -1022, -14};
+static const int FMT_EMAX[NFMT] = {15, 127, 127, 1023, 15};
 
 /* ------------------------------------------------------------------------ */
 /* Rounding (section 4: fl_p(x) = x(1+delta), |delta| <= u_p; Table 1).      */
@@ -133,15 +137,15 @@ typedef struct {
     const int32_t *row_ptr;
     const int32_t *col;
     const double *val;       /* fp64 */
-    double *sh[4];           /* sh[f][k]: value used by SpMV_f (fp16 scaled) */
-    int32_t *e;              /* fp16 row exponents */
+    double *sh[NFMT];        /* sh[f][k]: value used by SpMV_f (fp16 and q52 scaled) */
+    int32_t *e;              /* row exponents of the fp16 and q52 shadows */
 } orc_mat;
 
 static void mat_build(orc_mat *A, int64_t n, const int32_t *rp, const int32_t *ci, const double *v)
 {
     int64_t nnz = rp[n];
     A->n = n; A->row_ptr = rp; A->col = ci; A->val = v;
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < NFMT; ++f)
         A->sh[f] = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
     A->e = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) {
@@ -153,13 +157,16 @@ static void mat_build(orc_mat *A, int64_t n, const int32_t *rp, const int32_t *c
             A->sh[F32][k] = orc_rd(v[k], F32);
             A->sh[BF16][k] = orc_rd(v[k], BF16);
             A->sh[F16][k] = orc_rd(ldexp(v[k], -e), F16);
+            /* q52 shares the fp16 exponent range, so the same row scale keeps
+               the row's largest magnitude below its x_max */
+            A->sh[Q52][k] = orc_rd(ldexp(v[k], -e), Q52);
         }
     }
 }
 
 static void mat_free(orc_mat *A)
 {
-    for (int f = 0; f < 4; ++f) free(A->sh[f]);
+    for (int f = 0; f < NFMT; ++f) free(A->sh[f]);
     free(A->e);
 }
 
@@ -173,6 +180,17 @@ void orc_shadows(int64_t n, const int32_t *rp, const int32_t *ci, const double *
     memcpy(out_f32, A.sh[F32], sizeof(double) * (size_t)nnz);
     memcpy(out_bf16, A.sh[BF16], sizeof(double) * (size_t)nnz);
     memcpy(out_f16, A.sh[F16], sizeof(double) * (size_t)nnz);
+    memcpy(out_e, A.e, sizeof(int32_t) * (size_t)n);
+    mat_free(&A);
+}
+
+/* The q52 shadow (row-scaled values) and the row exponents. */
+void orc_shadow_q52(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                    double *out_q52, int32_t *out_e)
+{
+    orc_mat A;
+    mat_build(&A, n, rp, ci, v);
+    memcpy(out_q52, A.sh[Q52], sizeof(double) * (size_t)rp[n]);
     memcpy(out_e, A.e, sizeof(int32_t) * (size_t)n);
     mat_free(&A);
 }
@@ -195,7 +213,7 @@ static void mat_spmv(const orc_mat *A, int fs, int tier64, const double *p, doub
                 acc = fmaf((float)a[k], (float)p[A->col[k]], acc);
             row = (double)acc;
         }
-        if (fs == F16)
+        if (fs == F16 || fs == Q52)
             row = ldexp(row, A->e[i]);
         q[i] = rd_tier(row, tier64);
     }
@@ -421,6 +439,8 @@ static int argmax_row(const double *row)
 
 static double max_row(const double *row) { return row[argmax_row(row)]; }
 
+/* Cost of an action: c(f_s) + c(f_d) + c(f_a).  The cost settings give no
+ * value for q52 (actions 64..79); (a >> 4) & 3 charges it as fp16. */
 static double cost_of(const orc_policy *pol, int a)
 {
     return (pol->cost[(a >> 4) & 3] + pol->cost[(a >> 2) & 3]) + pol->cost[a & 3];
@@ -688,7 +708,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         }
         if (k >= prm->maxit) { status = 1; break; }
 
-        const int fs = (a >> 4) & 3, fd = (a >> 2) & 3, fa = a & 3;
+        const int fs = (a >> 4) & 7, fd = (a >> 2) & 3, fa = a & 3;   /* fs = 4: q52 storage */
         const int policy_active = !fell_back;
         const int training = policy_active && kind == POL_QTRAIN;
         h->hist_act[k] = (uint8_t)a;

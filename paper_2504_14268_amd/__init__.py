@@ -14,8 +14,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpcg.so")
 
-FP16, BF16, FP32, FP64 = 0, 1, 2, 3
-FORMATS = {"fp16": FP16, "bf16": BF16, "fp32": FP32, "fp64": FP64}
+FP16, BF16, FP32, FP64, Q52 = 0, 1, 2, 3, 4
+FORMATS = {"fp16": FP16, "bf16": BF16, "fp32": FP32, "fp64": FP64, "q52": Q52}
 POLICY_FIXED, POLICY_QTABLE, POLICY_QTABLE_TRAIN, POLICY_MLP = 0, 1, 2, 3
 CONVERGED, MAXIT, CONVERGED_FALLBACK, BREAKDOWN = 0, 1, 2, 3
 FLAG_REPLACED, FLAG_EXPLORED, FLAG_FALLBACK, FLAG_SWITCH = 1, 2, 4, 8
@@ -27,7 +27,7 @@ def action(f_spmv: int, f_dot: int, f_axpy: int) -> int:
 
 
 def decode(a: int):
-    return (a >> 4) & 3, (a >> 2) & 3, a & 3
+    return (a >> 4) & 7, (a >> 2) & 3, a & 3
 
 
 class PolicyDesc(C.Structure):
@@ -122,6 +122,7 @@ def lib():
             "mpcg_destroy": [vp],
             "mpcg_get_info": [vp, C.POINTER(MatrixInfo)],
             "mpcg_get_shadows": [vp, vp, vp, vp, vp],
+            "mpcg_get_shadow_q52": [vp, vp],
             "mpcg_residual_thresholds": [i32, d, vp],
             "mpcg_policy_create": [C.POINTER(PolicyDesc), C.POINTER(vp)],
             "mpcg_policy_destroy": [vp],
@@ -482,6 +483,11 @@ class Matrix:
         e = np.zeros(self.n, np.int8)
         _check(lib().mpcg_get_shadows(self.h, _np_ptr(f32), _np_ptr(bf), _np_ptr(hf), _np_ptr(e)), "shadows")
         return f32, bf, hf, e
+
+    def shadow_q52(self):
+        out = np.zeros(self.nnz, np.uint8)
+        _check(lib().mpcg_get_shadow_q52(self.h, _np_ptr(out)), "shadow_q52")
+        return out
 
     def op_spmv(self, fmt, tier64, p, q):
         _check(lib().mpcg_op_spmv(self.h, fmt, tier64, _t_ptr(p), _t_ptr(q)), "op_spmv")

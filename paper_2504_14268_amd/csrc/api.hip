@@ -272,6 +272,7 @@ struct mpcg_matrix {
   double *d_v64 = nullptr;
   float *d_v32 = nullptr;
   uint16_t *d_vbf = nullptr, *d_vh = nullptr;
+  uint8_t *d_v8 = nullptr;     // q52 shadow (row-scaled like fp16)
   int8_t *d_rexp = nullptr;
   // workspace
   double *d_xhi = nullptr;
@@ -315,12 +316,13 @@ struct mpcg_matrix {
     m.v32 = d_v32;
     m.vbf = d_vbf;
     m.vh = d_vh;
+    m.v8 = d_v8;
     m.rexp = d_rexp;
     return m;
   }
 
   void release() {
-    dfree(d_rp); dfree(d_ci); dfree(d_dc); dfree(d_pbf); dfree(d_ph); dfree(d_v64); dfree(d_v32); dfree(d_vbf); dfree(d_vh); dfree(d_rexp);
+    dfree(d_rp); dfree(d_ci); dfree(d_dc); dfree(d_pbf); dfree(d_ph); dfree(d_v64); dfree(d_v32); dfree(d_vbf); dfree(d_vh); dfree(d_v8); dfree(d_rexp);
     dfree(d_xhi); dfree(d_r32); dfree(d_p32); dfree(d_q32); dfree(d_xlo32);
     dfree(d_r64); dfree(d_p64); dfree(d_q64); dfree(d_xlo64);
     dfree(d_part0); dfree(d_part1); dfree(d_part2); dfree(d_scalar); dfree(d_ctl); dfree(d_pol);
@@ -556,17 +558,19 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   TRY_A(dmalloc(&A->d_v32, np));
   TRY_A(dmalloc(&A->d_vbf, np));
   TRY_A(dmalloc(&A->d_vh, np));
+  TRY_A(dmalloc(&A->d_v8, np));
   TRY_A(dmalloc(&A->d_rexp, (size_t)n));
   TRY_A(hipMemsetAsync(A->d_ci, 0, sizeof(int) * np, A->stream));
   TRY_A(hipMemsetAsync(A->d_v64, 0, sizeof(double) * np, A->stream));
   TRY_A(hipMemsetAsync(A->d_v32, 0, sizeof(float) * np, A->stream));
   TRY_A(hipMemsetAsync(A->d_vbf, 0, sizeof(uint16_t) * np, A->stream));
   TRY_A(hipMemsetAsync(A->d_vh, 0, sizeof(uint16_t) * np, A->stream));
+  TRY_A(hipMemsetAsync(A->d_v8, 0, np, A->stream));
   const hipMemcpyKind kind = mem_kind == MPCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   TRY_A(hipMemcpyAsync(A->d_rp, row_ptr, sizeof(int32_t) * (n + 1), kind, A->stream));
   TRY_A(hipMemcpyAsync(A->d_ci, col, sizeof(int32_t) * nnz, kind, A->stream));
   TRY_A(hipMemcpyAsync(A->d_v64, val, sizeof(double) * nnz, kind, A->stream));
-  launch_shadows(A->n, A->d_rp, A->d_v64, A->d_v32, A->d_vbf, A->d_vh, A->d_rexp, A->stream);
+  launch_shadows(A->n, A->d_rp, A->d_v64, A->d_v32, A->d_vbf, A->d_vh, A->d_v8, A->d_rexp, A->stream);
   TRY_A(hipGetLastError());
   TRY_A(dmalloc(&A->d_part0, (size_t)A->P2 + 64));
   TRY_A(dmalloc(&A->d_part1, (size_t)(A->n + kKaRows - 1) / kKaRows + 64));
@@ -629,6 +633,13 @@ int mpcg_get_info(mpcg_matrix *A, mpcg_matrix_info *info) {
   return MPCG_OK;
 }
 
+int mpcg_get_shadow_q52(mpcg_matrix *A, uint8_t *q52) {
+  if (!A || !q52) return fail(MPCG_ERR_INVALID, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  HIP_TRY(hipMemcpy(q52, A->d_v8, (size_t)A->nnz, hipMemcpyDeviceToHost));
+  return MPCG_OK;
+}
+
 int mpcg_get_shadows(mpcg_matrix *A, float *f32, uint16_t *bf16, uint16_t *f16, int8_t *rexp) {
   if (!A) return fail(MPCG_ERR_INVALID, "A is NULL");
   HIP_TRY(hipStreamSynchronize(A->stream));
@@ -644,7 +655,7 @@ int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out) {
   if (!desc || !out) return fail(MPCG_ERR_INVALID, "NULL argument");
   *out = nullptr;
   if (desc->kind < 0 || desc->kind > 3) return fail(MPCG_ERR_INVALID, "bad policy kind");
-  if (desc->fixed_action < 0 || desc->fixed_action > 63) return fail(MPCG_ERR_INVALID, "bad fixed_action");
+  if (desc->fixed_action < 0 || desc->fixed_action > 79) return fail(MPCG_ERR_INVALID, "bad fixed_action");
   if (desc->b_it < 1 || desc->b_res < 1 || desc->b_res > kMaxEdges + 1 || desc->t_bin < 1 || desc->w_stag < 1)
     return fail(MPCG_ERR_INVALID, "bad bin parameters");
   mpcg_policy *P = new (std::nothrow) mpcg_policy();
@@ -1702,7 +1713,7 @@ int mpcg_get_history(mpcg_matrix *A, double *rho, uint8_t *act, uint8_t *flags, 
 
 // ---------------------------------------------------------------- single ops
 int mpcg_op_spmv(mpcg_matrix *A, int fmt, int tier64, const void *p, void *q) {
-  if (!A || !p || !q || fmt < 0 || fmt > 3 || (tier64 != 0 && tier64 != 1))
+  if (!A || !p || !q || fmt < 0 || fmt > 4 || (tier64 != 0 && tier64 != 1))
     return fail(MPCG_ERR_INVALID, "bad argument");
   launch_op_spmv(A->mat(), fmt, tier64, p, q, A->stream);
   HIP_TRY(hipGetLastError());

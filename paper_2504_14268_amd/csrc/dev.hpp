@@ -9,7 +9,9 @@
 
 namespace mpcg {
 
-enum { FP16 = 0, BF16 = 1, FP32 = 2, FP64 = 3 };
+// Formats.  FP8 is Table 1's quarter precision q52 (5 exponent bits, 2
+// fraction bits: the top byte of an fp16), used only as matrix storage.
+enum { FP16 = 0, BF16 = 1, FP32 = 2, FP64 = 3, FP8 = 4 };
 
 constexpr int kBlock = 256;          // threads per block, every kernel
 constexpr int kWaves = kBlock / 64;  // 64-wide wavefronts
@@ -96,6 +98,8 @@ __device__ __forceinline__ float f16_bits_to_f32(uint16_t b) {
   _Float16 h = __builtin_bit_cast(_Float16, b);
   return (float)h;        // exact widening
 }
+// q52 bits: exactly the upper byte of the fp16 encoding of the same value.
+__device__ __forceinline__ float q52_bits_to_f32(uint8_t b) { return f16_bits_to_f32((uint16_t)((uint16_t)b << 8)); }
 __device__ __forceinline__ uint16_t f32_to_bf16_bits_exact(float x) {   // x already bf16-representable
   return (uint16_t)(__float_as_uint(x) >> 16);
 }

@@ -79,6 +79,13 @@ __device__ __forceinline__ void load_vals8(const Mat &A, int c, typename AccT<FS
     load8(A.v64 + c, v);
   } else if constexpr (FS == FP32) {
     load8(A.v32 + c, v);
+  } else if constexpr (FS == FP8) {
+    const uint2 w = *(const uint2 *)(A.v8 + c);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[j] = q52_bits_to_f32((uint8_t)(w.x >> (8 * j)));
+      v[4 + j] = q52_bits_to_f32((uint8_t)(w.y >> (8 * j)));
+    }
   } else {
     const uint4 w = *(const uint4 *)((FS == BF16 ? A.vbf : A.vh) + c);
     const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
@@ -211,10 +218,10 @@ __device__ __forceinline__ void block_tree_multi(const A (&leaf)[RPT], double (&
   __syncthreads();
 }
 
-// q_i = rd_tier(2^{e_i} acc) (e_i = 0 unless fp16)
+// q_i = rd_tier(2^{e_i} acc) (e_i = 0 unless fp16 or q52)
 template <int FS, typename V>
 __device__ __forceinline__ V spmv_out(const Mat &A, int i, typename AccT<FS>::type acc) {
-  if constexpr (FS == FP16) {
+  if constexpr (FS == FP16 || FS == FP8) {
     const double s = ldexp((double)acc, (int)A.rexp[i]);
     return (V)s;
   } else {
@@ -939,6 +946,7 @@ template <int FS> struct LdsWin { using type = float; static constexpr int cap =
 template <> struct LdsWin<FP64> { using type = double; static constexpr int cap = 2048; };
 template <> struct LdsWin<BF16> { using type = uint16_t; static constexpr int cap = 4096; };
 template <> struct LdsWin<FP16> { using type = uint16_t; static constexpr int cap = 4096; };
+template <> struct LdsWin<FP8> { using type = uint8_t; static constexpr int cap = 4096; };
 constexpr int kLdsWinBytes = 24576;
 constexpr int kLdsKa = (kLdsWinBytes + (kMaxGroupRows + 4) * 4) / 8;   // doubles
 
@@ -946,17 +954,20 @@ template <int FS> struct RawVals { float v[8]; };
 template <> struct RawVals<FP64> { double v[8]; };
 template <> struct RawVals<FP16> { uint4 w; };
 template <> struct RawVals<BF16> { uint4 w; };
+template <> struct RawVals<FP8> { uint2 w; };
 
 template <int FS>
 __device__ __forceinline__ void raw_load(const Mat &A, int c, RawVals<FS> &r) {
   if constexpr (FS == FP64) load8(A.v64 + c, r.v);
   else if constexpr (FS == FP32) load8(A.v32 + c, r.v);
+  else if constexpr (FS == FP8) r.w = *(const uint2 *)(A.v8 + c);
   else r.w = *(const uint4 *)((FS == BF16 ? A.vbf : A.vh) + c);
 }
 
 template <int FS>
 __device__ __forceinline__ void raw_to_lds(const RawVals<FS> &r, typename LdsWin<FS>::type *p) {
   if constexpr (FS == FP64 || FS == FP32) lds_store8(p, r.v);
+  else if constexpr (FS == FP8) *(uint2 *)p = r.w;
   else *(uint4 *)p = r.w;
 }
 
@@ -965,6 +976,7 @@ template <int FS>
 __device__ __forceinline__ typename AccT<FS>::type lds_widen(typename LdsWin<FS>::type x) {
   if constexpr (FS == BF16) return bf16_bits_to_f32(x);
   else if constexpr (FS == FP16) return f16_bits_to_f32(x);
+  else if constexpr (FS == FP8) return q52_bits_to_f32(x);
   else return x;
 }
 
@@ -1253,7 +1265,7 @@ __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, voi
       const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
       pi[j] = pn[j];
       ex[j] = 0;
-      if constexpr (FS == FP16) {
+      if constexpr (FS == FP16 || FS == FP8) {
         if (lr < grows) ex[j] = a.A.rexp[g0 + lr];
       }
     }
@@ -1267,7 +1279,7 @@ __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, voi
       valid[j] = lr < grows;
       qi[j] = (V)0;
       if (valid[j]) {
-        if constexpr (FS == FP16) qi[j] = (V)ldexp((double)acc[j], (int)ex[j]);
+        if constexpr (FS == FP16 || FS == FP8) qi[j] = (V)ldexp((double)acc[j], (int)ex[j]);
         else qi[j] = (V)acc[j];
         q[g0 + lr] = qi[j];
       }
@@ -1350,8 +1362,10 @@ __device__ __forceinline__ void ka_body(const KArgs &a, int g, double *lds) {
   const int mode = S.mode;
   if (a.slot_log && g == 0 && threadIdx.x == 0) a.slot_log[a.slot] = (int8_t)mode;
   if (mode == M_ITER) {
-    const int fs = (S.action >> 4) & 3;
+    const int fs = (S.action >> 4) & 7;   // 4: q52 storage (actions 64..79)
     switch (fs * 2 + S.tier) {
+    case 8: ka_iter<FP8, 0>(a, S, g, lds); break;
+    case 9: ka_iter<FP8, 1>(a, S, g, lds); break;
     case 0: ka_iter<FP16, 0>(a, S, g, lds); break;
     case 1: ka_iter<FP16, 1>(a, S, g, lds); break;
     case 2: ka_iter<BF16, 0>(a, S, g, lds); break;
@@ -1821,8 +1835,10 @@ __device__ __forceinline__ void ka_iter_all(const KArgs &a, const Ctl &S, void *
 __device__ __forceinline__ void ka_pass(const KArgs &a, const Ctl &S, void *lds) {
   const int mode = S.mode;
   if (mode == M_ITER) {
-    const int fs = (S.action >> 4) & 3;
+    const int fs = (S.action >> 4) & 7;
     switch (fs * 2 + S.tier) {
+    case 8: ka_iter_all<FP8, 0>(a, S, lds); break;
+    case 9: ka_iter_all<FP8, 1>(a, S, lds); break;
     case 0: ka_iter_all<FP16, 0>(a, S, lds); break;
     case 1: ka_iter_all<FP16, 1>(a, S, lds); break;
     case 2: ka_iter_all<BF16, 0>(a, S, lds); break;
@@ -2018,7 +2034,7 @@ void launch_dcol(int n, const int *rp, const int *ci, int16_t *dc, int *bad, hip
 // (2^14, 2^15]), fp32 = RNE(v), bf16 = RNE(v), fp16 = RNE(v 2^-e), all directly
 // from fp64.
 __global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const double *v, float *v32,
-                                                    uint16_t *vbf, uint16_t *vh, int8_t *rexp) {
+                                                    uint16_t *vbf, uint16_t *vh, uint8_t *v8, int8_t *rexp) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int s = rp[i], t = rp[i + 1];
@@ -2046,6 +2062,9 @@ __global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const 
     v32[k] = (float)x;
     vbf[k] = f32_to_bf16_bits_exact((float)round_narrow_f64<8, -126, 127>(x));
     vh[k] = f32_to_f16_bits_exact((float)round_narrow_f64<11, -14, 15>(ldexp(x, -e)));
+    // q52 (t = 3, same exponent range as fp16): its value's fp16 encoding has
+    // a zero low byte, and the high byte is the q52 encoding
+    v8[k] = (uint8_t)(f32_to_f16_bits_exact((float)round_narrow_f64<3, -14, 15>(ldexp(x, -e))) >> 8);
   }
 }
 
@@ -2200,9 +2219,9 @@ void launch_lock_modes(const BatchSys *sys, const int32_t *act, int nact, int32_
 }
 
 void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,
-                    int8_t *rexp, hipStream_t s) {
+                    uint8_t *v8, int8_t *rexp, hipStream_t s) {
   hipLaunchKernelGGL(k_shadows, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, rp, v, v32, vbf, vh,
-                     rexp);
+                     v8, rexp);
 }
 
 void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipStream_t s) {
@@ -2210,6 +2229,8 @@ void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipS
   const int G = (P + 7) / 8 * 8;
 #define MPCG_SPMV(FS, T) hipLaunchKernelGGL((k_op_spmv<FS, T>), dim3(G), dim3(kBlock), 0, s, A, p, q, P, G)
   switch (fs * 2 + tier) {
+  case 8: MPCG_SPMV(FP8, 0); break;
+  case 9: MPCG_SPMV(FP8, 1); break;
   case 0: MPCG_SPMV(FP16, 0); break;
   case 1: MPCG_SPMV(FP16, 1); break;
   case 2: MPCG_SPMV(BF16, 0); break;

@@ -22,7 +22,8 @@ struct Mat {
   const double *v64;
   const float *v32;
   const uint16_t *vbf, *vh;   // bf16 bits, fp16 bits (row-scaled)
-  const int8_t *rexp;         // fp16 row exponents
+  const uint8_t *v8;          // q52 bits (row-scaled like fp16)
+  const int8_t *rexp;         // row exponents of the fp16 and q52 shadows
 };
 
 // Solver vectors.  r, p, q, x_lo exist in a float and a double container; the

@@ -66,10 +66,15 @@ def test_shadows_bit_exact(M, name):
     assert np.array_equal((bf.astype(np.uint32) << 16).view(np.float32).astype(np.float64), sb)
     assert np.array_equal(hf.view(np.float16).astype(np.float64), sh)
     assert np.array_equal(e.astype(np.int32), oe)
+    # q52: each byte is the high byte of the fp16 encoding of the same value
+    q8 = m.shadow_q52()
+    oq, oqe = O.shadow_q52(A)
+    assert np.array_equal((q8.astype(np.uint16) << 8).view(np.float16).astype(np.float64), oq)
+    assert np.array_equal(oqe, oe)
 
 
 @pytest.mark.parametrize("name", list(MATS))
-@pytest.mark.parametrize("fs", [0, 1, 2, 3])
+@pytest.mark.parametrize("fs", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("tier", [0, 1])
 def test_spmv_bit_exact(M, name, fs, tier):
     A = MATS[name]()

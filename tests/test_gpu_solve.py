@@ -69,24 +69,28 @@ def test_fp64_cg_laplacian2d_64(M):
 
 @pytest.mark.parametrize("A_fn", [lambda: W.laplacian_3d(24), lambda: W.random_spd(20000, 7, 1.5)],
                          ids=["lap3d_24", "rspd_20000"])
-@pytest.mark.parametrize("act", [0 * 16 + 2 * 4 + 2, 1 * 16 + 2 * 4 + 2, 2 * 16 + 2 * 4 + 2, 63])
+@pytest.mark.parametrize("act", [0 * 16 + 2 * 4 + 2, 1 * 16 + 2 * 4 + 2, 2 * 16 + 2 * 4 + 2, 63,
+                                 4 * 16 + 2 * 4 + 2])
 def test_fixed_mixed(M, A_fn, act):
     A = A_fn()
     b = W.rhs(A.n, 2)
     P = M.Policy(kind=M.POLICY_FIXED, fixed_action=act)
-    x, res, h = gpu_solve(M, A, b, maxit=6000, policy=P, R=50)
-    xo, info = O.cg(A, b, tol=1e-8, maxit=6000, policy=O.OraclePolicy(fixed_action=act), replace_period=50)
+    fb = act >= 64       # q52 storage (u = 1/8) stagnates on the scaled random SPD: fp64 fallback
+    x, res, h = gpu_solve(M, A, b, maxit=6000, policy=P, R=50, fallback=fb)
+    xo, info = O.cg(A, b, tol=1e-8, maxit=6000, policy=O.OraclePolicy(fixed_action=act), replace_period=50,
+                    fallback=fb)
     assert_same(x, res, h, xo, info)
-    assert res["status"] == 0 and res["relres_true"] <= 1e-8
+    assert res["status"] in ((0, 2) if fb else (0,)) and res["relres_true"] <= 1e-8
     r = O.residual(A, b, x)
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-8
 
 
-def test_all_64_actions(M):
+def test_all_80_actions(M):
+    """The 64 actions over the four arithmetic formats and the 16 with q52 SpMV storage."""
     A = W.random_spd(3000, 11, 2.0)
     b = W.rhs(A.n, 12)
     m = M.Matrix(A)
-    for act in range(64):
+    for act in range(80):
         P = M.Policy(kind=M.POLICY_FIXED, fixed_action=act)
         x, res, h = gpu_solve(M, A, b, maxit=400, policy=P, R=50, fallback=(act % 2 == 0), m=m)
         xo, info = O.cg(A, b, tol=1e-8, maxit=400, policy=O.OraclePolicy(fixed_action=act),
