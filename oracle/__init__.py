@@ -83,7 +83,8 @@ class Policy(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("replace_period", C.c_int32),
-                ("fallback", C.c_int32), ("dot_order", C.c_int32)]
+                ("fallback", C.c_int32), ("dot_order", C.c_int32), ("precond", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -122,6 +123,7 @@ def lib():
         L.orc_shadows.argtypes = [i64, ip, ip, dp, dp, dp, dp, ip]
         L.orc_spmv.argtypes = [i64, ip, ip, dp, C.c_int, C.c_int, dp, dp]
         L.orc_shadow_q52.argtypes = [i64, ip, ip, dp, dp, ip]
+        L.orc_jacobi_inverse.argtypes = [i64, ip, ip, dp, C.POINTER(C.c_float)]
         L.orc_residual.argtypes = [i64, ip, ip, dp, dp, dp, dp]
         L.orc_dot.restype = d
         L.orc_dot.argtypes = [i64, dp, dp, C.c_int, C.c_int]
@@ -328,15 +330,23 @@ class OraclePolicy:
         return out
 
 
+def jacobi_inverse(A):
+    """The Jacobi preconditioner's inverse diagonal as stored (float32)."""
+    out = np.empty(A.n, dtype=np.float32)
+    lib().orc_jacobi_inverse(A.n, _p(_i32(A.row_ptr), C.c_int32), _p(_i32(A.col), C.c_int32), _p(_f64(A.val)),
+                             _p(out, C.c_float))
+    return out
+
+
 def cg(A, b, x0=None, tol=1e-8, maxit=1000, policy: OraclePolicy | None = None,
-       replace_period=0, fallback=False, order=ORDER_PAIRWISE, roll_cap=0, dump=0):
-    """Run the oracle solver.  Returns (x, info dict with histories)."""
+       replace_period=0, fallback=False, order=ORDER_PAIRWISE, roll_cap=0, dump=0, precond=0):
+    """Run the oracle solver (precond 1: Jacobi).  Returns (x, info dict with histories)."""
     n = A.n
     b = _f64(b)
     x0 = np.zeros(n) if x0 is None else _f64(x0)
     x = np.empty(n)
     pol = policy if policy is not None else OraclePolicy()
-    prm = Params(tol, maxit, replace_period, int(fallback), order)
+    prm = Params(tol, maxit, replace_period, int(fallback), order, int(precond), 0)
     res = Result()
     hist_rho = np.full(maxit + 1, np.nan)
     hist_act = np.zeros(max(maxit, 1), dtype=np.uint8)

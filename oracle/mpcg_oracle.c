@@ -58,6 +58,16 @@
  *     fallback (optional): on breakdown or stagnation, once per solve, fold x_lo
  *     into x_hi and restart as plain fp64 CG (fixed action 63) from x_hi.
  *
+ *   Preconditioned variant (section 3 with M != I; Jacobi M = diag(A), its
+ *   inverse kept in fp32): z = rd_fa(m * r) in acc(f_a); sigma = r^T z at f_d
+ *   (rho still from r^T r); at a start or replacement sigma = r64^T (m r64)
+ *   in fp64; p_0 = z_0; p = axpy_fa(beta, p, z); breakdown also when
+ *   sigma' <= 0.  A replacement restarts the direction (p = z, beta = 0): the
+ *   preconditioned recursion converges within a few iterations, far below the
+ *   true residual of a low-precision matrix, and keeping p across that gap
+ *   makes beta blow up; restarted, the solve is an fp64-residual iterative
+ *   refinement around low-precision PCG.
+ *
  *   Folding x_hi += x_lo is elementwise and skips an element whose sum is not
  *   finite, so a blown-up low-precision increment never destroys x_hi.
  */
@@ -556,6 +566,8 @@ typedef struct {
     int32_t replace_period;   /* R; 0 = replace only on the rho' <= tol trigger */
     int32_t fallback;
     int32_t dot_order;
+    int32_t precond;          /* 0: M = I; 1: Jacobi, M = diag(A) */
+    int32_t pad;
 } orc_params;
 
 typedef struct {
@@ -650,6 +662,44 @@ static void roll_log(orc_hist *h, const float *f, const float *fn, int a, double
     h->roll_done[i] = (uint8_t)done;
 }
 
+/* Jacobi preconditioner (section 3: z = M^-1 r with M approximating A; section
+ * 4.2: M is kept in fixed fp32).  M = diag(A), stored as its inverse
+ * m_i = rd_fp32(1 / a_ii) (the fp64 quotient rounded to fp32); a row without
+ * a diagonal entry gets m_i = 0. */
+static float *jacobi_inverse(int64_t n, const int32_t *rp, const int32_t *ci, const double *v)
+{
+    float *m = malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = 0.0f;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) m[i] = (float)(1.0 / v[k]);
+    }
+    return m;
+}
+
+/* The preconditioner solve z = M^-1 r at the precision of the vector updates
+ * (the paper's p2 slot is taken by f_a): the product m_i r_i in acc(f_a),
+ * rounded to f_a. */
+static void precond_apply(int64_t n, const float *m, const double *r, double *z, int fa)
+{
+    for (int64_t i = 0; i < n; ++i)
+        z[i] = fa == F64 ? (double)m[i] * r[i] : orc_rd((double)(m[i] * (float)r[i]), fa);
+}
+
+/* r64^T M^-1 r64 in fp64 (a start, restart or replacement). */
+static double precond_dot64(int64_t n, const float *m, const double *r64, double *work, int order)
+{
+    for (int64_t i = 0; i < n; ++i) work[i] = (double)m[i] * r64[i];
+    return orc_dot(n, r64, work, F64, order);
+}
+
+void orc_jacobi_inverse(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, float *out)
+{
+    float *m = jacobi_inverse(n, rp, ci, v);
+    memcpy(out, m, sizeof(float) * (size_t)n);
+    free(m);
+}
+
 int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
            const double *b, const double *x0, double *x_out,
            const orc_params *prm, orc_policy *pol, orc_result *res, orc_hist *h)
@@ -658,7 +708,9 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
     mat_build(&A, n, rp, ci, v);
     size_t bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
     double *xhi = malloc(bytes), *xlo = malloc(bytes), *r = malloc(bytes);
-    double *p = malloc(bytes), *q = malloc(bytes), *r64 = malloc(bytes);
+    double *p = malloc(bytes), *q = malloc(bytes), *r64 = malloc(bytes), *z = malloc(bytes);
+    const int pc = prm->precond;
+    float *minv = pc ? jacobi_inverse(n, rp, ci, v) : NULL;
     double *hist_rho = h->hist_rho;
     const int W = pol->w_stag;
     const int R = prm->replace_period;
@@ -697,7 +749,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             nrep_since = 0;
             if (rt <= prm->tol) { status = fell_back ? 2 : 0; break; }
             if (!isfinite(rt)) { status = 3; break; }
-            sigma = s64;
+            sigma = pc ? precond_dot64(n, minv, r64, z, prm->dot_order) : s64;
             int stag = orc_stag(hist_rho, k, W);
             s = orc_state(pol, k, rt, stag);
             orc_mlp_features(pol, k, hist_rho, stag, last_true, prev_a, feat);
@@ -705,6 +757,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             if (fell_back) explored = 0;
             tier = tier_of(a & 3);
             for (int64_t i = 0; i < n; ++i) { r[i] = rd_tier(r64[i], tier); p[i] = r[i]; }
+            if (pc) precond_apply(n, minv, r, p, a & 3);        /* p_0 = z_0 */
         }
         if (k >= prm->maxit) { status = 1; break; }
 
@@ -722,16 +775,22 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         double alpha = sigma / nu;
         if (k < h->dump_cap && h->hist_alpha) h->hist_alpha[k] = alpha;
         int broke = !(nu > 0.0 && isfinite(nu)) || !isfinite(alpha);
-        int converged = 0, stagnated = 0;
+        int converged = 0, stagnated = 0, dir_restart = 0;
         double sig_new = 0.0, rho_new = 0.0, beta = 0.0;
         int64_t kk = k;
         if (!broke) {
             orc_axpy(n, alpha, p, xlo, fa);
             orc_axpy(n, -alpha, q, r, fa);
-            sig_new = orc_dot(n, r, r, fd, prm->dot_order);
+            double sig_rr = orc_dot(n, r, r, fd, prm->dot_order);
+            sig_new = sig_rr;
+            if (pc) {                                             /* sigma' = r^T z */
+                precond_apply(n, minv, r, z, fa);
+                sig_new = orc_dot(n, r, z, fd, prm->dot_order);
+            }
             k += 1;
-            rho_new = sqrt(sig_new) / bnorm;
-            if ((R > 0 && k % R == 0) || rho_new <= prm->tol || !isfinite(sig_new)) {
+            rho_new = sqrt(sig_rr) / bnorm;
+            if ((R > 0 && k % R == 0) || rho_new <= prm->tol || !isfinite(sig_rr) || !isfinite(sig_new)) {
+                const double rho_rec = rho_new;
                 fold(n, xhi, xlo);
                 mat_residual(&A, b, xhi, r64);
                 double s64 = orc_dot(n, r64, r64, F64, prm->dot_order);
@@ -747,7 +806,10 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
                     broke = 1;
                 } else {
                     for (int64_t i = 0; i < n; ++i) r[i] = rd_tier(r64[i], tier);
-                    sig_new = s64;
+                    sig_new = pc ? precond_dot64(n, minv, r64, z, prm->dot_order) : s64;
+                    /* with M, a replacement that more than doubles the
+                       residual restarts the direction: p = z */
+                    dir_restart = pc && !(rt <= 2.0 * rho_rec);
                     rep_hist[0] = rep_hist[1]; rep_hist[1] = rep_hist[2]; rep_hist[2] = rt;
                     nrep_since++;
                     if (orc_stagnated(nrep_since, rep_hist)) stagnated = 1;
@@ -755,8 +817,9 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             }
             hist_rho[k] = rho_new;
             if (!broke && !converged) {
-                beta = sig_new / sigma;
-                if (!isfinite(beta)) broke = 1;
+                beta = dir_restart ? 0.0 : sig_new / sigma;
+                /* with M: r^T M^-1 r > 0 for r != 0 */
+                if (!isfinite(beta) || (pc && !(sig_new > 0.0))) broke = 1;
             }
         }
 
@@ -798,7 +861,13 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         if (k >= prm->maxit) { status = 1; break; }
 
         if (kk < h->dump_cap && h->hist_beta) h->hist_beta[kk] = beta;
-        xpay(n, beta, r, p, fa);
+        if (pc) {                                                 /* p = z + beta p */
+            precond_apply(n, minv, r, z, fa);
+            if (dir_restart) memcpy(p, z, bytes);
+            else xpay(n, beta, z, p, fa);
+        } else {
+            xpay(n, beta, r, p, fa);
+        }
         sigma = sig_new;
         prev_a = a;
         s = s_next;
@@ -826,7 +895,8 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
     res->iters = (int32_t)k;
     res->n_replace = nrep;
 out:
-    free(xhi); free(xlo); free(r); free(p); free(q); free(r64);
+    free(xhi); free(xlo); free(r); free(p); free(q); free(r64); free(z);
+    free(minv);
     mat_free(&A);
     return 0;
 }
