@@ -650,6 +650,22 @@ def main():
             log(f"[bench] rspd {name}: {r}")
         out["random_spd"] = {"n": R.n, "nnz": R.nnz, **rr,
                              "speedup_vs_fp64": round(rr["fp64"]["ms"] / rr["mixed"]["ms"], 3)}
+        # the same system with the Jacobi preconditioner (section 3's z = M^-1 r)
+        pj = {}
+        for name, pol, Rp in (("mixed", pol_mixed, 50), ("fp64", pol_fp64, 0)):
+            mR.set_policy(pol)
+            mR.set_options(replace_period=Rp, fallback=False, precond=1)
+            runs = []
+            for _ in range(3):
+                xRd.zero_()
+                runs.append(mR.solve(bRd, xRd, tol=tol, maxit=60000))
+            r = runs[-1]
+            assert r["status"] == 0 and r["relres_true"] <= tol, r
+            pj[name] = {"ms": round(float(np.median([q["time_ms"] for q in runs])), 3), "iters": r["iters"],
+                        "status": r["status"], "relres_true": r["relres_true"]}
+            log(f"[bench] rspd jacobi {name}: {r}")
+        out["random_spd"]["jacobi"] = {**pj, "speedup_vs_fp64_jacobi": round(pj["fp64"]["ms"] / pj["mixed"]["ms"], 3),
+                                       "speedup_vs_unpreconditioned_fp64": round(rr["fp64"]["ms"] / pj["mixed"]["ms"], 1)}
 
     if not args.no_cpu:
         import oracle as O

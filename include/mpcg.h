@@ -124,6 +124,17 @@ typedef struct {
                                   (col - row) when every one fits, which
                                   mpcg_create_csr detects; -1: always the
                                   32-bit indices; results do not depend on it */
+    int32_t precond;           /* 0: no preconditioner (M = I); 1: Jacobi,
+                                  M = diag(A) kept as the fp32 of 1 / a_ii
+                                  (section 3's z = M^-1 r, section 4.2's fixed
+                                  fp32 preconditioner).  z = rd_fa(m r) at the
+                                  update format, sigma = r.z at the dot format,
+                                  p = z + beta p; rho stays ||r|| / ||b||; at a
+                                  replacement sigma = r64.(M^-1 r64) in fp64,
+                                  and the direction restarts (p = z) when the
+                                  true residual exceeds twice the recursive one.
+                                  Not for batched solves.                       */
+    int32_t reserved;
 } mpcg_solve_opts;
 
 /* Per-kernel timing of the last solve made with opts.profile = 1.  One CG
@@ -195,6 +206,9 @@ int mpcg_get_info(mpcg_matrix *A, mpcg_matrix_info *info);
 /* Copies the shadows to host arrays: float[nnz], uint16 bf16 bits[nnz],
  * uint16 fp16 bits[nnz] (row-scaled values), int8 row exponents[n]. */
 int mpcg_get_shadows(mpcg_matrix *A, float *f32, uint16_t *bf16, uint16_t *f16, int8_t *rexp);
+/* Copies the Jacobi preconditioner, float[n]: the fp64 reciprocal of each
+ * diagonal entry rounded to fp32 (0 for a row without one). */
+int mpcg_get_precond(mpcg_matrix *A, float *minv);
 /* Copies the q52 shadow (Table 1's quarter precision, round to nearest even
  * from fp64, after the same exact per-row power-of-two scale as fp16) to a
  * host uint8 array[nnz] of its bit patterns. */

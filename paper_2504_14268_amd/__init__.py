@@ -44,7 +44,8 @@ class PolicyDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("replace_period", C.c_int32), ("fallback", C.c_int32),
                 ("chunk", C.c_int32), ("profile", C.c_int32),
-                ("spmv_rows", C.c_int32), ("index16", C.c_int32)]
+                ("spmv_rows", C.c_int32), ("index16", C.c_int32),
+                ("precond", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -123,6 +124,7 @@ def lib():
             "mpcg_get_info": [vp, C.POINTER(MatrixInfo)],
             "mpcg_get_shadows": [vp, vp, vp, vp, vp],
             "mpcg_get_shadow_q52": [vp, vp],
+            "mpcg_get_precond": [vp, vp],
             "mpcg_residual_thresholds": [i32, d, vp],
             "mpcg_policy_create": [C.POINTER(PolicyDesc), C.POINTER(vp)],
             "mpcg_policy_destroy": [vp],
@@ -445,8 +447,9 @@ class Matrix:
         _check(lib().mpcg_set_policy(self.h, policy.h if policy is not None else None), "set_policy")
         self.policy = policy
 
-    def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False, spmv_rows=0, index16=0):
-        o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, index16)
+    def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False, spmv_rows=0, index16=0,
+                    precond=0):
+        o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, index16, int(precond), 0)
         _check(lib().mpcg_set_options(self.h, C.byref(o)), "set_options")
 
     def solve(self, b, x, tol=1e-8, maxit=1000) -> dict:
@@ -483,6 +486,11 @@ class Matrix:
         e = np.zeros(self.n, np.int8)
         _check(lib().mpcg_get_shadows(self.h, _np_ptr(f32), _np_ptr(bf), _np_ptr(hf), _np_ptr(e)), "shadows")
         return f32, bf, hf, e
+
+    def precond_inverse(self):
+        out = np.zeros(self.n, np.float32)
+        _check(lib().mpcg_get_precond(self.h, _np_ptr(out)), "get_precond")
+        return out
 
     def shadow_q52(self):
         out = np.zeros(self.nnz, np.uint8)

@@ -279,6 +279,8 @@ struct mpcg_matrix {
   float *d_r32 = nullptr, *d_q32 = nullptr, *d_xlo32 = nullptr, *d_p32 = nullptr;
   double *d_r64 = nullptr, *d_q64 = nullptr, *d_xlo64 = nullptr, *d_p64 = nullptr;
   double *d_part0 = nullptr, *d_part1 = nullptr, *d_part2 = nullptr, *d_scalar = nullptr;
+  double *d_part1b = nullptr, *d_part2b = nullptr;   // preconditioned: r.(M^-1 r) partials
+  float *d_minv = nullptr;     // Jacobi preconditioner: fp32 of 1 / a_ii
   Ctl *d_ctl = nullptr;        // [2]
   Ctl *h_ctl = nullptr;        // pinned
   Ctl *h_poll = nullptr;       // pinned [2]: the control block after each chunk
@@ -299,7 +301,7 @@ struct mpcg_matrix {
   // policy
   mpcg_policy *pol = nullptr;
   mpcg_policy *defpol = nullptr;
-  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0};
+  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0, 0, 0};
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_chunk[2] = {nullptr, nullptr};
   int P2 = 0;
 
@@ -318,6 +320,7 @@ struct mpcg_matrix {
     m.vh = d_vh;
     m.v8 = d_v8;
     m.rexp = d_rexp;
+    m.minv = d_minv;
     return m;
   }
 
@@ -326,6 +329,7 @@ struct mpcg_matrix {
     dfree(d_xhi); dfree(d_r32); dfree(d_p32); dfree(d_q32); dfree(d_xlo32);
     dfree(d_r64); dfree(d_p64); dfree(d_q64); dfree(d_xlo64);
     dfree(d_part0); dfree(d_part1); dfree(d_part2); dfree(d_scalar); dfree(d_ctl); dfree(d_pol);
+    dfree(d_part1b); dfree(d_part2b); dfree(d_minv);
     dfree(d_hrho); dfree(d_reprho); dfree(d_hact); dfree(d_hflag); dfree(d_repk); dfree(d_slotlog);
     for (hipEvent_t e : pev) (void)hipEventDestroy(e);
     pev.clear();
@@ -454,6 +458,9 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
   a.part0 = A->d_part0;
   a.part1 = A->d_part1;
   a.part2 = A->d_part2;
+  a.part1b = A->d_part1b;
+  a.part2b = A->d_part2b;
+  a.precond = A->opts.precond;
   if (A->opts.index16 < 0) {   // 32-bit indices requested
     a.A.dc = nullptr;
     a.A.pbf = nullptr;
@@ -560,6 +567,7 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   TRY_A(dmalloc(&A->d_vh, np));
   TRY_A(dmalloc(&A->d_v8, np));
   TRY_A(dmalloc(&A->d_rexp, (size_t)n));
+  TRY_A(dmalloc(&A->d_minv, (size_t)n));
   TRY_A(hipMemsetAsync(A->d_ci, 0, sizeof(int) * np, A->stream));
   TRY_A(hipMemsetAsync(A->d_v64, 0, sizeof(double) * np, A->stream));
   TRY_A(hipMemsetAsync(A->d_v32, 0, sizeof(float) * np, A->stream));
@@ -570,11 +578,14 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   TRY_A(hipMemcpyAsync(A->d_rp, row_ptr, sizeof(int32_t) * (n + 1), kind, A->stream));
   TRY_A(hipMemcpyAsync(A->d_ci, col, sizeof(int32_t) * nnz, kind, A->stream));
   TRY_A(hipMemcpyAsync(A->d_v64, val, sizeof(double) * nnz, kind, A->stream));
-  launch_shadows(A->n, A->d_rp, A->d_v64, A->d_v32, A->d_vbf, A->d_vh, A->d_v8, A->d_rexp, A->stream);
+  launch_shadows(A->n, A->d_rp, A->d_ci, A->d_v64, A->d_v32, A->d_vbf, A->d_vh, A->d_v8, A->d_rexp, A->d_minv,
+                 A->stream);
   TRY_A(hipGetLastError());
   TRY_A(dmalloc(&A->d_part0, (size_t)A->P2 + 64));
   TRY_A(dmalloc(&A->d_part1, (size_t)(A->n + kKaRows - 1) / kKaRows + 64));
   TRY_A(dmalloc(&A->d_part2, (size_t)A->P2 + 64));
+  TRY_A(dmalloc(&A->d_part1b, (size_t)(A->n + kKaRows - 1) / kKaRows + 64));
+  TRY_A(dmalloc(&A->d_part2b, (size_t)A->P2 + 64));
   TRY_A(dmalloc(&A->d_scalar, 8));
   // 16-bit column deltas (col - row) when every one fits: the SpMV then reads
   // 2 bytes of index per entry instead of 4 (same columns, same order)
@@ -630,6 +641,13 @@ int mpcg_get_info(mpcg_matrix *A, mpcg_matrix_info *info) {
   info->n = A->n;
   info->nnz = A->nnz;
   info->index16 = A->d_dc ? 1 : 0;
+  return MPCG_OK;
+}
+
+int mpcg_get_precond(mpcg_matrix *A, float *minv) {
+  if (!A || !minv) return fail(MPCG_ERR_INVALID, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  HIP_TRY(hipMemcpy(minv, A->d_minv, sizeof(float) * (size_t)A->n, hipMemcpyDeviceToHost));
   return MPCG_OK;
 }
 
@@ -827,6 +845,7 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
   if (o->spmv_rows != 0 && o->spmv_rows != 512 && o->spmv_rows != 1024 && o->spmv_rows != 2048)
     return fail(MPCG_ERR_INVALID, "spmv_rows must be 0, 512, 1024 or 2048");
   if (o->index16 != 0 && o->index16 != -1) return fail(MPCG_ERR_INVALID, "index16 must be 0 or -1");
+  if (o->precond != 0 && o->precond != 1) return fail(MPCG_ERR_INVALID, "precond must be 0 or 1");
   A->opts = *o;
   return MPCG_OK;
 }
@@ -848,6 +867,7 @@ static int upload_start(mpcg_matrix *A, mpcg_policy *P, double tol, int32_t maxi
   c.prev_action = 63;
   c.R = A->opts.replace_period;
   c.fallback_enabled = A->opts.fallback ? 1 : 0;
+  c.precond = A->opts.precond;
   c.tol = tol;
   HIP_TRY(hipMemcpyAsync(A->d_ctl, A->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   return MPCG_OK;
@@ -1303,6 +1323,7 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
     if (!A[i] || !b[i] || !x[i]) return fail(MPCG_ERR_INVALID, "NULL system");
     if (!(tol[i] > 0.0) || !std::isfinite(tol[i])) return fail(MPCG_ERR_INVALID, "tol must be positive and finite");
     if (maxit[i] < 0 || maxit[i] > (1 << 29)) return fail(MPCG_ERR_INVALID, "maxit out of range");
+    if (A[i]->opts.precond) return fail(MPCG_ERR_INVALID, "batched solves are not preconditioned (precond = 0)");
     mpcg_policy *P = A[i]->pol ? A[i]->pol : A[i]->defpol;
     if (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->roll_cap > 0)
       return fail(MPCG_ERR_INVALID, "training policies and rollout logs are not batched (shared state)");

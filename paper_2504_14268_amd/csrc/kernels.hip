@@ -201,6 +201,18 @@ __device__ __forceinline__ Vo xpay_rt(int fa, double beta, Vo p, Vo r) {
   }
 }
 
+// Jacobi preconditioner solve of one element, z = rd_fa(m r) in acc(fa), with
+// m the fp32 reciprocal of the diagonal (fp64 vectors: the fp64 product).
+template <int FA>
+__device__ __forceinline__ float precond_z(float m, float r) { return rd_from_f32<FA>(m * r); }
+template <int FA>
+__device__ __forceinline__ double precond_z(float m, double r) { return (double)m * r; }
+__device__ __forceinline__ float precond_z_rt(int fa, float m, float r) {
+  const float t = m * r;
+  return fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
+}
+__device__ __forceinline__ double precond_z_rt(int, float m, double r) { return (double)m * r; }
+
 // Sums of RPT 256-row subtrees at once (one LDS round): each thread holds one
 // leaf per subtree.
 template <int RPT, typename A>
@@ -600,7 +612,7 @@ __device__ __forceinline__ void apply_decision(const Sx &a, int na, int ex, bool
 // Start / restart: rho_0 from the fp64 residual, first action.  Returns 1 when
 // the decision needs the block's MLP forward (features left in s_feat).
 template <bool FULL>
-__device__ __forceinline__ int init_t0(const Sx &a, double s64, float *s_feat) {
+__device__ __forceinline__ int init_t0(const Sx &a, double s64, double s64z, float *s_feat) {
   Ctl *c = a.ctl;
   const PolicyDev *P = a.pol;
   const int k = c->k;
@@ -620,7 +632,7 @@ __device__ __forceinline__ int init_t0(const Sx &a, double s64, float *s_feat) {
     set_done(c);
     return 0;
   }
-  c->sigma = s64;
+  c->sigma = s64z;   // r64.r64, or r64.(M^-1 r64) with a preconditioner
   // the state (and its stagnation flag, a history read) feeds only learned
   // policies and rollouts
   const bool need_state = FULL || P->kind != POL_FIXED;
@@ -663,8 +675,9 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
   if (completed && a.writer) a.h.rho[k] = rho;
   double beta = 0.0;
   if (completed && !broke && !converged) {
-    beta = c->sig_new / c->sigma;
-    if (!isfinite(beta)) broke = true;
+    beta = c->dir_restart ? 0.0 : c->sig_new / c->sigma;
+    // with M: r^T M^-1 r > 0 for r != 0
+    if (!isfinite(beta) || (c->precond && !(c->sig_new > 0.0))) broke = true;
   }
   int stag = 0, s_next = s;
   const bool need_state = FULL || P->kind != POL_FIXED;
@@ -756,10 +769,10 @@ __device__ __forceinline__ void finish_block(const Sx &a, bool completed, bool b
 }
 
 template <bool FULL>
-__device__ __forceinline__ void init_block(const Sx &a, double s64) {
+__device__ __forceinline__ void init_block(const Sx &a, double s64, double s64z) {
   __shared__ int s_need;
   __shared__ float s_feat[kMlpIn], s_logits[kNAct];
-  if (threadIdx.x == 0) s_need = init_t0<FULL>(a, s64, s_feat);
+  if (threadIdx.x == 0) s_need = init_t0<FULL>(a, s64, s64z, s_feat);
   __syncthreads();
   if constexpr (FULL) {
     if (s_need) {
@@ -770,12 +783,13 @@ __device__ __forceinline__ void init_block(const Sx &a, double s64) {
 }
 
 template <bool FULL>
-__device__ __forceinline__ void replace_block(const Sx &a, double s64) {
+__device__ __forceinline__ void replace_block(const Sx &a, double s64, double s64z) {
   __shared__ int s_f[3];
   if (threadIdx.x == 0) {
     Ctl *c = a.ctl;
     const int k = c->k;
     const double rt = sqrt(s64) / c->bnorm;
+    const double rho_rec = c->rho_new;   // the recursive residual being replaced
     if (c->nrep < a.h.cap_rep && a.writer) {
       a.h.rep_k[c->nrep] = k;
       a.h.rep_rho[c->nrep] = rt;
@@ -790,7 +804,10 @@ __device__ __forceinline__ void replace_block(const Sx &a, double s64) {
     } else if (!isfinite(rt)) {
       broke = 1;
     } else {
-      c->sig_new = s64;
+      c->sig_new = s64z;
+      // with M, a replacement that more than doubles the residual restarts
+      // the direction (p = z)
+      c->dir_restart = c->precond && !(rt <= 2.0 * rho_rec);
       c->rep_hist[0] = c->rep_hist[1];
       c->rep_hist[1] = c->rep_hist[2];
       c->rep_hist[2] = rt;
@@ -815,15 +832,18 @@ __device__ __forceinline__ void step_x(const Sx &x, const KArgs &a, const double
   if (c->mode == M_DONE || !c->pend_sigma) return;
   const int fd = (c->action >> 2) & 3;
   const double sig = have_pre ? tree_preloaded_rt(fd, pre) : reduce_partials_rt(fd, a.part2, a.P2);
+  // with a preconditioner sigma' = r.z; r.r still gives rho
+  const double sigz = c->precond ? reduce_partials_rt(fd, a.part2b, a.P2) : sig;
   __shared__ int s_fin;
   if (threadIdx.x == 0) {
     c->pend_sigma = 0;
-    c->sig_new = sig;
+    c->sig_new = sigz;
+    c->dir_restart = 0;
     c->k += 1;
     const int k = c->k;
     const double rho = sqrt(sig) / c->bnorm;
     c->rho_new = rho;
-    const bool rep = (c->R > 0 && k % c->R == 0) || rho <= c->tol || !isfinite(sig);
+    const bool rep = (c->R > 0 && k % c->R == 0) || rho <= c->tol || !isfinite(sig) || !isfinite(sigz);
     if (rep) {
       c->mode = M_REPLACE;
       c->k3op = c->fold_done ? K3_NONE : K3_FOLD;
@@ -884,10 +904,11 @@ __device__ __forceinline__ void step_b(const Sx &x, const KArgs &a, const double
       }
     }
     const double s64 = have_pre ? tree_preloaded<double>(pre) : partials_total<double>(a.part1, a.P1);
+    const double s64z = (c->precond && la != M_FINAL) ? partials_total<double>(a.part1b, a.P1) : s64;
     if (la == M_INIT) {
-      init_block<FULL>(x, s64);
+      init_block<FULL>(x, s64, s64z);
     } else if (la == M_REPLACE) {
-      replace_block<FULL>(x, s64);
+      replace_block<FULL>(x, s64, s64z);
     } else if (threadIdx.x == 0) {
       c->relres_true = sqrt(s64) / c->bnorm;
       set_done(c);
@@ -1304,25 +1325,31 @@ __device__ __forceinline__ void ka_residual(const KArgs &a, const Ctl &S, int g,
   const int n = a.A.n;
   const int g0 = g * a.grows;
   const int grows = min(a.grows, n - g0);
+  // with a preconditioner a start or replacement also sums r64.(M^-1 r64)
+  const bool pc = S.precond && (mode == M_INIT || mode == M_REPLACE);
   double bi[kRPT];
-  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  float mi[kRPT];
+  double t[4] = {0.0, 0.0, 0.0, 0.0}, tz[4] = {0.0, 0.0, 0.0, 0.0};
   auto pre = [&](int sb) {
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
       const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
       bi[j] = lr < grows ? a.v.b[g0 + lr] : 0.0;
+      mi[j] = (pc && lr < grows) ? a.A.minv[g0 + lr] : 0.0f;
     }
   };
   auto epi = [&](int sb, double (&acc)[kRPT]) {
-    double leaf[kRPT];
+    double leaf[kRPT], leafz[kRPT];
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
       const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
       leaf[j] = 0.0;
+      leafz[j] = 0.0;
       if (lr < grows) {
         const int i = g0 + lr;
         const double r = bi[j] - acc[j];
         leaf[j] = r * r;
+        leafz[j] = r * ((double)mi[j] * r);
         if (mode == M_INIT) {
           a.v.r64[i] = r;
         } else if (mode == M_REPLACE) {
@@ -1337,11 +1364,22 @@ __device__ __forceinline__ void ka_residual(const KArgs &a, const Ctl &S, int g,
     t[1] = sb == 1 ? s : t[1];
     t[2] = sb == 2 ? s : t[2];
     t[3] = sb == 3 ? s : t[3];
+    if (pc) {
+      block_tree_multi<kRPT>(leafz, s2);
+      const double sz = subtrees_rt<kRPT>(FP64, s2);
+      tz[0] = sb == 0 ? sz : tz[0];
+      tz[1] = sb == 1 ? sz : tz[1];
+      tz[2] = sb == 2 ? sz : tz[2];
+      tz[3] = sb == 3 ? sz : tz[3];
+    }
   };
   auto pref = [](int) {};
   if (a.A.dc) spmv_group<FP64, true>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pref, pre, epi);
   else spmv_group<FP64, false>(a.A, GatherPlain<double>{a.v.xhi}, g0, grows, lds, pref, pre, epi);
-  if (threadIdx.x == 0) a.part1[g] = group_tree(FP64, a.grows, t);
+  if (threadIdx.x == 0) {
+    a.part1[g] = group_tree(FP64, a.grows, t);
+    if (pc) a.part1b[g] = group_tree(FP64, a.grows, tz);
+  }
 }
 
 // x_hi += x_lo, x_lo = 0 over one 2048-element group (current tier).
@@ -1403,8 +1441,9 @@ __device__ __forceinline__ void load8_tail(const V *p, int base, int n, bool ful
   }
 }
 
-// x_lo and r updates and the sigma' partial on operands already loaded.
-template <int FA, int FD, typename V>
+// x_lo and r updates and the sigma' partial on operands already loaded; with
+// a preconditioner (PC) also z = M^-1 r and the partial of r.z.
+template <int FA, int FD, bool PC, typename V>
 __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool fold_now, int blk, const V (&pv)[8],
                                              const V (&qv)[8], V (&rv)[8], V (&xv)[8]) {
   constexpr int TIER = (FA == FP64);
@@ -1417,12 +1456,15 @@ __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool 
   const int n = a.A.n;
   const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   const bool full = base + 8 <= n;
-  Acc l[8];
+  Acc l[8], lz[8];
+  float mv[8];
+  if constexpr (PC) load8_tail(a.A.minv, base, n, full, mv);
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     xv[j] = axpy1<FA>(alpha, pv[j], xv[j]);
     rv[j] = axpy1<FA>(-alpha, qv[j], rv[j]);
     l[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], rv[j]) : (Acc)0;
+    if constexpr (PC) lz[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], precond_z<FA>(mv[j], rv[j])) : (Acc)0;
   }
   if (fold_now) {
 #pragma unroll
@@ -1447,9 +1489,13 @@ __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool 
   }
   const Acc t = block_tree(tree8(l));
   if (threadIdx.x == 0) a.part2[blk] = (double)t;
+  if constexpr (PC) {
+    const Acc tz = block_tree(tree8(lz));
+    if (threadIdx.x == 0) a.part2b[blk] = (double)tz;
+  }
 }
 
-template <int FA, int FD>
+template <int FA, int FD, bool PC>
 __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_now, int blk) {
   constexpr int TIER = (FA == FP64);
   using V = typename TierT<TIER>::type;
@@ -1464,12 +1510,15 @@ __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_
   load8_tail(q, base, n, full, qv);
   load8_tail(r, base, n, full, rv);
   load8_tail(xlo, base, n, full, xv);
-  kb_axpy_vals<FA, FD>(a, S, fold_now, blk, pv, qv, rv, xv);
+  kb_axpy_vals<FA, FD, PC>(a, S, fold_now, blk, pv, qv, rv, xv);
 }
 
 // Elementwise steps (KB or KX): p = r = rd_tier(r64) after a start; the
 // direction update, with a tier change when the next action needs one; the
-// fold of x_lo into x_hi before a replacement or a restart.
+// fold of x_lo into x_hi before a replacement or a restart.  With a
+// preconditioner (PC) the direction takes z = M^-1 r in place of r (p_0 = z_0;
+// p = z when the direction restarts).
+template <bool PC = false>
 __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, int blk) {
   const int op = S.k3op;
   const int n = a.A.n;
@@ -1481,16 +1530,32 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
       const int i = base + j;
       if (i >= n) break;
       const double r = a.v.r64[i];
-      if (S.tier) { a.v.p64[i] = r; a.v.xlo64[i] = 0.0; }
-      else { const float f = (float)r; a.v.r32[i] = f; a.v.p32[i] = f; a.v.xlo32[i] = 0.0f; }
+      if (S.tier) {
+        a.v.p64[i] = PC ? precond_z_rt(FP64, a.A.minv[i], r) : r;
+        a.v.xlo64[i] = 0.0;
+      } else {
+        const float f = (float)r;
+        a.v.r32[i] = f;
+        a.v.p32[i] = PC ? precond_z_rt(S.action & 3, a.A.minv[i], f) : f;
+        a.v.xlo32[i] = 0.0f;
+      }
     }
   } else if (op == K3_XPAY && !S.k3switch && base + 8 <= n) {   // the common case, vectorised
+    float mv[8];
+    if constexpr (PC) load8(a.A.minv + base, mv);
     if (S.tier_old) {
       double pv[8], rv[8];
       load8(a.v.p64 + base, pv);
       load8(a.v.r64 + base, rv);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) pv[j] = xpay_rt<double>(S.k3_fa, S.beta, pv[j], rv[j]);
+      for (int j = 0; j < 8; ++j) {
+        if constexpr (PC) {
+          const double z = precond_z_rt(FP64, mv[j], rv[j]);
+          pv[j] = S.dir_restart ? z : xpay_rt<double>(S.k3_fa, S.beta, pv[j], z);
+        } else {
+          pv[j] = xpay_rt<double>(S.k3_fa, S.beta, pv[j], rv[j]);
+        }
+      }
       store8(a.v.p64 + base, pv);
     } else {
       float pv[8], rv[8];
@@ -1500,8 +1565,14 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
       const float bf = (float)S.beta;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const float t = __builtin_fmaf(bf, pv[j], rv[j]);
-        pv[j] = fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
+        if constexpr (PC) {
+          const float z = precond_z_rt(fa, mv[j], rv[j]);
+          const float t = __builtin_fmaf(bf, pv[j], z);
+          pv[j] = S.dir_restart ? z : (fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t);
+        } else {
+          const float t = __builtin_fmaf(bf, pv[j], rv[j]);
+          pv[j] = fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
+        }
       }
       store8(a.v.p32 + base, pv);
     }
@@ -1511,7 +1582,13 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
       const int i = base + j;
       if (i >= n) break;
       if (told) {
-        const double pn = xpay_rt<double>(S.k3_fa, S.beta, a.v.p64[i], a.v.r64[i]);
+        double pn;
+        if constexpr (PC) {
+          const double z = precond_z_rt(FP64, a.A.minv[i], a.v.r64[i]);
+          pn = S.dir_restart ? z : xpay_rt<double>(S.k3_fa, S.beta, a.v.p64[i], z);
+        } else {
+          pn = xpay_rt<double>(S.k3_fa, S.beta, a.v.p64[i], a.v.r64[i]);
+        }
         if (S.k3switch) {
           fold1(a.v.xhi, i, a.v.xlo64[i]);
           a.v.p32[i] = (float)pn;
@@ -1521,7 +1598,13 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
           a.v.p64[i] = pn;
         }
       } else {
-        const float pn = xpay_rt<float>(S.k3_fa, S.beta, a.v.p32[i], a.v.r32[i]);
+        float pn;
+        if constexpr (PC) {
+          const float z = precond_z_rt(S.k3_fa, a.A.minv[i], a.v.r32[i]);
+          pn = S.dir_restart ? z : xpay_rt<float>(S.k3_fa, S.beta, a.v.p32[i], z);
+        } else {
+          pn = xpay_rt<float>(S.k3_fa, S.beta, a.v.p32[i], a.v.r32[i]);
+        }
         if (S.k3switch) {
           fold1(a.v.xhi, i, (double)a.v.xlo32[i]);
           a.v.p64[i] = (double)pn;
@@ -1536,11 +1619,12 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
 }
 
 #define MPCG_KB_CASE(FA, FD) \
-  case (FA) * 4 + (FD): kb_axpy<FA, FD>(a, S, fold_now, blk); break;
+  case (FA) * 4 + (FD): kb_axpy<FA, FD, PC>(a, S, fold_now, blk); break;
 #define MPCG_KB_VALS(FA, FD) \
-  case (FA) * 4 + (FD): kb_axpy_vals<FA, FD>(a, S, fold_now, blk, pv, qv, rv, xv); break;
+  case (FA) * 4 + (FD): kb_axpy_vals<FA, FD, PC>(a, S, fold_now, blk, pv, qv, rv, xv); break;
 
 // KB's vector work for 2048-element block blk.
+template <bool PC = false>
 __device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, bool fold_now, int blk) {
   if (bop == B_AXPY) {
     const int act = S.action;
@@ -1552,7 +1636,7 @@ __device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, b
     default: break;
     }
   } else if (bop == B_EXEC) {
-    exec_elementwise(a, S, blk);
+    exec_elementwise<PC>(a, S, blk);
   }
 }
 
@@ -1570,7 +1654,7 @@ __device__ __forceinline__ void kb_commit(Ctl &S, int bop, bool fold_now) {
 
 // KB's work on vector block blk of one system; block 0 commits the state.
 // The step's partials are loaded together with the control block.
-template <bool FULL = false>
+template <bool FULL = false, bool PC = false>
 __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
@@ -1605,7 +1689,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
       default: break;
       }
     } else {
-      kb_work(a, S, bop, fold_now, blk);
+      kb_work<PC>(a, S, bop, fold_now, blk);
     }
     if (blk == 0) {
       __syncthreads();
@@ -1618,7 +1702,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   if (!S.step_done) step_b<FULL>(x, a, pre, fast);
   const int bop = S.b_op;
   const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
-  kb_work(a, S, bop, fold_now, blk);
+  kb_work<PC>(a, S, bop, fold_now, blk);
   if (blk == 0) {   // commit the state after this kernel for KX
     __syncthreads();
     if (threadIdx.x == 0) kb_commit(S, bop, fold_now);
@@ -1631,7 +1715,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
 // elementwise operation; block 0 commits the state.  The partials come with
 // the control block, and the direction update's operands are issued before
 // the step's arithmetic, so the step's latency overlaps the vector loads.
-template <int TIER>
+template <int TIER, bool PC>
 __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S, int blk, const double (&pre)[8],
                                             bool have_pre) {
   using V = typename TierT<TIER>::type;
@@ -1639,10 +1723,12 @@ __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S,
   const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   const bool full = base + 8 <= n;
   V pv[8], rv[8];
+  float mv[8];
   __builtin_amdgcn_sched_barrier(0);
   if (full) {
     if constexpr (TIER) { load8(a.v.p64 + base, pv); load8(a.v.r64 + base, rv); }
     else { load8(a.v.p32 + base, pv); load8(a.v.r32 + base, rv); }
+    if constexpr (PC) load8(a.A.minv + base, mv);
   }
   __builtin_amdgcn_sched_barrier(0);
   step_x<false>(x, a, pre, have_pre);
@@ -1650,23 +1736,37 @@ __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S,
     if constexpr (TIER) {
       const double beta = S.beta;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) pv[j] = __builtin_fma(beta, pv[j], rv[j]);
+      for (int j = 0; j < 8; ++j) {
+        if constexpr (PC) {
+          const double z = precond_z<FP64>(mv[j], rv[j]);
+          pv[j] = S.dir_restart ? z : __builtin_fma(beta, pv[j], z);
+        } else {
+          pv[j] = __builtin_fma(beta, pv[j], rv[j]);
+        }
+      }
       store8(a.v.p64 + base, pv);
     } else {
       const int fa = S.k3_fa;
       const float bf = (float)S.beta;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const float t = __builtin_fmaf(bf, pv[j], rv[j]);
-        pv[j] = fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
+        if constexpr (PC) {
+          const float z = precond_z_rt(fa, mv[j], rv[j]);
+          const float t = __builtin_fmaf(bf, pv[j], z);
+          pv[j] = S.dir_restart ? z : (fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t);
+        } else {
+          const float t = __builtin_fmaf(bf, pv[j], rv[j]);
+          pv[j] = fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
+        }
       }
       store8(a.v.p32 + base, pv);
     }
   } else {
-    exec_elementwise(a, S, blk);
+    exec_elementwise<PC>(a, S, blk);
   }
 }
 
+template <bool PC = false>
 __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
@@ -1678,11 +1778,11 @@ __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   __syncthreads();
   const Sx x{&S, &SP, a.h, blk == 0, nullptr};
   if (!S.step_done && S.pend_sigma) {
-    if (S.tier) kx_iter_pre<1>(a, x, S, blk, pre, fast);
-    else kx_iter_pre<0>(a, x, S, blk, pre, fast);
+    if (S.tier) kx_iter_pre<1, PC>(a, x, S, blk, pre, fast);
+    else kx_iter_pre<0, PC>(a, x, S, blk, pre, fast);
   } else {
     if (!S.step_done) step_x<false>(x, a, pre, fast);
-    exec_elementwise(a, S, blk);
+    exec_elementwise<PC>(a, S, blk);
   }
   if (blk == 0) {   // commit the state after this kernel for the next KA and KB
     __syncthreads();
@@ -1698,6 +1798,12 @@ __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
 __global__ __launch_bounds__(kBlock) void k_b(KArgs a) { kb_body(a, blockIdx.x); }
 
 __global__ __launch_bounds__(kBlock) void k_x(KArgs a) { kx_body(a, blockIdx.x); }
+
+// The Jacobi-preconditioned variants of KB and KX (separate kernels, so the
+// unpreconditioned ones keep their register budget).
+__global__ __launch_bounds__(kBlock) void k_b_pc(KArgs a) { kb_body<false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_full_pc(KArgs a) { kb_body<true, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_x_pc(KArgs a) { kx_body<true>(a, blockIdx.x); }
 
 // KB whose replicated step is the full one (state features, the network's
 // decision at a start or a stop, rollout log by workgroup 0): for policies
@@ -1858,7 +1964,7 @@ __device__ __forceinline__ void ka_pass(const KArgs &a, const Ctl &S, void *lds)
 
 template <int FA, int FD>
 __device__ __forceinline__ void kb_axpy_all(const KArgs &a, const Ctl &S, bool fold_now) {
-  for (int blk = 0; blk < a.P2; ++blk) kb_axpy<FA, FD>(a, S, fold_now, blk);
+  for (int blk = 0; blk < a.P2; ++blk) kb_axpy<FA, FD, false>(a, S, fold_now, blk);
 }
 
 #define MPCG_KB_ALL(FA, FD) \
@@ -2033,8 +2139,9 @@ void launch_dcol(int n, const int *rp, const int *ci, int16_t *dc, int *bad, hip
 // Thread per row: fp16 row exponent e (largest magnitude scaled into
 // (2^14, 2^15]), fp32 = RNE(v), bf16 = RNE(v), fp16 = RNE(v 2^-e), all directly
 // from fp64.
-__global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const double *v, float *v32,
-                                                    uint16_t *vbf, uint16_t *vh, uint8_t *v8, int8_t *rexp) {
+__global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const int *ci, const double *v,
+                                                    float *v32, uint16_t *vbf, uint16_t *vh, uint8_t *v8,
+                                                    int8_t *rexp, float *minv) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int s = rp[i], t = rp[i + 1];
@@ -2057,8 +2164,10 @@ __global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const 
     e = e < -128 ? -128 : (e > 127 ? 127 : e);
   }
   rexp[i] = (int8_t)e;
+  float mi = 0.0f;   // Jacobi: the fp64 reciprocal of the diagonal, rounded to fp32
   for (int k = s; k < t; ++k) {
     const double x = v[k];
+    if (ci[k] == i) mi = (float)(1.0 / x);
     v32[k] = (float)x;
     vbf[k] = f32_to_bf16_bits_exact((float)round_narrow_f64<8, -126, 127>(x));
     vh[k] = f32_to_f16_bits_exact((float)round_narrow_f64<11, -14, 15>(ldexp(x, -e)));
@@ -2066,6 +2175,7 @@ __global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const 
     // a zero low byte, and the high byte is the q52 encoding
     v8[k] = (uint8_t)(f32_to_f16_bits_exact((float)round_narrow_f64<3, -14, 15>(ldexp(x, -e))) >> 8);
   }
+  minv[i] = mi;
 }
 
 // ---------------------------------------------------------------------------
@@ -2161,9 +2271,12 @@ static void launch_timed(K kern, int grid, const KArgs &a, hipStream_t s, hipEve
 }
 void launch_ka(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_a, a.G1, a, s, e0, e1); }
 void launch_kb(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  launch_timed(a.full ? k_b_full : k_b, a.P2, a, s, e0, e1);
+  if (a.precond) launch_timed(a.full ? k_b_full_pc : k_b_pc, a.P2, a, s, e0, e1);
+  else launch_timed(a.full ? k_b_full : k_b, a.P2, a, s, e0, e1);
 }
-void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_x, a.P2, a, s, e0, e1); }
+void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_timed(a.precond ? k_x_pc : k_x, a.P2, a, s, e0, e1);
+}
 void launch_step_b(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_step_b, 1, a, s, e0, e1); }
 void launch_step_x(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   launch_timed(a.net ? k_step_x_net : k_step_x, 1, a, s, e0, e1);
@@ -2218,10 +2331,10 @@ void launch_lock_modes(const BatchSys *sys, const int32_t *act, int nact, int32_
                                    nact, modes);
 }
 
-void launch_shadows(int n, const int *rp, const double *v, float *v32, uint16_t *vbf, uint16_t *vh,
-                    uint8_t *v8, int8_t *rexp, hipStream_t s) {
-  hipLaunchKernelGGL(k_shadows, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, rp, v, v32, vbf, vh,
-                     v8, rexp);
+void launch_shadows(int n, const int *rp, const int *ci, const double *v, float *v32, uint16_t *vbf,
+                    uint16_t *vh, uint8_t *v8, int8_t *rexp, float *minv, hipStream_t s) {
+  hipLaunchKernelGGL(k_shadows, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, rp, ci, v, v32, vbf, vh,
+                     v8, rexp, minv);
 }
 
 void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipStream_t s) {

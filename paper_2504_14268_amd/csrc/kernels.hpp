@@ -24,6 +24,7 @@ struct Mat {
   const uint16_t *vbf, *vh;   // bf16 bits, fp16 bits (row-scaled)
   const uint8_t *v8;          // q52 bits (row-scaled like fp16)
   const int8_t *rexp;         // row exponents of the fp16 and q52 shadows
+  const float *minv;          // Jacobi preconditioner: fp32 of 1 / a_ii (0 without a diagonal)
 };
 
 // Solver vectors.  r, p, q, x_lo exist in a float and a double container; the
@@ -87,7 +88,8 @@ struct Ctl {
   int32_t nrep_since, s, explored, prev_action;
   int32_t R, fallback_enabled, k3_fa, zero_solution;
   int32_t bnorm_ready, pend_sigma, b_op, step_done;
-  int32_t fold_done, pad_;
+  int32_t fold_done, precond;     // precond: 1 = Jacobi-preconditioned iteration
+  int32_t dir_restart, pad_;      // 1: the next direction update restarts (p = z)
   double tol, bnorm, sigma, sig_new, alpha, beta, rho_new, last_true, cost_sum, relres_true;
   double rep_hist[3];
   float feat[kMlpIn];
@@ -105,11 +107,14 @@ struct KArgs {
   Hist h;
   double *part0;       // partials of b.b (start)
   double *part1;       // KA partials (nu or ||r64||^2), one per KA workgroup
-  double *part2;       // KB partials (sigma'), one per 2048-element block
+  double *part2;       // KB partials (sigma' = r.r), one per 2048-element block
+  double *part1b;      // with a preconditioner: KA's partials of r64.(M^-1 r64)
+  double *part2b;      // with a preconditioner: KB's partials of r.z
   int P1;              // KA row groups (grows rows each)
   int grows;           // rows per KA group: 512, 1024 or 2048
   int P2;              // 2048-element vector blocks
   int G1;              // KA workgroups launched (P1 rounded up to 8)
+  int precond;         // 1: launch the preconditioned KB / KX variants (Ctl.precond set too)
   int8_t *slot_log;    // optional: KA records the mode of each slot (profiling)
   int slot;            // index of this slot (with slot_log)
 };
