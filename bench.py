@@ -650,6 +650,20 @@ def main():
             log(f"[bench] rspd {name}: {r}")
         out["random_spd"] = {"n": R.n, "nnz": R.nnz, **rr,
                              "speedup_vs_fp64": round(rr["fp64"]["ms"] / rr["mixed"]["ms"], 3)}
+        # the SpMV's time per launch against the random-access floor of its columns
+        mR.set_policy(pol_mixed)
+        mR.set_options(replace_period=50, fallback=False, profile=True)
+        xRd.zero_()
+        mR.solve(bRd, xRd, tol=tol, maxit=200)
+        prR = mR.profile()
+        ka_r_us = prR["ka_iter_ms"] / prR["n_iter_slots"] * 1e3
+        p32 = torch.from_numpy(np.random.default_rng(9).standard_normal(R.n).astype(np.float32)).cuda()
+        floor_us = mR.gather_floor(p32, 20)
+        out["random_spd"]["ka_us"] = round(ka_r_us, 2)
+        out["random_spd"]["ka_GB/s_algorithmic"] = round(ka_bytes(R.n, R.nnz, M.BF16, 4, 4) / (ka_r_us * 1e-6) / 1e9, 1)
+        out["random_spd"]["gather_floor_us"] = round(floor_us, 2)
+        out["random_spd"]["ka_vs_gather_floor"] = round(floor_us / ka_r_us, 3)
+        log(f"[bench] rspd KA {ka_r_us:.2f} us, flat gather floor {floor_us:.2f} us")
         # the same system with the Jacobi preconditioner (section 3's z = M^-1 r)
         pj = {}
         for name, pol, Rp in (("mixed", pol_mixed, 50), ("fp64", pol_fp64, 0)):

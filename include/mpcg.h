@@ -458,6 +458,17 @@ int mpcg_op_axpy(mpcg_matrix *A, int fmt, double alpha, const void *u, void *y);
 /* r (double[n], device) = b - A x in fp64 */
 int mpcg_op_residual(mpcg_matrix *A, const double *b, const double *x, double *r);
 
+/*
+ * Measurement of the SpMV's random-access floor for this matrix: a flat pass
+ * over its CSR entries that streams the int32 column indices and bf16 values
+ * (coalesced) and gathers p[col] for every entry, eight independent gathers in
+ * flight per thread, with no row structure and no output.  An SpMV over the
+ * same columns cannot gather faster.  p: device float[n].  Launched
+ * 2 + repeats times on the handle's stream; *us_per_launch (host) receives the
+ * mean of the last `repeats` launches (HIP events).
+ */
+int mpcg_gather_floor(mpcg_matrix *A, const float *p, int32_t repeats, double *us_per_launch);
+
 /* Copies the per-kernel timing of the last profiled solve (zeros otherwise). */
 int mpcg_get_profile(mpcg_matrix *A, mpcg_profile *out);
 

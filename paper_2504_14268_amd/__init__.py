@@ -144,6 +144,7 @@ def lib():
             "mpcg_op_spmv": [vp, C.c_int, C.c_int, vp, vp],
             "mpcg_op_dot": [vp, C.c_int, C.c_int, vp, vp, C.POINTER(d)],
             "mpcg_op_dot_noalloc": [vp, C.c_int, C.c_int, vp, vp, vp],
+            "mpcg_gather_floor": [vp, vp, i32, C.POINTER(d)],
             "mpcg_op_axpy": [vp, C.c_int, d, vp, vp],
             "mpcg_op_residual": [vp, vp, vp, vp],
             "mpcg_get_profile": [vp, C.POINTER(Profile)],
@@ -508,6 +509,12 @@ class Matrix:
     def op_dot_noalloc(self, fmt, tier64, u, v, out):
         """dot_f(u, v) into the device double out[0], with no allocation (mpcg_op_dot_noalloc)."""
         _check(lib().mpcg_op_dot_noalloc(self.h, fmt, tier64, _t_ptr(u), _t_ptr(v), _t_ptr(out)), "op_dot_noalloc")
+
+    def gather_floor(self, p, repeats=20) -> float:
+        """Mean microseconds of the flat-gather floor kernel over this matrix's columns."""
+        us = C.c_double(0.0)
+        _check(lib().mpcg_gather_floor(self.h, _t_ptr(p), repeats, C.byref(us)), "gather_floor")
+        return us.value
 
     def op_axpy(self, fmt, alpha, u, y):
         _check(lib().mpcg_op_axpy(self.h, fmt, alpha, _t_ptr(u), _t_ptr(y)), "op_axpy")

@@ -1770,6 +1770,26 @@ int mpcg_op_dot_noalloc(mpcg_matrix *A, int fmt, int tier64, const void *u, cons
   return MPCG_OK;
 }
 
+int mpcg_gather_floor(mpcg_matrix *A, const float *p, int32_t repeats, double *us_per_launch) {
+  if (!A || !p || !us_per_launch || repeats < 1) return fail(MPCG_ERR_INVALID, "bad argument");
+  int rc = ensure_ws(A);
+  if (rc) return rc;
+  const Mat m = A->mat();
+  float *sink = A->d_q32;   // written only for a NaN sum
+  launch_gather_floor(m, p, sink, A->stream);
+  launch_gather_floor(m, p, sink, A->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(A->ev_start, A->stream));
+  for (int i = 0; i < repeats; ++i) launch_gather_floor(m, p, sink, A->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(A->ev_end, A->stream));
+  HIP_TRY(hipEventSynchronize(A->ev_end));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, A->ev_start, A->ev_end));
+  *us_per_launch = (double)ms * 1e3 / repeats;
+  return MPCG_OK;
+}
+
 int mpcg_op_axpy(mpcg_matrix *A, int fmt, double alpha, const void *u, void *y) {
   if (!A || !u || !y || fmt < 0 || fmt > 3) return fail(MPCG_ERR_INVALID, "bad argument");
   launch_op_axpy(A->n, fmt, alpha, u, y, A->stream);

@@ -2380,6 +2380,40 @@ void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double
 }
 
 // ---------------------------------------------------------------------------
+// Measurement: the floor of an SpMV over the same index stream.  A flat pass
+// over the CSR entries: thread t of block b takes entries b*2048 + t + 256 j,
+// j < 8 (coalesced index and bf16 value loads), issues the eight gathers of p
+// together, and sums the products.  No row structure, no reductions: only the
+// matrix stream and one gather per entry with the most gathers in flight.  The
+// sum is stored only if it is NaN (never, for finite p), so no output traffic
+// is made, and the loads cannot be removed.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_gather_floor(const int *__restrict__ col, const uint16_t *__restrict__ val,
+                                                         const float *__restrict__ p, int nnz,
+                                                         float *__restrict__ sink) {
+  const int base = blockIdx.x * kVecBlock + threadIdx.x;
+  int c[8];
+  float v[8], x[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int i = base + kBlock * j;
+    c[j] = i < nnz ? col[i] : 0;
+    v[j] = i < nnz ? bf16_bits_to_f32(val[i]) : 0.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x[j] = p[c[j]];
+  float acc = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc = __builtin_fmaf(v[j], x[j], acc);
+  if (acc != acc) sink[0] = acc;
+}
+
+void launch_gather_floor(const Mat &A, const float *p, float *sink, hipStream_t s) {
+  const int grid = (A.nnz + kVecBlock - 1) / kVecBlock;
+  hipLaunchKernelGGL(k_gather_floor, dim3(grid), dim3(kBlock), 0, s, A.ci, A.vbf, p, A.nnz, sink);
+}
+
+// ---------------------------------------------------------------------------
 // The dot product without allocation: the same two kernels as launch_op_dot,
 // with the block partials in a file-scope device array instead of handle
 // memory.  In host code `scratch` names a host-side stand-in, not device

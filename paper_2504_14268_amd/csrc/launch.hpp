@@ -33,6 +33,8 @@ void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double
 hipError_t launch_op_dot_noalloc(int n, int fd, int tier, const void *u, const void *v, double *out,
                                  hipStream_t s);
 void launch_op_axpy(int n, int fa, double alpha, const void *u, void *y, hipStream_t s);
+// Flat gather of p over the CSR column stream (measurement of the random-access floor).
+void launch_gather_floor(const Mat &A, const float *p, float *sink, hipStream_t s);
 void launch_policy_decide(const PolicyDev *P, int m, const int64_t *k, const double *rho, const int32_t *stag,
                           const float *feat, int32_t *state, int32_t *action, hipStream_t s);
 }  // namespace mpcg
