@@ -105,7 +105,12 @@ typedef struct {
                                   is charged c(fp16)                             */
     uint64_t seed;             /* exploration draws                              */
     int32_t replace_period;    /* R seen by the MLP features                     */
-    int32_t reserved;
+    int32_t decision_period;   /* D: the policy acts at iterations k = 0 mod D
+                                  (and at a start or restart) and its action
+                                  holds in between; a decision's reward charges
+                                  the cost of every iteration it ran and its
+                                  Q update (and rollout) happens when it ends.
+                                  0 or 1: every iteration (section 4.1)        */
 } mpcg_policy_desc;
 
 typedef struct {

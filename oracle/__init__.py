@@ -77,7 +77,7 @@ class Policy(C.Structure):
         ("w1m", C.POINTER(C.c_float)), ("b1m", C.POINTER(C.c_float)),
         ("w2m", C.POINTER(C.c_float)), ("b2m", C.POINTER(C.c_float)),
         ("w3m", C.POINTER(C.c_float)), ("b3m", C.POINTER(C.c_float)),
-        ("replace_period", C.c_int32), ("pad", C.c_int32),
+        ("replace_period", C.c_int32), ("decision_period", C.c_int32),
     ]
 
 
@@ -279,7 +279,7 @@ class OraclePolicy:
 
     def __init__(self, kind=POL_FIXED, fixed_action=63, q=None, t_bin=1000, b_it=5,
                  b_res=10, w_stag=10, lr=0.1, gamma=0.9, w=(1.0, 0.1, 10.0), eps_min=1e-16,
-                 cost="C1", epsilon=0.0, seed=0, episode=0, mlp=None, replace_period=50):
+                 cost="C1", epsilon=0.0, seed=0, episode=0, mlp=None, replace_period=50, decision_period=1):
         self.s = Policy()
         s = self.s
         s.kind, s.fixed_action = kind, fixed_action
@@ -298,6 +298,7 @@ class OraclePolicy:
             s.cost[i] = costs[i]
         s.epsilon, s.seed, s.episode = epsilon, seed, episode
         s.replace_period = replace_period
+        s.decision_period = decision_period
         self.mlp = None
         if mlp is not None:
             self.set_mlp(mlp)

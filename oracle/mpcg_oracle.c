@@ -423,7 +423,7 @@ typedef struct {
     /* MLP policy: fp32 weights (bf16-representable) */
     const float *w1m, *b1m, *w2m, *b2m, *w3m, *b3m;
     int32_t replace_period;  /* R, used by the MLP features */
-    int32_t pad;
+    int32_t decision_period; /* D: the policy acts every D iterations (0, 1: every one) */
 } orc_policy;
 
 int orc_n_states(const orc_policy *pol) { return pol->b_res * pol->b_it * 2; }
@@ -456,17 +456,21 @@ static double cost_of(const orc_policy *pol, int a)
     return (pol->cost[(a >> 4) & 3] + pol->cost[(a >> 2) & 3]) + pol->cost[a & 3];
 }
 
-static double reward(const orc_policy *pol, int a, double rho, int converged)
+/* Reward of one decision (section 4.1) whose action ran n_it iterations: the
+ * accuracy term at the residual rho' after them, the cost of the n_it
+ * iterations, the convergence bonus.  n_it = 1 is the paper's per-iteration
+ * reward. */
+static double reward(const orc_policy *pol, int a, double rho, int converged, int64_t n_it)
 {
     double accterm = (rho <= pol->eps_min) ? -orc_log10(pol->eps_min) : -orc_log10(rho);
-    double r = pol->w1 * accterm - pol->w2 * cost_of(pol, a);
+    double r = pol->w1 * accterm - pol->w2 * (cost_of(pol, a) * (double)n_it);
     if (converged) r = r + pol->w3;
     return r;
 }
 
 double orc_reward(const orc_policy *pol, int a, double rho, int terminal)
 {
-    return reward(pol, a, rho, terminal);
+    return reward(pol, a, rho, terminal, 1);
 }
 
 static void q_update(orc_policy *pol, int s, int a, double target)
@@ -726,6 +730,10 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
     double sigma = 0.0, last_true = 0.0;
     int a = 63, s = 0, tier = 1, prev_a = 63, explored = 0;
     float feat[MLP_IN], feat_next[MLP_IN];
+    /* decision period (a reading; 1 is the paper's per-iteration decision):
+       the action chosen at iteration k_dec holds until the next multiple of D */
+    const int64_t D = pol->decision_period > 1 ? pol->decision_period : 1;
+    int64_t k_dec = 0;
 
     double bnorm = sqrt(orc_dot(n, b, b, F64, prm->dot_order));
     if (bnorm == 0.0) {
@@ -755,6 +763,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             orc_mlp_features(pol, k, hist_rho, stag, last_true, prev_a, feat);
             a = fell_back ? 63 : decide(pol, kind, feat, s, k, &explored);
             if (fell_back) explored = 0;
+            k_dec = k;
             tier = tier_of(a & 3);
             for (int64_t i = 0; i < n; ++i) { r[i] = rd_tier(r64[i], tier); p[i] = r[i]; }
             if (pc) precond_apply(n, minv, r, p, a & 3);        /* p_0 = z_0 */
@@ -833,15 +842,17 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             memcpy(feat_next, feat, sizeof(feat));
         }
 
+        /* iterations run under the current decision, the failed one included */
+        const int64_t n_it = (k > kk ? k : k + 1) - k_dec;
         if (converged) {
-            double rw = reward(pol, a, rho_new, 1);
+            double rw = reward(pol, a, rho_new, 1, n_it);
             if (training) q_update(pol, s, a, rw);
             if (policy_active) roll_log(h, feat, feat_next, a, rw, 1);
             status = fell_back ? 2 : 0;
             break;
         }
         if (broke || (stagnated && prm->fallback && !fell_back)) {
-            double rw = -pol->w2 * cost_of(pol, a) - pol->w3;
+            double rw = -pol->w2 * (cost_of(pol, a) * (double)n_it) - pol->w3;
             if (training) q_update(pol, s, a, rw);
             if (policy_active) roll_log(h, feat, feat_next, a, rw, 1);
             if (!prm->fallback || fell_back) { status = 3; break; }
@@ -853,8 +864,10 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             prev_a = a;
             continue;
         }
-        {
-            double rw = reward(pol, a, rho_new, 0);
+        /* a decision ends at a multiple of D, and when the budget cuts it */
+        const int dec_end = (k % D == 0) || k >= prm->maxit;
+        if (dec_end) {
+            double rw = reward(pol, a, rho_new, 0, n_it);
             if (training) q_update(pol, s, a, rw + pol->gamma * max_row(&pol->q[s_next * N_ACT]));
             if (policy_active) roll_log(h, feat, feat_next, a, rw, 0);
         }
@@ -870,10 +883,15 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         }
         sigma = sig_new;
         prev_a = a;
-        s = s_next;
-        memcpy(feat, feat_next, sizeof(feat));
-        a = fell_back ? 63 : decide(pol, kind, feat, s, k, &explored);
-        if (fell_back) explored = 0;
+        if (dec_end) {
+            s = s_next;
+            memcpy(feat, feat_next, sizeof(feat));
+            a = fell_back ? 63 : decide(pol, kind, feat, s, k, &explored);
+            if (fell_back) explored = 0;
+            k_dec = k;
+        } else {
+            explored = 0;                  /* the action holds */
+        }
         int nt = tier_of(a & 3);
         if (nt != tier) {
             fold(n, xhi, xlo);

@@ -37,7 +37,7 @@ class PolicyDesc(C.Structure):
         ("lr", C.c_double), ("gamma", C.c_double),
         ("w1", C.c_double), ("w2", C.c_double), ("w3", C.c_double), ("eps_min", C.c_double),
         ("cost", C.c_double * 4), ("seed", C.c_uint64),
-        ("replace_period", C.c_int32), ("reserved", C.c_int32),
+        ("replace_period", C.c_int32), ("decision_period", C.c_int32),
     ]
 
 
@@ -204,7 +204,7 @@ class Policy:
 
     def __init__(self, kind=POLICY_FIXED, fixed_action=63, t_bin=1000, b_it=5, b_res=10, w_stag=10,
                  lr=0.1, gamma=0.9, w=(1.0, 0.1, 10.0), eps_min=1e-16, cost="C1", seed=0,
-                 replace_period=50):
+                 replace_period=50, decision_period=1):
         d = PolicyDesc()
         d.kind, d.fixed_action, d.t_bin, d.b_it, d.b_res, d.w_stag = kind, fixed_action, t_bin, b_it, b_res, w_stag
         d.lr, d.gamma = lr, gamma
@@ -215,6 +215,7 @@ class Policy:
             d.cost[i] = costs[i]
         d.seed = seed
         d.replace_period = replace_period
+        d.decision_period = decision_period
         self.desc = d
         self.n_states = b_res * b_it * 2
         h = C.c_void_p()

@@ -240,6 +240,7 @@ struct mpcg_policy {
       for (int s = 0; s < n_states; ++s) p.qbest[s] = qbest[s];
     }
     p.replace_period = desc.replace_period;
+    p.decision_period = desc.decision_period;
     p.roll_cap = roll_cap;
     p.roll_feat = d_rf;
     p.roll_next = d_rn;
@@ -676,6 +677,7 @@ int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out) {
   if (desc->fixed_action < 0 || desc->fixed_action > 79) return fail(MPCG_ERR_INVALID, "bad fixed_action");
   if (desc->b_it < 1 || desc->b_res < 1 || desc->b_res > kMaxEdges + 1 || desc->t_bin < 1 || desc->w_stag < 1)
     return fail(MPCG_ERR_INVALID, "bad bin parameters");
+  if (desc->decision_period < 0) return fail(MPCG_ERR_INVALID, "negative decision_period");
   mpcg_policy *P = new (std::nothrow) mpcg_policy();
   if (!P) return fail(MPCG_ERR_NOMEM, "host allocation failed");
   P->desc = *desc;

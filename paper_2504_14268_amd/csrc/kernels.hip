@@ -353,9 +353,11 @@ __device__ double policy_cost(const PolicyDev *P, int a) {
   return (P->cost[(a >> 4) & 3] + P->cost[(a >> 2) & 3]) + P->cost[a & 3];
 }
 
-__device__ double policy_reward(const PolicyDev *P, int a, double rho, bool conv) {
+// Reward of a decision whose action ran n_it iterations (n_it = 1: the
+// per-iteration reward of section 4.1).
+__device__ double policy_reward(const PolicyDev *P, int a, double rho, bool conv, int n_it) {
   const double accterm = (rho <= P->eps_min) ? -log10_policy(P->eps_min) : -log10_policy(rho);
-  double r = P->w1 * accterm - P->w2 * policy_cost(P, a);
+  double r = P->w1 * accterm - P->w2 * (policy_cost(P, a) * (double)n_it);
   if (conv) r = r + P->w3;
   return r;
 }
@@ -643,6 +645,7 @@ __device__ __forceinline__ int init_t0(const Sx &a, double s64, double s64z, flo
   const int s = need_state ? policy_state(P, k, rt, stag) : 0;
   c->s = s;
   if (lags) mlp_features(P, k, hv.lag, stag, rt, c->prev_action, c->feat);
+  c->k_dec = k;
   if (c->fell_back) {
     apply_decision<FULL>(a, 63, 0, true);
     return 0;
@@ -690,8 +693,10 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
   } else if (want_feat) {
     for (int i = 0; i < kMlpIn; ++i) c->feat_next[i] = c->feat[i];
   }
+  // iterations run under the current decision, a failed one included
+  const int n_it = (completed ? k : k + 1) - c->k_dec;
   if (converged) {
-    const double rw = policy_reward(P, act, rho, true);
+    const double rw = policy_reward(P, act, rho, true, n_it);
     if (training && a.writer) q_update(P, s, act, rw);
     if (FULL && active && a.writer) roll_log(P, c->feat, c->feat_next, act, rw, 1);
     c->status = c->fell_back ? 2 : 0;
@@ -700,7 +705,7 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
     return 0;
   }
   if (broke || (stagnated && c->fallback_enabled && !c->fell_back)) {
-    const double rw = -P->w2 * policy_cost(P, act) - P->w3;
+    const double rw = -P->w2 * (policy_cost(P, act) * (double)n_it) - P->w3;
     if (training && a.writer) q_update(P, s, act, rw);
     if (FULL && active && a.writer) roll_log(P, c->feat, c->feat_next, act, rw, 1);
     if (!c->fallback_enabled || c->fell_back) {
@@ -716,8 +721,11 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
         c->k3op = K3_FOLD;
     return 0;
   }
-  if (training || (FULL && active && a.writer && P->roll_cap > 0)) {   // the reward has a reader
-    const double rw = policy_reward(P, act, rho, false);
+  // a decision ends at a multiple of the decision period, and when the budget cuts it
+  const int D = P->decision_period > 1 ? P->decision_period : 1;
+  const bool dec_end = (k % D == 0) || k >= c->maxit;
+  if (dec_end && (training || (FULL && active && a.writer && P->roll_cap > 0))) {   // the reward has a reader
+    const double rw = policy_reward(P, act, rho, false, n_it);
     if (training && a.writer) {
       const double *row = &P->q[s_next * kNAct];
       q_update(P, s, act, rw + P->gamma * row[q_argmax(row)]);
@@ -732,8 +740,13 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
   c->beta = beta;
   c->sigma = c->sig_new;
   c->prev_action = act;
-  c->s = s_next;
   c->k3_fa = act & 3;
+  if (!dec_end) {                 // the action holds until the decision ends
+    apply_decision<FULL>(a, act, 0, false);
+    return 0;
+  }
+  c->s = s_next;
+  c->k_dec = k;
   if (want_feat)
     for (int i = 0; i < kMlpIn; ++i) c->feat[i] = c->feat_next[i];
   if (c->fell_back) {

@@ -61,6 +61,7 @@ struct PolicyDev {
   int64_t episode;
   const float *W1, *b1, *W2, *b2, *W3, *b3;
   int32_t replace_period;
+  int32_t decision_period;       // the policy acts every decision_period iterations (<= 1: every one)
   int32_t roll_cap;
   float *roll_feat, *roll_next;
   int32_t *roll_act;
@@ -89,7 +90,8 @@ struct Ctl {
   int32_t R, fallback_enabled, k3_fa, zero_solution;
   int32_t bnorm_ready, pend_sigma, b_op, step_done;
   int32_t fold_done, precond;     // precond: 1 = Jacobi-preconditioned iteration
-  int32_t dir_restart, pad_;      // 1: the next direction update restarts (p = z)
+  int32_t dir_restart, k_dec;     // 1: the next direction update restarts (p = z);
+                                  // k_dec: iteration of the current decision
   double tol, bnorm, sigma, sig_new, alpha, beta, rho_new, last_true, cost_sum, relres_true;
   double rep_hist[3];
   float feat[kMlpIn];

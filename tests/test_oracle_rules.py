@@ -182,3 +182,52 @@ def test_truncation_at_maxit_bootstraps():
     boot = 1.0 + 0.1 * (R + 0.9 * 1.0 - 1.0)
     assert abs(pol.q[0, 42] - boot) < 1e-12
     assert abs(pol.q[0, 42] - (1.0 + 0.1 * (R - 1.0))) > 1e-3   # the terminal form differs
+
+
+# ---------------------------------------------------------------- decision period
+def test_decision_period_one_update_per_decision():
+    """Two eigencomponents: fp64 CG converges in two iterations.  With D = 1 the
+    two transitions update Q[s0, 63] and Q[s1, 63] (section 4.1).  With D = 8
+    the decision taken at k = 0 holds through both iterations and ends at
+    convergence: one terminal update of Q[s0, 63] toward
+    R = -log10 rho_2 - 0.1 * (6.0 * 2) + 10, the cost of both iterations."""
+    A = W.laplacian_2d(8)
+    ev, V = np.linalg.eigh(A.to_dense())
+    b = V[:, 2] + 0.5 * V[:, 40]
+    q0 = np.zeros((100, 64))
+    q0[:, 63] = 0.25
+    pol = O.OraclePolicy(kind=O.POL_QTRAIN, q=q0, epsilon=0.0, cost="C1", decision_period=8)
+    x, info = O.cg(A, b, tol=1e-10, maxit=5, policy=pol, replace_period=50)
+    assert info["status"] == 0 and info["iters"] == 2
+    rho2 = info["rho"][2]
+    s0 = pol.state(0, 1.0, 0)
+    R = (16.0 if rho2 <= 1e-16 else -math.log10(rho2)) - 0.1 * (6.0 * 2) + 10.0
+    assert abs(pol.q[s0, 63] - (0.25 + 0.1 * (R - 0.25))) < 1e-12
+    assert np.count_nonzero(pol.q != q0) == 1
+
+
+def test_decision_period_holds_the_action_and_logs_one_row_per_decision():
+    """A greedy table whose best action differs in every state: with D = 5 the
+    action changes only at k = 0, 5, 10, ...; with rollout logging each
+    decision leaves one row, whose reward charges its 5 iterations."""
+    A = W.laplacian_2d(20)
+    b = W.rhs(A.n, 7)
+    rng = np.random.default_rng(3)
+    q = rng.standard_normal((100, 64))
+    q[:, 42] += 5.0                      # fp32 actions mostly, so the solve runs long
+    q[::3, 26] += 7.0
+    pol = O.OraclePolicy(kind=O.POL_QTABLE, q=q, decision_period=5)
+    x, info = O.cg(A, b, tol=1e-8, maxit=60, policy=pol, replace_period=50, roll_cap=100)
+    acts = info["actions"]
+    k = info["iters"]
+    for i in range(1, k):
+        if i % 5:
+            assert acts[i] == acts[i - 1]
+    ro = info["rollouts"]
+    assert len(ro["act"]) == (k + 4) // 5
+    # the first decision's reward: accuracy at rho_5 minus 5 iterations of its cost
+    c = {0: 0.8, 1: 0.6, 2: 1.0, 3: 2.0}
+    a0 = int(acts[0])
+    cost = c[(a0 >> 4) & 3] + c[(a0 >> 2) & 3] + c[a0 & 3]
+    want = -math.log10(info["rho"][5]) - 0.1 * cost * 5
+    assert abs(float(ro["rew"][0]) - want) <= 1e-5 * max(1.0, abs(want))
