@@ -100,9 +100,25 @@ def build_systems(M, W, torch, seeds, n_hi=5e5, kappa_hi=1e8):
     return systems
 
 
-def train_qtable(M, systems, episodes, maxit, cost, seed=12345, rollouts=0):
-    """Trains a device Q-table (Algorithm 1) over the systems, episode sweeps."""
-    P = M.Policy(kind=M.POLICY_QTABLE_TRAIN, cost=cost, seed=seed)
+# Cost per format measured on this GPU (a labelled variation of the cost
+# settings C1 / C2): the fp64 kernels of an iteration take 1.8-1.9x the fp32
+# ones (SpMV 35.6 vs 19.4 us, axpy+dot 22.2 vs 11.5 us, direction 12.1 vs
+# 6.8 us on the 3D Laplacian 128^3), and fp16 / bf16 dots and updates run in
+# fp32 containers, at fp32's time.
+COST_HW = (1.0, 1.0, 1.0, 1.9)
+
+
+def cost_table(name):
+    return COST_HW if name == "Chw" else name
+
+
+def train_qtable(M, systems, episodes, maxit, cost, seed=12345, rollouts=0, w1=1.0, gamma=0.9, D=1, per_op=0):
+    """Trains a device Q-table (Algorithm 1) over the systems, episode sweeps.
+    w1: weight of the reward's accuracy term (section 4.1: 1.0); gamma: the
+    discount (section 5: 0.9); D: the decision period (1: every iteration);
+    per_op: one Q-table per operation (section 4.1) instead of a joint one."""
+    P = M.Policy(kind=M.POLICY_QTABLE_TRAIN, cost=cost_table(cost), seed=seed, w=(w1, 0.1, 10.0), gamma=gamma,
+                 decision_period=D, per_op=per_op)
     if rollouts:
         P.rollouts_enable(rollouts)
     res = M.train_qlearning(P, systems, episodes=episodes, maxit=maxit, tol=1e-8, eps_start=1.0,
@@ -254,10 +270,11 @@ def mlp_experiment(args, M, W, torch) -> dict:
     out["train_systems"] = len(systems)
     log(f"[mlp] {len(systems)} training systems built in {time.time() - t0:.1f} s")
     t0 = time.time()
-    P, res = train_qtable(M, systems, args.episodes, 1000, "C1", rollouts=1_000_000)
+    P, res = train_qtable(M, systems, args.episodes, 1000, "C1", rollouts=1_000_000, w1=args.w1)
     roll = P.rollouts()
     n = len(roll["act"])
-    out["qlearning"] = {"episodes": len(res), "wall_s": round(time.time() - t0, 1), "rollouts": n}
+    out["qlearning"] = {"episodes": len(res), "wall_s": round(time.time() - t0, 1), "rollouts": n,
+                        "reward_weights": [args.w1, 0.1, 10.0]}
     log(f"[mlp] Q-learning: {out['qlearning']}")
     for mm, _, _ in systems:
         mm.close()
@@ -289,9 +306,12 @@ def mlp_experiment(args, M, W, torch) -> dict:
     pols = {"fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=63),
             "fixed_mixed": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.BF16, M.FP32, M.FP32)),
             "qtable": greedy, "mlp_untrained": untrained, "mlp": mlp_pol}
-    rows, summ = evaluate_policies(M, W, torch, range(2000, 2000 + args.heldout_systems), pols, args.eval_maxit)
+    out["heldout"] = {"seeds": [2000, 2000 + args.heldout_systems - 1], "n_hi": args.heldout_n_hi,
+                      "maxit": args.eval_maxit}
+    rows, summ = evaluate_policies(M, W, torch, range(2000, 2000 + args.heldout_systems), pols, args.eval_maxit,
+                                   family=lambda sd: W.family_system(sd, n_hi=args.heldout_n_hi))
     out["heldout_summary"] = summ
-    out["heldout"] = rows
+    out["heldout_rows"] = rows
     return out
 
 
@@ -309,31 +329,44 @@ def qlearning_experiment(args, M, W, torch) -> dict:
     systems = build_systems(M, W, torch, train_seeds)
     out["train_setup_s"] = round(time.time() - t0, 1)
     log(f"[qlearning] {len(systems)} training systems built in {out['train_setup_s']} s")
-    for cost in ("C1", "C2"):
+    if args.variants:
+        variants = []
+        for v in args.variants.split(","):
+            f = v.split(":") + ["1.0", "0.9", "1", "0"][len(v.split(":")) - 1:]
+            variants.append((f[0], float(f[1]), float(f[2]), int(f[3]), int(f[4])))
+    else:
+        variants = [("C1", 1.0, 0.9, 1, 0), ("C2", 1.0, 0.9, 1, 0)] + (
+            [("C1", 0.0, 0.9, 1, 0), ("C2", 0.0, 0.9, 1, 0)] if args.w1_variation else [])
+    for cost, w1, gamma, D, per_op in variants:
+        lab = (cost + ("" if w1 == 1.0 else f"_w1_{w1:g}") + ("" if gamma == 0.9 else f"_g{gamma:g}")
+               + ("" if D == 1 else f"_D{D}") + ("_perop" if per_op else ""))
         t0 = time.time()
-        P, res = train_qtable(M, systems, args.episodes, 1000, cost)
+        P, res = train_qtable(M, systems, args.episodes, 1000, cost, w1=w1, gamma=gamma, D=D, per_op=per_op)
         dt = time.time() - t0
         it = np.array([r["iters"] for r in res])
         conv = np.array([r["status"] in (0, 2) for r in res])
         sweeps = np.array_split(np.arange(len(res)), args.episodes)
-        out[f"train_{cost}"] = {"wall_s": round(dt, 1), "episodes": len(res),
+        out[f"train_{lab}"] = {"wall_s": round(dt, 1), "episodes": len(res), "w1": w1, "gamma": gamma, "D": D,
+                               "per_op": per_op,
+                               "cost_table": list(cost_table(cost)) if cost == "Chw" else cost,
                                 "iterations": int(it.sum()),
                                 "converged_share_per_sweep": [round(float(conv[s].mean()), 3) for s in sweeps],
                                 "mean_cost_per_iteration_per_sweep": [
                                     round(float(sum(res[j]["cost_sum"] for j in s) / max(1, sum(res[j]["iters"] for j in s))), 3)
                                     for s in sweeps]}
-        log(f"[qlearning] {cost}: {out[f'train_{cost}']}")
-        policies[cost] = P
+        log(f"[qlearning] {lab}: {out[f'train_{lab}']}")
+        policies[lab] = (P, cost, D, per_op)
     for mm, _, _ in systems:
         mm.close()
     del systems
     fixed = M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.BF16, M.FP32, M.FP32))
     fp64 = M.Policy(kind=M.POLICY_FIXED, fixed_action=63)
     greedy = {}
-    for cost, P in policies.items():
-        g = M.Policy(kind=M.POLICY_QTABLE, cost=cost)
+    for lab, (P, cost, D, per_op) in policies.items():
+        g = M.Policy(kind=M.POLICY_QTABLE, cost=cost_table(cost), decision_period=D, per_op=per_op)
         g.set_qtable(P.qtable())
-        greedy[cost] = g
+        greedy[lab] = g
+    labels = ["fp64", "fixed_mixed"] + [f"learned_{lab}" for lab in greedy]
     rows = []
     for sd in held:
         A = W.family_system(sd)
@@ -341,8 +374,7 @@ def qlearning_experiment(args, M, W, torch) -> dict:
         b = torch.from_numpy(W.rhs(A.n, sd + 10000)).cuda()
         x = torch.empty(A.n, dtype=torch.float64, device="cuda")
         row = {"seed": sd, "name": A.name, "n": A.n, "nnz": A.nnz}
-        for lab, pol in (("fp64", fp64), ("fixed_mixed", fixed), ("learned_C1", greedy["C1"]),
-                         ("learned_C2", greedy["C2"])):
+        for lab, pol in [("fp64", fp64), ("fixed_mixed", fixed)] + [(f"learned_{k}", g) for k, g in greedy.items()]:
             mm.set_policy(pol)
             mm.set_options(replace_period=50, fallback=True)
             x.zero_()
@@ -354,11 +386,10 @@ def qlearning_experiment(args, M, W, torch) -> dict:
                 row[lab]["mix"] = mix_of(M, mm.history()["actions"])
         rows.append(row)
         log(f"[qlearning] held-out {sd} {A.name}: " +
-            ", ".join(f"{k} {row[k]['status']}/{row[k]['iters']}/{row[k]['ms']}ms" for k in
-                      ("fp64", "fixed_mixed", "learned_C1", "learned_C2")))
+            ", ".join(f"{k} {row[k]['status']}/{row[k]['iters']}/{row[k]['ms']}ms" for k in labels))
         mm.close()
     summ = {}
-    for lab in ("fp64", "fixed_mixed", "learned_C1", "learned_C2"):
+    for lab in labels:
         ok = [r for r in rows if r[lab]["status"] in (0, 2)]
         both = [r for r in rows if r[lab]["status"] in (0, 2) and r["fp64"]["status"] in (0, 2)]
         summ[lab] = {"success": f"{len(ok)}/{len(rows)}",
@@ -387,6 +418,16 @@ def main():
     ap.add_argument("--heldout-systems", type=int, default=50)
     ap.add_argument("--episodes", type=int, default=5)
     ap.add_argument("--eval-maxit", type=int, default=20000)
+    ap.add_argument("--w1-variation", action="store_true",
+                    help="also train with the reward's accuracy weight w1 = 0 (a labelled variation; "
+                         "section 4.1's weights are (1, 0.1, 10))")
+    ap.add_argument("--w1", type=float, default=1.0, help="accuracy weight of the MLP experiment's reward")
+    ap.add_argument("--variants", default="",
+                    help="Q-learning variants cost[:w1[:gamma[:D[:per_op]]]], comma separated (cost C1, C2 "
+                         "or Chw, the cost per format measured on this GPU; D the decision period; per_op 1 for "
+                         "one Q-table per operation); default: C1 and C2 with section 4.1's weights, a joint "
+                         "table, decisions every iteration")
+    ap.add_argument("--heldout-n-hi", type=float, default=5e5, help="largest held-out system size")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-policy leg")
     ap.add_argument("--batched", action="store_true",
                     help="batched experiment: 512 uneven systems in one persistent launch vs sequential solves")

@@ -111,6 +111,14 @@ typedef struct {
                                   the cost of every iteration it ran and its
                                   Q update (and rollout) happens when it ends.
                                   0 or 1: every iteration (section 4.1)        */
+    int32_t per_op;            /* 1: one Q-table per operation (section 4.1's
+                                  Q_j for SpMV, dot, update), Q_j(s, p) at
+                                  table row s, column 4 j + p; the greedy action
+                                  takes each table's argmax, exploration draws
+                                  per operation, and every Q_j is updated with
+                                  the shared reward.  0: one joint table over
+                                  the 64 actions                                 */
+    int32_t reserved;
 } mpcg_policy_desc;
 
 typedef struct {
@@ -139,7 +147,12 @@ typedef struct {
                                   and the direction restarts (p = z) when the
                                   true residual exceeds twice the recursive one.
                                   Not for batched solves.                       */
-    int32_t reserved;
+    int32_t stop_rule;         /* 0: converged when the true fp64 relres is <= tol
+                                  at a replacement (a recursive rho <= tol
+                                  triggers one); 1: section 5's termination, the
+                                  recursive rho < tol after at least 10
+                                  iterations, no true-residual check (the result
+                                  still reports the final x's true relres)     */
 } mpcg_solve_opts;
 
 /* Per-kernel timing of the last solve made with opts.profile = 1.  One CG

@@ -78,13 +78,14 @@ class Policy(C.Structure):
         ("w2m", C.POINTER(C.c_float)), ("b2m", C.POINTER(C.c_float)),
         ("w3m", C.POINTER(C.c_float)), ("b3m", C.POINTER(C.c_float)),
         ("replace_period", C.c_int32), ("decision_period", C.c_int32),
+        ("per_op", C.c_int32), ("pad2", C.c_int32),
     ]
 
 
 class Params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("replace_period", C.c_int32),
                 ("fallback", C.c_int32), ("dot_order", C.c_int32), ("precond", C.c_int32),
-                ("pad", C.c_int32)]
+                ("stop_rule", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -279,7 +280,8 @@ class OraclePolicy:
 
     def __init__(self, kind=POL_FIXED, fixed_action=63, q=None, t_bin=1000, b_it=5,
                  b_res=10, w_stag=10, lr=0.1, gamma=0.9, w=(1.0, 0.1, 10.0), eps_min=1e-16,
-                 cost="C1", epsilon=0.0, seed=0, episode=0, mlp=None, replace_period=50, decision_period=1):
+                 cost="C1", epsilon=0.0, seed=0, episode=0, mlp=None, replace_period=50, decision_period=1,
+                 per_op=0):
         self.s = Policy()
         s = self.s
         s.kind, s.fixed_action = kind, fixed_action
@@ -299,6 +301,7 @@ class OraclePolicy:
         s.epsilon, s.seed, s.episode = epsilon, seed, episode
         s.replace_period = replace_period
         s.decision_period = decision_period
+        s.per_op = int(per_op)
         self.mlp = None
         if mlp is not None:
             self.set_mlp(mlp)
@@ -340,14 +343,15 @@ def jacobi_inverse(A):
 
 
 def cg(A, b, x0=None, tol=1e-8, maxit=1000, policy: OraclePolicy | None = None,
-       replace_period=0, fallback=False, order=ORDER_PAIRWISE, roll_cap=0, dump=0, precond=0):
-    """Run the oracle solver (precond 1: Jacobi).  Returns (x, info dict with histories)."""
+       replace_period=0, fallback=False, order=ORDER_PAIRWISE, roll_cap=0, dump=0, precond=0, stop_rule=0):
+    """Run the oracle solver (precond 1: Jacobi; stop_rule 1: the paper's
+    termination, recursive rho < tol with k >= 10).  Returns (x, info dict with histories)."""
     n = A.n
     b = _f64(b)
     x0 = np.zeros(n) if x0 is None else _f64(x0)
     x = np.empty(n)
     pol = policy if policy is not None else OraclePolicy()
-    prm = Params(tol, maxit, replace_period, int(fallback), order, int(precond), 0)
+    prm = Params(tol, maxit, replace_period, int(fallback), order, int(precond), int(stop_rule))
     res = Result()
     hist_rho = np.full(maxit + 1, np.nan)
     hist_act = np.zeros(max(maxit, 1), dtype=np.uint8)

@@ -424,6 +424,8 @@ typedef struct {
     const float *w1m, *b1m, *w2m, *b2m, *w3m, *b3m;
     int32_t replace_period;  /* R, used by the MLP features */
     int32_t decision_period; /* D: the policy acts every D iterations (0, 1: every one) */
+    int32_t per_op;          /* 1: one Q-table per operation (section 4.1) in row[4 j + p] */
+    int32_t pad2;
 } orc_policy;
 
 int orc_n_states(const orc_policy *pol) { return pol->b_res * pol->b_it * 2; }
@@ -449,6 +451,47 @@ static int argmax_row(const double *row)
 
 static double max_row(const double *row) { return row[argmax_row(row)]; }
 
+/* Separate Q-tables per operation (section 4.1: Q_j over states x precisions,
+ * j = SpMV, dot, update), held in one table row per state: Q_j(s, p) =
+ * q[s][4 j + p].  The greedy action takes each operation's argmax (lowest
+ * index among ties). */
+static int argmax4(const double *t)
+{
+    int best = 0;
+    for (int p = 1; p < 4; ++p)
+        if (t[p] > t[best]) best = p;
+    return best;
+}
+
+static int greedy_row(const orc_policy *pol, const double *row)
+{
+    if (!pol->per_op) return argmax_row(row);
+    return 16 * argmax4(row) + 4 * argmax4(row + 4) + argmax4(row + 8);
+}
+
+/* Q update of the decision (s, a) toward reward R, bootstrapped from state
+ * s_next (s_next < 0: terminal).  With one table per operation each Q_j is
+ * updated toward R + gamma max_p Q_j(s', p) (the paper's per-table update). */
+static void q_learn(orc_policy *pol, int s, int a, double R, int s_next)
+{
+    if (!pol->per_op) {
+        double t = s_next < 0 ? R : R + pol->gamma * max_row(&pol->q[s_next * N_ACT]);
+        double *qsa = &pol->q[s * N_ACT + a];
+        *qsa = *qsa + pol->lr * (t - *qsa);
+        return;
+    }
+    for (int j = 0; j < 3; ++j) {
+        const int pj = (a >> (4 - 2 * j)) & 3;
+        double t = R;
+        if (s_next >= 0) {
+            const double *nx = &pol->q[s_next * N_ACT + 4 * j];
+            t = R + pol->gamma * nx[argmax4(nx)];
+        }
+        double *qsa = &pol->q[s * N_ACT + 4 * j + pj];
+        *qsa = *qsa + pol->lr * (t - *qsa);
+    }
+}
+
 /* Cost of an action: c(f_s) + c(f_d) + c(f_a).  The cost settings give no
  * value for q52 (actions 64..79); (a >> 4) & 3 charges it as fp16. */
 static double cost_of(const orc_policy *pol, int a)
@@ -473,11 +516,6 @@ double orc_reward(const orc_policy *pol, int a, double rho, int terminal)
     return reward(pol, a, rho, terminal, 1);
 }
 
-static void q_update(orc_policy *pol, int s, int a, double target)
-{
-    double *qsa = &pol->q[s * N_ACT + a];
-    *qsa = *qsa + pol->lr * (target - *qsa);
-}
 
 /* GELU, erf form, with erf from Abramowitz & Stegun 7.1.28 (rational, only + x /). */
 static float gelu(float x)
@@ -571,7 +609,8 @@ typedef struct {
     int32_t fallback;
     int32_t dot_order;
     int32_t precond;          /* 0: M = I; 1: Jacobi, M = diag(A) */
-    int32_t pad;
+    int32_t stop_rule;        /* 0: true fp64 relres <= tol at a replacement;
+                                 1: the paper's, recursive rho < tol with k >= 10 */
 } orc_params;
 
 typedef struct {
@@ -636,8 +675,25 @@ static int decide(const orc_policy *pol, int kind, const float *feat, int s, int
     case POL_FIXED:
         return pol->fixed_action;
     case POL_QTABLE:
-        return argmax_row(&pol->q[s * N_ACT]);
+        return greedy_row(pol, &pol->q[s * N_ACT]);
     case POL_QTRAIN: {
+        if (pol->per_op) {       /* an epsilon-greedy draw per operation, streams 2 .. 7 */
+            const double *row = &pol->q[s * N_ACT];
+            int a = 0;
+            for (int j = 0; j < 3; ++j) {
+                int pj;
+                double u0 = orc_uniform(pol->seed, (uint64_t)pol->episode, (uint64_t)k, (uint64_t)(2 + 2 * j));
+                if (u0 < pol->epsilon) {
+                    double u1 = orc_uniform(pol->seed, (uint64_t)pol->episode, (uint64_t)k, (uint64_t)(3 + 2 * j));
+                    pj = (int)(u1 * 4.0);
+                    *explored = 1;
+                } else {
+                    pj = argmax4(row + 4 * j);
+                }
+                a = a * 4 + pj;
+            }
+            return a;
+        }
         double u0 = orc_uniform(pol->seed, (uint64_t)pol->episode, (uint64_t)k, 0);
         if (u0 < pol->epsilon) {
             double u1 = orc_uniform(pol->seed, (uint64_t)pol->episode, (uint64_t)k, 1);
@@ -798,7 +854,14 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             }
             k += 1;
             rho_new = sqrt(sig_rr) / bnorm;
-            if ((R > 0 && k % R == 0) || rho_new <= prm->tol || !isfinite(sig_rr) || !isfinite(sig_new)) {
+            /* section 5's termination: the recursive residual below tol after
+               at least 10 iterations, with no true-residual check */
+            const int paper_stop = prm->stop_rule == 1 && rho_new < prm->tol && k >= 10 && isfinite(sig_rr) &&
+                                   isfinite(sig_new);
+            if (paper_stop) {
+                converged = 1;
+            } else if ((R > 0 && k % R == 0) || (prm->stop_rule == 0 && rho_new <= prm->tol) || !isfinite(sig_rr) ||
+                       !isfinite(sig_new)) {
                 const double rho_rec = rho_new;
                 fold(n, xhi, xlo);
                 mat_residual(&A, b, xhi, r64);
@@ -846,14 +909,14 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         const int64_t n_it = (k > kk ? k : k + 1) - k_dec;
         if (converged) {
             double rw = reward(pol, a, rho_new, 1, n_it);
-            if (training) q_update(pol, s, a, rw);
+            if (training) q_learn(pol, s, a, rw, -1);
             if (policy_active) roll_log(h, feat, feat_next, a, rw, 1);
             status = fell_back ? 2 : 0;
             break;
         }
         if (broke || (stagnated && prm->fallback && !fell_back)) {
             double rw = -pol->w2 * (cost_of(pol, a) * (double)n_it) - pol->w3;
-            if (training) q_update(pol, s, a, rw);
+            if (training) q_learn(pol, s, a, rw, -1);
             if (policy_active) roll_log(h, feat, feat_next, a, rw, 1);
             if (!prm->fallback || fell_back) { status = 3; break; }
             fell_back = 1;
@@ -868,7 +931,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         const int dec_end = (k % D == 0) || k >= prm->maxit;
         if (dec_end) {
             double rw = reward(pol, a, rho_new, 0, n_it);
-            if (training) q_update(pol, s, a, rw + pol->gamma * max_row(&pol->q[s_next * N_ACT]));
+            if (training) q_learn(pol, s, a, rw, s_next);
             if (policy_active) roll_log(h, feat, feat_next, a, rw, 0);
         }
         if (k >= prm->maxit) { status = 1; break; }
@@ -903,7 +966,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
 
     fold(n, xhi, xlo);
     for (int64_t i = 0; i < n; ++i) x_out[i] = xhi[i];
-    if (status == 0 || status == 2) {
+    if ((status == 0 || status == 2) && prm->stop_rule == 0) {
         res->relres_true = last_true;
     } else {
         mat_residual(&A, b, xhi, r64);

@@ -38,6 +38,7 @@ class PolicyDesc(C.Structure):
         ("w1", C.c_double), ("w2", C.c_double), ("w3", C.c_double), ("eps_min", C.c_double),
         ("cost", C.c_double * 4), ("seed", C.c_uint64),
         ("replace_period", C.c_int32), ("decision_period", C.c_int32),
+        ("per_op", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -45,7 +46,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("replace_period", C.c_int32), ("fallback", C.c_int32),
                 ("chunk", C.c_int32), ("profile", C.c_int32),
                 ("spmv_rows", C.c_int32), ("index16", C.c_int32),
-                ("precond", C.c_int32), ("reserved", C.c_int32)]
+                ("precond", C.c_int32), ("stop_rule", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -204,7 +205,7 @@ class Policy:
 
     def __init__(self, kind=POLICY_FIXED, fixed_action=63, t_bin=1000, b_it=5, b_res=10, w_stag=10,
                  lr=0.1, gamma=0.9, w=(1.0, 0.1, 10.0), eps_min=1e-16, cost="C1", seed=0,
-                 replace_period=50, decision_period=1):
+                 replace_period=50, decision_period=1, per_op=0):
         d = PolicyDesc()
         d.kind, d.fixed_action, d.t_bin, d.b_it, d.b_res, d.w_stag = kind, fixed_action, t_bin, b_it, b_res, w_stag
         d.lr, d.gamma = lr, gamma
@@ -216,6 +217,7 @@ class Policy:
         d.seed = seed
         d.replace_period = replace_period
         d.decision_period = decision_period
+        d.per_op = int(per_op)
         self.desc = d
         self.n_states = b_res * b_it * 2
         h = C.c_void_p()
@@ -450,8 +452,9 @@ class Matrix:
         self.policy = policy
 
     def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False, spmv_rows=0, index16=0,
-                    precond=0):
-        o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, index16, int(precond), 0)
+                    precond=0, stop_rule=0):
+        o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, index16, int(precond),
+                      int(stop_rule))
         _check(lib().mpcg_set_options(self.h, C.byref(o)), "set_options")
 
     def solve(self, b, x, tol=1e-8, maxit=1000) -> dict:

@@ -241,6 +241,7 @@ struct mpcg_policy {
     }
     p.replace_period = desc.replace_period;
     p.decision_period = desc.decision_period;
+    p.per_op = desc.per_op;
     p.roll_cap = roll_cap;
     p.roll_feat = d_rf;
     p.roll_next = d_rn;
@@ -302,7 +303,7 @@ struct mpcg_matrix {
   // policy
   mpcg_policy *pol = nullptr;
   mpcg_policy *defpol = nullptr;
-  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0, 0, 0};
+  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0, 0, 0};   // replace_period .. precond, stop_rule
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_chunk[2] = {nullptr, nullptr};
   int P2 = 0;
 
@@ -678,6 +679,7 @@ int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out) {
   if (desc->b_it < 1 || desc->b_res < 1 || desc->b_res > kMaxEdges + 1 || desc->t_bin < 1 || desc->w_stag < 1)
     return fail(MPCG_ERR_INVALID, "bad bin parameters");
   if (desc->decision_period < 0) return fail(MPCG_ERR_INVALID, "negative decision_period");
+  if (desc->per_op != 0 && desc->per_op != 1) return fail(MPCG_ERR_INVALID, "per_op must be 0 or 1");
   mpcg_policy *P = new (std::nothrow) mpcg_policy();
   if (!P) return fail(MPCG_ERR_NOMEM, "host allocation failed");
   P->desc = *desc;
@@ -702,14 +704,20 @@ int mpcg_policy_destroy(mpcg_policy *P) {
 int mpcg_policy_set_qtable(mpcg_policy *P, const double *q) {
   if (!P || !q) return fail(MPCG_ERR_INVALID, "NULL argument");
   HIP_TRY(hipMemcpy(P->d_q, q, sizeof(double) * (size_t)P->n_states * kNAct, hipMemcpyHostToDevice));
-  // the greedy action per state, by the device's rule (first strict maximum)
+  // the greedy action per state, by the device's rule (first strict maximum;
+  // per operation with one table per operation)
+  auto first_max = [](const double *row, int len) {
+    int best = 0;
+    double bv = row[0];
+    for (int a = 1; a < len; ++a)
+      if (row[a] > bv) { best = a; bv = row[a]; }
+    return best;
+  };
   P->qbest.resize((size_t)P->n_states);
   for (int s = 0; s < P->n_states; ++s) {
     const double *row = q + (size_t)s * kNAct;
-    int best = 0;
-    double bv = row[0];
-    for (int a = 1; a < kNAct; ++a)
-      if (row[a] > bv) { best = a; bv = row[a]; }
+    const int best = P->desc.per_op ? 16 * first_max(row, 4) + 4 * first_max(row + 4, 4) + first_max(row + 8, 4)
+                                    : first_max(row, kNAct);
     P->qbest[s] = (uint8_t)best;
   }
   return MPCG_OK;
@@ -848,6 +856,7 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
     return fail(MPCG_ERR_INVALID, "spmv_rows must be 0, 512, 1024 or 2048");
   if (o->index16 != 0 && o->index16 != -1) return fail(MPCG_ERR_INVALID, "index16 must be 0 or -1");
   if (o->precond != 0 && o->precond != 1) return fail(MPCG_ERR_INVALID, "precond must be 0 or 1");
+  if (o->stop_rule != 0 && o->stop_rule != 1) return fail(MPCG_ERR_INVALID, "stop_rule must be 0 or 1");
   A->opts = *o;
   return MPCG_OK;
 }
@@ -870,6 +879,7 @@ static int upload_start(mpcg_matrix *A, mpcg_policy *P, double tol, int32_t maxi
   c.R = A->opts.replace_period;
   c.fallback_enabled = A->opts.fallback ? 1 : 0;
   c.precond = A->opts.precond;
+  c.stop_rule = A->opts.stop_rule;
   c.tol = tol;
   HIP_TRY(hipMemcpyAsync(A->d_ctl, A->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   return MPCG_OK;

@@ -362,9 +362,44 @@ __device__ double policy_reward(const PolicyDev *P, int a, double rho, bool conv
   return r;
 }
 
-__device__ void q_update(const PolicyDev *P, int s, int a, double target) {
-  double *q = &P->q[s * kNAct + a];
-  *q = *q + P->lr * (target - *q);
+// One Q-table per operation (section 4.1: Q_j over states x precisions for
+// j = SpMV, dot, update) lives in the same table row: Q_j(s, p) = q[s][4 j + p].
+__device__ __forceinline__ int argmax4(const double *t) {
+  int best = 0;
+  double bv = t[0];
+  for (int p = 1; p < 4; ++p)
+    if (t[p] > bv) { best = p; bv = t[p]; }
+  return best;
+}
+
+__device__ __forceinline__ int q_greedy_row(const PolicyDev *P, const double *row) {
+  if (!P->per_op) return q_argmax(row);
+  return 16 * argmax4(row) + 4 * argmax4(row + 4) + argmax4(row + 8);
+}
+
+// Q update of decision (s, a) toward reward R, bootstrapped from s_next
+// (s_next < 0: terminal); per operation, each table toward R + gamma max_p Q_j(s', p).
+__device__ void q_learn(const PolicyDev *P, int s, int a, double R, int s_next) {
+  if (!P->per_op) {
+    double t = R;
+    if (s_next >= 0) {
+      const double *row = &P->q[s_next * kNAct];
+      t = R + P->gamma * row[q_argmax(row)];
+    }
+    double *q = &P->q[s * kNAct + a];
+    *q = *q + P->lr * (t - *q);
+    return;
+  }
+  for (int j = 0; j < 3; ++j) {
+    const int pj = (a >> (4 - 2 * j)) & 3;
+    double t = R;
+    if (s_next >= 0) {
+      const double *nx = &P->q[s_next * kNAct + 4 * j];
+      t = R + P->gamma * nx[argmax4(nx)];
+    }
+    double *q = &P->q[s * kNAct + 4 * j + pj];
+    *q = *q + P->lr * (t - *q);
+  }
 }
 
 __device__ double lg_clamped(const PolicyDev *P, double r) {
@@ -425,7 +460,7 @@ __device__ void roll_log(const PolicyDev *P, const float *f, const float *fn, in
 // has at most kQbestMax states (the same argmax, lowest index on ties), else
 // from the table.
 __device__ __forceinline__ int q_greedy(const PolicyDev *P, int s) {
-  return s < P->n_qbest ? (int)P->qbest[s] : q_argmax(&P->q[s * kNAct]);
+  return s < P->n_qbest ? (int)P->qbest[s] : q_greedy_row(P, &P->q[s * kNAct]);
 }
 
 template <bool FULL>
@@ -436,6 +471,23 @@ __device__ int decide_scalar(const PolicyDev *P, int s, int k, int *explored) {
   case POL_FIXED: return P->fixed_action;
   case POL_QTABLE: return q_greedy(P, s);
   case POL_QTRAIN: {
+    if (P->per_op) {   // an epsilon-greedy draw per operation, streams 2 .. 7
+      const double *row = &P->q[s * kNAct];
+      int a = 0;
+      for (int j = 0; j < 3; ++j) {
+        int pj;
+        const double u0 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, (uint64_t)(2 + 2 * j));
+        if (u0 < P->epsilon) {
+          const double u1 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, (uint64_t)(3 + 2 * j));
+          pj = (int)(u1 * 4.0);
+          *explored = 1;
+        } else {
+          pj = argmax4(row + 4 * j);
+        }
+        a = a * 4 + pj;
+      }
+      return a;
+    }
     const double u0 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, 0);
     if (u0 < P->epsilon) {
       const double u1 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, 1);
@@ -697,7 +749,7 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
   const int n_it = (completed ? k : k + 1) - c->k_dec;
   if (converged) {
     const double rw = policy_reward(P, act, rho, true, n_it);
-    if (training && a.writer) q_update(P, s, act, rw);
+    if (training && a.writer) q_learn(P, s, act, rw, -1);
     if (FULL && active && a.writer) roll_log(P, c->feat, c->feat_next, act, rw, 1);
     c->status = c->fell_back ? 2 : 0;
     c->relres_true = rho;
@@ -706,7 +758,7 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
   }
   if (broke || (stagnated && c->fallback_enabled && !c->fell_back)) {
     const double rw = -P->w2 * (policy_cost(P, act) * (double)n_it) - P->w3;
-    if (training && a.writer) q_update(P, s, act, rw);
+    if (training && a.writer) q_learn(P, s, act, rw, -1);
     if (FULL && active && a.writer) roll_log(P, c->feat, c->feat_next, act, rw, 1);
     if (!c->fallback_enabled || c->fell_back) {
       c->status = 3;
@@ -726,10 +778,7 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
   const bool dec_end = (k % D == 0) || k >= c->maxit;
   if (dec_end && (training || (FULL && active && a.writer && P->roll_cap > 0))) {   // the reward has a reader
     const double rw = policy_reward(P, act, rho, false, n_it);
-    if (training && a.writer) {
-      const double *row = &P->q[s_next * kNAct];
-      q_update(P, s, act, rw + P->gamma * row[q_argmax(row)]);
-    }
+    if (training && a.writer) q_learn(P, s, act, rw, s_next);
     if (FULL && active && a.writer) roll_log(P, c->feat, c->feat_next, act, rw, 0);
   }
   if (k >= c->maxit) {
@@ -856,18 +905,22 @@ __device__ __forceinline__ void step_x(const Sx &x, const KArgs &a, const double
     const int k = c->k;
     const double rho = sqrt(sig) / c->bnorm;
     c->rho_new = rho;
-    const bool rep = (c->R > 0 && k % c->R == 0) || rho <= c->tol || !isfinite(sig) || !isfinite(sigz);
+    // section 5's termination (stop_rule 1): the recursive residual below tol
+    // after at least 10 iterations, with no true-residual check
+    const bool paper_stop = c->stop_rule == 1 && rho < c->tol && k >= 10 && isfinite(sig) && isfinite(sigz);
+    const bool rep = !paper_stop && ((c->R > 0 && k % c->R == 0) || (c->stop_rule == 0 && rho <= c->tol) ||
+                                     !isfinite(sig) || !isfinite(sigz));
     if (rep) {
       c->mode = M_REPLACE;
       c->k3op = c->fold_done ? K3_NONE : K3_FOLD;
       s_fin = 0;
     } else {
-      s_fin = 1;
+      s_fin = paper_stop ? 2 : 1;
     }
     c->fold_done = 0;
   }
   __syncthreads();
-  if (s_fin) finish_block<FULL>(x, true, false, false, false);
+  if (s_fin) finish_block<FULL>(x, true, false, s_fin == 2, false);
   __syncthreads();
 }
 
@@ -1916,7 +1969,10 @@ __device__ __forceinline__ void finish_block_x(const KArgs &a, int tier, int zer
 
 // Requests the final true-residual check after a budget stop or a breakdown.
 __device__ __forceinline__ void request_final(Ctl *c) {
-  if (c->status == 1 || c->status == 3) {
+  // a budget stop, a breakdown, or a convergence on the recursive residual
+  // (stop_rule 1) gets the true residual of the final x
+  if (c->status == 1 || c->status == 3 || (c->stop_rule == 1 && !c->zero_solution && c->k > 0 &&
+                                           (c->status == 0 || c->status == 2))) {
     c->mode = M_FINAL;
     c->k3op = K3_NONE;
     c->pend_sigma = 0;
@@ -2267,7 +2323,7 @@ __global__ __launch_bounds__(kBlock) void k_policy_decide(const PolicyDev *P, in
     } else if (threadIdx.x == 0) {
       int ex = 0;
       state[idx] = s;
-      action[idx] = P->kind == POL_QTRAIN ? q_argmax(&P->q[s * kNAct]) : decide_scalar<true>(P, s, (int)k[idx], &ex);
+      action[idx] = P->kind == POL_QTRAIN ? q_greedy_row(P, &P->q[s * kNAct]) : decide_scalar<true>(P, s, (int)k[idx], &ex);
     }
   }
 }

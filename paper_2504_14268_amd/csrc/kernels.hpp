@@ -62,6 +62,7 @@ struct PolicyDev {
   const float *W1, *b1, *W2, *b2, *W3, *b3;
   int32_t replace_period;
   int32_t decision_period;       // the policy acts every decision_period iterations (<= 1: every one)
+  int32_t per_op;                // 1: one Q-table per operation, Q_j(s, p) = q[s][4 j + p]
   int32_t roll_cap;
   float *roll_feat, *roll_next;
   int32_t *roll_act;
@@ -92,6 +93,7 @@ struct Ctl {
   int32_t fold_done, precond;     // precond: 1 = Jacobi-preconditioned iteration
   int32_t dir_restart, k_dec;     // 1: the next direction update restarts (p = z);
                                   // k_dec: iteration of the current decision
+  int32_t stop_rule, pad2_;       // 1: stop when the recursive rho < tol with k >= 10
   double tol, bnorm, sigma, sig_new, alpha, beta, rho_new, last_true, cost_sum, relres_true;
   double rep_hist[3];
   float feat[kMlpIn];

@@ -82,3 +82,35 @@ def test_network_policy_with_decision_period(M):
     P.set_mlp(w)
     P.rollouts_enable(2000)
     run(M, M.Matrix(A), A, b, P, O.OraclePolicy(kind=O.POL_MLP, mlp=w, decision_period=10), 800, roll=2000)
+
+
+@pytest.mark.parametrize("D", [1, 50])
+def test_per_op_tables_qlearning_and_greedy(M, D):
+    """One Q-table per operation: training episodes (tables and rollouts after
+    each), then the greedy policy and its decisions, equal the oracle's."""
+    A = W.random_spd(12000, 47, W.spread_for_kappa(1e5))
+    b = W.rhs(A.n, 48)
+    P = M.Policy(kind=M.POLICY_QTABLE_TRAIN, cost="C2", seed=13, decision_period=D, per_op=1)
+    op = O.OraclePolicy(kind=O.POL_QTRAIN, cost="C2", seed=13, decision_period=D, per_op=1)
+    m = M.Matrix(A)
+    for e in (1, 2, 3):
+        eps = 1.0 - 0.4 * (e - 1)
+        P.set_episode(e, eps)
+        op.s.episode, op.s.epsilon = e, eps
+        run(M, m, A, b, P, op, 600)
+        assert np.array_equal(P.qtable(), op.q)
+    q = P.qtable()
+    G = M.Policy(kind=M.POLICY_QTABLE, decision_period=D, per_op=1)
+    G.set_qtable(q)
+    run(M, m, A, b, G, O.OraclePolicy(kind=O.POL_QTABLE, q=q, decision_period=D, per_op=1), 2000)
+    rng = np.random.default_rng(3)
+    k = rng.integers(0, 3000, 500)
+    rho = 10.0 ** rng.uniform(-17, 1, 500)
+    stag = rng.integers(0, 2, 500)
+    st, ac = G.decide(k, rho, stag)
+    opg = O.OraclePolicy(kind=O.POL_QTABLE, q=q, per_op=1)
+    for i in range(500):
+        s = opg.state(int(k[i]), float(rho[i]), int(stag[i]))
+        row = q[s]
+        want = 16 * int(np.argmax(row[0:4])) + 4 * int(np.argmax(row[4:8])) + int(np.argmax(row[8:12]))
+        assert st[i] == s and ac[i] == want

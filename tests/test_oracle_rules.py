@@ -231,3 +231,87 @@ def test_decision_period_holds_the_action_and_logs_one_row_per_decision():
     cost = c[(a0 >> 4) & 3] + c[(a0 >> 2) & 3] + c[a0 & 3]
     want = -math.log10(info["rho"][5]) - 0.1 * cost * 5
     assert abs(float(ro["rew"][0]) - want) <= 1e-5 * max(1.0, abs(want))
+
+
+# ---------------------------------------------------------------- one Q-table per operation
+def test_per_op_greedy_action():
+    """Q_0 = (0, 3, 1, 2), Q_1 = (5, 5, 0, 0) (a tie: the lower format),
+    Q_2 = (0, 0, 0, 1): the action is 16*1 + 4*0 + 3 = 19 (bf16 SpMV, fp16 dot,
+    fp64 update)."""
+    A = W.laplacian_2d(6)
+    b = W.rhs(A.n, 1)
+    q = np.zeros((100, 64))
+    q[0, 0:4], q[0, 4:8], q[0, 8:12] = (0, 3, 1, 2), (5, 5, 0, 0), (0, 0, 0, 1)
+    q[0, 19 + 20] = 100.0                  # the joint reading of the row would pick 39
+    pol = O.OraclePolicy(kind=O.POL_QTABLE, q=q, per_op=1)
+    _, info = O.cg(A, b, tol=1e-8, maxit=1, policy=pol, replace_period=50)
+    assert info["actions"][0] == 19
+    _, info = O.cg(A, b, tol=1e-8, maxit=1, policy=O.OraclePolicy(kind=O.POL_QTABLE, q=q), replace_period=50)
+    assert info["actions"][0] == 39
+
+
+def test_per_op_truncation_update_by_hand():
+    """The 2x2 system of test_truncation_at_maxit_bootstraps with one table per
+    operation, each preferring fp32 (Q_j(0, fp32) = 1): one fp32 iteration, then
+    the cut at maxit updates every table's fp32 entry toward R + 0.9 * 1 (the
+    bootstrap from state 0 again): Q_j(0, fp32) = 1 + 0.1 (R + 0.9 - 1)."""
+    A = W.CSR(2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, 2.0]))
+    b = np.array([1.0, 1.0])
+    q0 = np.zeros((100, 64))
+    q0[0, [2, 6, 10]] = 1.0
+    pol = O.OraclePolicy(kind=O.POL_QTRAIN, q=q0, epsilon=0.0, cost="C1", per_op=1)
+    _, info = O.cg(A, b, tol=1e-8, maxit=1, policy=pol, replace_period=50)
+    assert info["actions"].tolist() == [42]
+    R = -math.log10(info["rho"][1]) - 0.1 * 3.0
+    want = 1.0 + 0.1 * (R + 0.9 * 1.0 - 1.0)
+    for c in (2, 6, 10):
+        assert abs(pol.q[0, c] - want) < 1e-12
+    assert np.count_nonzero(pol.q != q0) == 3
+
+
+def test_per_op_exploration_draws():
+    """epsilon = 1: every operation draws its format from its own stream,
+    floor(4 u) with u = uniform(seed, episode, k, 3 + 2 j)."""
+    A = W.laplacian_2d(16)
+    b = W.rhs(A.n, 2)
+    pol = O.OraclePolicy(kind=O.POL_QTRAIN, epsilon=1.0, seed=11, episode=4, per_op=1)
+    x, info = O.cg(A, b, tol=1e-8, maxit=30, policy=pol, replace_period=50, fallback=True)
+    k = info["iters"] if info["fallback_at"] < 0 else info["fallback_at"]
+    want = [16 * int(O.uniform(11, 4, i, 3) * 4) + 4 * int(O.uniform(11, 4, i, 5) * 4) + int(O.uniform(11, 4, i, 7) * 4)
+            for i in range(k)]
+    assert info["actions"][:k].tolist() == want
+
+
+# ---------------------------------------------------------------- the paper's termination
+def test_paper_termination_needs_ten_iterations():
+    """An eigenvector right-hand side: fp64 CG's recursive residual falls below
+    1e-6 after one iteration.  Section 5's rule (rho < tol with k >= 10) runs
+    to exactly k = 10; the default rule stops at the first replacement (k = 1).
+    Either way the reported relres is the final x's true residual."""
+    A = W.laplacian_2d(8)
+    ev, V = np.linalg.eigh(A.to_dense())
+    b = V[:, 5].copy()
+    x1, i1 = O.cg(A, b, tol=1e-6, maxit=100, stop_rule=1)
+    x0, i0 = O.cg(A, b, tol=1e-6, maxit=100)
+    assert i0["iters"] == 1 and i1["iters"] == 10 and i1["status"] == 0
+    assert i1["rho"][1] < 1e-6 and np.all(i1["rho"][1:11] < 1e-6)
+    r = O.residual(A, b, x1)
+    assert i1["relres_true"] == np.sqrt(O.dot(r, r, O.F64)) / np.sqrt(O.dot(b, b, O.F64))
+    assert abs(i1["relres_true"] - np.linalg.norm(b - A.to_dense() @ x1) / np.linalg.norm(b)) <= 1e-15
+    assert i1["n_replace"] == 0
+
+
+def test_paper_termination_on_the_recursive_residual():
+    """bf16 updates: the recursive residual leaves the true one; the paper's
+    rule stops at the first k >= 10 with rho_k < tol on the recursion, whatever
+    the true residual (which the result still reports)."""
+    A = W.laplacian_2d(30)
+    b = W.rhs(A.n, 5)
+    x, info = O.cg(A, b, tol=1e-6, maxit=3000, policy=O.OraclePolicy(fixed_action=16 * 1 + 4 * 1 + 1),
+                   replace_period=0, stop_rule=1)
+    rho = info["rho"]
+    k = info["iters"]
+    assert info["status"] == 0 and k >= 10 and rho[k] < 1e-6
+    assert not any(rho[j] < 1e-6 for j in range(10, k))
+    r = O.residual(A, b, x)
+    assert info["relres_true"] == np.sqrt(O.dot(r, r, O.F64)) / np.sqrt(O.dot(b, b, O.F64))

@@ -210,3 +210,107 @@ def batch_system(seed: int, n_lo: float = 1e3, n_hi: float = 2e5,
         w = int(rng.integers(1, 16))
         return banded_spd(n, w, seed, spread_for_kappa(kappa))
     return random_spd(n, seed, spread_for_kappa(kappa), tmin=4, tmax=26)
+
+
+# ---------------------------------------------------------------------------
+# The paper's own synthetic families (section 5): inputs for the replication
+# mode, not for the benchmark.
+# ---------------------------------------------------------------------------
+def bbt_system(seed: int, n: int = 5000, density_reading: str = "pairs", ood: bool = False) -> CSR:
+    """A = B B^T + beta I (section 5.1): B sparse n x n with N(0, 1) values at
+    index pairs drawn uniformly with replacement, beta ~ U(1e-4, 1e-2).
+
+    The paper gives two sizes for B's pattern: about 1 % of its elements
+    nonzero, and 5,000 index pairs.  density_reading "pairs" takes n pairs (5,000
+    at n = 5,000), "percent" takes 1 % of n^2; ood scales the count by
+    U(0.8, 1.2) (the out-of-distribution sets).  Pairs that repeat add up."""
+    rng = np.random.default_rng(seed)
+    m = n if density_reading == "pairs" else int(round(0.01 * n * n))
+    if ood:
+        m = int(round(m * rng.uniform(0.8, 1.2)))
+    bi = rng.integers(0, n, m)
+    bj = rng.integers(0, n, m)
+    bv = rng.standard_normal(m)
+    beta = rng.uniform(1e-4, 1e-2)
+    # (B B^T)_{ik} = sum_j B_ij B_kj: pair every entry with every entry of the same column j
+    order = np.argsort(bj, kind="stable")
+    bi, bj, bv = bi[order], bj[order], bv[order]
+    starts = np.flatnonzero(np.r_[True, bj[1:] != bj[:-1]])
+    ends = np.r_[starts[1:], m]
+    rows, cols, vals = [], [], []
+    for s, e in zip(starts, ends):
+        ii = bi[s:e]
+        vv = bv[s:e]
+        rows.append(np.repeat(ii, e - s))
+        cols.append(np.tile(ii, e - s))
+        vals.append(np.outer(vv, vv).ravel())
+    rows.append(np.arange(n))
+    cols.append(np.arange(n))
+    vals.append(np.full(n, beta))
+    r = np.concatenate(rows).astype(np.int64)
+    c = np.concatenate(cols).astype(np.int64)
+    v = np.concatenate(vals)
+    # sum duplicate (i, k) entries in a fixed order (sorted keys), so the
+    # matrix is exactly symmetric
+    key = r * n + c
+    uk, inv = np.unique(key, return_inverse=True)
+    acc = np.zeros(uk.size)
+    np.add.at(acc, inv, v)
+    return _from_coo(n, (uk // n).astype(np.int64), (uk % n).astype(np.int64), acc,
+                     f"bbt_{n}_{density_reading}_{seed}")
+
+
+def poisson_subdomain(seed: int, N: int = 80):
+    """The 2D Poisson family of section 5.2: -lap u = f on a random subdomain
+    [ax, bx] x [ay, by] of [0, 2]^2 (ax ~ U(0, 1.9), bx = ax + U(0.1, 2 - ax),
+    likewise in y), N x N interior points, h = (b - a) / (N + 1) per direction,
+    the 5-point stencil (2/hx^2 + 2/hy^2 on the diagonal), Dirichlet data g
+    constant, linear or sinusoidal per edge and a source f zero, sinusoidal or
+    polynomial, each with equal probability.  Returns (A, b): b holds f and the
+    boundary values moved to the right-hand side."""
+    rng = np.random.default_rng(seed)
+    ax = rng.uniform(0.0, 1.9)
+    bx = ax + rng.uniform(0.1, 2.0 - ax)
+    ay = rng.uniform(0.0, 1.9)
+    by = ay + rng.uniform(0.1, 2.0 - ay)
+    hx, hy = (bx - ax) / (N + 1), (by - ay) / (N + 1)
+    cx, cy = 1.0 / (hx * hx), 1.0 / (hy * hy)
+    n = N * N
+    idx = np.arange(n, dtype=np.int64)
+    ix, iy = idx % N, idx // N
+    rows, cols, vals = [idx], [idx], [np.full(n, 2.0 * cx + 2.0 * cy)]
+    for cond, off, w in ((iy > 0, -N, cy), (ix > 0, -1, cx), (ix < N - 1, 1, cx), (iy < N - 1, N, cy)):
+        r = idx[cond]
+        rows.append(r)
+        cols.append(r + off)
+        vals.append(np.full(r.size, -w))
+    A = _from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals),
+                  f"poisson_{N}_{seed}")
+
+    def edge_fn():
+        kind = rng.integers(0, 3)
+        p, q = rng.uniform(-1.0, 1.0, 2)
+        if kind == 0:
+            return lambda t: np.full_like(t, p)
+        if kind == 1:
+            return lambda t: p + q * t
+        w = rng.uniform(0.5, 3.0)
+        return lambda t: p * np.sin(w * np.pi * t)
+
+    g_left, g_right, g_bottom, g_top = edge_fn(), edge_fn(), edge_fn(), edge_fn()
+    kind = rng.integers(0, 3)
+    c1, c2, c3 = rng.uniform(-1.0, 1.0, 3)
+    xs = ax + (ix + 1) * hx
+    ys = ay + (iy + 1) * hy
+    if kind == 0:
+        f = np.zeros(n)
+    elif kind == 1:
+        f = c1 * np.sin(np.pi * xs) * np.sin(np.pi * ys)
+    else:
+        f = c1 + c2 * xs * ys + c3 * xs * xs
+    b = f.copy()
+    b[ix == 0] += cx * g_left(ys[ix == 0])
+    b[ix == N - 1] += cx * g_right(ys[ix == N - 1])
+    b[iy == 0] += cy * g_bottom(xs[iy == 0])
+    b[iy == N - 1] += cy * g_top(xs[iy == N - 1])
+    return A, b
