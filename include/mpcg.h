@@ -116,8 +116,11 @@ typedef struct {
                                   table row s, column 4 j + p; the greedy action
                                   takes each table's argmax, exploration draws
                                   per operation, and every Q_j is updated with
-                                  the shared reward.  0: one joint table over
-                                  the 64 actions                                 */
+                                  the shared reward.  2: tables for the SpMV and
+                                  the dot only, the updates fixed in fp64
+                                  (section 4.2 keeps the residual update in full
+                                  precision).  0: one joint table over the 64
+                                  actions                                        */
     int32_t reserved;
 } mpcg_policy_desc;
 
@@ -153,6 +156,13 @@ typedef struct {
                                   recursive rho < tol after at least 10
                                   iterations, no true-residual check (the result
                                   still reports the final x's true relres)     */
+    int32_t rho_fp64;          /* 0: rho_k = sqrt(r.r)/||b|| with r.r at the dot
+                                  format (it is also sigma'); 1: rho_k from an
+                                  fp64 r.r of the stored recursive residual
+                                  (section 1 keeps residual computations in
+                                  fp64), sigma' still at the dot format.
+                                  Not for batched solves.                       */
+    int32_t reserved;
 } mpcg_solve_opts;
 
 /* Per-kernel timing of the last solve made with opts.profile = 1.  One CG

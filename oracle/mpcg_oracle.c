@@ -58,6 +58,10 @@
  *     fallback (optional): on breakdown or stagnation, once per solve, fold x_lo
  *     into x_hi and restart as plain fp64 CG (fixed action 63) from x_hi.
  *
+ *   rho_fp64 (section 1 keeps residual computations in fp64): rho' =
+ *   sqrt(dot64(r,r))/bnorm of the recursive r, while sigma' (beta's
+ *   numerator) stays dot_fd(r,r).
+ *
  *   Preconditioned variant (section 3 with M != I; Jacobi M = diag(A), its
  *   inverse kept in fp32): z = rd_fa(m * r) in acc(f_a); sigma = r^T z at f_d
  *   (rho still from r^T r); at a start or replacement sigma = r64^T (m r64)
@@ -424,7 +428,9 @@ typedef struct {
     const float *w1m, *b1m, *w2m, *b2m, *w3m, *b3m;
     int32_t replace_period;  /* R, used by the MLP features */
     int32_t decision_period; /* D: the policy acts every D iterations (0, 1: every one) */
-    int32_t per_op;          /* 1: one Q-table per operation (section 4.1) in row[4 j + p] */
+    int32_t per_op;          /* 1: one Q-table per operation (section 4.1) in row[4 j + p];
+                                2: tables for SpMV and dot only, updates in fp64
+                                (section 4.2: the residual update in full precision) */
     int32_t pad2;
 } orc_policy;
 
@@ -466,7 +472,7 @@ static int argmax4(const double *t)
 static int greedy_row(const orc_policy *pol, const double *row)
 {
     if (!pol->per_op) return argmax_row(row);
-    return 16 * argmax4(row) + 4 * argmax4(row + 4) + argmax4(row + 8);
+    return 16 * argmax4(row) + 4 * argmax4(row + 4) + (pol->per_op == 2 ? F64 : argmax4(row + 8));
 }
 
 /* Q update of the decision (s, a) toward reward R, bootstrapped from state
@@ -480,7 +486,7 @@ static void q_learn(orc_policy *pol, int s, int a, double R, int s_next)
         *qsa = *qsa + pol->lr * (t - *qsa);
         return;
     }
-    for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < (pol->per_op == 2 ? 2 : 3); ++j) {
         const int pj = (a >> (4 - 2 * j)) & 3;
         double t = R;
         if (s_next >= 0) {
@@ -611,6 +617,9 @@ typedef struct {
     int32_t precond;          /* 0: M = I; 1: Jacobi, M = diag(A) */
     int32_t stop_rule;        /* 0: true fp64 relres <= tol at a replacement;
                                  1: the paper's, recursive rho < tol with k >= 10 */
+    int32_t rho_fp64;         /* 1: rho' from dot64(r, r) of the recursive r
+                                 (residual computations in fp64, section 1);
+                                 sigma' stays dot_fd */
 } orc_params;
 
 typedef struct {
@@ -682,6 +691,10 @@ static int decide(const orc_policy *pol, int kind, const float *feat, int s, int
             int a = 0;
             for (int j = 0; j < 3; ++j) {
                 int pj;
+                if (j == 2 && pol->per_op == 2) {     /* updates fixed in fp64 */
+                    a = a * 4 + F64;
+                    break;
+                }
                 double u0 = orc_uniform(pol->seed, (uint64_t)pol->episode, (uint64_t)k, (uint64_t)(2 + 2 * j));
                 if (u0 < pol->epsilon) {
                     double u1 = orc_uniform(pol->seed, (uint64_t)pol->episode, (uint64_t)k, (uint64_t)(3 + 2 * j));
@@ -846,8 +859,8 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         if (!broke) {
             orc_axpy(n, alpha, p, xlo, fa);
             orc_axpy(n, -alpha, q, r, fa);
-            double sig_rr = orc_dot(n, r, r, fd, prm->dot_order);
-            sig_new = sig_rr;
+            double sig_rr = orc_dot(n, r, r, prm->rho_fp64 ? F64 : fd, prm->dot_order);
+            sig_new = prm->rho_fp64 ? orc_dot(n, r, r, fd, prm->dot_order) : sig_rr;
             if (pc) {                                             /* sigma' = r^T z */
                 precond_apply(n, minv, r, z, fa);
                 sig_new = orc_dot(n, r, z, fd, prm->dot_order);

@@ -303,7 +303,7 @@ struct mpcg_matrix {
   // policy
   mpcg_policy *pol = nullptr;
   mpcg_policy *defpol = nullptr;
-  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0, 0, 0};   // replace_period .. precond, stop_rule
+  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0, 0, 0, 0, 0};   // replace_period .. stop_rule, rho_fp64
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_chunk[2] = {nullptr, nullptr};
   int P2 = 0;
 
@@ -463,6 +463,7 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
   a.part1b = A->d_part1b;
   a.part2b = A->d_part2b;
   a.precond = A->opts.precond;
+  a.rho64 = A->opts.rho_fp64;
   if (A->opts.index16 < 0) {   // 32-bit indices requested
     a.A.dc = nullptr;
     a.A.pbf = nullptr;
@@ -679,7 +680,7 @@ int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out) {
   if (desc->b_it < 1 || desc->b_res < 1 || desc->b_res > kMaxEdges + 1 || desc->t_bin < 1 || desc->w_stag < 1)
     return fail(MPCG_ERR_INVALID, "bad bin parameters");
   if (desc->decision_period < 0) return fail(MPCG_ERR_INVALID, "negative decision_period");
-  if (desc->per_op != 0 && desc->per_op != 1) return fail(MPCG_ERR_INVALID, "per_op must be 0 or 1");
+  if (desc->per_op < 0 || desc->per_op > 2) return fail(MPCG_ERR_INVALID, "per_op must be 0, 1 or 2");
   mpcg_policy *P = new (std::nothrow) mpcg_policy();
   if (!P) return fail(MPCG_ERR_NOMEM, "host allocation failed");
   P->desc = *desc;
@@ -716,8 +717,10 @@ int mpcg_policy_set_qtable(mpcg_policy *P, const double *q) {
   P->qbest.resize((size_t)P->n_states);
   for (int s = 0; s < P->n_states; ++s) {
     const double *row = q + (size_t)s * kNAct;
-    const int best = P->desc.per_op ? 16 * first_max(row, 4) + 4 * first_max(row + 4, 4) + first_max(row + 8, 4)
-                                    : first_max(row, kNAct);
+    const int best = P->desc.per_op
+                         ? 16 * first_max(row, 4) + 4 * first_max(row + 4, 4) +
+                               (P->desc.per_op == 2 ? MPCG_FP64 : first_max(row + 8, 4))
+                         : first_max(row, kNAct);
     P->qbest[s] = (uint8_t)best;
   }
   return MPCG_OK;
@@ -857,6 +860,8 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
   if (o->index16 != 0 && o->index16 != -1) return fail(MPCG_ERR_INVALID, "index16 must be 0 or -1");
   if (o->precond != 0 && o->precond != 1) return fail(MPCG_ERR_INVALID, "precond must be 0 or 1");
   if (o->stop_rule != 0 && o->stop_rule != 1) return fail(MPCG_ERR_INVALID, "stop_rule must be 0 or 1");
+  if (o->rho_fp64 != 0 && o->rho_fp64 != 1) return fail(MPCG_ERR_INVALID, "rho_fp64 must be 0 or 1");
+  if (o->reserved != 0) return fail(MPCG_ERR_INVALID, "reserved must be 0");
   A->opts = *o;
   return MPCG_OK;
 }
@@ -880,6 +885,7 @@ static int upload_start(mpcg_matrix *A, mpcg_policy *P, double tol, int32_t maxi
   c.fallback_enabled = A->opts.fallback ? 1 : 0;
   c.precond = A->opts.precond;
   c.stop_rule = A->opts.stop_rule;
+  c.rho64 = A->opts.rho_fp64;
   c.tol = tol;
   HIP_TRY(hipMemcpyAsync(A->d_ctl, A->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   return MPCG_OK;
@@ -1336,6 +1342,7 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
     if (!(tol[i] > 0.0) || !std::isfinite(tol[i])) return fail(MPCG_ERR_INVALID, "tol must be positive and finite");
     if (maxit[i] < 0 || maxit[i] > (1 << 29)) return fail(MPCG_ERR_INVALID, "maxit out of range");
     if (A[i]->opts.precond) return fail(MPCG_ERR_INVALID, "batched solves are not preconditioned (precond = 0)");
+    if (A[i]->opts.rho_fp64) return fail(MPCG_ERR_INVALID, "batched solves take rho at the dot format (rho_fp64 = 0)");
     mpcg_policy *P = A[i]->pol ? A[i]->pol : A[i]->defpol;
     if (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->roll_cap > 0)
       return fail(MPCG_ERR_INVALID, "training policies and rollout logs are not batched (shared state)");

@@ -374,7 +374,7 @@ __device__ __forceinline__ int argmax4(const double *t) {
 
 __device__ __forceinline__ int q_greedy_row(const PolicyDev *P, const double *row) {
   if (!P->per_op) return q_argmax(row);
-  return 16 * argmax4(row) + 4 * argmax4(row + 4) + argmax4(row + 8);
+  return 16 * argmax4(row) + 4 * argmax4(row + 4) + (P->per_op == 2 ? FP64 : argmax4(row + 8));
 }
 
 // Q update of decision (s, a) toward reward R, bootstrapped from s_next
@@ -390,7 +390,7 @@ __device__ void q_learn(const PolicyDev *P, int s, int a, double R, int s_next) 
     *q = *q + P->lr * (t - *q);
     return;
   }
-  for (int j = 0; j < 3; ++j) {
+  for (int j = 0; j < (P->per_op == 2 ? 2 : 3); ++j) {
     const int pj = (a >> (4 - 2 * j)) & 3;
     double t = R;
     if (s_next >= 0) {
@@ -476,6 +476,10 @@ __device__ int decide_scalar(const PolicyDev *P, int s, int k, int *explored) {
       int a = 0;
       for (int j = 0; j < 3; ++j) {
         int pj;
+        if (j == 2 && P->per_op == 2) {   // updates fixed in fp64
+          a = a * 4 + FP64;
+          break;
+        }
         const double u0 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, (uint64_t)(2 + 2 * j));
         if (u0 < P->epsilon) {
           const double u1 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, (uint64_t)(3 + 2 * j));
@@ -893,9 +897,12 @@ __device__ __forceinline__ void step_x(const Sx &x, const KArgs &a, const double
   Ctl *c = x.ctl;
   if (c->mode == M_DONE || !c->pend_sigma) return;
   const int fd = (c->action >> 2) & 3;
-  const double sig = have_pre ? tree_preloaded_rt(fd, pre) : reduce_partials_rt(fd, a.part2, a.P2);
-  // with a preconditioner sigma' = r.z; r.r still gives rho
-  const double sigz = c->precond ? reduce_partials_rt(fd, a.part2b, a.P2) : sig;
+  // r.r gives rho: at the dot format, or in fp64 (rho64)
+  const int fr = c->rho64 ? FP64 : fd;
+  const double sig = have_pre ? tree_preloaded_rt(fr, pre) : reduce_partials_rt(fr, a.part2, a.P2);
+  // sigma' in the second partials: r.z with a preconditioner, r.r at the dot
+  // format when rho is taken in fp64
+  const double sigz = (c->precond || c->rho64) ? reduce_partials_rt(fd, a.part2b, a.P2) : sig;
   __shared__ int s_fin;
   if (threadIdx.x == 0) {
     c->pend_sigma = 0;
@@ -1508,13 +1515,17 @@ __device__ __forceinline__ void load8_tail(const V *p, int base, int n, bool ful
 }
 
 // x_lo and r updates and the sigma' partial on operands already loaded; with
-// a preconditioner (PC) also z = M^-1 r and the partial of r.z.
-template <int FA, int FD, bool PC, typename V>
+// a preconditioner (PC) also z = M^-1 r and the partial of r.z.  With R64 the
+// r.r partial (rho) is taken in fp64 and sigma' (r.r, or r.z with PC) at the
+// dot format goes to the second partial.
+template <int FA, int FD, bool PC, bool R64, typename V>
 __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool fold_now, int blk, const V (&pv)[8],
                                              const V (&qv)[8], V (&rv)[8], V (&xv)[8]) {
   constexpr int TIER = (FA == FP64);
   static_assert(sizeof(V) == sizeof(typename TierT<TIER>::type), "operands in the tier of fa");
   using Acc = typename AccT<FD>::type;
+  constexpr int FR = R64 ? FP64 : FD;
+  using AccR = typename AccT<FR>::type;
   V *xlo, *r;
   if constexpr (TIER) { xlo = a.v.xlo64; r = a.v.r64; }
   else { xlo = a.v.xlo32; r = a.v.r32; }
@@ -1522,15 +1533,17 @@ __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool 
   const int n = a.A.n;
   const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   const bool full = base + 8 <= n;
-  Acc l[8], lz[8];
+  AccR l[8];
+  Acc lz[8];
   float mv[8];
   if constexpr (PC) load8_tail(a.A.minv, base, n, full, mv);
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     xv[j] = axpy1<FA>(alpha, pv[j], xv[j]);
     rv[j] = axpy1<FA>(-alpha, qv[j], rv[j]);
-    l[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], rv[j]) : (Acc)0;
+    l[j] = (full || base + j < n) ? dot_leaf<FR>(rv[j], rv[j]) : (AccR)0;
     if constexpr (PC) lz[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], precond_z<FA>(mv[j], rv[j])) : (Acc)0;
+    else if constexpr (R64) lz[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], rv[j]) : (Acc)0;
   }
   if (fold_now) {
 #pragma unroll
@@ -1553,15 +1566,15 @@ __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool 
       }
     }
   }
-  const Acc t = block_tree(tree8(l));
+  const AccR t = block_tree(tree8(l));
   if (threadIdx.x == 0) a.part2[blk] = (double)t;
-  if constexpr (PC) {
+  if constexpr (PC || R64) {
     const Acc tz = block_tree(tree8(lz));
     if (threadIdx.x == 0) a.part2b[blk] = (double)tz;
   }
 }
 
-template <int FA, int FD, bool PC>
+template <int FA, int FD, bool PC, bool R64>
 __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_now, int blk) {
   constexpr int TIER = (FA == FP64);
   using V = typename TierT<TIER>::type;
@@ -1576,7 +1589,7 @@ __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_
   load8_tail(q, base, n, full, qv);
   load8_tail(r, base, n, full, rv);
   load8_tail(xlo, base, n, full, xv);
-  kb_axpy_vals<FA, FD, PC>(a, S, fold_now, blk, pv, qv, rv, xv);
+  kb_axpy_vals<FA, FD, PC, R64>(a, S, fold_now, blk, pv, qv, rv, xv);
 }
 
 // Elementwise steps (KB or KX): p = r = rd_tier(r64) after a start; the
@@ -1685,12 +1698,12 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
 }
 
 #define MPCG_KB_CASE(FA, FD) \
-  case (FA) * 4 + (FD): kb_axpy<FA, FD, PC>(a, S, fold_now, blk); break;
+  case (FA) * 4 + (FD): kb_axpy<FA, FD, PC, R64>(a, S, fold_now, blk); break;
 #define MPCG_KB_VALS(FA, FD) \
-  case (FA) * 4 + (FD): kb_axpy_vals<FA, FD, PC>(a, S, fold_now, blk, pv, qv, rv, xv); break;
+  case (FA) * 4 + (FD): kb_axpy_vals<FA, FD, PC, R64>(a, S, fold_now, blk, pv, qv, rv, xv); break;
 
 // KB's vector work for 2048-element block blk.
-template <bool PC = false>
+template <bool PC = false, bool R64 = false>
 __device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, bool fold_now, int blk) {
   if (bop == B_AXPY) {
     const int act = S.action;
@@ -1720,7 +1733,7 @@ __device__ __forceinline__ void kb_commit(Ctl &S, int bop, bool fold_now) {
 
 // KB's work on vector block blk of one system; block 0 commits the state.
 // The step's partials are loaded together with the control block.
-template <bool FULL = false, bool PC = false>
+template <bool FULL = false, bool PC = false, bool R64 = false>
 __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
@@ -1755,7 +1768,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
       default: break;
       }
     } else {
-      kb_work<PC>(a, S, bop, fold_now, blk);
+      kb_work<PC, R64>(a, S, bop, fold_now, blk);
     }
     if (blk == 0) {
       __syncthreads();
@@ -1768,7 +1781,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   if (!S.step_done) step_b<FULL>(x, a, pre, fast);
   const int bop = S.b_op;
   const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
-  kb_work<PC>(a, S, bop, fold_now, blk);
+  kb_work<PC, R64>(a, S, bop, fold_now, blk);
   if (blk == 0) {   // commit the state after this kernel for KX
     __syncthreads();
     if (threadIdx.x == 0) kb_commit(S, bop, fold_now);
@@ -1870,6 +1883,12 @@ __global__ __launch_bounds__(kBlock) void k_x(KArgs a) { kx_body(a, blockIdx.x);
 __global__ __launch_bounds__(kBlock) void k_b_pc(KArgs a) { kb_body<false, true>(a, blockIdx.x); }
 __global__ __launch_bounds__(kBlock) void k_b_full_pc(KArgs a) { kb_body<true, true>(a, blockIdx.x); }
 __global__ __launch_bounds__(kBlock) void k_x_pc(KArgs a) { kx_body<true>(a, blockIdx.x); }
+// KB with rho from an fp64 r.r (the residual norm kept in fp64) and sigma' at
+// the dot format in the second partial.
+__global__ __launch_bounds__(kBlock) void k_b_r64(KArgs a) { kb_body<false, false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_full_r64(KArgs a) { kb_body<true, false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_pc_r64(KArgs a) { kb_body<false, true, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_full_pc_r64(KArgs a) { kb_body<true, true, true>(a, blockIdx.x); }
 
 // KB whose replicated step is the full one (state features, the network's
 // decision at a start or a stop, rollout log by workgroup 0): for policies
@@ -2033,7 +2052,7 @@ __device__ __forceinline__ void ka_pass(const KArgs &a, const Ctl &S, void *lds)
 
 template <int FA, int FD>
 __device__ __forceinline__ void kb_axpy_all(const KArgs &a, const Ctl &S, bool fold_now) {
-  for (int blk = 0; blk < a.P2; ++blk) kb_axpy<FA, FD, false>(a, S, fold_now, blk);
+  for (int blk = 0; blk < a.P2; ++blk) kb_axpy<FA, FD, false, false>(a, S, fold_now, blk);
 }
 
 #define MPCG_KB_ALL(FA, FD) \
@@ -2340,7 +2359,9 @@ static void launch_timed(K kern, int grid, const KArgs &a, hipStream_t s, hipEve
 }
 void launch_ka(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_a, a.G1, a, s, e0, e1); }
 void launch_kb(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (a.precond) launch_timed(a.full ? k_b_full_pc : k_b_pc, a.P2, a, s, e0, e1);
+  if (a.rho64 && a.precond) launch_timed(a.full ? k_b_full_pc_r64 : k_b_pc_r64, a.P2, a, s, e0, e1);
+  else if (a.rho64) launch_timed(a.full ? k_b_full_r64 : k_b_r64, a.P2, a, s, e0, e1);
+  else if (a.precond) launch_timed(a.full ? k_b_full_pc : k_b_pc, a.P2, a, s, e0, e1);
   else launch_timed(a.full ? k_b_full : k_b, a.P2, a, s, e0, e1);
 }
 void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

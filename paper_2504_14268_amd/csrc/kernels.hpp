@@ -93,7 +93,8 @@ struct Ctl {
   int32_t fold_done, precond;     // precond: 1 = Jacobi-preconditioned iteration
   int32_t dir_restart, k_dec;     // 1: the next direction update restarts (p = z);
                                   // k_dec: iteration of the current decision
-  int32_t stop_rule, pad2_;       // 1: stop when the recursive rho < tol with k >= 10
+  int32_t stop_rule, rho64;       // stop_rule 1: stop when the recursive rho < tol with k >= 10;
+                                  // rho64 1: rho from an fp64 r.r, sigma' at the dot format
   double tol, bnorm, sigma, sig_new, alpha, beta, rho_new, last_true, cost_sum, relres_true;
   double rep_hist[3];
   float feat[kMlpIn];
@@ -119,6 +120,7 @@ struct KArgs {
   int P2;              // 2048-element vector blocks
   int G1;              // KA workgroups launched (P1 rounded up to 8)
   int precond;         // 1: launch the preconditioned KB / KX variants (Ctl.precond set too)
+  int rho64;           // 1: launch the KB variant with rho in fp64 (Ctl.rho64 set too)
   int8_t *slot_log;    // optional: KA records the mode of each slot (profiling)
   int slot;            // index of this slot (with slot_log)
 };

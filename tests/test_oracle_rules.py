@@ -8,6 +8,7 @@ from the definitions in the comments, or comes from an independent library
 import math
 
 import numpy as np
+import pytest
 
 import oracle as O
 import workloads as W
@@ -280,6 +281,76 @@ def test_per_op_exploration_draws():
     want = [16 * int(O.uniform(11, 4, i, 3) * 4) + 4 * int(O.uniform(11, 4, i, 5) * 4) + int(O.uniform(11, 4, i, 7) * 4)
             for i in range(k)]
     assert info["actions"][:k].tolist() == want
+
+
+def test_per_op_fp64_updates_greedy_and_update_by_hand():
+    """per_op = 2: tables for the SpMV and the dot only, the updates in fp64
+    whatever Q_2 holds.  Q_0 prefers bf16, Q_1 fp32, Q_2 fp16: the action is
+    16*1 + 4*2 + 3 = 27.  In training with epsilon 0 the cut at maxit = 1
+    moves the two tables' chosen entries toward R + 0.9 max Q_j(0, .), and
+    Q_2 is left as it was."""
+    A = W.CSR(2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, 2.0]))
+    b = np.array([1.0, 1.0])
+    q0 = np.zeros((100, 64))
+    q0[0, 1], q0[0, 6], q0[0, 8] = 1.0, 1.0, 5.0
+    _, info = O.cg(A, b, tol=1e-8, maxit=1, policy=O.OraclePolicy(kind=O.POL_QTABLE, q=q0, per_op=2),
+                   replace_period=50)
+    assert info["actions"].tolist() == [27]
+    pol = O.OraclePolicy(kind=O.POL_QTRAIN, q=q0, epsilon=0.0, cost="C1", per_op=2)
+    _, info = O.cg(A, b, tol=1e-8, maxit=1, policy=pol, replace_period=50)
+    assert info["actions"].tolist() == [27]
+    R = -math.log10(info["rho"][1]) - 0.1 * (0.6 + 1.0 + 2.0)
+    for c in (1, 6):
+        assert abs(pol.q[0, c] - (1.0 + 0.1 * (R + 0.9 * 1.0 - 1.0))) < 1e-12
+    assert np.count_nonzero(pol.q != q0) == 2 and pol.q[0, 8] == 5.0
+
+
+def test_per_op_fp64_updates_exploration_draws():
+    """per_op = 2 with epsilon = 1: the SpMV and the dot draw from streams 3
+    and 5, the update stays fp64 and stream 7 is never read."""
+    A = W.laplacian_2d(16)
+    b = W.rhs(A.n, 2)
+    pol = O.OraclePolicy(kind=O.POL_QTRAIN, epsilon=1.0, seed=11, episode=4, per_op=2)
+    x, info = O.cg(A, b, tol=1e-8, maxit=30, policy=pol, replace_period=50, fallback=True)
+    k = info["iters"] if info["fallback_at"] < 0 else info["fallback_at"]
+    want = [16 * int(O.uniform(11, 4, i, 3) * 4) + 4 * int(O.uniform(11, 4, i, 5) * 4) + 3 for i in range(k)]
+    assert info["actions"][:k].tolist() == want
+
+
+# ---------------------------------------------------------------- rho in fp64
+def test_rho_fp64_by_hand():
+    """A = diag(1, 4), b = 2^-14 (1, 1), action 51 (fp64 SpMV and updates, fp16
+    dots).  By hand: nu = 5 s^2 (exact in every format), alpha = rd(2/5),
+    r_1 = s (rd(1 - alpha), rd(1 - 4 alpha)).  With rho_fp64, rho_1 is the fp64
+    norm of r_1 over ||b|| = s sqrt(2); without it, rho_1 comes from the fp16
+    dot, whose operands 0.6 s fall in fp16's subnormal range (steps of 2^-24).
+    sigma' is dot_fp16(r, r) either way, so the iterates agree bit for bit."""
+    s = 2.0 ** -14
+    A = W.CSR(2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, 4.0]))
+    b = np.array([s, s])
+    pol = O.OraclePolicy(fixed_action=51)
+    alpha = 2.0 / 5.0
+    a, c = 1.0 - alpha, 1.0 - 4.0 * alpha
+    want64 = np.sqrt(a * a + c * c) / np.sqrt(2.0)
+    h = [abs(float(np.float16(v * s))) * 2.0 ** 24 for v in (a, c)]   # integers: fp16 subnormal units
+    assert all(v == int(v) for v in h)
+    want16 = np.sqrt(h[0] ** 2 + h[1] ** 2) / np.sqrt(2.0) / 1024.0
+    x1, i1 = O.cg(A, b, tol=1e-300, maxit=2, policy=pol, replace_period=50, rho_fp64=1)
+    x0, i0 = O.cg(A, b, tol=1e-300, maxit=2, policy=pol, replace_period=50, rho_fp64=0)
+    assert i1["rho"][1] == want64 and i0["rho"][1] == want16 and want16 != want64
+    assert np.array_equal(x1, x0) and i1["iters"] == i0["iters"] == 2
+
+
+@pytest.mark.parametrize("act", [63, 16 * 1 + 4 * 3 + 2])
+def test_rho_fp64_changes_nothing_with_fp64_dots(act):
+    """With the dot already in fp64 the two readings of rho coincide."""
+    A = W.laplacian_2d(12)
+    b = W.rhs(A.n, 3)
+    pol = O.OraclePolicy(fixed_action=act)
+    x1, i1 = O.cg(A, b, tol=1e-9, maxit=300, policy=pol, replace_period=50, rho_fp64=1)
+    x0, i0 = O.cg(A, b, tol=1e-9, maxit=300, policy=pol, replace_period=50)
+    k = i0["iters"]
+    assert i1["iters"] == k and np.array_equal(i1["rho"][:k + 1], i0["rho"][:k + 1]) and np.array_equal(x1, x0)
 
 
 # ---------------------------------------------------------------- the paper's termination
