@@ -236,6 +236,8 @@ def evaluate_policies(M, W, torch, seeds, policies: dict, maxit: int, family=Non
             mm.set_options(replace_period=50, fallback=True, profile=False)
             x.zero_()
             r = mm.solve(b, x, tol=1e-8, maxit=maxit)
+            if A.n >= 1_000_000:
+                log(f"[eval] {sd} {A.name} {lab}: {r['status']}/{r['iters']}/{r['time_ms']:.1f}ms")
             row[lab] = {"status": r["status"], "iters": r["iters"], "ms": round(r["time_ms"], 3),
                         "relres_true": r["relres_true"], "cost_sum": r["cost_sum"], "fallback_at": r["fallback_at"]}
             if lab not in ("fp64",):
@@ -306,9 +308,10 @@ def mlp_experiment(args, M, W, torch) -> dict:
     pols = {"fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=63),
             "fixed_mixed": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.BF16, M.FP32, M.FP32)),
             "qtable": greedy, "mlp_untrained": untrained, "mlp": mlp_pol}
-    out["heldout"] = {"seeds": [2000, 2000 + args.heldout_systems - 1], "n_hi": args.heldout_n_hi,
+    s0 = args.heldout_seed0
+    out["heldout"] = {"seeds": [s0, s0 + args.heldout_systems - 1], "n_hi": args.heldout_n_hi,
                       "maxit": args.eval_maxit}
-    rows, summ = evaluate_policies(M, W, torch, range(2000, 2000 + args.heldout_systems), pols, args.eval_maxit,
+    rows, summ = evaluate_policies(M, W, torch, range(s0, s0 + args.heldout_systems), pols, args.eval_maxit,
                                    family=lambda sd: W.family_system(sd, n_hi=args.heldout_n_hi))
     out["heldout_summary"] = summ
     out["heldout_rows"] = rows
@@ -521,6 +524,7 @@ def main():
                          "one Q-table per operation); default: C1 and C2 with section 4.1's weights, a joint "
                          "table, decisions every iteration")
     ap.add_argument("--heldout-n-hi", type=float, default=5e5, help="largest held-out system size")
+    ap.add_argument("--heldout-seed0", type=int, default=2000, help="first held-out seed of the MLP experiment")
     ap.add_argument("--paper", action="store_true",
                     help="section 5's setting on its synthetic families (per-operation Q-tables, rho < 1e-6 "
                          "with k >= 10, T_max 1000) against fp64 CG")
