@@ -80,12 +80,21 @@ def mix_of(M, actions) -> dict:
     a = np.asarray(actions, dtype=np.int64)
     if a.size == 0:
         return {}
-    names = ("fp16", "bf16", "fp32", "fp64", "q52")
+    names = ("fp16", "bf16", "fp32", "fp64", "q52", "tf32")
+    fm = formats_of(M, a)
     out = {}
-    for op, shift, mask in (("spmv", 4, 7), ("dot", 2, 3), ("axpy", 0, 3)):
-        f = (a >> shift) & mask
-        out[op] = {names[i]: round(float(np.mean(f == i)), 3) for i in range(5) if np.any(f == i)}
+    for j, op in enumerate(("spmv", "dot", "axpy")):
+        f = fm[:, j]
+        out[op] = {names[i]: round(float(np.mean(f == i)), 3) for i in range(6) if np.any(f == i)}
     return out
+
+
+def formats_of(M, actions) -> np.ndarray:
+    """[len, 3] format codes (spmv, dot, axpy) of action codes, by the library's decoding."""
+    a = np.asarray(actions, dtype=np.int64)
+    u, inv = np.unique(a, return_inverse=True)
+    table = np.array([M.decode(int(v)) for v in u], dtype=np.int64).reshape(-1, 3)
+    return table[inv.reshape(-1)]
 
 
 def build_systems(M, W, torch, seeds, n_hi=5e5, kappa_hi=1e8):
@@ -320,13 +329,16 @@ def mlp_experiment(args, M, W, torch) -> dict:
 
 def paper_experiment(args, M, W, torch) -> dict:
     """Section 5's setting on its two synthetic families: one Q-table per
-    operation (section 4.1), cost settings C1 and C2 (tf32 dropped), 10
+    operation (section 4.1) over fp16, bf16, tf32, fp32 and fp64, cost
+    settings C1 and C2, 10
     training matrices x 200 episodes, epsilon 1 -> 0.1, the termination
     rho < 1e-6 with k >= 10 and T_max = 1000, no periodic residual replacement;
     then 100 test matrices against fp64 CG: iterations, the relative error
     against a direct solve, and the share of each format per operation (the
     analogues of Tables 2-4; the paper's matrices and seeds are not published,
-    so the comparison is qualitative)."""
+    so the comparison is qualitative).  Both readings of a low-precision
+    operation are run: the paper's emulation (an fp64 operation whose result is
+    rounded) and the hardware one (formats in memory and arithmetic)."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as spl
 
@@ -337,77 +349,84 @@ def paper_experiment(args, M, W, torch) -> dict:
     tol, T = 1e-6, 1000
     out = {"experiment": "paper setting (section 5)", "tol": tol, "T_max": T, "k_min": 10,
            "train_matrices": args.paper_train, "episodes_per_matrix": args.paper_episodes,
-           "test_matrices": args.paper_test, "per_op": args.paper_per_op, "rho_fp64": args.paper_rho64}
-    names = ("fp16", "bf16", "fp32", "fp64")
-    for fam, gen in families.items():
-        t0 = time.time()
-        train = []
-        for sd in range(3000, 3000 + args.paper_train):
-            A, b = gen(sd)
-            mm = M.Matrix(A)
-            mm.set_options(replace_period=0, fallback=False, stop_rule=1, rho_fp64=args.paper_rho64)
-            train.append((mm, torch.from_numpy(np.ascontiguousarray(b)).cuda(),
-                          torch.empty(A.n, dtype=torch.float64, device="cuda")))
-        tables = {}
-        fo = {"train_setup_s": round(time.time() - t0, 1)}
-        for cost in ("C1", "C2"):
-            P = M.Policy(kind=M.POLICY_QTABLE_TRAIN, cost=cost, seed=31, per_op=args.paper_per_op)
+           "test_matrices": args.paper_test, "per_op": args.paper_per_op, "rho_fp64": args.paper_rho64,
+           "formats": ["fp16", "bf16", "fp32", "fp64"] + (["tf32"] if args.paper_nfmt == 5 else [])}
+    names = ("fp16", "bf16", "fp32", "fp64", "q52", "tf32")
+    for reading in args.paper_readings.split(","):
+        emu = {"emulation": 1, "hardware": 0}[reading]
+        out[reading] = {}
+        for fam, gen in families.items():
             t0 = time.time()
-            res = M.train_qlearning(P, train, episodes=args.paper_episodes, maxit=T, tol=tol, eps_start=1.0,
-                                    eps_end=0.1, order=1)
-            fo[f"train_{cost}_s"] = round(time.time() - t0, 1)
-            fo[f"train_{cost}_converged_share"] = round(float(np.mean([r["status"] == 0 for r in res])), 3)
-            g = M.Policy(kind=M.POLICY_QTABLE, cost=cost, per_op=args.paper_per_op)
-            g.set_qtable(P.qtable())
-            tables[cost] = g
-            log(f"[paper] {fam} {cost}: trained {len(res)} episodes in {fo[f'train_{cost}_s']} s")
-        for mm, _, _ in train:
-            mm.close()
-        # the fixed legs isolate the storage format of A: SpMV at fp16, bf16 or
-        # fp32, everything else in fp64
-        pols = {"fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=63),
-                "spmv_fp16_rest_fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.FP16, M.FP64, M.FP64)),
-                "spmv_bf16_rest_fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.BF16, M.FP64, M.FP64)),
-                "spmv_fp32_rest_fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.FP32, M.FP64, M.FP64)),
-                "RL_C1": tables["C1"], "RL_C2": tables["C2"]}
-        stats = {k: {"iters": [], "err": [], "ms": [], "status": [], "mix": np.zeros((3, 4))} for k in pols}
-        for sd in range(4000, 4000 + args.paper_test):
-            A, b = gen(sd)
-            S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
-            x_ref = spl.spsolve(S.tocsc(), b)
-            mm = M.Matrix(A)
-            bd = torch.from_numpy(np.ascontiguousarray(b)).cuda()
-            xd = torch.empty(A.n, dtype=torch.float64, device="cuda")
-            for k, pol in pols.items():
-                mm.set_policy(pol)
-                mm.set_options(replace_period=0, fallback=False, stop_rule=1, rho_fp64=args.paper_rho64)
-                xd.zero_()
-                r = mm.solve(bd, xd, tol=tol, maxit=T)
-                x = xd.cpu().numpy()
-                st = stats[k]
-                st["iters"].append(r["iters"])
-                st["status"].append(r["status"])
-                st["ms"].append(r["time_ms"])
-                st["err"].append(float(np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)))
-                acts = mm.history()["actions"].astype(np.int64)
-                for j, sh in enumerate((4, 2, 0)):
-                    st["mix"][j] += np.bincount((acts >> sh) & 3, minlength=4)
-            mm.close()
-        fo["test"] = {}
-        for k, st in stats.items():
-            it, er, stt = np.array(st["iters"]), np.array(st["err"]), np.array(st["status"])
-            mix = st["mix"] / np.maximum(st["mix"].sum(axis=1, keepdims=True), 1)
-            fo["test"][k] = {"mean_iters": round(float(it.mean()), 1), "std_iters": round(float(it.std()), 1),
-                             "p75_iters": float(np.percentile(it, 75)),
-                             "status_counts": {int(v): int(np.sum(stt == v)) for v in np.unique(stt)},
-                             "mean_rel_error": float(er.mean()), "max_rel_error": float(er.max()),
-                             "median_rel_error": float(np.median(er)),
-                             "p25_p75_rel_error": [float(np.percentile(er, 25)), float(np.percentile(er, 75))],
-                             "total_ms": round(float(np.sum(st["ms"])), 2),
-                             "mix": {op: {names[f]: round(float(mix[j, f]), 3) for f in range(4)}
-                                     for j, op in enumerate(("spmv", "dot", "update"))}}
-        log(f"[paper] {fam}: " + json.dumps({k: (v["mean_iters"], v["mean_rel_error"]) for k, v in fo["test"].items()}))
-        out[fam] = fo
+            train = []
+            for sd in range(3000, 3000 + args.paper_train):
+                A, b = gen(sd)
+                mm = M.Matrix(A)
+                mm.set_options(replace_period=0, fallback=False, stop_rule=1, rho_fp64=args.paper_rho64,
+                               emulate=emu)
+                train.append((mm, torch.from_numpy(np.ascontiguousarray(b)).cuda(),
+                              torch.empty(A.n, dtype=torch.float64, device="cuda")))
+            tables = {}
+            fo = {"train_setup_s": round(time.time() - t0, 1)}
+            for cost in ("C1", "C2"):
+                P = M.Policy(kind=M.POLICY_QTABLE_TRAIN, cost=cost, seed=31, per_op=args.paper_per_op,
+                             nfmt=args.paper_nfmt)
+                t0 = time.time()
+                res = M.train_qlearning(P, train, episodes=args.paper_episodes, maxit=T, tol=tol, eps_start=1.0,
+                                        eps_end=0.1, order=1)
+                fo[f"train_{cost}_s"] = round(time.time() - t0, 1)
+                fo[f"train_{cost}_converged_share"] = round(float(np.mean([r["status"] == 0 for r in res])), 3)
+                g = M.Policy(kind=M.POLICY_QTABLE, cost=cost, per_op=args.paper_per_op, nfmt=args.paper_nfmt)
+                g.set_qtable(P.qtable())
+                tables[cost] = g
+                log(f"[paper] {reading} {fam} {cost}: trained {len(res)} episodes in {fo[f'train_{cost}_s']} s")
+            for mm, _, _ in train:
+                mm.close()
+            # the fixed legs isolate the storage format of A: SpMV at fp16, bf16 or
+            # fp32, everything else in fp64
+            pols = {"fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=63),
+                    "spmv_fp16_rest_fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.FP16, M.FP64, M.FP64)),
+                    "spmv_bf16_rest_fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.BF16, M.FP64, M.FP64)),
+                    "spmv_fp32_rest_fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.FP32, M.FP64, M.FP64)),
+                    "RL_C1": tables["C1"], "RL_C2": tables["C2"]}
+            stats = {k: {"iters": [], "err": [], "ms": [], "status": [], "mix": np.zeros((3, 6))} for k in pols}
+            for sd in range(4000, 4000 + args.paper_test):
+                A, b = gen(sd)
+                S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+                x_ref = spl.spsolve(S.tocsc(), b)
+                mm = M.Matrix(A)
+                bd = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+                xd = torch.empty(A.n, dtype=torch.float64, device="cuda")
+                for k, pol in pols.items():
+                    mm.set_policy(pol)
+                    mm.set_options(replace_period=0, fallback=False, stop_rule=1, rho_fp64=args.paper_rho64,
+                               emulate=emu)
+                    xd.zero_()
+                    r = mm.solve(bd, xd, tol=tol, maxit=T)
+                    x = xd.cpu().numpy()
+                    st = stats[k]
+                    st["iters"].append(r["iters"])
+                    st["status"].append(r["status"])
+                    st["ms"].append(r["time_ms"])
+                    st["err"].append(float(np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)))
+                    fm = formats_of(M, mm.history()["actions"][:r["iters"]])
+                    for j in range(3):
+                        st["mix"][j] += np.bincount(fm[:, j], minlength=6)[:6]
+                mm.close()
+            fo["test"] = {}
+            for k, st in stats.items():
+                it, er, stt = np.array(st["iters"]), np.array(st["err"]), np.array(st["status"])
+                mix = st["mix"] / np.maximum(st["mix"].sum(axis=1, keepdims=True), 1)
+                fo["test"][k] = {"mean_iters": round(float(it.mean()), 1), "std_iters": round(float(it.std()), 1),
+                                 "p75_iters": float(np.percentile(it, 75)),
+                                 "status_counts": {int(v): int(np.sum(stt == v)) for v in np.unique(stt)},
+                                 "mean_rel_error": float(er.mean()), "max_rel_error": float(er.max()),
+                                 "median_rel_error": float(np.median(er)),
+                                 "p25_p75_rel_error": [float(np.percentile(er, 25)), float(np.percentile(er, 75))],
+                                 "total_ms": round(float(np.sum(st["ms"])), 2),
+                                 "mix": {op: {names[f]: round(float(mix[j, f]), 3) for f in range(6) if f != 4}
+                                         for j, op in enumerate(("spmv", "dot", "update"))}}
+            log(f"[paper] {reading} {fam}: " + json.dumps({k: (v["mean_iters"], v["mean_rel_error"]) for k, v in fo["test"].items()}))
+            out[reading][fam] = fo
     return out
 
 
@@ -533,6 +552,11 @@ def main():
     ap.add_argument("--paper-per-op", type=int, default=2, choices=(1, 2),
                     help="1: a table per operation for SpMV, dot and updates; 2: SpMV and dot, updates in fp64")
     ap.add_argument("--paper-test", type=int, default=100)
+    ap.add_argument("--paper-readings", default="emulation,hardware",
+                    help="emulation: the paper's reading (fp64 operations, results rounded to each "
+                         "operation's format); hardware: this library's formats in memory and arithmetic")
+    ap.add_argument("--paper-nfmt", type=int, default=5, choices=(4, 5),
+                    help="5: the paper's format set with tf32 (emulated), 4: without it")
     ap.add_argument("--paper-rho64", type=int, default=1, choices=(0, 1),
                     help="1: rho from an fp64 r.r (the paper keeps residual computations in fp64)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-policy leg")

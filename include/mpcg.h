@@ -22,12 +22,17 @@
  *     the stream given at creation, in order; entry points that return host data
  *     synchronise that stream before returning.
  *   - The library never frees caller memory; handles own what they allocate.
- *   - Formats: MPCG_FP16 = 0, MPCG_BF16 = 1, MPCG_FP32 = 2, MPCG_FP64 = 3, and
+ *   - Formats: MPCG_FP16 = 0, MPCG_BF16 = 1, MPCG_FP32 = 2, MPCG_FP64 = 3,
  *     MPCG_Q52 = 4 (Table 1's quarter precision: 1 sign, 5 exponent, 2 fraction
- *     bits; matrix storage of the SpMV only).
+ *     bits; matrix storage of the SpMV only), and MPCG_TF32 = 5 (section 5's
+ *     format set: 1 sign, 8 exponent, 10 fraction bits, i.e. fp32's range with
+ *     fp16's significand; gfx950 has no tf32 storage or arithmetic, so values
+ *     are rounded to it and held in fp32 containers, at fp32's bytes and time).
  *     An action is a = 16*f_spmv + 4*f_dot + f_axpy: 0..63 for the four
- *     arithmetic formats (the learned policies' action set), 64..79 for q52
- *     SpMV storage with f_dot, f_axpy in 0..3 (fixed policies).
+ *     arithmetic formats (the joint table's and the network's action set),
+ *     64..79 for q52 SpMV storage with f_dot, f_axpy in 0..3 (fixed policies),
+ *     and 128..252 = 128 + 25*d_spmv + 5*d_dot + d_axpy over the digits
+ *     0..3 (the four formats) and 4 (tf32) when a slot is tf32.
  *   - Vector "tier": vectors of an iteration whose axpy format is fp64 are stored
  *     as double, otherwise as float (tier64 = 1 / 0).
  */
@@ -57,6 +62,7 @@ extern "C" {
 #define MPCG_FP32 2
 #define MPCG_FP64 3
 #define MPCG_Q52 4
+#define MPCG_TF32 5
 
 #define MPCG_MEM_HOST 0
 #define MPCG_MEM_DEVICE 1
@@ -91,7 +97,7 @@ typedef struct mpcg_policy mpcg_policy;
  */
 typedef struct {
     int32_t kind;              /* MPCG_POLICY_*                                  */
-    int32_t fixed_action;      /* used by MPCG_POLICY_FIXED (0..79)              */
+    int32_t fixed_action;      /* used by MPCG_POLICY_FIXED (0..79, 128..252)    */
     int32_t t_bin;             /* iteration-bin horizon (1000)                   */
     int32_t b_it;              /* iteration bins (5)                             */
     int32_t b_res;             /* residual bins (10), in [1, 17]                 */
@@ -121,7 +127,12 @@ typedef struct {
                                   (section 4.2 keeps the residual update in full
                                   precision).  0: one joint table over the 64
                                   actions                                        */
-    int32_t reserved;
+    int32_t nfmt;              /* formats per operation table: 4 (0 reads as 4),
+                                  or 5 with tf32 as digit 4 (section 5's set
+                                  {fp16, bf16, tf32, fp32, fp64}); Q_j(s, d) at
+                                  column nfmt*j + d; 5 needs per_op 1 or 2 for
+                                  the table policies                           */
+    double cost_tf32;          /* c(tf32) (section 5: 0.8 in C1, 0.5 in C2)     */
 } mpcg_policy_desc;
 
 typedef struct {
@@ -162,7 +173,15 @@ typedef struct {
                                   (section 1 keeps residual computations in
                                   fp64), sigma' still at the dot format.
                                   Not for batched solves.                       */
-    int32_t reserved;
+    int32_t emulate;           /* 0: the hardware reading (matrix stored in the
+                                  SpMV format, operands rounded, low-precision
+                                  vectors in fp32 containers); 1: the paper's
+                                  emulation reading of fl_p(op) (section 4):
+                                  every operation computes in fp64 and rounds
+                                  its result to its format (each q_i of the
+                                  SpMV, the total of a dot, each updated
+                                  element), all vectors in fp64.  Not for q52
+                                  actions or batched solves.                    */
 } mpcg_solve_opts;
 
 /* Per-kernel timing of the last solve made with opts.profile = 1.  One CG
@@ -241,6 +260,17 @@ int mpcg_get_precond(mpcg_matrix *A, float *minv);
  * from fp64, after the same exact per-row power-of-two scale as fp16) to a
  * host uint8 array[nnz] of its bit patterns. */
 int mpcg_get_shadow_q52(mpcg_matrix *A, uint8_t *q52);
+/* Action code of a format triple (the encoding above): f_spmv one of the six
+ * formats, f_dot and f_axpy one of fp16, bf16, fp32, fp64, tf32 (the four
+ * arithmetic formats with a q52 SpMV).  Returns the code (>= 0) or
+ * MPCG_ERR_INVALID. */
+int mpcg_action(int f_spmv, int f_dot, int f_axpy);
+/* The formats of an action code; MPCG_ERR_INVALID for a code outside 0..79,
+ * 128..252. */
+int mpcg_action_formats(int action, int32_t *f_spmv, int32_t *f_dot, int32_t *f_axpy);
+/* Copies the tf32 shadow (round to nearest even from fp64 to 11 significant
+ * bits in fp32's exponent range, no row scale) to a host float array[nnz]. */
+int mpcg_get_shadow_tf32(mpcg_matrix *A, float *tf32);
 
 /* ---------------------------------------------------------------- policies */
 
@@ -463,10 +493,12 @@ int mpcg_get_history(mpcg_matrix *A, double *rho, uint8_t *act, uint8_t *flags, 
  * p, q, u, v, y are float[n] (tier64 = 0) or double[n] (tier64 = 1).
  */
 /* q = SpMV_f(A, p): row fma chain in CSR order, accumulated in fp32 (f != 3) or
- * fp64 (f = 3), output rounded to the tier; f = MPCG_Q52 reads the q52 shadow. */
+ * fp64 (f = 3), output rounded to the tier; f = MPCG_Q52 reads the q52 shadow,
+ * f = MPCG_TF32 the tf32 shadow. */
 int mpcg_op_spmv(mpcg_matrix *A, int fmt, int tier64, const void *p, void *q);
 /* *out (host) = dot_f(u, v): operands rounded to f, products in the accumulation
- * format, pairwise sum over the zero-padded power-of-two length. */
+ * format, pairwise sum over the zero-padded power-of-two length; f is one of
+ * the four arithmetic formats or MPCG_TF32 (fp32 accumulation). */
 int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out);
 /*
  * mpcg_op_dot without any allocation, for callers that cannot allocate device
@@ -481,7 +513,7 @@ int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *
  * threads) race and must be serialised by the caller.
  */
 int mpcg_op_dot_noalloc(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out);
-/* y = rd_f(fma(alpha, u, y)) (tier of f) */
+/* y = rd_f(fma(alpha, u, y)) (tier of f; MPCG_TF32: fp32 containers) */
 int mpcg_op_axpy(mpcg_matrix *A, int fmt, double alpha, const void *u, void *y);
 /* r (double[n], device) = b - A x in fp64 */
 int mpcg_op_residual(mpcg_matrix *A, const double *b, const double *x, double *r);

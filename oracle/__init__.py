@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mpcg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-F16, BF16, F32, F64, Q52 = 0, 1, 2, 3, 4
+F16, BF16, F32, F64, Q52, TF32 = 0, 1, 2, 3, 4, 5
 ORDER_PAIRWISE, ORDER_SEQ = 0, 1
 POL_FIXED, POL_QTABLE, POL_QTRAIN, POL_MLP = 0, 1, 2, 3
 FL_REPLACED, FL_EXPLORED, FL_FALLBACK, FL_SWITCH = 1, 2, 4, 8
@@ -78,14 +78,14 @@ class Policy(C.Structure):
         ("w2m", C.POINTER(C.c_float)), ("b2m", C.POINTER(C.c_float)),
         ("w3m", C.POINTER(C.c_float)), ("b3m", C.POINTER(C.c_float)),
         ("replace_period", C.c_int32), ("decision_period", C.c_int32),
-        ("per_op", C.c_int32), ("pad2", C.c_int32),
+        ("per_op", C.c_int32), ("nfmt", C.c_int32), ("cost_tf32", C.c_double),
     ]
 
 
 class Params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("replace_period", C.c_int32),
                 ("fallback", C.c_int32), ("dot_order", C.c_int32), ("precond", C.c_int32),
-                ("stop_rule", C.c_int32), ("rho_fp64", C.c_int32)]
+                ("stop_rule", C.c_int32), ("rho_fp64", C.c_int32), ("emulate", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -124,6 +124,8 @@ def lib():
         L.orc_shadows.argtypes = [i64, ip, ip, dp, dp, dp, dp, ip]
         L.orc_spmv.argtypes = [i64, ip, ip, dp, C.c_int, C.c_int, dp, dp]
         L.orc_shadow_q52.argtypes = [i64, ip, ip, dp, dp, ip]
+        L.orc_shadow_tf32.argtypes = [i64, ip, ip, dp, dp]
+        L.orc_act_decode.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_jacobi_inverse.argtypes = [i64, ip, ip, dp, C.POINTER(C.c_float)]
         L.orc_residual.argtypes = [i64, ip, ip, dp, dp, dp, dp]
         L.orc_dot.restype = d
@@ -201,6 +203,13 @@ def shadow_q52(A):
     return v, e
 
 
+def shadow_tf32(A):
+    """tf32 shadow values (as float64) of the CSR matrix A."""
+    v = np.empty(A.nnz)
+    lib().orc_shadow_tf32(A.n, _p(_i32(A.row_ptr), C.c_int32), _p(_i32(A.col), C.c_int32), _p(_f64(A.val)), _p(v))
+    return v
+
+
 def spmv(A, p, fs: int, tier64: int):
     p = _f64(p)
     q = np.empty(A.n)
@@ -272,7 +281,25 @@ def residual_edges(b_res: int = 10, eps_min_exp: int = 16):
     return out
 
 
-COSTS = {"C1": (0.8, 0.6, 1.0, 2.0), "C2": (0.5, 0.4, 1.5, 3.0)}
+# c(fp16), c(bf16), c(fp32), c(fp64), c(tf32) (section 5)
+COSTS = {"C1": (0.8, 0.6, 1.0, 2.0, 0.8), "C2": (0.5, 0.4, 1.5, 3.0, 0.5)}
+
+
+def action(fs, fd, fa):
+    """Action code of (f_s, f_d, f_a): 16 f_s + 4 f_d + f_a over the four
+    arithmetic formats; with tf32 in a slot, 128 + 25 d_s + 5 d_d + d_a over the
+    digits (fp16, bf16, fp32, fp64, tf32) = 0..4."""
+    d = [4 if f == TF32 else f for f in (fs, fd, fa)]
+    if 4 in d:
+        return 128 + 25 * d[0] + 5 * d[1] + d[2]
+    return 16 * d[0] + 4 * d[1] + d[2]
+
+
+def act_decode(a):
+    """(f_s, f_d, f_a) of an action code, as the oracle's solver reads it."""
+    fs, fd, fa = C.c_int(), C.c_int(), C.c_int()
+    lib().orc_act_decode(int(a), C.byref(fs), C.byref(fd), C.byref(fa))
+    return fs.value, fd.value, fa.value
 
 
 class OraclePolicy:
@@ -281,7 +308,7 @@ class OraclePolicy:
     def __init__(self, kind=POL_FIXED, fixed_action=63, q=None, t_bin=1000, b_it=5,
                  b_res=10, w_stag=10, lr=0.1, gamma=0.9, w=(1.0, 0.1, 10.0), eps_min=1e-16,
                  cost="C1", epsilon=0.0, seed=0, episode=0, mlp=None, replace_period=50, decision_period=1,
-                 per_op=0):
+                 per_op=0, nfmt=4):
         self.s = Policy()
         s = self.s
         s.kind, s.fixed_action = kind, fixed_action
@@ -298,6 +325,8 @@ class OraclePolicy:
         costs = COSTS[cost] if isinstance(cost, str) else cost
         for i in range(4):
             s.cost[i] = costs[i]
+        s.cost_tf32 = costs[4] if len(costs) > 4 else costs[0]
+        s.nfmt = int(nfmt)
         s.epsilon, s.seed, s.episode = epsilon, seed, episode
         s.replace_period = replace_period
         s.decision_period = decision_period
@@ -344,16 +373,18 @@ def jacobi_inverse(A):
 
 def cg(A, b, x0=None, tol=1e-8, maxit=1000, policy: OraclePolicy | None = None,
        replace_period=0, fallback=False, order=ORDER_PAIRWISE, roll_cap=0, dump=0, precond=0, stop_rule=0,
-       rho_fp64=0):
+       rho_fp64=0, emulate=0):
     """Run the oracle solver (precond 1: Jacobi; stop_rule 1: the paper's
     termination, recursive rho < tol with k >= 10; rho_fp64 1: rho from an
-    fp64 r.r).  Returns (x, info dict with histories)."""
+    fp64 r.r; emulate 1: the paper's reading, fp64 operations whose results are
+    rounded to the operation's format).  Returns (x, info dict with histories)."""
     n = A.n
     b = _f64(b)
     x0 = np.zeros(n) if x0 is None else _f64(x0)
     x = np.empty(n)
     pol = policy if policy is not None else OraclePolicy()
-    prm = Params(tol, maxit, replace_period, int(fallback), order, int(precond), int(stop_rule), int(rho_fp64))
+    prm = Params(tol, maxit, replace_period, int(fallback), order, int(precond), int(stop_rule), int(rho_fp64),
+                 int(emulate))
     res = Result()
     hist_rho = np.full(maxit + 1, np.nan)
     hist_act = np.zeros(max(maxit, 1), dtype=np.uint8)

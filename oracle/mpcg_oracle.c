@@ -58,6 +58,11 @@
  *     fallback (optional): on breakdown or stagnation, once per solve, fold x_lo
  *     into x_hi and restart as plain fp64 CG (fixed action 63) from x_hi.
  *
+ *   emulate (the paper's reading of fl_p(op)): every operation computes in
+ *   fp64 and rounds its result to its format (SpMV: each q_i; dots: the
+ *   total; updates and the preconditioner solve: each element); r, p, q and
+ *   x_lo are fp64 vectors, so there is no tier switch.
+ *
  *   rho_fp64 (section 1 keeps residual computations in fp64): rho' =
  *   sqrt(dot64(r,r))/bnorm of the recursive r, while sigma' (beta's
  *   numerator) stays dot_fd(r,r).
@@ -87,12 +92,35 @@
 #define Q52 4   /* Table 1's quarter precision: 5 exponent bits, t = 3 (the printed
                    t is garbled; u = 2^-3 = 0.125 as printed fixes it); used
                    only as the SpMV's matrix storage */
-#define NFMT 5
+#define TF32 5  /* tf32, in section 5's format set but not in Table 1: fp32's
+                   exponent range (e_min -126, e_max 127) with fp16's 11-bit
+                   significand; values are held in fp32 containers */
+#define NFMT 6
 
 /* Table 1: significand bits t (with the implicit bit), e_min, e_max. */
-static const int FMT_T[NFMT] = {11, 8, 24, 53, 3};
-static const int FMT_EMIN[NFMT] = {-14, -126, -126, -1022, -14};
-static const int FMT_EMAX[NFMT] = {15, 127, 127, 1023, 15};
+static const int FMT_T[NFMT] = {11, 8, 24, 53, 3, 11};
+static const int FMT_EMIN[NFMT] = {-14, -126, -126, -1022, -14, -126};
+static const int FMT_EMAX[NFMT] = {15, 127, 127, 1023, 15, 127};
+
+/* Actions.  0..63: 16 f_s + 4 f_d + f_a over {fp16, bf16, fp32, fp64};
+ * 64..79: a q52 SpMV with 4 f_d + f_a; 128..252: 128 + 25 d_s + 5 d_d + d_a
+ * over the digits {0: fp16, 1: bf16, 2: fp32, 3: fp64, 4: tf32} (an action
+ * without a tf32 digit keeps its 0..63 code). */
+static int dig_fmt(int d) { return d == 4 ? TF32 : d; }
+static int fmt_dig(int f) { return f == TF32 ? 4 : f; }
+static int act_fs(int a) { return a < 64 ? (a >> 4) & 3 : a < 80 ? Q52 : dig_fmt((a - 128) / 25); }
+static int act_fd(int a) { return a < 80 ? (a >> 2) & 3 : dig_fmt(((a - 128) / 5) % 5); }
+static int act_fa(int a) { return a < 80 ? a & 3 : dig_fmt((a - 128) % 5); }
+static int act_compose(int ds, int dd, int da)
+{
+    if (ds == 4 || dd == 4 || da == 4) return 128 + 25 * ds + 5 * dd + da;
+    return 16 * ds + 4 * dd + da;
+}
+int orc_act_decode(int a, int *fs, int *fd, int *fa)
+{
+    *fs = act_fs(a); *fd = act_fd(a); *fa = act_fa(a);
+    return 0;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Rounding (section 4: fl_p(x) = x(1+delta), |delta| <= u_p; Table 1).      */
@@ -174,6 +202,7 @@ static void mat_build(orc_mat *A, int64_t n, const int32_t *rp, const int32_t *c
             /* q52 shares the fp16 exponent range, so the same row scale keeps
                the row's largest magnitude below its x_max */
             A->sh[Q52][k] = orc_rd(ldexp(v[k], -e), Q52);
+            A->sh[TF32][k] = orc_rd(v[k], TF32);    /* fp32's range: no scale */
         }
     }
 }
@@ -195,6 +224,15 @@ void orc_shadows(int64_t n, const int32_t *rp, const int32_t *ci, const double *
     memcpy(out_bf16, A.sh[BF16], sizeof(double) * (size_t)nnz);
     memcpy(out_f16, A.sh[F16], sizeof(double) * (size_t)nnz);
     memcpy(out_e, A.e, sizeof(int32_t) * (size_t)n);
+    mat_free(&A);
+}
+
+/* The tf32 shadow. */
+void orc_shadow_tf32(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double *out_tf32)
+{
+    orc_mat A;
+    mat_build(&A, n, rp, ci, v);
+    memcpy(out_tf32, A.sh[TF32], sizeof(double) * (size_t)rp[n]);
     mat_free(&A);
 }
 
@@ -420,7 +458,7 @@ typedef struct {
     double res_edges[16];    /* b_res - 1 thresholds, decreasing */
     double *q;               /* [n_states][64] */
     double lr, gamma, w1, w2, w3, eps_min;
-    double cost[4];
+    double cost[4];          /* c(fp16), c(bf16), c(fp32), c(fp64) */
     double epsilon;
     uint64_t seed;
     int64_t episode;
@@ -431,7 +469,9 @@ typedef struct {
     int32_t per_op;          /* 1: one Q-table per operation (section 4.1) in row[4 j + p];
                                 2: tables for SpMV and dot only, updates in fp64
                                 (section 4.2: the residual update in full precision) */
-    int32_t pad2;
+    int32_t nfmt;            /* formats per operation table: 4, or 5 with tf32
+                                (digit 4; per-operation tables only) */
+    double cost_tf32;        /* c(tf32) */
 } orc_policy;
 
 int orc_n_states(const orc_policy *pol) { return pol->b_res * pol->b_it * 2; }
@@ -458,13 +498,15 @@ static int argmax_row(const double *row)
 static double max_row(const double *row) { return row[argmax_row(row)]; }
 
 /* Separate Q-tables per operation (section 4.1: Q_j over states x precisions,
- * j = SpMV, dot, update), held in one table row per state: Q_j(s, p) =
- * q[s][4 j + p].  The greedy action takes each operation's argmax (lowest
- * index among ties). */
-static int argmax4(const double *t)
+ * j = SpMV, dot, update), held in one table row per state: Q_j(s, d) =
+ * q[s][S j + d] with S = nfmt formats per table and d the format digit.  The
+ * greedy action takes each operation's argmax (lowest digit among ties). */
+static int n_fmt(const orc_policy *pol) { return pol->nfmt == 5 ? 5 : 4; }
+
+static int argmax_n(const double *t, int S)
 {
     int best = 0;
-    for (int p = 1; p < 4; ++p)
+    for (int p = 1; p < S; ++p)
         if (t[p] > t[best]) best = p;
     return best;
 }
@@ -472,7 +514,8 @@ static int argmax4(const double *t)
 static int greedy_row(const orc_policy *pol, const double *row)
 {
     if (!pol->per_op) return argmax_row(row);
-    return 16 * argmax4(row) + 4 * argmax4(row + 4) + (pol->per_op == 2 ? F64 : argmax4(row + 8));
+    const int S = n_fmt(pol);
+    return act_compose(argmax_n(row, S), argmax_n(row + S, S), pol->per_op == 2 ? F64 : argmax_n(row + 2 * S, S));
 }
 
 /* Q update of the decision (s, a) toward reward R, bootstrapped from state
@@ -486,23 +529,29 @@ static void q_learn(orc_policy *pol, int s, int a, double R, int s_next)
         *qsa = *qsa + pol->lr * (t - *qsa);
         return;
     }
+    const int S = n_fmt(pol);
+    const int dj[3] = {fmt_dig(act_fs(a)), fmt_dig(act_fd(a)), fmt_dig(act_fa(a))};
     for (int j = 0; j < (pol->per_op == 2 ? 2 : 3); ++j) {
-        const int pj = (a >> (4 - 2 * j)) & 3;
         double t = R;
         if (s_next >= 0) {
-            const double *nx = &pol->q[s_next * N_ACT + 4 * j];
-            t = R + pol->gamma * nx[argmax4(nx)];
+            const double *nx = &pol->q[s_next * N_ACT + S * j];
+            t = R + pol->gamma * nx[argmax_n(nx, S)];
         }
-        double *qsa = &pol->q[s * N_ACT + 4 * j + pj];
+        double *qsa = &pol->q[s * N_ACT + S * j + dj[j]];
         *qsa = *qsa + pol->lr * (t - *qsa);
     }
 }
 
 /* Cost of an action: c(f_s) + c(f_d) + c(f_a).  The cost settings give no
- * value for q52 (actions 64..79); (a >> 4) & 3 charges it as fp16. */
+ * value for q52 (actions 64..79); it is charged as fp16. */
+static double cost_fmt(const orc_policy *pol, int f)
+{
+    return f == TF32 ? pol->cost_tf32 : f == Q52 ? pol->cost[F16] : pol->cost[f];
+}
+
 static double cost_of(const orc_policy *pol, int a)
 {
-    return (pol->cost[(a >> 4) & 3] + pol->cost[(a >> 2) & 3]) + pol->cost[a & 3];
+    return (cost_fmt(pol, act_fs(a)) + cost_fmt(pol, act_fd(a))) + cost_fmt(pol, act_fa(a));
 }
 
 /* Reward of one decision (section 4.1) whose action ran n_it iterations: the
@@ -620,6 +669,9 @@ typedef struct {
     int32_t rho_fp64;         /* 1: rho' from dot64(r, r) of the recursive r
                                  (residual computations in fp64, section 1);
                                  sigma' stays dot_fd */
+    int32_t emulate;          /* 1: the paper's emulation reading: every
+                                 operation computes in fp64 and rounds its
+                                 result to its format; vectors in fp64 */
 } orc_params;
 
 typedef struct {
@@ -688,24 +740,23 @@ static int decide(const orc_policy *pol, int kind, const float *feat, int s, int
     case POL_QTRAIN: {
         if (pol->per_op) {       /* an epsilon-greedy draw per operation, streams 2 .. 7 */
             const double *row = &pol->q[s * N_ACT];
-            int a = 0;
+            const int S = n_fmt(pol);
+            int d[3];
             for (int j = 0; j < 3; ++j) {
-                int pj;
                 if (j == 2 && pol->per_op == 2) {     /* updates fixed in fp64 */
-                    a = a * 4 + F64;
+                    d[j] = F64;
                     break;
                 }
                 double u0 = orc_uniform(pol->seed, (uint64_t)pol->episode, (uint64_t)k, (uint64_t)(2 + 2 * j));
                 if (u0 < pol->epsilon) {
                     double u1 = orc_uniform(pol->seed, (uint64_t)pol->episode, (uint64_t)k, (uint64_t)(3 + 2 * j));
-                    pj = (int)(u1 * 4.0);
+                    d[j] = (int)(u1 * (double)S);
                     *explored = 1;
                 } else {
-                    pj = argmax4(row + 4 * j);
+                    d[j] = argmax_n(row + S * j, S);
                 }
-                a = a * 4 + pj;
             }
-            return a;
+            return act_compose(d[0], d[1], d[2]);
         }
         double u0 = orc_uniform(pol->seed, (uint64_t)pol->episode, (uint64_t)k, 0);
         if (u0 < pol->epsilon) {
@@ -759,6 +810,37 @@ static void precond_apply(int64_t n, const float *m, const double *r, double *z,
         z[i] = fa == F64 ? (double)m[i] * r[i] : orc_rd((double)(m[i] * (float)r[i]), fa);
 }
 
+/* The paper's emulation reading (section 4's fl_p(op), and its low-precision
+ * emulation): an operation at format p computes in fp64 and rounds its result
+ * to p.  The SpMV rounds each q_i (fp64 row fma chain, no row scale), a dot
+ * rounds the fp64 pairwise total, an update rounds each fp64 fma, the
+ * preconditioner solve rounds each m_i r_i.  The vectors stay in fp64. */
+static void spmv_emul(const orc_mat *A, int fs, const double *p, double *q)
+{
+    mat_spmv(A, F64, 1, p, q);
+    for (int64_t i = 0; i < A->n; ++i) q[i] = orc_rd(q[i], fs);
+}
+
+static double dot_emul(int64_t n, const double *u, const double *v, int fd, int order)
+{
+    return orc_rd(orc_dot(n, u, v, F64, order), fd);
+}
+
+static void axpy_emul(int64_t n, double alpha, const double *u, double *y, int fa)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = orc_rd(fma(alpha, u[i], y[i]), fa);
+}
+
+static void xpay_emul(int64_t n, double beta, const double *r, double *p, int fa)
+{
+    for (int64_t i = 0; i < n; ++i) p[i] = orc_rd(fma(beta, p[i], r[i]), fa);
+}
+
+static void precond_emul(int64_t n, const float *m, const double *r, double *z, int fa)
+{
+    for (int64_t i = 0; i < n; ++i) z[i] = orc_rd((double)m[i] * r[i], fa);
+}
+
 /* r64^T M^-1 r64 in fp64 (a start, restart or replacement). */
 static double precond_dot64(int64_t n, const float *m, const double *r64, double *work, int order)
 {
@@ -783,6 +865,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
     double *xhi = malloc(bytes), *xlo = malloc(bytes), *r = malloc(bytes);
     double *p = malloc(bytes), *q = malloc(bytes), *r64 = malloc(bytes), *z = malloc(bytes);
     const int pc = prm->precond;
+    const int emul = prm->emulate;
     float *minv = pc ? jacobi_inverse(n, rp, ci, v) : NULL;
     double *hist_rho = h->hist_rho;
     const int W = pol->w_stag;
@@ -833,13 +916,16 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             a = fell_back ? 63 : decide(pol, kind, feat, s, k, &explored);
             if (fell_back) explored = 0;
             k_dec = k;
-            tier = tier_of(a & 3);
+            tier = emul ? 1 : tier_of(act_fa(a));
             for (int64_t i = 0; i < n; ++i) { r[i] = rd_tier(r64[i], tier); p[i] = r[i]; }
-            if (pc) precond_apply(n, minv, r, p, a & 3);        /* p_0 = z_0 */
+            if (pc) {                                           /* p_0 = z_0 */
+                if (emul) precond_emul(n, minv, r, p, act_fa(a));
+                else precond_apply(n, minv, r, p, act_fa(a));
+            }
         }
         if (k >= prm->maxit) { status = 1; break; }
 
-        const int fs = (a >> 4) & 7, fd = (a >> 2) & 3, fa = a & 3;   /* fs = 4: q52 storage */
+        const int fs = act_fs(a), fd = act_fd(a), fa = act_fa(a);
         const int policy_active = !fell_back;
         const int training = policy_active && kind == POL_QTRAIN;
         h->hist_act[k] = (uint8_t)a;
@@ -848,8 +934,9 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
 
         if (k < h->dump_cap && h->dump_p) memcpy(&h->dump_p[k * n], p, bytes);
         if (k < h->dump_cap && h->dump_r) memcpy(&h->dump_r[k * n], r, bytes);
-        mat_spmv(&A, fs, tier, p, q);
-        double nu = orc_dot(n, p, q, fd, prm->dot_order);
+        if (emul) spmv_emul(&A, fs, p, q);
+        else mat_spmv(&A, fs, tier, p, q);
+        double nu = emul ? dot_emul(n, p, q, fd, prm->dot_order) : orc_dot(n, p, q, fd, prm->dot_order);
         double alpha = sigma / nu;
         if (k < h->dump_cap && h->hist_alpha) h->hist_alpha[k] = alpha;
         int broke = !(nu > 0.0 && isfinite(nu)) || !isfinite(alpha);
@@ -857,13 +944,25 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         double sig_new = 0.0, rho_new = 0.0, beta = 0.0;
         int64_t kk = k;
         if (!broke) {
-            orc_axpy(n, alpha, p, xlo, fa);
-            orc_axpy(n, -alpha, q, r, fa);
-            double sig_rr = orc_dot(n, r, r, prm->rho_fp64 ? F64 : fd, prm->dot_order);
-            sig_new = prm->rho_fp64 ? orc_dot(n, r, r, fd, prm->dot_order) : sig_rr;
+            if (emul) {
+                axpy_emul(n, alpha, p, xlo, fa);
+                axpy_emul(n, -alpha, q, r, fa);
+            } else {
+                orc_axpy(n, alpha, p, xlo, fa);
+                orc_axpy(n, -alpha, q, r, fa);
+            }
+            double sig_rr = prm->rho_fp64 ? orc_dot(n, r, r, F64, prm->dot_order)
+                            : emul ? dot_emul(n, r, r, fd, prm->dot_order) : orc_dot(n, r, r, fd, prm->dot_order);
+            sig_new = !prm->rho_fp64 ? sig_rr
+                      : emul ? dot_emul(n, r, r, fd, prm->dot_order) : orc_dot(n, r, r, fd, prm->dot_order);
             if (pc) {                                             /* sigma' = r^T z */
-                precond_apply(n, minv, r, z, fa);
-                sig_new = orc_dot(n, r, z, fd, prm->dot_order);
+                if (emul) {
+                    precond_emul(n, minv, r, z, fa);
+                    sig_new = dot_emul(n, r, z, fd, prm->dot_order);
+                } else {
+                    precond_apply(n, minv, r, z, fa);
+                    sig_new = orc_dot(n, r, z, fd, prm->dot_order);
+                }
             }
             k += 1;
             rho_new = sqrt(sig_rr) / bnorm;
@@ -951,9 +1050,13 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
 
         if (kk < h->dump_cap && h->hist_beta) h->hist_beta[kk] = beta;
         if (pc) {                                                 /* p = z + beta p */
-            precond_apply(n, minv, r, z, fa);
+            if (emul) precond_emul(n, minv, r, z, fa);
+            else precond_apply(n, minv, r, z, fa);
             if (dir_restart) memcpy(p, z, bytes);
+            else if (emul) xpay_emul(n, beta, z, p, fa);
             else xpay(n, beta, z, p, fa);
+        } else if (emul) {
+            xpay_emul(n, beta, r, p, fa);
         } else {
             xpay(n, beta, r, p, fa);
         }
@@ -968,7 +1071,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         } else {
             explored = 0;                  /* the action holds */
         }
-        int nt = tier_of(a & 3);
+        int nt = emul ? 1 : tier_of(act_fa(a));
         if (nt != tier) {
             fold(n, xhi, xlo);
             for (int64_t i = 0; i < n; ++i) { r[i] = rd_tier(r[i], nt); p[i] = rd_tier(p[i], nt); }

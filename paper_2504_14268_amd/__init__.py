@@ -14,20 +14,28 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpcg.so")
 
-FP16, BF16, FP32, FP64, Q52 = 0, 1, 2, 3, 4
-FORMATS = {"fp16": FP16, "bf16": BF16, "fp32": FP32, "fp64": FP64, "q52": Q52}
+FP16, BF16, FP32, FP64, Q52, TF32 = 0, 1, 2, 3, 4, 5
+FORMATS = {"fp16": FP16, "bf16": BF16, "fp32": FP32, "fp64": FP64, "q52": Q52, "tf32": TF32}
 POLICY_FIXED, POLICY_QTABLE, POLICY_QTABLE_TRAIN, POLICY_MLP = 0, 1, 2, 3
 CONVERGED, MAXIT, CONVERGED_FALLBACK, BREAKDOWN = 0, 1, 2, 3
 FLAG_REPLACED, FLAG_EXPLORED, FLAG_FALLBACK, FLAG_SWITCH = 1, 2, 4, 8
-COSTS = {"C1": (0.8, 0.6, 1.0, 2.0), "C2": (0.5, 0.4, 1.5, 3.0)}
+# c(fp16), c(bf16), c(fp32), c(fp64), c(tf32)
+COSTS = {"C1": (0.8, 0.6, 1.0, 2.0, 0.8), "C2": (0.5, 0.4, 1.5, 3.0, 0.5)}
 
 
 def action(f_spmv: int, f_dot: int, f_axpy: int) -> int:
-    return 16 * f_spmv + 4 * f_dot + f_axpy
+    """The library's action code of a format triple (mpcg_action)."""
+    a = lib().mpcg_action(f_spmv, f_dot, f_axpy)
+    if a < 0:
+        _check(a, "mpcg_action")
+    return a
 
 
 def decode(a: int):
-    return (a >> 4) & 7, (a >> 2) & 3, a & 3
+    """(f_spmv, f_dot, f_axpy) of an action code, as the library reads it."""
+    fs, fd, fa = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().mpcg_action_formats(int(a), C.byref(fs), C.byref(fd), C.byref(fa)), "action_formats")
+    return fs.value, fd.value, fa.value
 
 
 class PolicyDesc(C.Structure):
@@ -38,7 +46,7 @@ class PolicyDesc(C.Structure):
         ("w1", C.c_double), ("w2", C.c_double), ("w3", C.c_double), ("eps_min", C.c_double),
         ("cost", C.c_double * 4), ("seed", C.c_uint64),
         ("replace_period", C.c_int32), ("decision_period", C.c_int32),
-        ("per_op", C.c_int32), ("reserved", C.c_int32),
+        ("per_op", C.c_int32), ("nfmt", C.c_int32), ("cost_tf32", C.c_double),
     ]
 
 
@@ -47,7 +55,7 @@ class SolveOpts(C.Structure):
                 ("chunk", C.c_int32), ("profile", C.c_int32),
                 ("spmv_rows", C.c_int32), ("index16", C.c_int32),
                 ("precond", C.c_int32), ("stop_rule", C.c_int32),
-                ("rho_fp64", C.c_int32), ("reserved", C.c_int32)]
+                ("rho_fp64", C.c_int32), ("emulate", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -126,6 +134,9 @@ def lib():
             "mpcg_get_info": [vp, C.POINTER(MatrixInfo)],
             "mpcg_get_shadows": [vp, vp, vp, vp, vp],
             "mpcg_get_shadow_q52": [vp, vp],
+            "mpcg_get_shadow_tf32": [vp, vp],
+            "mpcg_action": [C.c_int, C.c_int, C.c_int],
+            "mpcg_action_formats": [C.c_int, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
             "mpcg_get_precond": [vp, vp],
             "mpcg_residual_thresholds": [i32, d, vp],
             "mpcg_policy_create": [C.POINTER(PolicyDesc), C.POINTER(vp)],
@@ -206,7 +217,7 @@ class Policy:
 
     def __init__(self, kind=POLICY_FIXED, fixed_action=63, t_bin=1000, b_it=5, b_res=10, w_stag=10,
                  lr=0.1, gamma=0.9, w=(1.0, 0.1, 10.0), eps_min=1e-16, cost="C1", seed=0,
-                 replace_period=50, decision_period=1, per_op=0):
+                 replace_period=50, decision_period=1, per_op=0, nfmt=4):
         d = PolicyDesc()
         d.kind, d.fixed_action, d.t_bin, d.b_it, d.b_res, d.w_stag = kind, fixed_action, t_bin, b_it, b_res, w_stag
         d.lr, d.gamma = lr, gamma
@@ -215,6 +226,8 @@ class Policy:
         costs = COSTS[cost] if isinstance(cost, str) else cost
         for i in range(4):
             d.cost[i] = costs[i]
+        d.cost_tf32 = costs[4] if len(costs) > 4 else costs[0]
+        d.nfmt = int(nfmt)
         d.seed = seed
         d.replace_period = replace_period
         d.decision_period = decision_period
@@ -453,9 +466,9 @@ class Matrix:
         self.policy = policy
 
     def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False, spmv_rows=0, index16=0,
-                    precond=0, stop_rule=0, rho_fp64=0):
+                    precond=0, stop_rule=0, rho_fp64=0, emulate=0):
         o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, index16, int(precond),
-                      int(stop_rule), int(rho_fp64), 0)
+                      int(stop_rule), int(rho_fp64), int(emulate))
         _check(lib().mpcg_set_options(self.h, C.byref(o)), "set_options")
 
     def solve(self, b, x, tol=1e-8, maxit=1000) -> dict:
@@ -496,6 +509,11 @@ class Matrix:
     def precond_inverse(self):
         out = np.zeros(self.n, np.float32)
         _check(lib().mpcg_get_precond(self.h, _np_ptr(out)), "get_precond")
+        return out
+
+    def shadow_tf32(self):
+        out = np.zeros(self.nnz, np.float32)
+        _check(lib().mpcg_get_shadow_tf32(self.h, _np_ptr(out)), "shadow_tf32")
         return out
 
     def shadow_q52(self):

@@ -223,6 +223,8 @@ struct mpcg_policy {
     p.w3 = desc.w3;
     p.eps_min = desc.eps_min;
     for (int i = 0; i < 4; ++i) p.cost[i] = desc.cost[i];
+    p.cost[FP8] = desc.cost[MPCG_FP16];   // a q52 SpMV is charged as fp16
+    p.cost[TF32] = desc.cost_tf32;
     p.epsilon = epsilon;
     p.seed = desc.seed;
     p.episode = episode;
@@ -242,6 +244,7 @@ struct mpcg_policy {
     p.replace_period = desc.replace_period;
     p.decision_period = desc.decision_period;
     p.per_op = desc.per_op;
+    p.nfmt = desc.nfmt == 5 ? 5 : 4;
     p.roll_cap = roll_cap;
     p.roll_feat = d_rf;
     p.roll_next = d_rn;
@@ -275,6 +278,7 @@ struct mpcg_matrix {
   float *d_v32 = nullptr;
   uint16_t *d_vbf = nullptr, *d_vh = nullptr;
   uint8_t *d_v8 = nullptr;     // q52 shadow (row-scaled like fp16)
+  float *d_vtf = nullptr;      // tf32 shadow (fp32 containers)
   int8_t *d_rexp = nullptr;
   // workspace
   double *d_xhi = nullptr;
@@ -321,13 +325,14 @@ struct mpcg_matrix {
     m.vbf = d_vbf;
     m.vh = d_vh;
     m.v8 = d_v8;
+    m.vtf = d_vtf;
     m.rexp = d_rexp;
     m.minv = d_minv;
     return m;
   }
 
   void release() {
-    dfree(d_rp); dfree(d_ci); dfree(d_dc); dfree(d_pbf); dfree(d_ph); dfree(d_v64); dfree(d_v32); dfree(d_vbf); dfree(d_vh); dfree(d_v8); dfree(d_rexp);
+    dfree(d_rp); dfree(d_ci); dfree(d_dc); dfree(d_pbf); dfree(d_ph); dfree(d_v64); dfree(d_v32); dfree(d_vbf); dfree(d_vh); dfree(d_v8); dfree(d_vtf); dfree(d_rexp);
     dfree(d_xhi); dfree(d_r32); dfree(d_p32); dfree(d_q32); dfree(d_xlo32);
     dfree(d_r64); dfree(d_p64); dfree(d_q64); dfree(d_xlo64);
     dfree(d_part0); dfree(d_part1); dfree(d_part2); dfree(d_scalar); dfree(d_ctl); dfree(d_pol);
@@ -361,6 +366,8 @@ static void default_desc(mpcg_policy_desc *d) {
   d->eps_min = 1e-16;
   const double c1[4] = {0.8, 0.6, 1.0, 2.0};
   for (int i = 0; i < 4; ++i) d->cost[i] = c1[i];
+  d->cost_tf32 = 0.8;
+  d->nfmt = 4;
   d->replace_period = 50;
 }
 
@@ -569,6 +576,7 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   TRY_A(dmalloc(&A->d_vbf, np));
   TRY_A(dmalloc(&A->d_vh, np));
   TRY_A(dmalloc(&A->d_v8, np));
+  TRY_A(dmalloc(&A->d_vtf, np));
   TRY_A(dmalloc(&A->d_rexp, (size_t)n));
   TRY_A(dmalloc(&A->d_minv, (size_t)n));
   TRY_A(hipMemsetAsync(A->d_ci, 0, sizeof(int) * np, A->stream));
@@ -577,12 +585,13 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
   TRY_A(hipMemsetAsync(A->d_vbf, 0, sizeof(uint16_t) * np, A->stream));
   TRY_A(hipMemsetAsync(A->d_vh, 0, sizeof(uint16_t) * np, A->stream));
   TRY_A(hipMemsetAsync(A->d_v8, 0, np, A->stream));
+  TRY_A(hipMemsetAsync(A->d_vtf, 0, sizeof(float) * np, A->stream));
   const hipMemcpyKind kind = mem_kind == MPCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   TRY_A(hipMemcpyAsync(A->d_rp, row_ptr, sizeof(int32_t) * (n + 1), kind, A->stream));
   TRY_A(hipMemcpyAsync(A->d_ci, col, sizeof(int32_t) * nnz, kind, A->stream));
   TRY_A(hipMemcpyAsync(A->d_v64, val, sizeof(double) * nnz, kind, A->stream));
-  launch_shadows(A->n, A->d_rp, A->d_ci, A->d_v64, A->d_v32, A->d_vbf, A->d_vh, A->d_v8, A->d_rexp, A->d_minv,
-                 A->stream);
+  launch_shadows(A->n, A->d_rp, A->d_ci, A->d_v64, A->d_v32, A->d_vbf, A->d_vh, A->d_v8, A->d_vtf, A->d_rexp,
+                 A->d_minv, A->stream);
   TRY_A(hipGetLastError());
   TRY_A(dmalloc(&A->d_part0, (size_t)A->P2 + 64));
   TRY_A(dmalloc(&A->d_part1, (size_t)(A->n + kKaRows - 1) / kKaRows + 64));
@@ -661,6 +670,35 @@ int mpcg_get_shadow_q52(mpcg_matrix *A, uint8_t *q52) {
   return MPCG_OK;
 }
 
+int mpcg_action(int f_spmv, int f_dot, int f_axpy) {
+  auto dig = [](int f) { return f == MPCG_TF32 ? 4 : (f >= 0 && f <= 3 ? f : -1); };
+  const int dd = dig(f_dot), da = dig(f_axpy);
+  if (dd < 0 || da < 0) return fail(MPCG_ERR_INVALID, "f_dot and f_axpy must be fp16, bf16, fp32, fp64 or tf32");
+  if (f_spmv == MPCG_Q52) {
+    if (dd == 4 || da == 4) return fail(MPCG_ERR_INVALID, "a q52 SpMV takes the four arithmetic formats");
+    return 64 + 4 * dd + da;
+  }
+  const int ds = dig(f_spmv);
+  if (ds < 0) return fail(MPCG_ERR_INVALID, "bad f_spmv");
+  return act_compose(ds, dd, da);
+}
+
+int mpcg_action_formats(int action, int32_t *f_spmv, int32_t *f_dot, int32_t *f_axpy) {
+  if (!f_spmv || !f_dot || !f_axpy) return fail(MPCG_ERR_INVALID, "NULL argument");
+  if (!act_valid(action)) return fail(MPCG_ERR_INVALID, "bad action code");
+  *f_spmv = act_fs(action);
+  *f_dot = act_fd(action);
+  *f_axpy = act_fa(action);
+  return MPCG_OK;
+}
+
+int mpcg_get_shadow_tf32(mpcg_matrix *A, float *tf32) {
+  if (!A || !tf32) return fail(MPCG_ERR_INVALID, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  HIP_TRY(hipMemcpy(tf32, A->d_vtf, sizeof(float) * (size_t)A->nnz, hipMemcpyDeviceToHost));
+  return MPCG_OK;
+}
+
 int mpcg_get_shadows(mpcg_matrix *A, float *f32, uint16_t *bf16, uint16_t *f16, int8_t *rexp) {
   if (!A) return fail(MPCG_ERR_INVALID, "A is NULL");
   HIP_TRY(hipStreamSynchronize(A->stream));
@@ -676,7 +714,12 @@ int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out) {
   if (!desc || !out) return fail(MPCG_ERR_INVALID, "NULL argument");
   *out = nullptr;
   if (desc->kind < 0 || desc->kind > 3) return fail(MPCG_ERR_INVALID, "bad policy kind");
-  if (desc->fixed_action < 0 || desc->fixed_action > 79) return fail(MPCG_ERR_INVALID, "bad fixed_action");
+  if (!act_valid(desc->fixed_action)) return fail(MPCG_ERR_INVALID, "bad fixed_action (0..79 or 128..252)");
+  if (desc->nfmt != 0 && desc->nfmt != 4 && desc->nfmt != 5) return fail(MPCG_ERR_INVALID, "nfmt must be 4 or 5");
+  if (desc->nfmt == 5 && desc->per_op == 0 &&
+      (desc->kind == MPCG_POLICY_QTABLE || desc->kind == MPCG_POLICY_QTABLE_TRAIN))
+    return fail(MPCG_ERR_INVALID, "tf32 in the format set (nfmt 5) needs one table per operation (per_op 1 or 2)");
+  if (!(desc->cost_tf32 >= 0.0) || !std::isfinite(desc->cost_tf32)) return fail(MPCG_ERR_INVALID, "bad cost_tf32");
   if (desc->b_it < 1 || desc->b_res < 1 || desc->b_res > kMaxEdges + 1 || desc->t_bin < 1 || desc->w_stag < 1)
     return fail(MPCG_ERR_INVALID, "bad bin parameters");
   if (desc->decision_period < 0) return fail(MPCG_ERR_INVALID, "negative decision_period");
@@ -717,9 +760,10 @@ int mpcg_policy_set_qtable(mpcg_policy *P, const double *q) {
   P->qbest.resize((size_t)P->n_states);
   for (int s = 0; s < P->n_states; ++s) {
     const double *row = q + (size_t)s * kNAct;
+    const int S = P->desc.nfmt == 5 ? 5 : 4;
     const int best = P->desc.per_op
-                         ? 16 * first_max(row, 4) + 4 * first_max(row + 4, 4) +
-                               (P->desc.per_op == 2 ? MPCG_FP64 : first_max(row + 8, 4))
+                         ? act_compose(first_max(row, S), first_max(row + S, S),
+                                       P->desc.per_op == 2 ? MPCG_FP64 : first_max(row + 2 * S, S))
                          : first_max(row, kNAct);
     P->qbest[s] = (uint8_t)best;
   }
@@ -861,7 +905,7 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
   if (o->precond != 0 && o->precond != 1) return fail(MPCG_ERR_INVALID, "precond must be 0 or 1");
   if (o->stop_rule != 0 && o->stop_rule != 1) return fail(MPCG_ERR_INVALID, "stop_rule must be 0 or 1");
   if (o->rho_fp64 != 0 && o->rho_fp64 != 1) return fail(MPCG_ERR_INVALID, "rho_fp64 must be 0 or 1");
-  if (o->reserved != 0) return fail(MPCG_ERR_INVALID, "reserved must be 0");
+  if (o->emulate != 0 && o->emulate != 1) return fail(MPCG_ERR_INVALID, "emulate must be 0 or 1");
   A->opts = *o;
   return MPCG_OK;
 }
@@ -886,6 +930,7 @@ static int upload_start(mpcg_matrix *A, mpcg_policy *P, double tol, int32_t maxi
   c.precond = A->opts.precond;
   c.stop_rule = A->opts.stop_rule;
   c.rho64 = A->opts.rho_fp64;
+  c.emul = A->opts.emulate;
   c.tol = tol;
   HIP_TRY(hipMemcpyAsync(A->d_ctl, A->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   return MPCG_OK;
@@ -911,6 +956,8 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   if (rc) return rc;
   mpcg_policy *P = A->pol ? A->pol : A->defpol;
   if (P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
+  if (A->opts.emulate && P->desc.kind == MPCG_POLICY_FIXED && act_fs(P->desc.fixed_action) == FP8)
+    return fail(MPCG_ERR_INVALID, "the emulation reading has no q52 SpMV (Table 1's q52 is storage only here)");
   hipStream_t st = A->stream;
   HIP_TRY(hipStreamSynchronize(st));   // staging buffers below are reused
 
@@ -1343,10 +1390,13 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
     if (maxit[i] < 0 || maxit[i] > (1 << 29)) return fail(MPCG_ERR_INVALID, "maxit out of range");
     if (A[i]->opts.precond) return fail(MPCG_ERR_INVALID, "batched solves are not preconditioned (precond = 0)");
     if (A[i]->opts.rho_fp64) return fail(MPCG_ERR_INVALID, "batched solves take rho at the dot format (rho_fp64 = 0)");
+    if (A[i]->opts.emulate) return fail(MPCG_ERR_INVALID, "batched solves run the hardware reading (emulate = 0)");
     mpcg_policy *P = A[i]->pol ? A[i]->pol : A[i]->defpol;
     if (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->roll_cap > 0)
       return fail(MPCG_ERR_INVALID, "training policies and rollout logs are not batched (shared state)");
     if (P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
+    if (P->desc.fixed_action >= 128 || P->desc.nfmt == 5)
+      return fail(MPCG_ERR_INVALID, "batched solves take the four arithmetic formats and q52 (no tf32)");
     pols[i] = P;
     int rc = ensure_ws(A[i]);
     if (rc) return rc;
@@ -1753,7 +1803,7 @@ int mpcg_get_history(mpcg_matrix *A, double *rho, uint8_t *act, uint8_t *flags, 
 
 // ---------------------------------------------------------------- single ops
 int mpcg_op_spmv(mpcg_matrix *A, int fmt, int tier64, const void *p, void *q) {
-  if (!A || !p || !q || fmt < 0 || fmt > 4 || (tier64 != 0 && tier64 != 1))
+  if (!A || !p || !q || fmt < 0 || fmt > 5 || (tier64 != 0 && tier64 != 1))
     return fail(MPCG_ERR_INVALID, "bad argument");
   launch_op_spmv(A->mat(), fmt, tier64, p, q, A->stream);
   HIP_TRY(hipGetLastError());
@@ -1770,7 +1820,7 @@ int mpcg_op_residual(mpcg_matrix *A, const double *b, const double *x, double *r
 }
 
 int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out) {
-  if (!A || !u || !v || !out || fmt < 0 || fmt > 3 || (tier64 != 0 && tier64 != 1))
+  if (!A || !u || !v || !out || fmt < 0 || fmt > 5 || fmt == MPCG_Q52 || (tier64 != 0 && tier64 != 1))
     return fail(MPCG_ERR_INVALID, "bad argument");
   launch_op_dot(A->n, fmt, tier64, u, v, A->d_part2, A->P2, A->d_scalar, A->stream);
   HIP_TRY(hipGetLastError());
@@ -1780,7 +1830,7 @@ int mpcg_op_dot(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *
 }
 
 int mpcg_op_dot_noalloc(mpcg_matrix *A, int fmt, int tier64, const void *u, const void *v, double *out) {
-  if (!A || !u || !v || !out || fmt < 0 || fmt > 3 || (tier64 != 0 && tier64 != 1))
+  if (!A || !u || !v || !out || fmt < 0 || fmt > 5 || fmt == MPCG_Q52 || (tier64 != 0 && tier64 != 1))
     return fail(MPCG_ERR_INVALID, "bad argument");
   if ((int64_t)(A->n + kVecBlock - 1) / kVecBlock > kNoAllocPartials)
     return fail(MPCG_ERR_INVALID, "n exceeds the allocation-free dot's limit of " +
@@ -1810,7 +1860,7 @@ int mpcg_gather_floor(mpcg_matrix *A, const float *p, int32_t repeats, double *u
 }
 
 int mpcg_op_axpy(mpcg_matrix *A, int fmt, double alpha, const void *u, void *y) {
-  if (!A || !u || !y || fmt < 0 || fmt > 3) return fail(MPCG_ERR_INVALID, "bad argument");
+  if (!A || !u || !y || fmt < 0 || fmt > 5 || fmt == MPCG_Q52) return fail(MPCG_ERR_INVALID, "bad argument");
   launch_op_axpy(A->n, fmt, alpha, u, y, A->stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(A->stream));

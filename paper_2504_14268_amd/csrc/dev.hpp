@@ -10,8 +10,25 @@
 namespace mpcg {
 
 // Formats.  FP8 is Table 1's quarter precision q52 (5 exponent bits, 2
-// fraction bits: the top byte of an fp16), used only as matrix storage.
-enum { FP16 = 0, BF16 = 1, FP32 = 2, FP64 = 3, FP8 = 4 };
+// fraction bits: the top byte of an fp16), used only as matrix storage.  TF32
+// (section 5's format set) has fp32's exponent range and fp16's 11-bit
+// significand; gfx950 has no tf32 arithmetic or storage, so its values are
+// rounded to it and held in fp32 containers.
+enum { FP16 = 0, BF16 = 1, FP32 = 2, FP64 = 3, FP8 = 4, TF32 = 5 };
+
+// Actions.  0..63: 16 f_s + 4 f_d + f_a over {fp16, bf16, fp32, fp64};
+// 64..79: a q52 SpMV with 4 f_d + f_a; 128..252: 128 + 25 d_s + 5 d_d + d_a
+// over the digits {0: fp16, 1: bf16, 2: fp32, 3: fp64, 4: tf32} (an action
+// without a tf32 digit keeps its 0..63 code).
+__host__ __device__ inline int act_dig_fmt(int d) { return d == 4 ? TF32 : d; }
+__host__ __device__ inline int act_fmt_dig(int f) { return f == TF32 ? 4 : f; }
+__host__ __device__ inline int act_fs(int a) { return a < 64 ? (a >> 4) & 3 : a < 80 ? FP8 : act_dig_fmt((a - 128) / 25); }
+__host__ __device__ inline int act_fd(int a) { return a < 80 ? (a >> 2) & 3 : act_dig_fmt(((a - 128) / 5) % 5); }
+__host__ __device__ inline int act_fa(int a) { return a < 80 ? a & 3 : act_dig_fmt((a - 128) % 5); }
+__host__ __device__ inline int act_compose(int ds, int dd, int da) {
+  return (ds == 4 || dd == 4 || da == 4) ? 128 + 25 * ds + 5 * dd + da : 16 * ds + 4 * dd + da;
+}
+__host__ __device__ inline bool act_valid(int a) { return (a >= 0 && a < 80) || (a >= 128 && a <= 252); }
 
 constexpr int kBlock = 256;          // threads per block, every kernel
 constexpr int kWaves = kBlock / 64;  // 64-wide wavefronts
@@ -79,10 +96,21 @@ __device__ __forceinline__ float rd_bf16_from_f32(float x) {
   return __uint_as_float(u & 0xffff0000u);
 }
 
+// fp32 source, tf32 target: fp32's exponent range with 11 significant bits,
+// so RNE is a carry into bit 13 (subnormals included, overflow carries into
+// the infinity pattern); inf/nan passed through.
+__device__ __forceinline__ float rd_tf32_from_f32(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return x;
+  u += 0xfffu + ((u >> 13) & 1u);
+  return __uint_as_float(u & 0xffffe000u);
+}
+
 template <int F>
 __device__ __forceinline__ float rd_from_f32(float x) {
   if constexpr (F == FP16) return rd_f16_from_f32(x);
   else if constexpr (F == BF16) return rd_bf16_from_f32(x);
+  else if constexpr (F == TF32) return rd_tf32_from_f32(x);
   else return x;
 }
 
@@ -90,7 +118,25 @@ template <int F>
 __device__ __forceinline__ float rd_from_f64_to_f32(double x) {
   if constexpr (F == FP16) return (float)round_narrow_f64<11, -14, 15>(x);
   else if constexpr (F == BF16) return (float)round_narrow_f64<8, -126, 127>(x);
+  else if constexpr (F == TF32) return (float)round_narrow_f64<11, -126, 127>(x);
   else return (float)x;   // v_cvt_f32_f64: RNE
+}
+
+// Runtime-format rounding of an fp64 value to format f, as a double (the
+// paper's emulation reading rounds each operation's fp64 result).
+__device__ __forceinline__ double rd_rt_f64(int f, double x) {
+  switch (f) {
+  case FP16: return round_narrow_f64<11, -14, 15>(x);
+  case BF16: return round_narrow_f64<8, -126, 127>(x);
+  case FP32: return (double)(float)x;
+  case TF32: return round_narrow_f64<11, -126, 127>(x);
+  default: return x;
+  }
+}
+
+// Runtime-format rounding of an fp32 value (fp32 and fp64 formats: unchanged).
+__device__ __forceinline__ float rd_rt_f32(int f, float t) {
+  return f == FP16 ? rd_f16_from_f32(t) : f == BF16 ? rd_bf16_from_f32(t) : f == TF32 ? rd_tf32_from_f32(t) : t;
 }
 
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }

@@ -79,6 +79,8 @@ __device__ __forceinline__ void load_vals8(const Mat &A, int c, typename AccT<FS
     load8(A.v64 + c, v);
   } else if constexpr (FS == FP32) {
     load8(A.v32 + c, v);
+  } else if constexpr (FS == TF32) {
+    load8(A.vtf + c, v);
   } else if constexpr (FS == FP8) {
     const uint2 w = *(const uint2 *)(A.v8 + c);
 #pragma unroll
@@ -193,11 +195,7 @@ __device__ __forceinline__ Vo xpay_rt(int fa, double beta, Vo p, Vo r) {
     return __builtin_fma(beta, p, r);
   } else {
     const float t = __builtin_fmaf((float)beta, p, r);
-    switch (fa) {
-    case FP16: return rd_f16_from_f32(t);
-    case BF16: return rd_bf16_from_f32(t);
-    default: return t;
-    }
+    return rd_rt_f32(fa, t);
   }
 }
 
@@ -207,10 +205,7 @@ template <int FA>
 __device__ __forceinline__ float precond_z(float m, float r) { return rd_from_f32<FA>(m * r); }
 template <int FA>
 __device__ __forceinline__ double precond_z(float m, double r) { return (double)m * r; }
-__device__ __forceinline__ float precond_z_rt(int fa, float m, float r) {
-  const float t = m * r;
-  return fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
-}
+__device__ __forceinline__ float precond_z_rt(int fa, float m, float r) { return rd_rt_f32(fa, m * r); }
 __device__ __forceinline__ double precond_z_rt(int, float m, double r) { return (double)m * r; }
 
 // Sums of RPT 256-row subtrees at once (one LDS round): each thread holds one
@@ -265,6 +260,7 @@ __device__ __forceinline__ void dot_leaf_multi_rt(int fd, const V (&u)[RPT], con
   case FP16: dot_leaf_multi<FP16, RPT>(u, v, valid, out); break;
   case BF16: dot_leaf_multi<BF16, RPT>(u, v, valid, out); break;
   case FP32: dot_leaf_multi<FP32, RPT>(u, v, valid, out); break;
+  case TF32: dot_leaf_multi<TF32, RPT>(u, v, valid, out); break;
   default: dot_leaf_multi<FP64, RPT>(u, v, valid, out); break;
   }
 }
@@ -275,6 +271,7 @@ __device__ __forceinline__ double dot_leaf_block_rt(int fd, V u, V v, bool valid
   case FP16: return dot_leaf_block<FP16>(u, v, valid);
   case BF16: return dot_leaf_block<BF16>(u, v, valid);
   case FP32: return dot_leaf_block<FP32>(u, v, valid);
+  case TF32: return dot_leaf_block<TF32>(u, v, valid);
   default: return dot_leaf_block<FP64>(u, v, valid);
   }
 }
@@ -350,7 +347,7 @@ __device__ int q_argmax(const double *row) {
 }
 
 __device__ double policy_cost(const PolicyDev *P, int a) {
-  return (P->cost[(a >> 4) & 3] + P->cost[(a >> 2) & 3]) + P->cost[a & 3];
+  return (P->cost[act_fs(a)] + P->cost[act_fd(a)]) + P->cost[act_fa(a)];
 }
 
 // Reward of a decision whose action ran n_it iterations (n_it = 1: the
@@ -363,18 +360,22 @@ __device__ double policy_reward(const PolicyDev *P, int a, double rho, bool conv
 }
 
 // One Q-table per operation (section 4.1: Q_j over states x precisions for
-// j = SpMV, dot, update) lives in the same table row: Q_j(s, p) = q[s][4 j + p].
-__device__ __forceinline__ int argmax4(const double *t) {
+// j = SpMV, dot, update) lives in the same table row: Q_j(s, d) = q[s][S j + d]
+// with S = nfmt formats per table and d the format digit (4: tf32).
+__device__ __forceinline__ int n_fmt(const PolicyDev *P) { return P->nfmt == 5 ? 5 : 4; }
+
+__device__ __forceinline__ int argmax_n(const double *t, int S) {
   int best = 0;
   double bv = t[0];
-  for (int p = 1; p < 4; ++p)
+  for (int p = 1; p < S; ++p)
     if (t[p] > bv) { best = p; bv = t[p]; }
   return best;
 }
 
 __device__ __forceinline__ int q_greedy_row(const PolicyDev *P, const double *row) {
   if (!P->per_op) return q_argmax(row);
-  return 16 * argmax4(row) + 4 * argmax4(row + 4) + (P->per_op == 2 ? FP64 : argmax4(row + 8));
+  const int S = n_fmt(P);
+  return act_compose(argmax_n(row, S), argmax_n(row + S, S), P->per_op == 2 ? FP64 : argmax_n(row + 2 * S, S));
 }
 
 // Q update of decision (s, a) toward reward R, bootstrapped from s_next
@@ -390,14 +391,15 @@ __device__ void q_learn(const PolicyDev *P, int s, int a, double R, int s_next) 
     *q = *q + P->lr * (t - *q);
     return;
   }
+  const int S = n_fmt(P);
+  const int dj[3] = {act_fmt_dig(act_fs(a)), act_fmt_dig(act_fd(a)), act_fmt_dig(act_fa(a))};
   for (int j = 0; j < (P->per_op == 2 ? 2 : 3); ++j) {
-    const int pj = (a >> (4 - 2 * j)) & 3;
     double t = R;
     if (s_next >= 0) {
-      const double *nx = &P->q[s_next * kNAct + 4 * j];
-      t = R + P->gamma * nx[argmax4(nx)];
+      const double *nx = &P->q[s_next * kNAct + S * j];
+      t = R + P->gamma * nx[argmax_n(nx, S)];
     }
-    double *q = &P->q[s * kNAct + 4 * j + pj];
+    double *q = &P->q[s * kNAct + S * j + dj[j]];
     *q = *q + P->lr * (t - *q);
   }
 }
@@ -473,24 +475,23 @@ __device__ int decide_scalar(const PolicyDev *P, int s, int k, int *explored) {
   case POL_QTRAIN: {
     if (P->per_op) {   // an epsilon-greedy draw per operation, streams 2 .. 7
       const double *row = &P->q[s * kNAct];
-      int a = 0;
+      const int S = n_fmt(P);
+      int d[3];
       for (int j = 0; j < 3; ++j) {
-        int pj;
         if (j == 2 && P->per_op == 2) {   // updates fixed in fp64
-          a = a * 4 + FP64;
+          d[j] = FP64;
           break;
         }
         const double u0 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, (uint64_t)(2 + 2 * j));
         if (u0 < P->epsilon) {
           const double u1 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, (uint64_t)(3 + 2 * j));
-          pj = (int)(u1 * 4.0);
+          d[j] = (int)(u1 * (double)S);
           *explored = 1;
         } else {
-          pj = argmax4(row + 4 * j);
+          d[j] = argmax_n(row + S * j, S);
         }
-        a = a * 4 + pj;
       }
-      return a;
+      return act_compose(d[0], d[1], d[2]);
     }
     const double u0 = counter_uniform(P->seed, (uint64_t)P->episode, (uint64_t)k, 0);
     if (u0 < P->epsilon) {
@@ -645,7 +646,7 @@ __device__ __forceinline__ void apply_decision(const Sx &a, int na, int ex, bool
     set_done(c);
     return;
   }
-  const int nt = ((na & 3) == FP64) ? 1 : 0;
+  const int nt = (c->emul || act_fa(na) == FP64) ? 1 : 0;
   if (from_init) {
     c->k3op = K3_COPY;
     c->k3switch = 0;
@@ -793,7 +794,7 @@ __device__ __forceinline__ int finish_t0(const Sx &a, bool completed, bool broke
   c->beta = beta;
   c->sigma = c->sig_new;
   c->prev_action = act;
-  c->k3_fa = act & 3;
+  c->k3_fa = act_fa(act);
   if (!dec_end) {                 // the action holds until the decision ends
     apply_decision<FULL>(a, act, 0, false);
     return 0;
@@ -896,13 +897,18 @@ template <bool FULL>
 __device__ __forceinline__ void step_x(const Sx &x, const KArgs &a, const double (&pre)[8], bool have_pre) {
   Ctl *c = x.ctl;
   if (c->mode == M_DONE || !c->pend_sigma) return;
-  const int fd = (c->action >> 2) & 3;
+  const int fd = act_fd(c->action);
   // r.r gives rho: at the dot format, or in fp64 (rho64)
-  const int fr = c->rho64 ? FP64 : fd;
-  const double sig = have_pre ? tree_preloaded_rt(fr, pre) : reduce_partials_rt(fr, a.part2, a.P2);
+  const int fr = (c->rho64 || c->emul) ? FP64 : fd;
+  double sig = have_pre ? tree_preloaded_rt(fr, pre) : reduce_partials_rt(fr, a.part2, a.P2);
   // sigma' in the second partials: r.z with a preconditioner, r.r at the dot
   // format when rho is taken in fp64
-  const double sigz = (c->precond || c->rho64) ? reduce_partials_rt(fd, a.part2b, a.P2) : sig;
+  double sigz = (c->precond || c->rho64) ? reduce_partials_rt(c->emul ? FP64 : fd, a.part2b, a.P2) : sig;
+  if (c->emul) {   // emulation: fp64 totals rounded to the dot format (rho64: rho unrounded)
+    if (c->precond || c->rho64) sigz = rd_rt_f64(fd, sigz);
+    if (!c->rho64) sig = rd_rt_f64(fd, sig);
+    if (!c->precond && !c->rho64) sigz = sig;
+  }
   __shared__ int s_fin;
   if (threadIdx.x == 0) {
     c->pend_sigma = 0;
@@ -944,8 +950,11 @@ __device__ __forceinline__ void step_b(const Sx &x, const KArgs &a, const double
   Ctl *c = x.ctl;
   const int la = c->mode;   // what KA has just executed
   if (la == M_ITER) {
-    const int fd = (c->action >> 2) & 3;
-    const double nu = have_pre ? tree_preloaded_rt(fd, pre) : reduce_partials_rt(fd, a.part1, a.P1);
+    const int fd = act_fd(c->action);
+    // emulation: the fp64 total rounded to the dot format
+    const int fn = c->emul ? FP64 : fd;
+    double nu = have_pre ? tree_preloaded_rt(fn, pre) : reduce_partials_rt(fn, a.part1, a.P1);
+    if (c->emul) nu = rd_rt_f64(fd, nu);
     const double alpha = c->sigma / nu;
     if (!(nu > 0.0 && isfinite(nu)) || !isfinite(alpha)) {
       finish_block<FULL>(x, false, true, false, false);
@@ -1054,13 +1063,14 @@ template <int FS>
 __device__ __forceinline__ void raw_load(const Mat &A, int c, RawVals<FS> &r) {
   if constexpr (FS == FP64) load8(A.v64 + c, r.v);
   else if constexpr (FS == FP32) load8(A.v32 + c, r.v);
+  else if constexpr (FS == TF32) load8(A.vtf + c, r.v);
   else if constexpr (FS == FP8) r.w = *(const uint2 *)(A.v8 + c);
   else r.w = *(const uint4 *)((FS == BF16 ? A.vbf : A.vh) + c);
 }
 
 template <int FS>
 __device__ __forceinline__ void raw_to_lds(const RawVals<FS> &r, typename LdsWin<FS>::type *p) {
-  if constexpr (FS == FP64 || FS == FP32) lds_store8(p, r.v);
+  if constexpr (FS == FP64 || FS == FP32 || FS == TF32) lds_store8(p, r.v);
   else if constexpr (FS == FP8) *(uint2 *)p = r.w;
   else *(uint4 *)p = r.w;
 }
@@ -1332,14 +1342,18 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
   }
 }
 
-template <int FS, int TIER>
+// EMUL: the paper's emulation reading, an fp64 SpMV whose q_i are rounded to
+// the action's SpMV format, and the nu partials in fp64.
+template <int FS, int TIER, bool EMUL = false>
 __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, void *lds) {
   using V = typename TierT<TIER>::type;
   using Acc = typename AccT<FS>::type;
+  static_assert(!EMUL || (FS == FP64 && TIER == 1), "emulation runs the fp64 path");
   const V *p;
   V *q;
   if constexpr (TIER) { p = a.v.p64; q = a.v.q64; } else { p = a.v.p32; q = a.v.q32; }
-  const int fd = (S.action >> 2) & 3;
+  const int fd = EMUL ? FP64 : act_fd(S.action);
+  const int fs_round = act_fs(S.action);
   const int n = a.A.n;
   const int g0 = g * a.grows;
   const int grows = min(a.grows, n - g0);
@@ -1375,6 +1389,7 @@ __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, voi
       if (valid[j]) {
         if constexpr (FS == FP16 || FS == FP8) qi[j] = (V)ldexp((double)acc[j], (int)ex[j]);
         else qi[j] = (V)acc[j];
+        if constexpr (EMUL) qi[j] = rd_rt_f64(fs_round, qi[j]);
         q[g0 + lr] = qi[j];
       }
     }
@@ -1472,9 +1487,13 @@ __device__ __forceinline__ void ka_body(const KArgs &a, int g, double *lds) {
   const Ctl &S = a.ctl[0];
   const int mode = S.mode;
   if (a.slot_log && g == 0 && threadIdx.x == 0) a.slot_log[a.slot] = (int8_t)mode;
-  if (mode == M_ITER) {
-    const int fs = (S.action >> 4) & 7;   // 4: q52 storage (actions 64..79)
+  if (mode == M_ITER && S.emul) {
+    ka_iter<FP64, 1, true>(a, S, g, lds);
+  } else if (mode == M_ITER) {
+    const int fs = act_fs(S.action);   // 4: q52 storage, 5: tf32
     switch (fs * 2 + S.tier) {
+    case 10: ka_iter<TF32, 0>(a, S, g, lds); break;
+    case 11: ka_iter<TF32, 1>(a, S, g, lds); break;
     case 8: ka_iter<FP8, 0>(a, S, g, lds); break;
     case 9: ka_iter<FP8, 1>(a, S, g, lds); break;
     case 0: ka_iter<FP16, 0>(a, S, g, lds); break;
@@ -1541,8 +1560,20 @@ __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool 
   for (int j = 0; j < 8; ++j) {
     xv[j] = axpy1<FA>(alpha, pv[j], xv[j]);
     rv[j] = axpy1<FA>(-alpha, qv[j], rv[j]);
+    if constexpr (FA == FP64) {
+      if (S.emul) {   // emulation: each fp64 update rounded to the update format
+        xv[j] = rd_rt_f64(act_fa(S.action), xv[j]);
+        rv[j] = rd_rt_f64(act_fa(S.action), rv[j]);
+      }
+    }
     l[j] = (full || base + j < n) ? dot_leaf<FR>(rv[j], rv[j]) : (AccR)0;
-    if constexpr (PC) lz[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], precond_z<FA>(mv[j], rv[j])) : (Acc)0;
+    if constexpr (PC) {
+      V zj = precond_z<FA>(mv[j], rv[j]);
+      if constexpr (FA == FP64) {
+        if (S.emul) zj = rd_rt_f64(act_fa(S.action), zj);
+      }
+      lz[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], zj) : (Acc)0;
+    }
     else if constexpr (R64) lz[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], rv[j]) : (Acc)0;
   }
   if (fold_now) {
@@ -1610,12 +1641,14 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
       if (i >= n) break;
       const double r = a.v.r64[i];
       if (S.tier) {
-        a.v.p64[i] = PC ? precond_z_rt(FP64, a.A.minv[i], r) : r;
+        a.v.p64[i] = PC ? (S.emul ? rd_rt_f64(act_fa(S.action), precond_z_rt(FP64, a.A.minv[i], r))
+                                  : precond_z_rt(FP64, a.A.minv[i], r))
+                        : r;
         a.v.xlo64[i] = 0.0;
       } else {
         const float f = (float)r;
         a.v.r32[i] = f;
-        a.v.p32[i] = PC ? precond_z_rt(S.action & 3, a.A.minv[i], f) : f;
+        a.v.p32[i] = PC ? precond_z_rt(act_fa(S.action), a.A.minv[i], f) : f;
         a.v.xlo32[i] = 0.0f;
       }
     }
@@ -1629,11 +1662,13 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if constexpr (PC) {
-          const double z = precond_z_rt(FP64, mv[j], rv[j]);
+          double z = precond_z_rt(FP64, mv[j], rv[j]);
+          if (S.emul) z = rd_rt_f64(S.k3_fa, z);
           pv[j] = S.dir_restart ? z : xpay_rt<double>(S.k3_fa, S.beta, pv[j], z);
         } else {
           pv[j] = xpay_rt<double>(S.k3_fa, S.beta, pv[j], rv[j]);
         }
+        if (S.emul && !(PC && S.dir_restart)) pv[j] = rd_rt_f64(S.k3_fa, pv[j]);
       }
       store8(a.v.p64 + base, pv);
     } else {
@@ -1647,10 +1682,10 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
         if constexpr (PC) {
           const float z = precond_z_rt(fa, mv[j], rv[j]);
           const float t = __builtin_fmaf(bf, pv[j], z);
-          pv[j] = S.dir_restart ? z : (fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t);
+          pv[j] = S.dir_restart ? z : rd_rt_f32(fa, t);
         } else {
           const float t = __builtin_fmaf(bf, pv[j], rv[j]);
-          pv[j] = fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
+          pv[j] = rd_rt_f32(fa, t);
         }
       }
       store8(a.v.p32 + base, pv);
@@ -1663,11 +1698,13 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
       if (told) {
         double pn;
         if constexpr (PC) {
-          const double z = precond_z_rt(FP64, a.A.minv[i], a.v.r64[i]);
+          double z = precond_z_rt(FP64, a.A.minv[i], a.v.r64[i]);
+          if (S.emul) z = rd_rt_f64(S.k3_fa, z);
           pn = S.dir_restart ? z : xpay_rt<double>(S.k3_fa, S.beta, a.v.p64[i], z);
         } else {
           pn = xpay_rt<double>(S.k3_fa, S.beta, a.v.p64[i], a.v.r64[i]);
         }
+        if (S.emul && !(PC && S.dir_restart)) pn = rd_rt_f64(S.k3_fa, pn);
         if (S.k3switch) {
           fold1(a.v.xhi, i, a.v.xlo64[i]);
           a.v.p32[i] = (float)pn;
@@ -1698,20 +1735,23 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
 }
 
 #define MPCG_KB_CASE(FA, FD) \
-  case (FA) * 4 + (FD): kb_axpy<FA, FD, PC, R64>(a, S, fold_now, blk); break;
+  case (FA) * 8 + (FD): kb_axpy<FA, FD, PC, R64>(a, S, fold_now, blk); break;
 #define MPCG_KB_VALS(FA, FD) \
-  case (FA) * 4 + (FD): kb_axpy_vals<FA, FD, PC, R64>(a, S, fold_now, blk, pv, qv, rv, xv); break;
+  case (FA) * 8 + (FD): kb_axpy_vals<FA, FD, PC, R64>(a, S, fold_now, blk, pv, qv, rv, xv); break;
 
 // KB's vector work for 2048-element block blk.
 template <bool PC = false, bool R64 = false>
 __device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, bool fold_now, int blk) {
   if (bop == B_AXPY) {
     const int act = S.action;
-    switch ((act & 3) * 4 + ((act >> 2) & 3)) {
+    switch (S.emul ? FP64 * 8 + FP64 : act_fa(act) * 8 + act_fd(act)) {
       MPCG_KB_CASE(FP16, FP16) MPCG_KB_CASE(FP16, BF16) MPCG_KB_CASE(FP16, FP32) MPCG_KB_CASE(FP16, FP64)
       MPCG_KB_CASE(BF16, FP16) MPCG_KB_CASE(BF16, BF16) MPCG_KB_CASE(BF16, FP32) MPCG_KB_CASE(BF16, FP64)
       MPCG_KB_CASE(FP32, FP16) MPCG_KB_CASE(FP32, BF16) MPCG_KB_CASE(FP32, FP32) MPCG_KB_CASE(FP32, FP64)
       MPCG_KB_CASE(FP64, FP16) MPCG_KB_CASE(FP64, BF16) MPCG_KB_CASE(FP64, FP32) MPCG_KB_CASE(FP64, FP64)
+      MPCG_KB_CASE(FP16, TF32) MPCG_KB_CASE(BF16, TF32) MPCG_KB_CASE(FP32, TF32) MPCG_KB_CASE(FP64, TF32)
+      MPCG_KB_CASE(TF32, FP16) MPCG_KB_CASE(TF32, BF16) MPCG_KB_CASE(TF32, FP32) MPCG_KB_CASE(TF32, FP64)
+      MPCG_KB_CASE(TF32, TF32)
     default: break;
     }
   } else if (bop == B_EXEC) {
@@ -1746,7 +1786,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   const Sx x{&S, &SP, a.h, blk == 0};
   const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   const bool blk_full = (blk + 1) * kVecBlock <= a.A.n;   // block-uniform
-  if (!S.step_done && S.mode == M_ITER && (S.action & 3) != FP64 && blk_full) {
+  if (!S.step_done && S.mode == M_ITER && !S.emul && act_fa(S.action) != FP64 && blk_full) {
     // an iteration in the fp32 containers on a whole block: the four operands
     // are in flight while the alpha step runs
     float pv[8], qv[8], rv[8], xv[8];
@@ -1761,10 +1801,13 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
     const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
     if (bop == B_AXPY) {
       const int act = S.action;
-      switch ((act & 3) * 4 + ((act >> 2) & 3)) {
+      switch (act_fa(act) * 8 + act_fd(act)) {
         MPCG_KB_VALS(FP16, FP16) MPCG_KB_VALS(FP16, BF16) MPCG_KB_VALS(FP16, FP32) MPCG_KB_VALS(FP16, FP64)
         MPCG_KB_VALS(BF16, FP16) MPCG_KB_VALS(BF16, BF16) MPCG_KB_VALS(BF16, FP32) MPCG_KB_VALS(BF16, FP64)
         MPCG_KB_VALS(FP32, FP16) MPCG_KB_VALS(FP32, BF16) MPCG_KB_VALS(FP32, FP32) MPCG_KB_VALS(FP32, FP64)
+        MPCG_KB_VALS(FP16, TF32) MPCG_KB_VALS(BF16, TF32) MPCG_KB_VALS(FP32, TF32)
+        MPCG_KB_VALS(TF32, FP16) MPCG_KB_VALS(TF32, BF16) MPCG_KB_VALS(TF32, FP32) MPCG_KB_VALS(TF32, FP64)
+        MPCG_KB_VALS(TF32, TF32)
       default: break;
       }
     } else {
@@ -1817,11 +1860,13 @@ __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S,
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if constexpr (PC) {
-          const double z = precond_z<FP64>(mv[j], rv[j]);
+          double z = precond_z<FP64>(mv[j], rv[j]);
+          if (S.emul) z = rd_rt_f64(S.k3_fa, z);
           pv[j] = S.dir_restart ? z : __builtin_fma(beta, pv[j], z);
         } else {
           pv[j] = __builtin_fma(beta, pv[j], rv[j]);
         }
+        if (S.emul && !(PC && S.dir_restart)) pv[j] = rd_rt_f64(S.k3_fa, pv[j]);
       }
       store8(a.v.p64 + base, pv);
     } else {
@@ -1832,10 +1877,10 @@ __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S,
         if constexpr (PC) {
           const float z = precond_z_rt(fa, mv[j], rv[j]);
           const float t = __builtin_fmaf(bf, pv[j], z);
-          pv[j] = S.dir_restart ? z : (fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t);
+          pv[j] = S.dir_restart ? z : rd_rt_f32(fa, t);
         } else {
           const float t = __builtin_fmaf(bf, pv[j], rv[j]);
-          pv[j] = fa == FP16 ? rd_f16_from_f32(t) : fa == BF16 ? rd_bf16_from_f32(t) : t;
+          pv[j] = rd_rt_f32(fa, t);
         }
       }
       store8(a.v.p32 + base, pv);
@@ -2229,7 +2274,7 @@ void launch_dcol(int n, const int *rp, const int *ci, int16_t *dc, int *bad, hip
 // from fp64.
 __global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const int *ci, const double *v,
                                                     float *v32, uint16_t *vbf, uint16_t *vh, uint8_t *v8,
-                                                    int8_t *rexp, float *minv) {
+                                                    float *vtf, int8_t *rexp, float *minv) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int s = rp[i], t = rp[i + 1];
@@ -2262,6 +2307,7 @@ __global__ __launch_bounds__(kBlock) void k_shadows(int n, const int *rp, const 
     // q52 (t = 3, same exponent range as fp16): its value's fp16 encoding has
     // a zero low byte, and the high byte is the q52 encoding
     v8[k] = (uint8_t)(f32_to_f16_bits_exact((float)round_narrow_f64<3, -14, 15>(ldexp(x, -e))) >> 8);
+    vtf[k] = rd_from_f64_to_f32<TF32>(x);   // fp32's range: no row scale
   }
   minv[i] = mi;
 }
@@ -2422,9 +2468,9 @@ void launch_lock_modes(const BatchSys *sys, const int32_t *act, int nact, int32_
 }
 
 void launch_shadows(int n, const int *rp, const int *ci, const double *v, float *v32, uint16_t *vbf,
-                    uint16_t *vh, uint8_t *v8, int8_t *rexp, float *minv, hipStream_t s) {
+                    uint16_t *vh, uint8_t *v8, float *vtf, int8_t *rexp, float *minv, hipStream_t s) {
   hipLaunchKernelGGL(k_shadows, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, rp, ci, v, v32, vbf, vh,
-                     v8, rexp, minv);
+                     v8, vtf, rexp, minv);
 }
 
 void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipStream_t s) {
@@ -2432,6 +2478,8 @@ void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipS
   const int G = (P + 7) / 8 * 8;
 #define MPCG_SPMV(FS, T) hipLaunchKernelGGL((k_op_spmv<FS, T>), dim3(G), dim3(kBlock), 0, s, A, p, q, P, G)
   switch (fs * 2 + tier) {
+  case 10: MPCG_SPMV(TF32, 0); break;
+  case 11: MPCG_SPMV(TF32, 1); break;
   case 8: MPCG_SPMV(FP8, 0); break;
   case 9: MPCG_SPMV(FP8, 1); break;
   case 0: MPCG_SPMV(FP16, 0); break;
@@ -2456,6 +2504,8 @@ void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double
                    hipStream_t s) {
 #define MPCG_DOT(FD, T) hipLaunchKernelGGL((k_op_dot<FD, T>), dim3(P2), dim3(kBlock), 0, s, n, u, v, part)
   switch (fd * 2 + tier) {
+  case 10: MPCG_DOT(TF32, 0); break;
+  case 11: MPCG_DOT(TF32, 1); break;
   case 0: MPCG_DOT(FP16, 0); break;
   case 1: MPCG_DOT(FP16, 1); break;
   case 2: MPCG_DOT(BF16, 0); break;
@@ -2555,6 +2605,7 @@ void launch_op_axpy(int n, int fa, double alpha, const void *u, void *y, hipStre
   case FP16: hipLaunchKernelGGL((k_op_axpy<FP16>), g, dim3(kBlock), 0, s, n, alpha, u, y); break;
   case BF16: hipLaunchKernelGGL((k_op_axpy<BF16>), g, dim3(kBlock), 0, s, n, alpha, u, y); break;
   case FP32: hipLaunchKernelGGL((k_op_axpy<FP32>), g, dim3(kBlock), 0, s, n, alpha, u, y); break;
+  case TF32: hipLaunchKernelGGL((k_op_axpy<TF32>), g, dim3(kBlock), 0, s, n, alpha, u, y); break;
   default: hipLaunchKernelGGL((k_op_axpy<FP64>), g, dim3(kBlock), 0, s, n, alpha, u, y); break;
   }
 }

@@ -23,6 +23,7 @@ struct Mat {
   const float *v32;
   const uint16_t *vbf, *vh;   // bf16 bits, fp16 bits (row-scaled)
   const uint8_t *v8;          // q52 bits (row-scaled like fp16)
+  const float *vtf;           // tf32 values (fp32 containers)
   const int8_t *rexp;         // row exponents of the fp16 and q52 shadows
   const float *minv;          // Jacobi preconditioner: fp32 of 1 / a_ii (0 without a diagonal)
 };
@@ -55,14 +56,15 @@ struct PolicyDev {
   double edges[kMaxEdges];
   double *q;
   double lr, gamma, w1, w2, w3, eps_min;
-  double cost[4];
+  double cost[6];                // c(f) by format code: fp16, bf16, fp32, fp64, q52 (= fp16), tf32
   double epsilon;
   uint64_t seed;
   int64_t episode;
   const float *W1, *b1, *W2, *b2, *W3, *b3;
   int32_t replace_period;
   int32_t decision_period;       // the policy acts every decision_period iterations (<= 1: every one)
-  int32_t per_op;                // 1: one Q-table per operation, Q_j(s, p) = q[s][4 j + p]
+  int32_t per_op;                // 1: one Q-table per operation, Q_j(s, d) = q[s][nfmt j + d]
+  int32_t nfmt;                  // formats per operation table: 4, or 5 (digit 4: tf32)
   int32_t roll_cap;
   float *roll_feat, *roll_next;
   int32_t *roll_act;
@@ -95,6 +97,8 @@ struct Ctl {
                                   // k_dec: iteration of the current decision
   int32_t stop_rule, rho64;       // stop_rule 1: stop when the recursive rho < tol with k >= 10;
                                   // rho64 1: rho from an fp64 r.r, sigma' at the dot format
+  int32_t emul, pad3_;            // 1: the paper's emulation reading (fp64 operations, results
+                                  // rounded to their formats, fp64 vectors)
   double tol, bnorm, sigma, sig_new, alpha, beta, rho_new, last_true, cost_sum, relres_true;
   double rep_hist[3];
   float feat[kMlpIn];

@@ -23,7 +23,7 @@ void launch_lock_modes(const BatchSys *sys, const int32_t *act, int nact, int32_
 void launch_pack16(int np, const uint16_t *v, const int16_t *dc, uint32_t *out, hipStream_t s);
 void launch_dcol(int n, const int *rp, const int *ci, int16_t *dc, int *bad, hipStream_t s);
 void launch_shadows(int n, const int *rp, const int *ci, const double *v, float *v32, uint16_t *vbf,
-                    uint16_t *vh, uint8_t *v8, int8_t *rexp, float *minv, hipStream_t s);
+                    uint16_t *vh, uint8_t *v8, float *vtf, int8_t *rexp, float *minv, hipStream_t s);
 void launch_op_spmv(const Mat &A, int fs, int tier, const void *p, void *q, hipStream_t s);
 void launch_op_residual(const Mat &A, const double *b, const double *x, double *r, hipStream_t s);
 void launch_op_dot(int n, int fd, int tier, const void *u, const void *v, double *part, int P2, double *out,

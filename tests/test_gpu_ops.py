@@ -71,10 +71,12 @@ def test_shadows_bit_exact(M, name):
     oq, oqe = O.shadow_q52(A)
     assert np.array_equal((q8.astype(np.uint16) << 8).view(np.float16).astype(np.float64), oq)
     assert np.array_equal(oqe, oe)
+    # tf32: held in fp32 containers
+    assert np.array_equal(m.shadow_tf32().astype(np.float64), O.shadow_tf32(A))
 
 
 @pytest.mark.parametrize("name", list(MATS))
-@pytest.mark.parametrize("fs", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("fs", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("tier", [0, 1])
 def test_spmv_bit_exact(M, name, fs, tier):
     A = MATS[name]()
@@ -91,7 +93,7 @@ def test_spmv_bit_exact(M, name, fs, tier):
 
 
 @pytest.mark.parametrize("n", [1, 7, 2048, 2049, 100003, 1 << 20])
-@pytest.mark.parametrize("fd", [0, 1, 2, 3])
+@pytest.mark.parametrize("fd", [0, 1, 2, 3, 5])
 @pytest.mark.parametrize("tier", [0, 1])
 def test_dot_bit_exact(M, n, fd, tier):
     A = eye(n)                       # only the size matters here
@@ -101,6 +103,9 @@ def test_dot_bit_exact(M, n, fd, tier):
     v = rng.standard_normal(A.n)
     if fd == 0:
         u[::97] *= 3e4          # some operands overflow fp16 -> inf is part of the definition
+    if fd == 5:
+        u[::89] *= 1e30         # far beyond fp16, inside tf32's (fp32's) range
+        v[::83] *= 1e-40        # fp32 subnormals: tf32 keeps 2^-136 steps
     if tier == 0:
         u, v = u.astype(np.float32).astype(np.float64), v.astype(np.float32).astype(np.float64)
     got = m.op_dot(fd, tier, dev(u, tier), dev(v, tier))
@@ -108,7 +113,7 @@ def test_dot_bit_exact(M, n, fd, tier):
     assert got == want or (np.isnan(got) and np.isnan(want))
 
 
-@pytest.mark.parametrize("fa", [0, 1, 2, 3])
+@pytest.mark.parametrize("fa", [0, 1, 2, 3, 5])
 def test_axpy_bit_exact(M, fa):
     n = 10007
     A = eye(n)
