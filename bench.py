@@ -647,9 +647,9 @@ def main():
               flush=True)
         return
 
-    def solve(pol, R, maxit=5000, profile=False):
+    def solve(pol, R, maxit=5000, profile=False, vec16=0):
         m.set_policy(pol)
-        m.set_options(replace_period=R, fallback=False, profile=profile)
+        m.set_options(replace_period=R, fallback=False, profile=profile, vec16=vec16)
         xd.zero_()
         return m.solve(bd, xd, tol=tol, maxit=maxit)
 
@@ -681,6 +681,24 @@ def main():
     assert rq["status"] == 0 and rq["relres_true"] <= tol, rq
     q52_ms = float(np.median([r["time_ms"] for r in q52_runs]))
     log(f"[bench] q52: {rq['iters']} it, relres {rq['relres_true']:.3e}, device {q52_ms:.2f} ms")
+
+    # 16-bit vector storage: bf16 updates with r, p, x_lo in bf16 containers
+    # against fp32 containers, 200 iterations of the same action
+    act_b16 = M.action(M.BF16, M.FP32, M.BF16)
+    pol_b16 = M.Policy(kind=M.POLICY_FIXED, fixed_action=act_b16)
+    v16 = {}
+    for v in (0, 1):
+        solve(pol_b16, 50, maxit=200, vec16=v)
+        rv = solve(pol_b16, 50, maxit=200, vec16=v, profile=True)
+        pv = m.profile()
+        it = pv["n_iter_slots"]
+        v16[v] = {"iters": rv["iters"], "us_per_iteration": round(1e3 * rv["time_ms"] / rv["iters"], 2),
+                  "ka_us": round(1e3 * pv["ka_iter_ms"] / it, 2), "kb_us": round(1e3 * pv["kb_iter_ms"] / it, 2),
+                  "kx_us": round(1e3 * pv["kx_iter_ms"] / it, 2)}
+        # plain timing (no events) of the same 200 iterations
+        v16[v]["ms_200_iterations"] = round(float(np.median([solve(pol_b16, 50, maxit=200, vec16=v)["time_ms"]
+                                                             for _ in range(3)])), 3)
+    log(f"[bench] bf16 updates, fp32 vs bf16 containers: {v16}")
 
     fp64_runs = [solve(pol_fp64, 0) for _ in range(max(1, args.steps // 2))]
     r64 = fp64_runs[-1]
@@ -770,6 +788,10 @@ def main():
             "kx_fp64": {"avg_us": round(k3_64_us, 3), "GB/s": round(bytes_k3_64 / (k3_64_us * 1e-6) / 1e9, 1)},
             "profiled_solve_ms": round(rp["time_ms"], 3),
         },
+        "vector_storage_16bit": {
+            "action": "SpMV bf16, dot fp32, updates bf16, R=50, 200 iterations",
+            "fp32_containers": v16[0], "bf16_containers": v16[1],
+            "speedup": round(v16[0]["ms_200_iterations"] / v16[1]["ms_200_iterations"], 3)},
         "q52_storage": {
             "action": "SpMV in q52 storage (row-scaled, fp32 accumulation), dot fp32, axpy fp32, R=50",
             "ms": round(q52_ms, 3), "iters": rq["iters"], "relres_true": rq["relres_true"],

@@ -182,6 +182,14 @@ typedef struct {
                                   SpMV, the total of a dot, each updated
                                   element), all vectors in fp64.  Not for q52
                                   actions or batched solves.                    */
+    int32_t vec16;             /* 1: 16-bit vector storage: while the update
+                                  format is bf16, r, p and x_lo are held in bf16
+                                  containers (q stays fp32), so a start,
+                                  replacement or tier change rounds r and p to
+                                  bf16 instead of fp32; the updates themselves
+                                  are unchanged.  Not with precond, rho_fp64,
+                                  emulate or batched solves.                    */
+    int32_t reserved;          /* 0 */
 } mpcg_solve_opts;
 
 /* Per-kernel timing of the last solve made with opts.profile = 1.  One CG

@@ -85,7 +85,8 @@ class Policy(C.Structure):
 class Params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("replace_period", C.c_int32),
                 ("fallback", C.c_int32), ("dot_order", C.c_int32), ("precond", C.c_int32),
-                ("stop_rule", C.c_int32), ("rho_fp64", C.c_int32), ("emulate", C.c_int32)]
+                ("stop_rule", C.c_int32), ("rho_fp64", C.c_int32), ("emulate", C.c_int32),
+                ("vec16", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -373,18 +374,19 @@ def jacobi_inverse(A):
 
 def cg(A, b, x0=None, tol=1e-8, maxit=1000, policy: OraclePolicy | None = None,
        replace_period=0, fallback=False, order=ORDER_PAIRWISE, roll_cap=0, dump=0, precond=0, stop_rule=0,
-       rho_fp64=0, emulate=0):
+       rho_fp64=0, emulate=0, vec16=0):
     """Run the oracle solver (precond 1: Jacobi; stop_rule 1: the paper's
     termination, recursive rho < tol with k >= 10; rho_fp64 1: rho from an
     fp64 r.r; emulate 1: the paper's reading, fp64 operations whose results are
-    rounded to the operation's format).  Returns (x, info dict with histories)."""
+    rounded to the operation's format; vec16 1: bf16 containers for r, p and
+    x_lo when the updates are bf16).  Returns (x, info dict with histories)."""
     n = A.n
     b = _f64(b)
     x0 = np.zeros(n) if x0 is None else _f64(x0)
     x = np.empty(n)
     pol = policy if policy is not None else OraclePolicy()
     prm = Params(tol, maxit, replace_period, int(fallback), order, int(precond), int(stop_rule), int(rho_fp64),
-                 int(emulate))
+                 int(emulate), int(vec16))
     res = Result()
     hist_rho = np.full(maxit + 1, np.nan)
     hist_act = np.zeros(max(maxit, 1), dtype=np.uint8)

@@ -63,6 +63,11 @@
  *   total; updates and the preconditioner solve: each element); r, p, q and
  *   x_lo are fp64 vectors, so there is no tier switch.
  *
+ *   vec16: with f_a = bf16 the vectors r, p and x_lo are held in bf16
+ *   containers (16-bit vector storage); the updates already round them to
+ *   bf16, so the only change is at a start, replacement or tier switch, where
+ *   r and p are rounded to bf16 instead of fp32.  q stays fp32.
+ *
  *   rho_fp64 (section 1 keeps residual computations in fp64): rho' =
  *   sqrt(dot64(r,r))/bnorm of the recursive r, while sigma' (beta's
  *   numerator) stays dot_fd(r,r).
@@ -150,8 +155,10 @@ void orc_rd_array(const double *x, double *y, int64_t n, int f)
         y[i] = orc_rd(x[i], f);
 }
 
-static double rd_tier(double x, int tier64) { return tier64 ? x : orc_rd(x, F32); }
-static int tier_of(int f) { return f == F64; }
+/* Vector containers ("tiers"): 0 fp32, 1 fp64, 2 bf16 (vec16: updates in
+ * bf16 keep r, p and x_lo in 16-bit containers; q stays fp32). */
+static double rd_tier(double x, int tier) { return tier == 1 ? x : orc_rd(x, tier == 2 ? BF16 : F32); }
+static int tier_of(int f, int vec16) { return f == F64 ? 1 : (vec16 && f == BF16) ? 2 : 0; }
 
 /* fp16 row exponent: e with max|a| * 2^-e in (2^14, 2^15], clamped to int8. */
 int orc_row_exp(const double *v, int64_t len)
@@ -672,6 +679,9 @@ typedef struct {
     int32_t emulate;          /* 1: the paper's emulation reading: every
                                  operation computes in fp64 and rounds its
                                  result to its format; vectors in fp64 */
+    int32_t vec16;            /* 1: with bf16 updates, r, p and x_lo live in
+                                 bf16 containers: a start, replacement or tier
+                                 switch rounds r and p to bf16 (not fp32) */
 } orc_params;
 
 typedef struct {
@@ -916,7 +926,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
             a = fell_back ? 63 : decide(pol, kind, feat, s, k, &explored);
             if (fell_back) explored = 0;
             k_dec = k;
-            tier = emul ? 1 : tier_of(act_fa(a));
+            tier = emul ? 1 : tier_of(act_fa(a), prm->vec16);
             for (int64_t i = 0; i < n; ++i) { r[i] = rd_tier(r64[i], tier); p[i] = r[i]; }
             if (pc) {                                           /* p_0 = z_0 */
                 if (emul) precond_emul(n, minv, r, p, act_fa(a));
@@ -935,7 +945,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         if (k < h->dump_cap && h->dump_p) memcpy(&h->dump_p[k * n], p, bytes);
         if (k < h->dump_cap && h->dump_r) memcpy(&h->dump_r[k * n], r, bytes);
         if (emul) spmv_emul(&A, fs, p, q);
-        else mat_spmv(&A, fs, tier, p, q);
+        else mat_spmv(&A, fs, tier == 1, p, q);
         double nu = emul ? dot_emul(n, p, q, fd, prm->dot_order) : orc_dot(n, p, q, fd, prm->dot_order);
         double alpha = sigma / nu;
         if (k < h->dump_cap && h->hist_alpha) h->hist_alpha[k] = alpha;
@@ -1071,7 +1081,7 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         } else {
             explored = 0;                  /* the action holds */
         }
-        int nt = emul ? 1 : tier_of(act_fa(a));
+        int nt = emul ? 1 : tier_of(act_fa(a), prm->vec16);
         if (nt != tier) {
             fold(n, xhi, xlo);
             for (int64_t i = 0; i < n; ++i) { r[i] = rd_tier(r[i], nt); p[i] = rd_tier(p[i], nt); }

@@ -283,6 +283,7 @@ struct mpcg_matrix {
   // workspace
   double *d_xhi = nullptr;
   float *d_r32 = nullptr, *d_q32 = nullptr, *d_xlo32 = nullptr, *d_p32 = nullptr;
+  uint16_t *d_r16 = nullptr, *d_p16 = nullptr, *d_x16 = nullptr;   // bf16 containers (vec16)
   double *d_r64 = nullptr, *d_q64 = nullptr, *d_xlo64 = nullptr, *d_p64 = nullptr;
   double *d_part0 = nullptr, *d_part1 = nullptr, *d_part2 = nullptr, *d_scalar = nullptr;
   double *d_part1b = nullptr, *d_part2b = nullptr;   // preconditioned: r.(M^-1 r) partials
@@ -307,7 +308,7 @@ struct mpcg_matrix {
   // policy
   mpcg_policy *pol = nullptr;
   mpcg_policy *defpol = nullptr;
-  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0, 0, 0, 0, 0};   // replace_period .. stop_rule, rho_fp64
+  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // replace_period .. emulate, vec16
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_chunk[2] = {nullptr, nullptr};
   int P2 = 0;
 
@@ -334,6 +335,7 @@ struct mpcg_matrix {
   void release() {
     dfree(d_rp); dfree(d_ci); dfree(d_dc); dfree(d_pbf); dfree(d_ph); dfree(d_v64); dfree(d_v32); dfree(d_vbf); dfree(d_vh); dfree(d_v8); dfree(d_vtf); dfree(d_rexp);
     dfree(d_xhi); dfree(d_r32); dfree(d_p32); dfree(d_q32); dfree(d_xlo32);
+    dfree(d_r16); dfree(d_p16); dfree(d_x16);
     dfree(d_r64); dfree(d_p64); dfree(d_q64); dfree(d_xlo64);
     dfree(d_part0); dfree(d_part1); dfree(d_part2); dfree(d_scalar); dfree(d_ctl); dfree(d_pol);
     dfree(d_part1b); dfree(d_part2b); dfree(d_minv);
@@ -394,6 +396,7 @@ static int ensure_ws(mpcg_matrix *A) {
   HIP_TRY(dmalloc(&A->d_q32, n)); HIP_TRY(dmalloc(&A->d_xlo32, n));
   HIP_TRY(dmalloc(&A->d_r64, n)); HIP_TRY(dmalloc(&A->d_p64, n));
   HIP_TRY(dmalloc(&A->d_q64, n)); HIP_TRY(dmalloc(&A->d_xlo64, n));
+  HIP_TRY(dmalloc(&A->d_r16, n)); HIP_TRY(dmalloc(&A->d_p16, n)); HIP_TRY(dmalloc(&A->d_x16, n));
   return MPCG_OK;
 }
 
@@ -455,6 +458,7 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
   a.v.r64 = A->d_r64; a.v.q64 = A->d_q64; a.v.xlo64 = A->d_xlo64;
   a.v.p32 = A->d_p32;
   a.v.p64 = A->d_p64;
+  a.v.r16 = A->d_r16; a.v.p16 = A->d_p16; a.v.x16 = A->d_x16;
   a.ctl = A->d_ctl;
   a.pol = A->d_pol;
   a.h.rho = A->d_hrho;
@@ -471,6 +475,7 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
   a.part2b = A->d_part2b;
   a.precond = A->opts.precond;
   a.rho64 = A->opts.rho_fp64;
+  a.vec16 = A->opts.vec16;
   if (A->opts.index16 < 0) {   // 32-bit indices requested
     a.A.dc = nullptr;
     a.A.pbf = nullptr;
@@ -906,6 +911,10 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
   if (o->stop_rule != 0 && o->stop_rule != 1) return fail(MPCG_ERR_INVALID, "stop_rule must be 0 or 1");
   if (o->rho_fp64 != 0 && o->rho_fp64 != 1) return fail(MPCG_ERR_INVALID, "rho_fp64 must be 0 or 1");
   if (o->emulate != 0 && o->emulate != 1) return fail(MPCG_ERR_INVALID, "emulate must be 0 or 1");
+  if (o->vec16 != 0 && o->vec16 != 1) return fail(MPCG_ERR_INVALID, "vec16 must be 0 or 1");
+  if (o->vec16 && (o->precond || o->rho_fp64 || o->emulate))
+    return fail(MPCG_ERR_INVALID, "vec16 runs without the preconditioner, fp64 rho and the emulation reading");
+  if (o->reserved != 0) return fail(MPCG_ERR_INVALID, "reserved must be 0");
   A->opts = *o;
   return MPCG_OK;
 }
@@ -931,6 +940,7 @@ static int upload_start(mpcg_matrix *A, mpcg_policy *P, double tol, int32_t maxi
   c.stop_rule = A->opts.stop_rule;
   c.rho64 = A->opts.rho_fp64;
   c.emul = A->opts.emulate;
+  c.vec16 = A->opts.vec16;
   c.tol = tol;
   HIP_TRY(hipMemcpyAsync(A->d_ctl, A->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   return MPCG_OK;
@@ -1391,6 +1401,7 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
     if (A[i]->opts.precond) return fail(MPCG_ERR_INVALID, "batched solves are not preconditioned (precond = 0)");
     if (A[i]->opts.rho_fp64) return fail(MPCG_ERR_INVALID, "batched solves take rho at the dot format (rho_fp64 = 0)");
     if (A[i]->opts.emulate) return fail(MPCG_ERR_INVALID, "batched solves run the hardware reading (emulate = 0)");
+    if (A[i]->opts.vec16) return fail(MPCG_ERR_INVALID, "batched solves keep fp32 vector containers (vec16 = 0)");
     mpcg_policy *P = A[i]->pol ? A[i]->pol : A[i]->defpol;
     if (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->roll_cap > 0)
       return fail(MPCG_ERR_INVALID, "training policies and rollout logs are not batched (shared state)");

@@ -27,6 +27,16 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 
+// The file is compiled as six objects in parallel (MPCG_KPART = 1..6): the
+// SpMV kernels, the plain KB kernels, the preconditioned and fp64-rho KB
+// kernels (two objects: 3 and 6), everything else with every host launcher,
+// and the batched kernels.  Without MPCG_KPART it is one object holding all
+// of them.
+#ifndef MPCG_KPART
+#define MPCG_KPART 0
+#endif
+#define MPCG_IN_PART(n) (MPCG_KPART == 0 || MPCG_KPART == (n))
+
 namespace mpcg {
 
 // ---------------------------------------------------------------------------
@@ -187,6 +197,34 @@ struct GatherPlain {
   __device__ __forceinline__ V value(int c) const { return p[c]; }
   template <typename Acc> __device__ __forceinline__ Acc get(int c) const { return to_acc<Acc>(p[c]); }
 };
+
+// Gather from a bf16 container (16-bit vector storage): exact widening.
+struct GatherBf16 {
+  const uint16_t *p;
+  template <typename Acc> __device__ __forceinline__ Acc get(int c) const { return (Acc)bf16_bits_to_f32(p[c]); }
+};
+
+// 8 bf16 values of a 16-bit container (16 bytes, 8-aligned position), widened.
+__device__ __forceinline__ void load8_bf16(const uint16_t *p, float (&v)[8]) {
+  const uint4 w = *(const uint4 *)p;
+  const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    v[2 * j] = bf16_bits_to_f32((uint16_t)(ws[j] & 0xffffu));
+    v[2 * j + 1] = bf16_bits_to_f32((uint16_t)(ws[j] >> 16));
+  }
+}
+// 8 bf16-representable floats stored as bits.
+__device__ __forceinline__ void store8_bf16(uint16_t *p, const float (&v)[8]) {
+  uint32_t ws[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    ws[j] = (uint32_t)f32_to_bf16_bits_exact(v[2 * j]) | ((uint32_t)f32_to_bf16_bits_exact(v[2 * j + 1]) << 16);
+  *(uint4 *)p = make_uint4(ws[0], ws[1], ws[2], ws[3]);
+}
+__device__ __forceinline__ uint16_t bf16_bits_of(double x) {   // RNE from fp64 to bf16, as bits
+  return f32_to_bf16_bits_exact(rd_from_f64_to_f32<BF16>(x));
+}
 
 // p_new = rd_fa(fma_acc(rd_acc(beta), p, r)) in the tier of fa
 template <typename Vo>
@@ -646,7 +684,7 @@ __device__ __forceinline__ void apply_decision(const Sx &a, int na, int ex, bool
     set_done(c);
     return;
   }
-  const int nt = (c->emul || act_fa(na) == FP64) ? 1 : 0;
+  const int nt = (c->emul || act_fa(na) == FP64) ? 1 : (c->vec16 && act_fa(na) == BF16) ? 2 : 0;
   if (from_init) {
     c->k3op = K3_COPY;
     c->k3switch = 0;
@@ -1344,7 +1382,8 @@ __device__ __forceinline__ void spmv_group(const Mat &A, const G &gather, int g0
 
 // EMUL: the paper's emulation reading, an fp64 SpMV whose q_i are rounded to
 // the action's SpMV format, and the nu partials in fp64.
-template <int FS, int TIER, bool EMUL = false>
+// P16: p in the bf16 container (16-bit vector storage), q in fp32.
+template <int FS, int TIER, bool EMUL = false, bool P16 = false>
 __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, void *lds) {
   using V = typename TierT<TIER>::type;
   using Acc = typename AccT<FS>::type;
@@ -1364,7 +1403,8 @@ __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, voi
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
       const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
-      pn[j] = lr < grows ? p[g0 + lr] : (V)0;
+      if constexpr (P16) pn[j] = lr < grows ? (V)bf16_bits_to_f32(a.v.p16[g0 + lr]) : (V)0;
+      else pn[j] = lr < grows ? p[g0 + lr] : (V)0;
     }
   };
   auto pre = [&](int sb) {
@@ -1401,8 +1441,13 @@ __device__ __forceinline__ void ka_iter(const KArgs &a, const Ctl &S, int g, voi
     t[2] = sb == 2 ? s : t[2];
     t[3] = sb == 3 ? s : t[3];
   };
-  if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref, pre, epi);
-  else spmv_group<FS, false>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref, pre, epi);
+  if constexpr (P16) {
+    if (a.A.dc) spmv_group<FS, true>(a.A, GatherBf16{a.v.p16}, g0, grows, lds, pref, pre, epi);
+    else spmv_group<FS, false>(a.A, GatherBf16{a.v.p16}, g0, grows, lds, pref, pre, epi);
+  } else {
+    if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref, pre, epi);
+    else spmv_group<FS, false>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref, pre, epi);
+  }
   if (threadIdx.x == 0) a.part1[g] = group_tree(fd, a.grows, t);
 }
 
@@ -1441,7 +1486,9 @@ __device__ __forceinline__ void ka_residual(const KArgs &a, const Ctl &S, int g,
         if (mode == M_INIT) {
           a.v.r64[i] = r;
         } else if (mode == M_REPLACE) {
-          if (S.tier) a.v.r64[i] = r; else a.v.r32[i] = (float)r;
+          if (S.tier == 1) a.v.r64[i] = r;
+          else if (S.tier == 2) a.v.r16[i] = bf16_bits_of(r);
+          else a.v.r32[i] = (float)r;
         }
       }
     }
@@ -1477,17 +1524,32 @@ __device__ __forceinline__ void fold_group(const KArgs &a, int tier, int g) {
   for (int j = 0; j < 8; ++j) {
     const int i = base + j;
     if (i >= n) break;
-    if (tier) { fold1(a.v.xhi, i, a.v.xlo64[i]); a.v.xlo64[i] = 0.0; }
+    if (tier == 1) { fold1(a.v.xhi, i, a.v.xlo64[i]); a.v.xlo64[i] = 0.0; }
+    else if (tier == 2) { fold1(a.v.xhi, i, (double)bf16_bits_to_f32(a.v.x16[i])); a.v.x16[i] = 0; }
     else { fold1(a.v.xhi, i, (double)a.v.xlo32[i]); a.v.xlo32[i] = 0.0f; }
   }
 }
 
 // KA's work on row group g of one system.
+// V16: the variant that also runs iterations whose p is in the bf16
+// container (16-bit vector storage, tier 2).
+template <bool V16 = false>
 __device__ __forceinline__ void ka_body(const KArgs &a, int g, double *lds) {
   const Ctl &S = a.ctl[0];
   const int mode = S.mode;
   if (a.slot_log && g == 0 && threadIdx.x == 0) a.slot_log[a.slot] = (int8_t)mode;
-  if (mode == M_ITER && S.emul) {
+  if (V16 && mode == M_ITER && S.tier == 2) {
+    if constexpr (V16) {
+      switch (act_fs(S.action)) {
+      case FP16: ka_iter<FP16, 0, false, true>(a, S, g, lds); break;
+      case BF16: ka_iter<BF16, 0, false, true>(a, S, g, lds); break;
+      case FP32: ka_iter<FP32, 0, false, true>(a, S, g, lds); break;
+      case FP8: ka_iter<FP8, 0, false, true>(a, S, g, lds); break;
+      case TF32: ka_iter<TF32, 0, false, true>(a, S, g, lds); break;
+      default: ka_iter<FP64, 0, false, true>(a, S, g, lds); break;
+      }
+    }
+  } else if (mode == M_ITER && S.emul) {
     ka_iter<FP64, 1, true>(a, S, g, lds);
   } else if (mode == M_ITER) {
     const int fs = act_fs(S.action);   // 4: q52 storage, 5: tf32
@@ -1510,12 +1572,47 @@ __device__ __forceinline__ void ka_body(const KArgs &a, int g, double *lds) {
   }
 }
 
+// Kernels launched from part 4, defined in parts 1-3, 5 and 6.
+__global__ __launch_bounds__(kBlock, 2) void k_batched(const BatchSys *sys, const int32_t *order, int nsys,
+                                                     int32_t *queue);
+__global__ __launch_bounds__(kBlock) void k_a_lock(const BatchSys *sys, const SysBlk *tab, int ntab, int nround);
+__global__ __launch_bounds__(kBlock) void k_b_lock(const BatchSys *sys, const SysBlk *tab, int ntab);
+__global__ __launch_bounds__(kBlock) void k_x_lock(const BatchSys *sys, const SysBlk *tab, int ntab);
+__global__ __launch_bounds__(kBlock) void k_step_b_lock(const BatchSys *sys, const int32_t *act);
+__global__ __launch_bounds__(kBlock) void k_step_x_lock(const BatchSys *sys, const int32_t *act);
+__global__ __launch_bounds__(kBlock) void k_start_lock(const BatchSys *sys, const SysBlk *tab);
+__global__ __launch_bounds__(kBlock) void k_finish_lock(const BatchSys *sys, const SysBlk *tab);
+__global__ __launch_bounds__(kBlock) void k_modes_lock(const BatchSys *sys, const int32_t *act, int nact,
+                                                       int32_t *modes);
+
+__global__ __launch_bounds__(kBlock) void k_a(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_a16(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b16(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_full(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_full16(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_pc(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_full_pc(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_r64(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_full_r64(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_pc_r64(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_full_pc_r64(KArgs a);
+
+#if MPCG_IN_PART(1)
+__global__ __launch_bounds__(kBlock) void k_a16(KArgs a) {
+  const int g = xcd_group(a.G1);
+  if (g >= a.P1) return;
+  __shared__ double lds[kLdsKa];
+  ka_body<true>(a, g, lds);
+}
+
 __global__ __launch_bounds__(kBlock) void k_a(KArgs a) {
   const int g = xcd_group(a.G1);
   if (g >= a.P1) return;
   __shared__ double lds[kLdsKa];
   ka_body(a, g, lds);
 }
+#endif  // part 1
 
 // ---------------------------------------------------------------------------
 // KB: x_lo = axpy(alpha, p, x_lo), r = axpy(-alpha, q, r), partial of
@@ -1628,13 +1725,64 @@ __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_
 // fold of x_lo into x_hi before a replacement or a restart.  With a
 // preconditioner (PC) the direction takes z = M^-1 r in place of r (p_0 = z_0;
 // p = z when the direction restarts).
-template <bool PC = false>
+// V16: also the bf16 containers (tier 2; no preconditioner there).
+template <bool PC = false, bool V16 = false>
 __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, int blk) {
   const int op = S.k3op;
   const int n = a.A.n;
   const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   if (op == K3_FOLD) {
     fold_group(a, S.tier, blk);
+  } else if (V16 && op == K3_COPY && S.tier == 2) {   // r = p = rd_bf16(r64), x_lo = 0
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      if (i >= n) break;
+      const uint16_t rb = bf16_bits_of(a.v.r64[i]);
+      a.v.r16[i] = rb;
+      a.v.p16[i] = rb;
+      a.v.x16[i] = 0;
+    }
+  } else if (V16 && op == K3_XPAY && !S.k3switch && base + 8 <= n && S.tier_old == 2) {
+    float pv[8], rv[8];
+    load8_bf16(a.v.p16 + base, pv);
+    load8_bf16(a.v.r16 + base, rv);
+    const int fa = S.k3_fa;
+    const float bf = (float)S.beta;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) pv[j] = rd_rt_f32(fa, __builtin_fmaf(bf, pv[j], rv[j]));
+    store8_bf16(a.v.p16 + base, pv);
+  } else if (V16 && op == K3_XPAY) {
+    // any pair of containers: the direction update in the old tier, then (on
+    // a tier change) the fold of x_lo and r, p rounded into the new tier
+    const int told = S.tier_old, nt = S.tier;
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      if (i >= n) break;
+      double pn, rold, xold;
+      if (told == 1) {
+        pn = xpay_rt<double>(S.k3_fa, S.beta, a.v.p64[i], a.v.r64[i]);
+        rold = a.v.r64[i];
+        xold = a.v.xlo64[i];
+      } else {
+        const float pp = told == 2 ? bf16_bits_to_f32(a.v.p16[i]) : a.v.p32[i];
+        const float rr = told == 2 ? bf16_bits_to_f32(a.v.r16[i]) : a.v.r32[i];
+        pn = (double)xpay_rt<float>(S.k3_fa, S.beta, pp, rr);
+        rold = (double)rr;
+        xold = told == 2 ? (double)bf16_bits_to_f32(a.v.x16[i]) : (double)a.v.xlo32[i];
+      }
+      const int to = S.k3switch ? nt : told;
+      if (S.k3switch) fold1(a.v.xhi, i, xold);
+      if (to == 1) {
+        a.v.p64[i] = pn;
+        if (S.k3switch) { a.v.r64[i] = rold; a.v.xlo64[i] = 0.0; }
+      } else if (to == 2) {
+        a.v.p16[i] = bf16_bits_of(pn);
+        if (S.k3switch) { a.v.r16[i] = bf16_bits_of(rold); a.v.x16[i] = 0; }
+      } else {
+        a.v.p32[i] = (float)pn;
+        if (S.k3switch) { a.v.r32[i] = (float)rold; a.v.xlo32[i] = 0.0f; }
+      }
+    }
   } else if (op == K3_COPY) {
     for (int j = 0; j < 8; ++j) {
       const int i = base + j;
@@ -1740,9 +1888,77 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
   case (FA) * 8 + (FD): kb_axpy_vals<FA, FD, PC, R64>(a, S, fold_now, blk, pv, qv, rv, xv); break;
 
 // KB's vector work for 2048-element block blk.
-template <bool PC = false, bool R64 = false>
+// x_lo and r updates with bf16 updates in the bf16 containers (16-bit vector
+// storage), and the sigma' partial: the arithmetic of the fp32-container path.
+template <int FD>
+__device__ __forceinline__ void kb_axpy16(const KArgs &a, const Ctl &S, bool fold_now, int blk) {
+  using Acc = typename AccT<FD>::type;
+  const int n = a.A.n;
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
+  const bool full = base + 8 <= n;
+  float pv[8], qv[8], rv[8], xv[8];
+  if (full) {
+    load8_bf16(a.v.p16 + base, pv);
+    load8(a.v.q32 + base, qv);
+    load8_bf16(a.v.r16 + base, rv);
+    load8_bf16(a.v.x16 + base, xv);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      const bool in = i < n;
+      pv[j] = in ? bf16_bits_to_f32(a.v.p16[i]) : 0.0f;
+      qv[j] = in ? a.v.q32[i] : 0.0f;
+      rv[j] = in ? bf16_bits_to_f32(a.v.r16[i]) : 0.0f;
+      xv[j] = in ? bf16_bits_to_f32(a.v.x16[i]) : 0.0f;
+    }
+  }
+  const double alpha = S.alpha;
+  Acc l[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    xv[j] = axpy1<BF16>(alpha, pv[j], xv[j]);
+    rv[j] = axpy1<BF16>(-alpha, qv[j], rv[j]);
+    l[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], rv[j]) : (Acc)0;
+  }
+  if (fold_now) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      if (i < n) fold1(a.v.xhi, i, (double)xv[j]);
+      xv[j] = 0.0f;
+    }
+  }
+  if (full) {
+    store8_bf16(a.v.x16 + base, xv);
+    store8_bf16(a.v.r16 + base, rv);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      if (i < n) {
+        a.v.x16[i] = f32_to_bf16_bits_exact(xv[j]);
+        a.v.r16[i] = f32_to_bf16_bits_exact(rv[j]);
+      }
+    }
+  }
+  const Acc t = block_tree(tree8(l));
+  if (threadIdx.x == 0) a.part2[blk] = (double)t;
+}
+
+template <bool PC = false, bool R64 = false, bool V16 = false>
 __device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, bool fold_now, int blk) {
-  if (bop == B_AXPY) {
+  if (V16 && bop == B_AXPY && S.tier == 2) {
+    if constexpr (V16) {
+      switch (act_fd(S.action)) {
+      case FP16: kb_axpy16<FP16>(a, S, fold_now, blk); break;
+      case BF16: kb_axpy16<BF16>(a, S, fold_now, blk); break;
+      case FP32: kb_axpy16<FP32>(a, S, fold_now, blk); break;
+      case TF32: kb_axpy16<TF32>(a, S, fold_now, blk); break;
+      default: kb_axpy16<FP64>(a, S, fold_now, blk); break;
+      }
+    }
+  } else if (bop == B_AXPY) {
     const int act = S.action;
     switch (S.emul ? FP64 * 8 + FP64 : act_fa(act) * 8 + act_fd(act)) {
       MPCG_KB_CASE(FP16, FP16) MPCG_KB_CASE(FP16, BF16) MPCG_KB_CASE(FP16, FP32) MPCG_KB_CASE(FP16, FP64)
@@ -1755,7 +1971,7 @@ __device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, b
     default: break;
     }
   } else if (bop == B_EXEC) {
-    exec_elementwise<PC>(a, S, blk);
+    exec_elementwise<PC, V16>(a, S, blk);
   }
 }
 
@@ -1773,7 +1989,7 @@ __device__ __forceinline__ void kb_commit(Ctl &S, int bop, bool fold_now) {
 
 // KB's work on vector block blk of one system; block 0 commits the state.
 // The step's partials are loaded together with the control block.
-template <bool FULL = false, bool PC = false, bool R64 = false>
+template <bool FULL = false, bool PC = false, bool R64 = false, bool V16 = false>
 __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
@@ -1786,7 +2002,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   const Sx x{&S, &SP, a.h, blk == 0};
   const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   const bool blk_full = (blk + 1) * kVecBlock <= a.A.n;   // block-uniform
-  if (!S.step_done && S.mode == M_ITER && !S.emul && act_fa(S.action) != FP64 && blk_full) {
+  if (!S.step_done && S.mode == M_ITER && !S.emul && S.tier == 0 && act_fa(S.action) != FP64 && blk_full) {
     // an iteration in the fp32 containers on a whole block: the four operands
     // are in flight while the alpha step runs
     float pv[8], qv[8], rv[8], xv[8];
@@ -1811,7 +2027,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
       default: break;
       }
     } else {
-      kb_work<PC, R64>(a, S, bop, fold_now, blk);
+      kb_work<PC, R64, V16>(a, S, bop, fold_now, blk);
     }
     if (blk == 0) {
       __syncthreads();
@@ -1824,7 +2040,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   if (!S.step_done) step_b<FULL>(x, a, pre, fast);
   const int bop = S.b_op;
   const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
-  kb_work<PC, R64>(a, S, bop, fold_now, blk);
+  kb_work<PC, R64, V16>(a, S, bop, fold_now, blk);
   if (blk == 0) {   // commit the state after this kernel for KX
     __syncthreads();
     if (threadIdx.x == 0) kb_commit(S, bop, fold_now);
@@ -1837,7 +2053,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
 // elementwise operation; block 0 commits the state.  The partials come with
 // the control block, and the direction update's operands are issued before
 // the step's arithmetic, so the step's latency overlaps the vector loads.
-template <int TIER, bool PC>
+template <int TIER, bool PC, bool V16 = false>
 __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S, int blk, const double (&pre)[8],
                                             bool have_pre) {
   using V = typename TierT<TIER>::type;
@@ -1886,11 +2102,37 @@ __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S,
       store8(a.v.p32 + base, pv);
     }
   } else {
-    exec_elementwise<PC>(a, S, blk);
+    exec_elementwise<PC, V16>(a, S, blk);
   }
 }
 
-template <bool PC = false>
+// KX's work on a block whose r and p are in the bf16 containers (tier 2):
+// the step, then the direction update on the operands already loaded.
+__device__ __forceinline__ void kx_iter16(const KArgs &a, const Sx &x, Ctl &S, int blk, const double (&pre)[8],
+                                          bool have_pre) {
+  const int n = a.A.n;
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
+  const bool full = base + 8 <= n;
+  float pv[8], rv[8];
+  __builtin_amdgcn_sched_barrier(0);
+  if (full) {
+    load8_bf16(a.v.p16 + base, pv);
+    load8_bf16(a.v.r16 + base, rv);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  step_x<false>(x, a, pre, have_pre);
+  if (S.k3op == K3_XPAY && !S.k3switch && full) {
+    const int fa = S.k3_fa;
+    const float bf = (float)S.beta;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) pv[j] = rd_rt_f32(fa, __builtin_fmaf(bf, pv[j], rv[j]));
+    store8_bf16(a.v.p16 + base, pv);
+  } else {
+    exec_elementwise<false, true>(a, S, blk);
+  }
+}
+
+template <bool PC = false, bool V16 = false>
 __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
@@ -1902,11 +2144,12 @@ __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   __syncthreads();
   const Sx x{&S, &SP, a.h, blk == 0, nullptr};
   if (!S.step_done && S.pend_sigma) {
-    if (S.tier) kx_iter_pre<1, PC>(a, x, S, blk, pre, fast);
-    else kx_iter_pre<0, PC>(a, x, S, blk, pre, fast);
+    if (V16 && S.tier == 2) kx_iter16(a, x, S, blk, pre, fast);
+    else if (S.tier) kx_iter_pre<1, PC, V16>(a, x, S, blk, pre, fast);
+    else kx_iter_pre<0, PC, V16>(a, x, S, blk, pre, fast);
   } else {
     if (!S.step_done) step_x<false>(x, a, pre, fast);
-    exec_elementwise<PC>(a, S, blk);
+    exec_elementwise<PC, V16>(a, S, blk);
   }
   if (blk == 0) {   // commit the state after this kernel for the next KA and KB
     __syncthreads();
@@ -1919,27 +2162,47 @@ __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   }
 }
 
+#if MPCG_IN_PART(2)
 __global__ __launch_bounds__(kBlock) void k_b(KArgs a) { kb_body(a, blockIdx.x); }
 
-__global__ __launch_bounds__(kBlock) void k_x(KArgs a) { kx_body(a, blockIdx.x); }
-
-// The Jacobi-preconditioned variants of KB and KX (separate kernels, so the
-// unpreconditioned ones keep their register budget).
-__global__ __launch_bounds__(kBlock) void k_b_pc(KArgs a) { kb_body<false, true>(a, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void k_b_full_pc(KArgs a) { kb_body<true, true>(a, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void k_x_pc(KArgs a) { kx_body<true>(a, blockIdx.x); }
-// KB with rho from an fp64 r.r (the residual norm kept in fp64) and sigma' at
-// the dot format in the second partial.
-__global__ __launch_bounds__(kBlock) void k_b_r64(KArgs a) { kb_body<false, false, true>(a, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void k_b_full_r64(KArgs a) { kb_body<true, false, true>(a, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void k_b_pc_r64(KArgs a) { kb_body<false, true, true>(a, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void k_b_full_pc_r64(KArgs a) { kb_body<true, true, true>(a, blockIdx.x); }
+// The variants with the bf16 vector tier (16-bit vector storage).
+__global__ __launch_bounds__(kBlock) void k_b16(KArgs a) { kb_body<false, false, false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_full16(KArgs a) { kb_body<true, false, false, true>(a, blockIdx.x); }
 
 // KB whose replicated step is the full one (state features, the network's
 // decision at a start or a stop, rollout log by workgroup 0): for policies
 // that read but never write shared policy state during a solve.  Their
 // end-of-iteration decision runs once, in the one-block step kernel before KX.
 __global__ __launch_bounds__(kBlock) void k_b_full(KArgs a) { kb_body<true>(a, blockIdx.x); }
+#endif  // part 2
+
+#if MPCG_IN_PART(3)
+// The Jacobi-preconditioned variants of KB (separate kernels, so the
+// unpreconditioned ones keep their register budget).
+__global__ __launch_bounds__(kBlock) void k_b_pc(KArgs a) { kb_body<false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_full_pc(KArgs a) { kb_body<true, true>(a, blockIdx.x); }
+// KB with rho from an fp64 r.r (the residual norm kept in fp64) and sigma' at
+// the dot format in the second partial.
+__global__ __launch_bounds__(kBlock) void k_b_r64(KArgs a) { kb_body<false, false, true>(a, blockIdx.x); }
+#endif  // part 3
+
+#if MPCG_IN_PART(6)
+__global__ __launch_bounds__(kBlock) void k_b_full_r64(KArgs a) { kb_body<true, false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_pc_r64(KArgs a) { kb_body<false, true, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_full_pc_r64(KArgs a) { kb_body<true, true, true>(a, blockIdx.x); }
+#endif  // part 6
+
+#if MPCG_IN_PART(4) || MPCG_KPART == 5   // device steps shared with the batched kernels
+#if MPCG_IN_PART(4)
+__global__ __launch_bounds__(kBlock) void k_x(KArgs a) { kx_body(a, blockIdx.x); }
+#endif
+// the bf16 vector tier (16-bit vector storage) and the Jacobi-preconditioned KX
+#if MPCG_IN_PART(4)
+__global__ __launch_bounds__(kBlock) void k_x16(KArgs a) { kx_body<false, true>(a, blockIdx.x); }
+#endif
+#if MPCG_IN_PART(4)
+__global__ __launch_bounds__(kBlock) void k_x_pc(KArgs a) { kx_body<true>(a, blockIdx.x); }
+#endif
 #undef MPCG_KB_CASE
 #undef MPCG_KB_VALS
 
@@ -1982,15 +2245,21 @@ __device__ __forceinline__ void step_x_body(const KArgs &a, float *wl = nullptr)
   copy_words(&a.ctl[1], &S, sizeof(Ctl));
 }
 
+#if MPCG_IN_PART(4)
 __global__ __launch_bounds__(kBlock) void k_step_b(KArgs a) { step_b_body(a); }
+#endif
 
+#if MPCG_IN_PART(4)
 __global__ __launch_bounds__(kBlock) void k_step_x(KArgs a) { step_x_body(a); }
+#endif
 
 // The one-block step of a network policy, with the weights staged in LDS.
+#if MPCG_IN_PART(4)
 __global__ __launch_bounds__(kBlock) void k_step_x_net(KArgs a) {
   __shared__ float wl[kNetLds];
   step_x_body(a, wl);
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // start / finish
@@ -2006,6 +2275,7 @@ __device__ __forceinline__ void start_block(const KArgs &a, int blk) {
       a.v.xhi[i] = a.v.xout[i];
       a.v.xlo32[i] = 0.0f;
       a.v.xlo64[i] = 0.0;
+      if (a.v.x16) a.v.x16[i] = 0;
       const double bi = a.v.b[i];
       l[j] = bi * bi;
     } else {
@@ -2016,7 +2286,9 @@ __device__ __forceinline__ void start_block(const KArgs &a, int blk) {
   if (threadIdx.x == 0) a.part0[blk] = t;
 }
 
+#if MPCG_IN_PART(4)
 __global__ __launch_bounds__(kBlock) void k_start(KArgs a) { start_block(a, blockIdx.x); }
+#endif
 
 // x = x_hi + x_lo over block blk (tier and zero-solution flag of the final state).
 __device__ __forceinline__ void finish_block_x(const KArgs &a, int tier, int zero, int blk) {
@@ -2025,7 +2297,8 @@ __device__ __forceinline__ void finish_block_x(const KArgs &a, int tier, int zer
   for (int j = 0; j < 8; ++j) {
     const int i = base + j;
     if (i >= n) break;
-    if (tier) { fold1(a.v.xhi, i, a.v.xlo64[i]); a.v.xlo64[i] = 0.0; }
+    if (tier == 1) { fold1(a.v.xhi, i, a.v.xlo64[i]); a.v.xlo64[i] = 0.0; }
+    else if (tier == 2) { fold1(a.v.xhi, i, (double)bf16_bits_to_f32(a.v.x16[i])); a.v.x16[i] = 0; }
     else { fold1(a.v.xhi, i, (double)a.v.xlo32[i]); a.v.xlo32[i] = 0.0f; }
     a.v.xout[i] = zero ? 0.0 : a.v.xhi[i];
   }
@@ -2046,12 +2319,17 @@ __device__ __forceinline__ void request_final(Ctl *c) {
 
 // x = x_hi + x_lo; requests the final true-residual check after a budget stop
 // or a breakdown.
+#if MPCG_IN_PART(4)
 __global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
   const Ctl *c = &a.ctl[0];
   finish_block_x(a, c->tier, c->zero_solution, blockIdx.x);
   if (blockIdx.x == 0 && threadIdx.x == 0) request_final(&a.ctl[0]);
 }
+#endif
 
+#endif  // parts 4, 5
+
+#if MPCG_IN_PART(5)
 // ---------------------------------------------------------------------------
 // Batched persistent solve: each workgroup takes whole systems from a queue
 // (an atomic counter over a host-given order) and runs the same slot program as
@@ -2234,6 +2512,9 @@ __global__ __launch_bounds__(kBlock) void k_modes_lock(const BatchSys *sys, cons
   if (i < nact) modes[i] = sys[act[i]].a.ctl[0].mode;
 }
 
+#endif  // part 5
+
+#if MPCG_IN_PART(4)
 // ---------------------------------------------------------------------------
 // setup: 16-bit column deltas dc[k] = col[k] - row, thread per row; *bad = 1
 // when a delta leaves the int16 range (the caller then drops the array).
@@ -2403,15 +2684,18 @@ static void launch_timed(K kern, int grid, const KArgs &a, hipStream_t s, hipEve
   if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0, a);
   else hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
 }
-void launch_ka(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_a, a.G1, a, s, e0, e1); }
+void launch_ka(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_timed(a.vec16 ? k_a16 : k_a, a.G1, a, s, e0, e1);
+}
 void launch_kb(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (a.rho64 && a.precond) launch_timed(a.full ? k_b_full_pc_r64 : k_b_pc_r64, a.P2, a, s, e0, e1);
   else if (a.rho64) launch_timed(a.full ? k_b_full_r64 : k_b_r64, a.P2, a, s, e0, e1);
   else if (a.precond) launch_timed(a.full ? k_b_full_pc : k_b_pc, a.P2, a, s, e0, e1);
+  else if (a.vec16) launch_timed(a.full ? k_b_full16 : k_b16, a.P2, a, s, e0, e1);
   else launch_timed(a.full ? k_b_full : k_b, a.P2, a, s, e0, e1);
 }
 void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  launch_timed(a.precond ? k_x_pc : k_x, a.P2, a, s, e0, e1);
+  launch_timed(a.precond ? k_x_pc : a.vec16 ? k_x16 : k_x, a.P2, a, s, e0, e1);
 }
 void launch_step_b(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_step_b, 1, a, s, e0, e1); }
 void launch_step_x(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -2615,5 +2899,7 @@ void launch_policy_decide(const PolicyDev *P, int m, const int64_t *k, const dou
   const int g = m < 1024 ? (m > 0 ? m : 1) : 1024;
   hipLaunchKernelGGL(k_policy_decide, dim3(g), dim3(kBlock), 0, s, P, m, k, rho, stag, feat, state, action);
 }
+
+#endif  // part 4
 
 }  // namespace mpcg

@@ -38,6 +38,7 @@ struct Vecs {
   double *r64, *q64, *xlo64;
   float *p32;     // direction
   double *p64;
+  uint16_t *r16, *p16, *x16;   // bf16 containers of r, p, x_lo (16-bit vector storage)
 };
 
 struct Hist {
@@ -97,8 +98,9 @@ struct Ctl {
                                   // k_dec: iteration of the current decision
   int32_t stop_rule, rho64;       // stop_rule 1: stop when the recursive rho < tol with k >= 10;
                                   // rho64 1: rho from an fp64 r.r, sigma' at the dot format
-  int32_t emul, pad3_;            // 1: the paper's emulation reading (fp64 operations, results
-                                  // rounded to their formats, fp64 vectors)
+  int32_t emul, vec16;            // emul 1: the paper's emulation reading (fp64 operations,
+                                  // results rounded to their formats, fp64 vectors); vec16 1:
+                                  // bf16 updates keep r, p, x_lo in bf16 containers (tier 2)
   double tol, bnorm, sigma, sig_new, alpha, beta, rho_new, last_true, cost_sum, relres_true;
   double rep_hist[3];
   float feat[kMlpIn];
@@ -125,6 +127,7 @@ struct KArgs {
   int G1;              // KA workgroups launched (P1 rounded up to 8)
   int precond;         // 1: launch the preconditioned KB / KX variants (Ctl.precond set too)
   int rho64;           // 1: launch the KB variant with rho in fp64 (Ctl.rho64 set too)
+  int vec16;           // 1: launch the KA/KB/KX variants with the bf16 vector tier
   int8_t *slot_log;    // optional: KA records the mode of each slot (profiling)
   int slot;            // index of this slot (with slot_log)
 };
