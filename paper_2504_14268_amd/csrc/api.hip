@@ -975,6 +975,10 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   if (rc) return rc;
 
   KArgs a = make_args(A, b, x);
+  // the kernels with tf32 and the emulation reading, when the options or the
+  // policy can use them
+  a.ext = (A->opts.emulate || (P->desc.kind == MPCG_POLICY_FIXED && P->desc.fixed_action >= 128) ||
+           P->desc.nfmt == 5) ? 1 : 0;
   // Q-learning writes the table during the solve: one-block steps.  The
   // network and rollout logging only read shared state: every KB workgroup
   // runs the full step (workgroup 0 writing the logs), and the per-iteration

@@ -27,11 +27,12 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 
-// The file is compiled as six objects in parallel (MPCG_KPART = 1..6): the
-// SpMV kernels, the plain KB kernels, the preconditioned and fp64-rho KB
-// kernels (two objects: 3 and 6), everything else with every host launcher,
-// and the batched kernels.  Without MPCG_KPART it is one object holding all
-// of them.
+// The file is compiled as eight objects in parallel (MPCG_KPART = 1..8): the
+// plain SpMV kernel (1), the plain KB kernels (2), the preconditioned and
+// fp64-rho KB kernels (3, 6), everything else with every host launcher (4),
+// the batched kernels (5), and the tf32 / emulation / bf16-vector variants of
+// the SpMV (7) and of KB (8).  Without MPCG_KPART it is one object holding
+// all of them.
 #ifndef MPCG_KPART
 #define MPCG_KPART 0
 #endif
@@ -931,21 +932,26 @@ __device__ __forceinline__ void replace_block(const Sx &a, double s64, double s6
 // ---------------------------------------------------------------------------
 // Before KX: the end of an iteration (KB's sigma'): replacement test, then
 // beta, policy update and next action.
-template <bool FULL>
+// EXT: with the emulation reading's rounding of the totals (plain kernels
+// leave it out).
+template <bool FULL, bool EXT = true>
 __device__ __forceinline__ void step_x(const Sx &x, const KArgs &a, const double (&pre)[8], bool have_pre) {
   Ctl *c = x.ctl;
   if (c->mode == M_DONE || !c->pend_sigma) return;
   const int fd = act_fd(c->action);
   // r.r gives rho: at the dot format, or in fp64 (rho64)
-  const int fr = (c->rho64 || c->emul) ? FP64 : fd;
+  const bool emul = EXT && c->emul;
+  const int fr = (c->rho64 || emul) ? FP64 : fd;
   double sig = have_pre ? tree_preloaded_rt(fr, pre) : reduce_partials_rt(fr, a.part2, a.P2);
   // sigma' in the second partials: r.z with a preconditioner, r.r at the dot
   // format when rho is taken in fp64
-  double sigz = (c->precond || c->rho64) ? reduce_partials_rt(c->emul ? FP64 : fd, a.part2b, a.P2) : sig;
-  if (c->emul) {   // emulation: fp64 totals rounded to the dot format (rho64: rho unrounded)
-    if (c->precond || c->rho64) sigz = rd_rt_f64(fd, sigz);
-    if (!c->rho64) sig = rd_rt_f64(fd, sig);
-    if (!c->precond && !c->rho64) sigz = sig;
+  double sigz = (c->precond || c->rho64) ? reduce_partials_rt(emul ? FP64 : fd, a.part2b, a.P2) : sig;
+  if constexpr (EXT) {
+    if (emul) {   // emulation: fp64 totals rounded to the dot format (rho64: rho unrounded)
+      if (c->precond || c->rho64) sigz = rd_rt_f64(fd, sigz);
+      if (!c->rho64) sig = rd_rt_f64(fd, sig);
+      if (!c->precond && !c->rho64) sigz = sig;
+    }
   }
   __shared__ int s_fin;
   if (threadIdx.x == 0) {
@@ -983,16 +989,19 @@ __device__ __forceinline__ void step_x(const Sx &x, const KArgs &a) {
 
 // Before KB: KA's partials -- nu (alpha, breakdown) after an iteration, the
 // residual norm after a start, replacement or final check.
-template <bool FULL>
+template <bool FULL, bool EXT = true>
 __device__ __forceinline__ void step_b(const Sx &x, const KArgs &a, const double (&pre)[8], bool have_pre) {
   Ctl *c = x.ctl;
   const int la = c->mode;   // what KA has just executed
   if (la == M_ITER) {
     const int fd = act_fd(c->action);
     // emulation: the fp64 total rounded to the dot format
-    const int fn = c->emul ? FP64 : fd;
+    const bool emul = EXT && c->emul;
+    const int fn = emul ? FP64 : fd;
     double nu = have_pre ? tree_preloaded_rt(fn, pre) : reduce_partials_rt(fn, a.part1, a.P1);
-    if (c->emul) nu = rd_rt_f64(fd, nu);
+    if constexpr (EXT) {
+      if (emul) nu = rd_rt_f64(fd, nu);
+    }
     const double alpha = c->sigma / nu;
     if (!(nu > 0.0 && isfinite(nu)) || !isfinite(alpha)) {
       finish_block<FULL>(x, false, true, false, false);
@@ -1533,7 +1542,9 @@ __device__ __forceinline__ void fold_group(const KArgs &a, int tier, int g) {
 // KA's work on row group g of one system.
 // V16: the variant that also runs iterations whose p is in the bf16
 // container (16-bit vector storage, tier 2).
-template <bool V16 = false>
+// EXT: the tf32 formats and the emulation reading (kernels launched when the
+// policy or the options can use them; the plain variant keeps its code small).
+template <bool V16 = false, bool EXT = true>
 __device__ __forceinline__ void ka_body(const KArgs &a, int g, double *lds) {
   const Ctl &S = a.ctl[0];
   const int mode = S.mode;
@@ -1549,13 +1560,16 @@ __device__ __forceinline__ void ka_body(const KArgs &a, int g, double *lds) {
       default: ka_iter<FP64, 0, false, true>(a, S, g, lds); break;
       }
     }
-  } else if (mode == M_ITER && S.emul) {
-    ka_iter<FP64, 1, true>(a, S, g, lds);
+  } else if (EXT && mode == M_ITER && S.emul) {
+    if constexpr (EXT) ka_iter<FP64, 1, true>(a, S, g, lds);
+  } else if (EXT && mode == M_ITER && act_fs(S.action) == TF32) {
+    if constexpr (EXT) {
+      if (S.tier) ka_iter<TF32, 1>(a, S, g, lds);
+      else ka_iter<TF32, 0>(a, S, g, lds);
+    }
   } else if (mode == M_ITER) {
-    const int fs = act_fs(S.action);   // 4: q52 storage, 5: tf32
+    const int fs = act_fs(S.action);   // 4: q52 storage
     switch (fs * 2 + S.tier) {
-    case 10: ka_iter<TF32, 0>(a, S, g, lds); break;
-    case 11: ka_iter<TF32, 1>(a, S, g, lds); break;
     case 8: ka_iter<FP8, 0>(a, S, g, lds); break;
     case 9: ka_iter<FP8, 1>(a, S, g, lds); break;
     case 0: ka_iter<FP16, 0>(a, S, g, lds); break;
@@ -1572,7 +1586,7 @@ __device__ __forceinline__ void ka_body(const KArgs &a, int g, double *lds) {
   }
 }
 
-// Kernels launched from part 4, defined in parts 1-3, 5 and 6.
+// Kernels launched from part 4, defined in the other parts.
 __global__ __launch_bounds__(kBlock, 2) void k_batched(const BatchSys *sys, const int32_t *order, int nsys,
                                                      int32_t *queue);
 __global__ __launch_bounds__(kBlock) void k_a_lock(const BatchSys *sys, const SysBlk *tab, int ntab, int nround);
@@ -1586,7 +1600,10 @@ __global__ __launch_bounds__(kBlock) void k_modes_lock(const BatchSys *sys, cons
                                                        int32_t *modes);
 
 __global__ __launch_bounds__(kBlock) void k_a(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_a_ext(KArgs a);
 __global__ __launch_bounds__(kBlock) void k_a16(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_ext(KArgs a);
+__global__ __launch_bounds__(kBlock) void k_b_full_ext(KArgs a);
 __global__ __launch_bounds__(kBlock) void k_b(KArgs a);
 __global__ __launch_bounds__(kBlock) void k_b16(KArgs a);
 __global__ __launch_bounds__(kBlock) void k_b_full(KArgs a);
@@ -1599,20 +1616,30 @@ __global__ __launch_bounds__(kBlock) void k_b_pc_r64(KArgs a);
 __global__ __launch_bounds__(kBlock) void k_b_full_pc_r64(KArgs a);
 
 #if MPCG_IN_PART(1)
-__global__ __launch_bounds__(kBlock) void k_a16(KArgs a) {
-  const int g = xcd_group(a.G1);
-  if (g >= a.P1) return;
-  __shared__ double lds[kLdsKa];
-  ka_body<true>(a, g, lds);
-}
-
 __global__ __launch_bounds__(kBlock) void k_a(KArgs a) {
   const int g = xcd_group(a.G1);
   if (g >= a.P1) return;
   __shared__ double lds[kLdsKa];
-  ka_body(a, g, lds);
+  ka_body<false, false>(a, g, lds);
 }
 #endif  // part 1
+
+#if MPCG_IN_PART(7)
+// the tf32 / emulation variant and the bf16-vector variant
+__global__ __launch_bounds__(kBlock) void k_a_ext(KArgs a) {
+  const int g = xcd_group(a.G1);
+  if (g >= a.P1) return;
+  __shared__ double lds[kLdsKa];
+  ka_body<false, true>(a, g, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_a16(KArgs a) {
+  const int g = xcd_group(a.G1);
+  if (g >= a.P1) return;
+  __shared__ double lds[kLdsKa];
+  ka_body<true, true>(a, g, lds);
+}
+#endif  // part 7
 
 // ---------------------------------------------------------------------------
 // KB: x_lo = axpy(alpha, p, x_lo), r = axpy(-alpha, q, r), partial of
@@ -1634,7 +1661,7 @@ __device__ __forceinline__ void load8_tail(const V *p, int base, int n, bool ful
 // a preconditioner (PC) also z = M^-1 r and the partial of r.z.  With R64 the
 // r.r partial (rho) is taken in fp64 and sigma' (r.r, or r.z with PC) at the
 // dot format goes to the second partial.
-template <int FA, int FD, bool PC, bool R64, typename V>
+template <int FA, int FD, bool PC, bool R64, bool EXT, typename V>
 __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool fold_now, int blk, const V (&pv)[8],
                                              const V (&qv)[8], V (&rv)[8], V (&xv)[8]) {
   constexpr int TIER = (FA == FP64);
@@ -1657,7 +1684,7 @@ __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool 
   for (int j = 0; j < 8; ++j) {
     xv[j] = axpy1<FA>(alpha, pv[j], xv[j]);
     rv[j] = axpy1<FA>(-alpha, qv[j], rv[j]);
-    if constexpr (FA == FP64) {
+    if constexpr (FA == FP64 && EXT) {
       if (S.emul) {   // emulation: each fp64 update rounded to the update format
         xv[j] = rd_rt_f64(act_fa(S.action), xv[j]);
         rv[j] = rd_rt_f64(act_fa(S.action), rv[j]);
@@ -1666,7 +1693,7 @@ __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool 
     l[j] = (full || base + j < n) ? dot_leaf<FR>(rv[j], rv[j]) : (AccR)0;
     if constexpr (PC) {
       V zj = precond_z<FA>(mv[j], rv[j]);
-      if constexpr (FA == FP64) {
+      if constexpr (FA == FP64 && EXT) {
         if (S.emul) zj = rd_rt_f64(act_fa(S.action), zj);
       }
       lz[j] = (full || base + j < n) ? dot_leaf<FD>(rv[j], zj) : (Acc)0;
@@ -1702,7 +1729,7 @@ __device__ __forceinline__ void kb_axpy_vals(const KArgs &a, const Ctl &S, bool 
   }
 }
 
-template <int FA, int FD, bool PC, bool R64>
+template <int FA, int FD, bool PC, bool R64, bool EXT = true>
 __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_now, int blk) {
   constexpr int TIER = (FA == FP64);
   using V = typename TierT<TIER>::type;
@@ -1717,7 +1744,7 @@ __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_
   load8_tail(q, base, n, full, qv);
   load8_tail(r, base, n, full, rv);
   load8_tail(xlo, base, n, full, xv);
-  kb_axpy_vals<FA, FD, PC, R64>(a, S, fold_now, blk, pv, qv, rv, xv);
+  kb_axpy_vals<FA, FD, PC, R64, EXT>(a, S, fold_now, blk, pv, qv, rv, xv);
 }
 
 // Elementwise steps (KB or KX): p = r = rd_tier(r64) after a start; the
@@ -1726,8 +1753,9 @@ __device__ __forceinline__ void kb_axpy(const KArgs &a, const Ctl &S, bool fold_
 // preconditioner (PC) the direction takes z = M^-1 r in place of r (p_0 = z_0;
 // p = z when the direction restarts).
 // V16: also the bf16 containers (tier 2; no preconditioner there).
-template <bool PC = false, bool V16 = false>
+template <bool PC = false, bool V16 = false, bool EXT = true>
 __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, int blk) {
+  [[maybe_unused]] const bool emul = EXT && S.emul;   // the emulation reading: EXT kernels only
   const int op = S.k3op;
   const int n = a.A.n;
   const int base = blk * kVecBlock + threadIdx.x * kVecPer;
@@ -1789,9 +1817,13 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
       if (i >= n) break;
       const double r = a.v.r64[i];
       if (S.tier) {
-        a.v.p64[i] = PC ? (S.emul ? rd_rt_f64(act_fa(S.action), precond_z_rt(FP64, a.A.minv[i], r))
+        if constexpr (EXT) {
+          a.v.p64[i] = PC ? (emul ? rd_rt_f64(act_fa(S.action), precond_z_rt(FP64, a.A.minv[i], r))
                                   : precond_z_rt(FP64, a.A.minv[i], r))
-                        : r;
+                          : r;
+        } else {
+          a.v.p64[i] = PC ? precond_z_rt(FP64, a.A.minv[i], r) : r;
+        }
         a.v.xlo64[i] = 0.0;
       } else {
         const float f = (float)r;
@@ -1811,12 +1843,16 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
       for (int j = 0; j < 8; ++j) {
         if constexpr (PC) {
           double z = precond_z_rt(FP64, mv[j], rv[j]);
-          if (S.emul) z = rd_rt_f64(S.k3_fa, z);
+          if constexpr (EXT) {
+            if (emul) z = rd_rt_f64(S.k3_fa, z);
+          }
           pv[j] = S.dir_restart ? z : xpay_rt<double>(S.k3_fa, S.beta, pv[j], z);
         } else {
           pv[j] = xpay_rt<double>(S.k3_fa, S.beta, pv[j], rv[j]);
         }
-        if (S.emul && !(PC && S.dir_restart)) pv[j] = rd_rt_f64(S.k3_fa, pv[j]);
+        if constexpr (EXT) {
+          if (emul && !(PC && S.dir_restart)) pv[j] = rd_rt_f64(S.k3_fa, pv[j]);
+        }
       }
       store8(a.v.p64 + base, pv);
     } else {
@@ -1847,12 +1883,16 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
         double pn;
         if constexpr (PC) {
           double z = precond_z_rt(FP64, a.A.minv[i], a.v.r64[i]);
-          if (S.emul) z = rd_rt_f64(S.k3_fa, z);
+          if constexpr (EXT) {
+            if (emul) z = rd_rt_f64(S.k3_fa, z);
+          }
           pn = S.dir_restart ? z : xpay_rt<double>(S.k3_fa, S.beta, a.v.p64[i], z);
         } else {
           pn = xpay_rt<double>(S.k3_fa, S.beta, a.v.p64[i], a.v.r64[i]);
         }
-        if (S.emul && !(PC && S.dir_restart)) pn = rd_rt_f64(S.k3_fa, pn);
+        if constexpr (EXT) {
+          if (emul && !(PC && S.dir_restart)) pn = rd_rt_f64(S.k3_fa, pn);
+        }
         if (S.k3switch) {
           fold1(a.v.xhi, i, a.v.xlo64[i]);
           a.v.p32[i] = (float)pn;
@@ -1883,9 +1923,9 @@ __device__ __forceinline__ void exec_elementwise(const KArgs &a, const Ctl &S, i
 }
 
 #define MPCG_KB_CASE(FA, FD) \
-  case (FA) * 8 + (FD): kb_axpy<FA, FD, PC, R64>(a, S, fold_now, blk); break;
+  case (FA) * 8 + (FD): kb_axpy<FA, FD, PC, R64, EXT>(a, S, fold_now, blk); break;
 #define MPCG_KB_VALS(FA, FD) \
-  case (FA) * 8 + (FD): kb_axpy_vals<FA, FD, PC, R64>(a, S, fold_now, blk, pv, qv, rv, xv); break;
+  case (FA) * 8 + (FD): kb_axpy_vals<FA, FD, PC, R64, EXT>(a, S, fold_now, blk, pv, qv, rv, xv); break;
 
 // KB's vector work for 2048-element block blk.
 // x_lo and r updates with bf16 updates in the bf16 containers (16-bit vector
@@ -1946,7 +1986,7 @@ __device__ __forceinline__ void kb_axpy16(const KArgs &a, const Ctl &S, bool fol
   if (threadIdx.x == 0) a.part2[blk] = (double)t;
 }
 
-template <bool PC = false, bool R64 = false, bool V16 = false>
+template <bool PC = false, bool R64 = false, bool V16 = false, bool EXT = true>
 __device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, bool fold_now, int blk) {
   if (V16 && bop == B_AXPY && S.tier == 2) {
     if constexpr (V16) {
@@ -1960,18 +2000,27 @@ __device__ __forceinline__ void kb_work(const KArgs &a, const Ctl &S, int bop, b
     }
   } else if (bop == B_AXPY) {
     const int act = S.action;
-    switch (S.emul ? FP64 * 8 + FP64 : act_fa(act) * 8 + act_fd(act)) {
-      MPCG_KB_CASE(FP16, FP16) MPCG_KB_CASE(FP16, BF16) MPCG_KB_CASE(FP16, FP32) MPCG_KB_CASE(FP16, FP64)
-      MPCG_KB_CASE(BF16, FP16) MPCG_KB_CASE(BF16, BF16) MPCG_KB_CASE(BF16, FP32) MPCG_KB_CASE(BF16, FP64)
-      MPCG_KB_CASE(FP32, FP16) MPCG_KB_CASE(FP32, BF16) MPCG_KB_CASE(FP32, FP32) MPCG_KB_CASE(FP32, FP64)
-      MPCG_KB_CASE(FP64, FP16) MPCG_KB_CASE(FP64, BF16) MPCG_KB_CASE(FP64, FP32) MPCG_KB_CASE(FP64, FP64)
-      MPCG_KB_CASE(FP16, TF32) MPCG_KB_CASE(BF16, TF32) MPCG_KB_CASE(FP32, TF32) MPCG_KB_CASE(FP64, TF32)
-      MPCG_KB_CASE(TF32, FP16) MPCG_KB_CASE(TF32, BF16) MPCG_KB_CASE(TF32, FP32) MPCG_KB_CASE(TF32, FP64)
-      MPCG_KB_CASE(TF32, TF32)
-    default: break;
+    const int key = (EXT && S.emul) ? FP64 * 8 + FP64 : act_fa(act) * 8 + act_fd(act);
+    if (EXT && (act_fa(act) == TF32 || act_fd(act) == TF32) && !S.emul) {
+      if constexpr (EXT) {
+        switch (key) {
+          MPCG_KB_CASE(FP16, TF32) MPCG_KB_CASE(BF16, TF32) MPCG_KB_CASE(FP32, TF32) MPCG_KB_CASE(FP64, TF32)
+          MPCG_KB_CASE(TF32, FP16) MPCG_KB_CASE(TF32, BF16) MPCG_KB_CASE(TF32, FP32) MPCG_KB_CASE(TF32, FP64)
+          MPCG_KB_CASE(TF32, TF32)
+        default: break;
+        }
+      }
+    } else {
+      switch (key) {
+        MPCG_KB_CASE(FP16, FP16) MPCG_KB_CASE(FP16, BF16) MPCG_KB_CASE(FP16, FP32) MPCG_KB_CASE(FP16, FP64)
+        MPCG_KB_CASE(BF16, FP16) MPCG_KB_CASE(BF16, BF16) MPCG_KB_CASE(BF16, FP32) MPCG_KB_CASE(BF16, FP64)
+        MPCG_KB_CASE(FP32, FP16) MPCG_KB_CASE(FP32, BF16) MPCG_KB_CASE(FP32, FP32) MPCG_KB_CASE(FP32, FP64)
+        MPCG_KB_CASE(FP64, FP16) MPCG_KB_CASE(FP64, BF16) MPCG_KB_CASE(FP64, FP32) MPCG_KB_CASE(FP64, FP64)
+      default: break;
+      }
     }
   } else if (bop == B_EXEC) {
-    exec_elementwise<PC, V16>(a, S, blk);
+    exec_elementwise<PC, V16, EXT>(a, S, blk);
   }
 }
 
@@ -1989,7 +2038,7 @@ __device__ __forceinline__ void kb_commit(Ctl &S, int bop, bool fold_now) {
 
 // KB's work on vector block blk of one system; block 0 commits the state.
 // The step's partials are loaded together with the control block.
-template <bool FULL = false, bool PC = false, bool R64 = false, bool V16 = false>
+template <bool FULL = false, bool PC = false, bool R64 = false, bool V16 = false, bool EXT = true>
 __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
@@ -2002,7 +2051,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
   const Sx x{&S, &SP, a.h, blk == 0};
   const int base = blk * kVecBlock + threadIdx.x * kVecPer;
   const bool blk_full = (blk + 1) * kVecBlock <= a.A.n;   // block-uniform
-  if (!S.step_done && S.mode == M_ITER && !S.emul && S.tier == 0 && act_fa(S.action) != FP64 && blk_full) {
+  if (!S.step_done && S.mode == M_ITER && !(EXT && S.emul) && S.tier == 0 && act_fa(S.action) != FP64 && blk_full) {
     // an iteration in the fp32 containers on a whole block: the four operands
     // are in flight while the alpha step runs
     float pv[8], qv[8], rv[8], xv[8];
@@ -2012,22 +2061,30 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
     load8(a.v.r32 + base, rv);
     load8(a.v.xlo32 + base, xv);
     __builtin_amdgcn_sched_barrier(0);
-    step_b<FULL>(x, a, pre, fast);
+    step_b<FULL, EXT>(x, a, pre, fast);
     const int bop = S.b_op;
     const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
     if (bop == B_AXPY) {
       const int act = S.action;
-      switch (act_fa(act) * 8 + act_fd(act)) {
-        MPCG_KB_VALS(FP16, FP16) MPCG_KB_VALS(FP16, BF16) MPCG_KB_VALS(FP16, FP32) MPCG_KB_VALS(FP16, FP64)
-        MPCG_KB_VALS(BF16, FP16) MPCG_KB_VALS(BF16, BF16) MPCG_KB_VALS(BF16, FP32) MPCG_KB_VALS(BF16, FP64)
-        MPCG_KB_VALS(FP32, FP16) MPCG_KB_VALS(FP32, BF16) MPCG_KB_VALS(FP32, FP32) MPCG_KB_VALS(FP32, FP64)
-        MPCG_KB_VALS(FP16, TF32) MPCG_KB_VALS(BF16, TF32) MPCG_KB_VALS(FP32, TF32)
-        MPCG_KB_VALS(TF32, FP16) MPCG_KB_VALS(TF32, BF16) MPCG_KB_VALS(TF32, FP32) MPCG_KB_VALS(TF32, FP64)
-        MPCG_KB_VALS(TF32, TF32)
-      default: break;
+      if (EXT && (act_fa(act) == TF32 || act_fd(act) == TF32)) {
+        if constexpr (EXT) {
+          switch (act_fa(act) * 8 + act_fd(act)) {
+            MPCG_KB_VALS(FP16, TF32) MPCG_KB_VALS(BF16, TF32) MPCG_KB_VALS(FP32, TF32)
+            MPCG_KB_VALS(TF32, FP16) MPCG_KB_VALS(TF32, BF16) MPCG_KB_VALS(TF32, FP32) MPCG_KB_VALS(TF32, FP64)
+            MPCG_KB_VALS(TF32, TF32)
+          default: break;
+          }
+        }
+      } else {
+        switch (act_fa(act) * 8 + act_fd(act)) {
+          MPCG_KB_VALS(FP16, FP16) MPCG_KB_VALS(FP16, BF16) MPCG_KB_VALS(FP16, FP32) MPCG_KB_VALS(FP16, FP64)
+          MPCG_KB_VALS(BF16, FP16) MPCG_KB_VALS(BF16, BF16) MPCG_KB_VALS(BF16, FP32) MPCG_KB_VALS(BF16, FP64)
+          MPCG_KB_VALS(FP32, FP16) MPCG_KB_VALS(FP32, BF16) MPCG_KB_VALS(FP32, FP32) MPCG_KB_VALS(FP32, FP64)
+        default: break;
+        }
       }
     } else {
-      kb_work<PC, R64, V16>(a, S, bop, fold_now, blk);
+      kb_work<PC, R64, V16, EXT>(a, S, bop, fold_now, blk);
     }
     if (blk == 0) {
       __syncthreads();
@@ -2037,10 +2094,10 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
     }
     return;
   }
-  if (!S.step_done) step_b<FULL>(x, a, pre, fast);
+  if (!S.step_done) step_b<FULL, EXT>(x, a, pre, fast);
   const int bop = S.b_op;
   const bool fold_now = (bop == B_AXPY) && S.R > 0 && (S.k + 1) % S.R == 0;
-  kb_work<PC, R64, V16>(a, S, bop, fold_now, blk);
+  kb_work<PC, R64, V16, EXT>(a, S, bop, fold_now, blk);
   if (blk == 0) {   // commit the state after this kernel for KX
     __syncthreads();
     if (threadIdx.x == 0) kb_commit(S, bop, fold_now);
@@ -2053,7 +2110,7 @@ __device__ __forceinline__ void kb_body(const KArgs &a, int blk) {
 // elementwise operation; block 0 commits the state.  The partials come with
 // the control block, and the direction update's operands are issued before
 // the step's arithmetic, so the step's latency overlaps the vector loads.
-template <int TIER, bool PC, bool V16 = false>
+template <int TIER, bool PC, bool V16 = false, bool EXT = true>
 __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S, int blk, const double (&pre)[8],
                                             bool have_pre) {
   using V = typename TierT<TIER>::type;
@@ -2069,7 +2126,7 @@ __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S,
     if constexpr (PC) load8(a.A.minv + base, mv);
   }
   __builtin_amdgcn_sched_barrier(0);
-  step_x<false>(x, a, pre, have_pre);
+  step_x<false, EXT>(x, a, pre, have_pre);
   if (S.k3op == K3_XPAY && !S.k3switch && full) {
     if constexpr (TIER) {
       const double beta = S.beta;
@@ -2077,12 +2134,16 @@ __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S,
       for (int j = 0; j < 8; ++j) {
         if constexpr (PC) {
           double z = precond_z<FP64>(mv[j], rv[j]);
-          if (S.emul) z = rd_rt_f64(S.k3_fa, z);
+          if constexpr (EXT) {
+            if (S.emul) z = rd_rt_f64(S.k3_fa, z);
+          }
           pv[j] = S.dir_restart ? z : __builtin_fma(beta, pv[j], z);
         } else {
           pv[j] = __builtin_fma(beta, pv[j], rv[j]);
         }
-        if (S.emul && !(PC && S.dir_restart)) pv[j] = rd_rt_f64(S.k3_fa, pv[j]);
+        if constexpr (EXT) {
+          if (S.emul && !(PC && S.dir_restart)) pv[j] = rd_rt_f64(S.k3_fa, pv[j]);
+        }
       }
       store8(a.v.p64 + base, pv);
     } else {
@@ -2102,7 +2163,7 @@ __device__ __forceinline__ void kx_iter_pre(const KArgs &a, const Sx &x, Ctl &S,
       store8(a.v.p32 + base, pv);
     }
   } else {
-    exec_elementwise<PC, V16>(a, S, blk);
+    exec_elementwise<PC, V16, EXT>(a, S, blk);
   }
 }
 
@@ -2132,7 +2193,7 @@ __device__ __forceinline__ void kx_iter16(const KArgs &a, const Sx &x, Ctl &S, i
   }
 }
 
-template <bool PC = false, bool V16 = false>
+template <bool PC = false, bool V16 = false, bool EXT = true>
 __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   __shared__ Ctl S;
   __shared__ PolicyDev SP;
@@ -2145,11 +2206,11 @@ __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
   const Sx x{&S, &SP, a.h, blk == 0, nullptr};
   if (!S.step_done && S.pend_sigma) {
     if (V16 && S.tier == 2) kx_iter16(a, x, S, blk, pre, fast);
-    else if (S.tier) kx_iter_pre<1, PC, V16>(a, x, S, blk, pre, fast);
-    else kx_iter_pre<0, PC, V16>(a, x, S, blk, pre, fast);
+    else if (S.tier) kx_iter_pre<1, PC, V16, EXT>(a, x, S, blk, pre, fast);
+    else kx_iter_pre<0, PC, V16, EXT>(a, x, S, blk, pre, fast);
   } else {
-    if (!S.step_done) step_x<false>(x, a, pre, fast);
-    exec_elementwise<PC, V16>(a, S, blk);
+    if (!S.step_done) step_x<false, EXT>(x, a, pre, fast);
+    exec_elementwise<PC, V16, EXT>(a, S, blk);
   }
   if (blk == 0) {   // commit the state after this kernel for the next KA and KB
     __syncthreads();
@@ -2163,18 +2224,22 @@ __device__ __forceinline__ void kx_body(const KArgs &a, int blk) {
 }
 
 #if MPCG_IN_PART(2)
-__global__ __launch_bounds__(kBlock) void k_b(KArgs a) { kb_body(a, blockIdx.x); }
-
-// The variants with the bf16 vector tier (16-bit vector storage).
-__global__ __launch_bounds__(kBlock) void k_b16(KArgs a) { kb_body<false, false, false, true>(a, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void k_b_full16(KArgs a) { kb_body<true, false, false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b(KArgs a) { kb_body<false, false, false, false, false>(a, blockIdx.x); }
 
 // KB whose replicated step is the full one (state features, the network's
 // decision at a start or a stop, rollout log by workgroup 0): for policies
 // that read but never write shared policy state during a solve.  Their
 // end-of-iteration decision runs once, in the one-block step kernel before KX.
-__global__ __launch_bounds__(kBlock) void k_b_full(KArgs a) { kb_body<true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_full(KArgs a) { kb_body<true, false, false, false, false>(a, blockIdx.x); }
 #endif  // part 2
+
+#if MPCG_IN_PART(8)
+// The tf32 / emulation variants and the bf16 vector tier (16-bit vector storage).
+__global__ __launch_bounds__(kBlock) void k_b_ext(KArgs a) { kb_body<false, false, false, false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_full_ext(KArgs a) { kb_body<true, false, false, false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b16(KArgs a) { kb_body<false, false, false, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_b_full16(KArgs a) { kb_body<true, false, false, true>(a, blockIdx.x); }
+#endif  // part 8
 
 #if MPCG_IN_PART(3)
 // The Jacobi-preconditioned variants of KB (separate kernels, so the
@@ -2194,7 +2259,8 @@ __global__ __launch_bounds__(kBlock) void k_b_full_pc_r64(KArgs a) { kb_body<tru
 
 #if MPCG_IN_PART(4) || MPCG_KPART == 5   // device steps shared with the batched kernels
 #if MPCG_IN_PART(4)
-__global__ __launch_bounds__(kBlock) void k_x(KArgs a) { kx_body(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_x(KArgs a) { kx_body<false, false, false>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_x_ext(KArgs a) { kx_body<false, false, true>(a, blockIdx.x); }
 #endif
 // the bf16 vector tier (16-bit vector storage) and the Jacobi-preconditioned KX
 #if MPCG_IN_PART(4)
@@ -2375,7 +2441,7 @@ __device__ __forceinline__ void ka_pass(const KArgs &a, const Ctl &S, void *lds)
 
 template <int FA, int FD>
 __device__ __forceinline__ void kb_axpy_all(const KArgs &a, const Ctl &S, bool fold_now) {
-  for (int blk = 0; blk < a.P2; ++blk) kb_axpy<FA, FD, false, false>(a, S, fold_now, blk);
+  for (int blk = 0; blk < a.P2; ++blk) kb_axpy<FA, FD, false, false, false>(a, S, fold_now, blk);
 }
 
 #define MPCG_KB_ALL(FA, FD) \
@@ -2685,17 +2751,18 @@ static void launch_timed(K kern, int grid, const KArgs &a, hipStream_t s, hipEve
   else hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
 }
 void launch_ka(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  launch_timed(a.vec16 ? k_a16 : k_a, a.G1, a, s, e0, e1);
+  launch_timed(a.vec16 ? k_a16 : a.ext ? k_a_ext : k_a, a.G1, a, s, e0, e1);
 }
 void launch_kb(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (a.rho64 && a.precond) launch_timed(a.full ? k_b_full_pc_r64 : k_b_pc_r64, a.P2, a, s, e0, e1);
   else if (a.rho64) launch_timed(a.full ? k_b_full_r64 : k_b_r64, a.P2, a, s, e0, e1);
   else if (a.precond) launch_timed(a.full ? k_b_full_pc : k_b_pc, a.P2, a, s, e0, e1);
   else if (a.vec16) launch_timed(a.full ? k_b_full16 : k_b16, a.P2, a, s, e0, e1);
+  else if (a.ext) launch_timed(a.full ? k_b_full_ext : k_b_ext, a.P2, a, s, e0, e1);
   else launch_timed(a.full ? k_b_full : k_b, a.P2, a, s, e0, e1);
 }
 void launch_kx(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  launch_timed(a.precond ? k_x_pc : a.vec16 ? k_x16 : k_x, a.P2, a, s, e0, e1);
+  launch_timed(a.precond ? k_x_pc : a.vec16 ? k_x16 : a.ext ? k_x_ext : k_x, a.P2, a, s, e0, e1);
 }
 void launch_step_b(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) { launch_timed(k_step_b, 1, a, s, e0, e1); }
 void launch_step_x(const KArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

@@ -128,6 +128,7 @@ struct KArgs {
   int precond;         // 1: launch the preconditioned KB / KX variants (Ctl.precond set too)
   int rho64;           // 1: launch the KB variant with rho in fp64 (Ctl.rho64 set too)
   int vec16;           // 1: launch the KA/KB/KX variants with the bf16 vector tier
+  int ext;             // 1: launch the variants with tf32 and the emulation reading
   int8_t *slot_log;    // optional: KA records the mode of each slot (profiling)
   int slot;            // index of this slot (with slot_log)
 };
