@@ -104,6 +104,7 @@ class Hist(C.Structure):
         ("roll_done", C.POINTER(C.c_uint8)), ("roll_n", C.c_int32), ("dump_cap", C.c_int32),
         ("hist_alpha", C.POINTER(C.c_double)), ("hist_beta", C.POINTER(C.c_double)),
         ("dump_p", C.POINTER(C.c_double)), ("dump_r", C.POINTER(C.c_double)),
+        ("dump_s", C.POINTER(C.c_double)),
     ]
 
 
@@ -156,6 +157,8 @@ def lib():
         L.orc_cg.argtypes = [i64, ip, ip, dp, dp, dp, dp, C.POINTER(Params), C.POINTER(Policy),
                              C.POINTER(Result), C.POINTER(Hist)]
         L.orc_cg_plain.restype = C.c_int
+        L.orc_cg_sr.argtypes = [i64, ip, ip, dp, dp, dp, dp, C.c_int, C.POINTER(Params), C.POINTER(Result),
+                                C.POINTER(Hist)]
         L.orc_cg_plain.argtypes = [i64, ip, ip, dp, dp, dp, d, C.c_int32, ip, dp]
         _lib = L
     return _lib
@@ -426,6 +429,48 @@ def cg(A, b, x0=None, tol=1e-8, maxit=1000, policy: OraclePolicy | None = None,
     if roll is not None:
         m = h.roll_n
         info["rollouts"] = {key: v[:m].copy() for key, v in roll.items()}
+    return x, info
+
+
+def cg_sr(A, b, action, x0=None, tol=1e-8, maxit=1000, replace_period=0, order=ORDER_PAIRWISE, dump=0):
+    """Run the oracle's single-reduction CG (Chronopoulos-Gear: one SpMV and
+    both inner products per iteration) with a fixed action.  dump > 0 keeps
+    alpha, beta and the p, r, s used by the first `dump` iterations.
+    Returns (x, info dict with histories)."""
+    n = A.n
+    b = _f64(b)
+    x0 = np.zeros(n) if x0 is None else _f64(x0)
+    x = np.empty(n)
+    prm = Params(tol, maxit, replace_period, 0, order, 0, 0, 0, 0, 0)
+    res = Result()
+    hist_rho = np.full(maxit + 1, np.nan)
+    hist_act = np.zeros(max(maxit, 1), dtype=np.uint8)
+    hist_flag = np.zeros(max(maxit, 1), dtype=np.uint8)
+    rep_cap = maxit + 2
+    rep_k = np.zeros(rep_cap, dtype=np.int32)
+    rep_rho = np.zeros(rep_cap)
+    h = Hist()
+    h.hist_rho, h.hist_act, h.hist_flag = _p(hist_rho), _p(hist_act, C.c_uint8), _p(hist_flag, C.c_uint8)
+    h.rep_k, h.rep_rho, h.rep_cap = _p(rep_k, C.c_int32), _p(rep_rho), rep_cap
+    dumps = None
+    if dump > 0:
+        dumps = dict(alpha=np.full(dump, np.nan), beta=np.full(dump, np.nan),
+                     p=np.zeros((dump, n)), r=np.zeros((dump, n)), s=np.zeros((dump, n)))
+        h.dump_cap = dump
+        h.hist_alpha, h.hist_beta = _p(dumps["alpha"]), _p(dumps["beta"])
+        h.dump_p, h.dump_r, h.dump_s = _p(dumps["p"]), _p(dumps["r"]), _p(dumps["s"])
+    rc = lib().orc_cg_sr(n, _p(_i32(A.row_ptr), C.c_int32), _p(_i32(A.col), C.c_int32), _p(_f64(A.val)),
+                         _p(b), _p(x0), _p(x), int(action), C.byref(prm), C.byref(res), C.byref(h))
+    if rc != 0:
+        raise ValueError(f"single-reduction CG takes actions 0..79, not {action}")
+    k = res.iters
+    nrep = min(res.n_replace, rep_cap)
+    info = dict(status=res.status, iters=k, n_replace=res.n_replace, fallback_at=res.fallback_at,
+                relres_true=res.relres_true, cost_sum=res.cost_sum,
+                rho=hist_rho[:k + 1].copy(), actions=hist_act[:k].copy(), flags=hist_flag[:k].copy(),
+                rep_k=rep_k[:nrep].copy(), rep_rho=rep_rho[:nrep].copy())
+    if dumps is not None:
+        info["dump"] = dumps
     return x, info
 
 

@@ -717,6 +717,8 @@ typedef struct {
     double *hist_beta;         /* [dump_cap] or NULL */
     double *dump_p;            /* [dump_cap][n] direction used by iteration k, or NULL */
     double *dump_r;            /* [dump_cap][n] residual r at the start of iteration k, or NULL */
+    double *dump_s;            /* single-reduction CG: [dump_cap][n] s (the recurrence
+                                  for A p) used by iteration k, or NULL */
 } orc_hist;
 
 /* Stagnation flag of the state (a reading: the paper's state has no such
@@ -1104,6 +1106,149 @@ int orc_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
 out:
     free(xhi); free(xlo); free(r); free(p); free(q); free(r64); free(z);
     free(minv);
+    mat_free(&A);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-reduction CG (Chronopoulos and Gear, 1989).                        */
+/* ------------------------------------------------------------------------ */
+/* The CG iteration of section 3 rearranged so that both inner products of an
+ * iteration are taken together, right after its one SpMV: with w = A r,
+ *   gamma_k = r_k.r_k,  delta_k = r_k.w_k,
+ *   beta_k  = gamma_k / gamma_{k-1}            (beta_0 = 0),
+ *   alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+ *                                              (alpha_0 = gamma_0 / delta_0),
+ *   p_k = r_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}   (s_k = A p_k),
+ *   x_{k+1} = x_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k.
+ * In exact arithmetic the iterates are those of section 3's CG.
+ *
+ * Precision (a fixed action, as in section 4.2's operation list): the SpMV
+ * w = A r at f_s, both inner products at f_d, the four vector updates at f_a
+ * (each element rounded to f_a, vectors held in fp32 or, for f_a = fp64, fp64
+ * containers), alpha and beta in fp64, x = x_hi (fp64) + x_lo (f_a) as in the
+ * main solver.  True-residual replacement (every R iterations, and when the
+ * recursive rho_k = sqrt(gamma_k) / ||b|| is <= tol) folds x_lo into x_hi,
+ * sets r = rd(b - A x_hi) and, before the next update, recomputes s = A p at
+ * f_s (the replacement of the recurrences' vectors by their true values used
+ * for pipelined CG by Cools et al., 2018).  Stops when the true fp64 relres
+ * is <= tol at a replacement, after maxit iterations, or when
+ * delta_k - beta_k gamma_k / alpha_{k-1} is not positive or a scalar is not
+ * finite (breakdown).  No fallback and no policy: cost_sum is 0.
+ * History: rho_k is the true relres at the start and at replacements, the
+ * recursive one otherwise; act[k] is the action; FL_REPLACED marks the
+ * iteration that ended at a replacement. */
+int orc_cg_sr(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+              const double *b, const double *x0, double *x_out, int action,
+              const orc_params *prm, orc_result *res, orc_hist *h)
+{
+    memset(res, 0, sizeof(*res));
+    res->fallback_at = -1;
+    h->roll_n = 0;
+    if (action < 0 || action >= 80) return -1;           /* the 4-format set and q52 SpMV */
+    orc_mat A;
+    mat_build(&A, n, rp, ci, v);
+    size_t bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *xhi = malloc(bytes), *xlo = malloc(bytes), *r = malloc(bytes), *w = malloc(bytes);
+    double *p = malloc(bytes), *sv = malloc(bytes), *r64 = malloc(bytes);
+    const int fs = act_fs(action), fd = act_fd(action), fa = act_fa(action);
+    const int tier = fa == F64 ? 1 : 0;
+    const int R = prm->replace_period;
+    const int order = prm->dot_order;
+    double *hist_rho = h->hist_rho;
+    int64_t k = 0;
+    int nrep = 0, status = -1;
+    double gamma_old = 0.0, alpha_old = 0.0, last_true = 0.0;
+
+    double bnorm = sqrt(orc_dot(n, b, b, F64, order));
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x_out[i] = 0.0;
+        hist_rho[0] = 0.0;
+        res->status = 0;
+        goto out;
+    }
+    for (int64_t i = 0; i < n; ++i) { xhi[i] = x0[i]; xlo[i] = 0.0; }
+
+    /* start: the true residual; the first pass then takes beta = 0 */
+    mat_residual(&A, b, xhi, r64);
+    last_true = sqrt(orc_dot(n, r64, r64, F64, order)) / bnorm;
+    hist_rho[0] = last_true;
+    if (last_true <= prm->tol) { status = 0; goto done; }
+    if (!isfinite(last_true)) { status = 3; goto done; }
+    if (prm->maxit <= 0) { status = 1; goto done; }
+    for (int64_t i = 0; i < n; ++i) r[i] = rd_tier(r64[i], tier);
+    int first = 1, sync = 1;     /* sync: the pass after a start or replacement */
+
+    for (;;) {
+        mat_spmv(&A, fs, tier, r, w);
+        if (sync && !first) mat_spmv(&A, fs, tier, p, sv);   /* s = A p again */
+        const double gamma = orc_dot(n, r, r, fd, order);
+        const double delta = orc_dot(n, r, w, fd, order);
+        int replace = 0;
+        if (!sync) {
+            const double rho = sqrt(gamma) / bnorm;
+            hist_rho[k] = rho;
+            if (rho <= prm->tol) replace = 1;                 /* check it */
+            else if (k >= prm->maxit) { status = 1; break; }
+        }
+        if (!replace) {
+            sync = 0;
+            const double beta = first ? 0.0 : gamma / gamma_old;
+            const double den = first ? delta : delta - beta * gamma / alpha_old;
+            const double alpha = gamma / den;
+            if (!(den > 0.0) || !isfinite(alpha) || !isfinite(beta) || !isfinite(gamma)) { status = 3; break; }
+            if (k < h->dump_cap && h->hist_alpha) h->hist_alpha[k] = alpha;
+            if (k < h->dump_cap && h->hist_beta) h->hist_beta[k] = beta;
+            if (first) {
+                memcpy(p, r, bytes);
+                memcpy(sv, w, bytes);
+            } else {
+                xpay(n, beta, r, p, fa);
+                xpay(n, beta, w, sv, fa);
+            }
+            if (k < h->dump_cap && h->dump_p) memcpy(&h->dump_p[k * n], p, bytes);
+            if (k < h->dump_cap && h->dump_r) memcpy(&h->dump_r[k * n], r, bytes);
+            if (k < h->dump_cap && h->dump_s) memcpy(&h->dump_s[k * n], sv, bytes);
+            orc_axpy(n, alpha, p, xlo, fa);
+            orc_axpy(n, -alpha, sv, r, fa);
+            h->hist_act[k] = (uint8_t)action;
+            h->hist_flag[k] = 0;
+            gamma_old = gamma;
+            alpha_old = alpha;
+            first = 0;
+            k += 1;
+            replace = R > 0 && k % R == 0;
+        }
+        if (replace) {
+            fold(n, xhi, xlo);
+            mat_residual(&A, b, xhi, r64);
+            const double rt = sqrt(orc_dot(n, r64, r64, F64, order)) / bnorm;
+            if (nrep < h->rep_cap) { h->rep_k[nrep] = (int32_t)k; h->rep_rho[nrep] = rt; }
+            nrep++;
+            if (k > 0) h->hist_flag[k - 1] |= FL_REPLACED;
+            hist_rho[k] = rt;
+            last_true = rt;
+            if (rt <= prm->tol) { status = 0; break; }
+            if (!isfinite(rt)) { status = 3; break; }
+            if (k >= prm->maxit) { status = 1; break; }
+            for (int64_t i = 0; i < n; ++i) r[i] = rd_tier(r64[i], tier);
+            sync = 1;
+        }
+    }
+done:
+    fold(n, xhi, xlo);
+    for (int64_t i = 0; i < n; ++i) x_out[i] = xhi[i];
+    if (status == 0) {
+        res->relres_true = last_true;
+    } else {
+        mat_residual(&A, b, xhi, r64);
+        res->relres_true = sqrt(orc_dot(n, r64, r64, F64, order)) / bnorm;
+    }
+    res->status = status;
+    res->iters = (int32_t)k;
+    res->n_replace = nrep;
+out:
+    free(xhi); free(xlo); free(r); free(w); free(p); free(sv); free(r64);
     mat_free(&A);
     return 0;
 }
