@@ -574,6 +574,8 @@ def main():
     ap.add_argument("--counters-maxit", type=int, default=5000,
                     help="iteration budget of the counter run's solve")
     ap.add_argument("--counters-fp64", action="store_true", help="counter run with the fp64 action")
+    ap.add_argument("--counters-variant", type=int, choices=[0, 1], default=0,
+                    help="counter run with the single-reduction CG (1)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU only (--gpus {args.gpus} requested); "
@@ -636,10 +638,11 @@ def main():
         pol = pol_fp64 if args.counters_fp64 else pol_mixed
         fs, vb = (M.FP64, 8) if args.counters_fp64 else (M.BF16, 4)
         m.set_policy(pol)
-        m.set_options(replace_period=0 if args.counters_fp64 else 50, fallback=False)
+        m.set_options(replace_period=0 if args.counters_fp64 else 50, fallback=False, variant=args.counters_variant)
         r = m.solve(bd, xd, tol=tol, maxit=args.counters_maxit)
         print(json.dumps({"counters_run": True, "system": A.name, "n": A.n, "nnz": A.nnz,
-                          "action": "fp64" if args.counters_fp64 else "mixed", "copy_bytes": COPY_BYTES,
+                          "action": "fp64" if args.counters_fp64 else "mixed", "variant": args.counters_variant,
+                          "copy_bytes": COPY_BYTES,
                           "iters": r["iters"], "relres_true": r["relres_true"], "kernel_hash": kernel_hash(),
                           "algorithmic_bytes_per_launch_ka": ka_bytes(A.n, A.nnz, fs, vb, 4),
                           "moved_bytes_per_launch_ka": ka_bytes(A.n, A.nnz, fs, vb,
@@ -647,9 +650,9 @@ def main():
               flush=True)
         return
 
-    def solve(pol, R, maxit=5000, profile=False, vec16=0):
+    def solve(pol, R, maxit=5000, profile=False, vec16=0, variant=0):
         m.set_policy(pol)
-        m.set_options(replace_period=R, fallback=False, profile=profile, vec16=vec16)
+        m.set_options(replace_period=R, fallback=False, profile=profile, vec16=vec16, variant=variant)
         xd.zero_()
         return m.solve(bd, xd, tol=tol, maxit=maxit)
 
@@ -705,6 +708,20 @@ def main():
     assert r64["status"] == 0, r64
     fp64_ms = float(np.median([r["time_ms"] for r in fp64_runs]))
     log(f"[bench] fp64: {r64['iters']} it, relres {r64['relres_true']:.3e}, device {fp64_ms:.2f} ms")
+
+    # single-reduction CG (two launches per iteration), the same actions
+    sr = {}
+    for name, pol, R in (("mixed", pol_mixed, 50), ("fp64", pol_fp64, 0)):
+        solve(pol, R, variant=1)
+        runs = [solve(pol, R, variant=1) for _ in range(max(1, args.steps // 2))]
+        rs = runs[-1]
+        assert rs["status"] == 0 and rs["relres_true"] <= tol, rs
+        sr[name] = {"ms": round(float(np.median([r["time_ms"] for r in runs])), 3), "iters": rs["iters"],
+                    "n_replace": rs["n_replace"], "relres_true": rs["relres_true"]}
+    sr["mixed"]["speedup_vs_three_launch_mixed"] = round(dev_ms / sr["mixed"]["ms"], 3)
+    sr["mixed"]["speedup_vs_fp64"] = round(fp64_ms / sr["mixed"]["ms"], 3)
+    sr["fp64"]["speedup_vs_three_launch_fp64"] = round(fp64_ms / sr["fp64"]["ms"], 3)
+    log(f"[bench] single-reduction CG: {sr}")
 
     # profiled solves: HIP events around every launch of the same kernels
     rp = solve(pol_mixed, 50, profile=True)
@@ -788,6 +805,9 @@ def main():
             "kx_fp64": {"avg_us": round(k3_64_us, 3), "GB/s": round(bytes_k3_64 / (k3_64_us * 1e-6) / 1e9, 1)},
             "profiled_solve_ms": round(rp["time_ms"], 3),
         },
+        "single_reduction": dict(
+            variant="Chronopoulos-Gear CG: SpMV w = A r with both inner products fused, s = A p by "
+                    "recurrence, two launches per iteration", **sr),
         "vector_storage_16bit": {
             "action": "SpMV bf16, dot fp32, updates bf16, R=50, 200 iterations",
             "fp32_containers": v16[0], "bf16_containers": v16[1],

@@ -189,7 +189,21 @@ typedef struct {
                                   bf16 instead of fp32; the updates themselves
                                   are unchanged.  Not with precond, rho_fp64,
                                   emulate or batched solves.                    */
-    int32_t reserved;          /* 0 */
+    int32_t variant;           /* 0: the CG iteration of section 3 (three
+                                  launches per iteration); 1: single-reduction
+                                  CG (Chronopoulos and Gear, 1989): one SpMV
+                                  w = A r followed by both inner products,
+                                  gamma = r.r and delta = r.w, s = A p carried
+                                  by a recurrence, two launches per iteration;
+                                  in exact arithmetic the iterates of variant
+                                  0.  A replacement also recomputes s = A p.
+                                  Fixed policies with actions 0..79 only; not
+                                  with fallback, precond, stop_rule, rho_fp64,
+                                  emulate, vec16, profile or batched solves.
+                                  Low-precision updates make the recurrence
+                                  for s drift faster than section 3's
+                                  iteration; breakdown then ends the solve
+                                  with status MPCG_BREAKDOWN.                   */
 } mpcg_solve_opts;
 
 /* Per-kernel timing of the last solve made with opts.profile = 1.  One CG

@@ -56,7 +56,7 @@ class SolveOpts(C.Structure):
                 ("spmv_rows", C.c_int32), ("index16", C.c_int32),
                 ("precond", C.c_int32), ("stop_rule", C.c_int32),
                 ("rho_fp64", C.c_int32), ("emulate", C.c_int32),
-                ("vec16", C.c_int32), ("reserved", C.c_int32)]
+                ("vec16", C.c_int32), ("variant", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -467,9 +467,10 @@ class Matrix:
         self.policy = policy
 
     def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False, spmv_rows=0, index16=0,
-                    precond=0, stop_rule=0, rho_fp64=0, emulate=0, vec16=0):
+                    precond=0, stop_rule=0, rho_fp64=0, emulate=0, vec16=0, variant=0):
+        """variant 1: single-reduction CG (Chronopoulos-Gear), two launches per iteration."""
         o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, index16, int(precond),
-                      int(stop_rule), int(rho_fp64), int(emulate), int(vec16), 0)
+                      int(stop_rule), int(rho_fp64), int(emulate), int(vec16), int(variant))
         _check(lib().mpcg_set_options(self.h, C.byref(o)), "set_options")
 
     def solve(self, b, x, tol=1e-8, maxit=1000) -> dict:

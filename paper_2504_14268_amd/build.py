@@ -26,9 +26,9 @@ HIPCC_FLAGS = [
 ]
 
 
-# (source, extra flags, object): kernels.hip is compiled as eight parts in
+# (source, extra flags, object): kernels.hip is compiled as nine parts in
 # parallel (its MPCG_KPART selects the kernels of each object).
-UNITS = [("kernels.hip", [f"-DMPCG_KPART={k}"], f"kernels_p{k}.o") for k in range(1, 9)] + [
+UNITS = [("kernels.hip", [f"-DMPCG_KPART={k}"], f"kernels_p{k}.o") for k in range(1, 10)] + [
     ("mlp.hip", [], "mlp.o"), ("api.hip", [], "api.o")]
 
 

@@ -288,6 +288,10 @@ struct mpcg_matrix {
   double *d_part0 = nullptr, *d_part1 = nullptr, *d_part2 = nullptr, *d_scalar = nullptr;
   double *d_part1b = nullptr, *d_part2b = nullptr;   // preconditioned: r.(M^-1 r) partials
   float *d_minv = nullptr;     // Jacobi preconditioner: fp32 of 1 / a_ii
+  float *d_s32 = nullptr;      // single-reduction CG: s, the recurrence for A p
+  double *d_s64 = nullptr;
+  SrCtl *d_sr = nullptr;       // single-reduction CG: [2] control blocks
+  SrCtl *h_sr = nullptr;       // pinned [3]: the start state and the state after each chunk
   Ctl *d_ctl = nullptr;        // [2]
   Ctl *h_ctl = nullptr;        // pinned
   Ctl *h_poll = nullptr;       // pinned [2]: the control block after each chunk
@@ -308,7 +312,7 @@ struct mpcg_matrix {
   // policy
   mpcg_policy *pol = nullptr;
   mpcg_policy *defpol = nullptr;
-  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // replace_period .. emulate, vec16
+  mpcg_solve_opts opts{50, 0, 32, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // replace_period .. vec16, variant
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_chunk[2] = {nullptr, nullptr};
   int P2 = 0;
 
@@ -339,6 +343,9 @@ struct mpcg_matrix {
     dfree(d_r64); dfree(d_p64); dfree(d_q64); dfree(d_xlo64);
     dfree(d_part0); dfree(d_part1); dfree(d_part2); dfree(d_scalar); dfree(d_ctl); dfree(d_pol);
     dfree(d_part1b); dfree(d_part2b); dfree(d_minv);
+    dfree(d_s32); dfree(d_s64); dfree(d_sr);
+    if (h_sr) (void)hipHostFree(h_sr);
+    h_sr = nullptr;
     dfree(d_hrho); dfree(d_reprho); dfree(d_hact); dfree(d_hflag); dfree(d_repk); dfree(d_slotlog);
     for (hipEvent_t e : pev) (void)hipEventDestroy(e);
     pev.clear();
@@ -486,6 +493,133 @@ static KArgs make_args(mpcg_matrix *A, const double *b, double *x) {
   a.G1 = round_up(a.P1, 8);
   a.P2 = A->P2;
   return a;
+}
+
+// Chunk sizes follow the predicted end of the solve: from the last two polls,
+// the recursive residual's decay per iteration gives the iterations still
+// needed; once they fit in the chunk already in flight, the next chunks
+// shrink (to no fewer than 4 slots), so few idle slots run after the stop.
+struct ChunkPlan {
+  int chunk;
+  double tol;
+  int poll_k[2] = {-1, -1};   // last two polled (iteration, residual), newest first
+  double poll_rho[2] = {0.0, 0.0};
+  int in_flight = 0;          // slots of the newest enqueued chunk
+  int next() const {
+    if (poll_k[1] < 0 || poll_k[0] <= poll_k[1] || !(poll_rho[0] > 0.0) || !(poll_rho[1] > poll_rho[0]) ||
+        !std::isfinite(poll_rho[1]) || !(tol > 0.0))
+      return chunk;
+    if (poll_rho[0] <= tol) return std::min(chunk, 4);
+    const double rate = std::log(poll_rho[0] / poll_rho[1]) / (double)(poll_k[0] - poll_k[1]);   // < 0
+    const double need = std::log(tol / poll_rho[0]) / rate - (double)in_flight + 4.0;
+    if (!(need < (double)chunk)) return chunk;
+    return std::max(std::min(chunk, 4), (int)std::ceil(need));
+  }
+  void observe(int k, double rho) {
+    poll_k[1] = poll_k[0];
+    poll_rho[1] = poll_rho[0];
+    poll_k[0] = k;
+    poll_rho[0] = rho;
+  }
+};
+
+// Single-reduction CG (opts.variant = 1): one slot is KS1 (SpMV w = A r with
+// the partials of r.r and r.w, or an fp64 residual) and KS2 (scalar step and
+// the vector updates); the device decides each slot's phase, the host only
+// enqueues chunks of slots and polls the control block between them.
+static int solve_sr(mpcg_matrix *A, mpcg_policy *P, const double *b, double *x, double tol, int32_t maxit,
+                    mpcg_result *res) {
+  hipStream_t st = A->stream;
+  const size_t n = (size_t)A->n;
+  if (!A->d_sr) {
+    HIP_TRY(dmalloc(&A->d_s32, n));
+    HIP_TRY(dmalloc(&A->d_s64, n));
+    HIP_TRY(dmalloc(&A->d_sr, 2));
+    HIP_TRY(hipHostMalloc((void **)&A->h_sr, 3 * sizeof(SrCtl), hipHostMallocDefault));
+  }
+  const int act = P->desc.fixed_action;
+  SrCtl &c = A->h_sr[2];
+  std::memset(&c, 0, sizeof(SrCtl));
+  c.mode = SR_START;
+  c.maxit = maxit;
+  c.R = A->opts.replace_period;
+  c.status = -1;
+  c.first = 1;
+  c.action = act;
+  c.fs = act_fs(act);
+  c.fd = act_fd(act);
+  c.fa = act_fa(act);
+  c.tier = c.fa == FP64 ? 1 : 0;
+  c.tol = tol;
+  HIP_TRY(hipMemcpyAsync(A->d_sr, &c, sizeof(SrCtl), hipMemcpyHostToDevice, st));
+
+  const KArgs k = make_args(A, b, x);
+  SrArgs a{};
+  a.A = k.A;
+  a.v = k.v;
+  a.s32 = A->d_s32;
+  a.s64 = A->d_s64;
+  a.ctl = A->d_sr;
+  a.h = k.h;
+  a.pg = A->d_part1;
+  a.pd = A->d_part1b;
+  a.P1 = k.P1;
+  a.grows = k.grows;
+  a.G1 = k.G1;
+  a.P2 = k.P2;
+  a.tier = c.tier;
+
+  const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
+  // a start, one slot per iteration, up to two more per replacement, a final check
+  const int64_t max_slots = 3 * (int64_t)maxit + 16;
+  int64_t slots = 0;
+  int ci = 0;
+  ChunkPlan plan{chunk, tol};
+  HIP_TRY(hipEventRecord(A->ev_start, st));
+  while (slots < max_slots) {
+    const int m = (int)std::min<int64_t>(plan.next(), max_slots - slots);
+    plan.in_flight = m;
+    const int idx = ci & 1;
+    for (int j = 0; j < m; ++j) {
+      a.par = (int)((slots + j) & 1);
+      launch_sr_slot(a, st);
+    }
+    HIP_TRY(hipGetLastError());
+    slots += m;
+    // the state after the chunk's last slot
+    HIP_TRY(hipMemcpyAsync(&A->h_sr[idx], A->d_sr + (slots & 1), sizeof(SrCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(A->ev_chunk[idx], st));
+    if (ci > 0) {
+      const int pidx = (ci - 1) & 1;
+      HIP_TRY(hipEventSynchronize(A->ev_chunk[pidx]));
+      const SrCtl &pc = A->h_sr[pidx];
+      if (pc.mode == SR_DONE) break;
+      plan.observe(pc.k, pc.rho_new);
+    }
+    ci++;
+  }
+  HIP_TRY(hipEventRecord(A->ev_end, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  SrCtl &f = A->h_sr[2];
+  HIP_TRY(hipMemcpy(&f, A->d_sr + (slots & 1), sizeof(SrCtl), hipMemcpyDeviceToHost));
+  if (f.mode != SR_DONE) return fail(MPCG_ERR_DEVICE, "single-reduction solver did not reach a final state");
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, A->ev_start, A->ev_end));
+  std::memset(res, 0, sizeof(*res));
+  res->status = f.status;
+  res->iters = f.k;
+  res->n_replace = f.nrep;
+  res->fallback_at = -1;
+  res->relres_true = f.relres_true;
+  res->cost_sum = 0.0;
+  res->time_ms = ms;
+  res->slots = (int32_t)slots;
+  res->spmv_rows = a.grows;
+  res->index16 = a.A.dc ? 1 : 0;
+  A->last_iters = f.k;
+  A->last_nrep = f.nrep;
+  std::memset(&A->prof, 0, sizeof(A->prof));
+  return MPCG_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -914,7 +1048,12 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
   if (o->vec16 != 0 && o->vec16 != 1) return fail(MPCG_ERR_INVALID, "vec16 must be 0 or 1");
   if (o->vec16 && (o->precond || o->rho_fp64 || o->emulate))
     return fail(MPCG_ERR_INVALID, "vec16 runs without the preconditioner, fp64 rho and the emulation reading");
-  if (o->reserved != 0) return fail(MPCG_ERR_INVALID, "reserved must be 0");
+  if (o->variant != 0 && o->variant != 1) return fail(MPCG_ERR_INVALID, "variant must be 0 or 1");
+  if (o->variant == 1 &&
+      (o->fallback || o->precond || o->stop_rule || o->rho_fp64 || o->emulate || o->vec16 || o->profile))
+    return fail(MPCG_ERR_INVALID,
+                "the single-reduction variant runs without fallback, precond, stop_rule, rho_fp64, emulate, "
+                "vec16 and profile");
   A->opts = *o;
   return MPCG_OK;
 }
@@ -968,8 +1107,11 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   if (P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
   if (A->opts.emulate && P->desc.kind == MPCG_POLICY_FIXED && act_fs(P->desc.fixed_action) == FP8)
     return fail(MPCG_ERR_INVALID, "the emulation reading has no q52 SpMV (Table 1's q52 is storage only here)");
+  if (A->opts.variant == 1 && (P->desc.kind != MPCG_POLICY_FIXED || P->desc.fixed_action >= 80))
+    return fail(MPCG_ERR_INVALID, "the single-reduction variant takes a fixed policy with an action 0..79");
   hipStream_t st = A->stream;
   HIP_TRY(hipStreamSynchronize(st));   // staging buffers below are reused
+  if (A->opts.variant == 1) return solve_sr(A, P, b, x, tol, maxit, res);
 
   rc = upload_start(A, P, tol, maxit, st);
   if (rc) return rc;
@@ -1014,26 +1156,10 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   int64_t chunk_first[2] = {0, 0};
   int chunk_m[2] = {0, 0};
   bool pending[2] = {false, false};
-  // Chunk sizes follow the predicted end of the solve: from the last two polls,
-  // the recursive residual's decay per iteration gives the iterations still
-  // needed; once they fit in the chunk already in flight, the next chunks
-  // shrink (to no fewer than 4 slots), so few idle slots run after the stop.
-  int poll_k[2] = {-1, -1};   // last two polled (iteration, residual), newest first
-  double poll_rho[2] = {0.0, 0.0};
-  int in_flight = 0;          // slots of the newest enqueued chunk
-  auto next_chunk = [&]() -> int {
-    if (poll_k[1] < 0 || poll_k[0] <= poll_k[1] || !(poll_rho[0] > 0.0) || !(poll_rho[1] > poll_rho[0]) ||
-        !std::isfinite(poll_rho[1]) || !(tol > 0.0))
-      return chunk;
-    if (poll_rho[0] <= tol) return std::min(chunk, 4);
-    const double rate = std::log(poll_rho[0] / poll_rho[1]) / (double)(poll_k[0] - poll_k[1]);   // < 0
-    const double need = std::log(tol / poll_rho[0]) / rate - (double)in_flight + 4.0;
-    if (!(need < (double)chunk)) return chunk;
-    return std::max(std::min(chunk, 4), (int)std::ceil(need));
-  };
+  ChunkPlan plan{chunk, tol};
   while (slots < max_slots) {
-    const int m = (int)std::min<int64_t>(next_chunk(), max_slots - slots);
-    in_flight = m;
+    const int m = (int)std::min<int64_t>(plan.next(), max_slots - slots);
+    plan.in_flight = m;
     const int idx = ci & 1;
     chunk_first[idx] = slots;
     chunk_m[idx] = m;
@@ -1076,10 +1202,7 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
         done = true;
         break;
       }
-      poll_k[1] = poll_k[0];
-      poll_rho[1] = poll_rho[0];
-      poll_k[0] = pc.k;
-      poll_rho[0] = pc.rho_new;
+      plan.observe(pc.k, pc.rho_new);
     }
     ci++;
   }
@@ -1406,6 +1529,7 @@ int mpcg_solve_batched(int32_t nsys, mpcg_matrix *const *A, const double *const 
     if (A[i]->opts.rho_fp64) return fail(MPCG_ERR_INVALID, "batched solves take rho at the dot format (rho_fp64 = 0)");
     if (A[i]->opts.emulate) return fail(MPCG_ERR_INVALID, "batched solves run the hardware reading (emulate = 0)");
     if (A[i]->opts.vec16) return fail(MPCG_ERR_INVALID, "batched solves keep fp32 vector containers (vec16 = 0)");
+    if (A[i]->opts.variant) return fail(MPCG_ERR_INVALID, "batched solves run section 3's iteration (variant = 0)");
     mpcg_policy *P = A[i]->pol ? A[i]->pol : A[i]->defpol;
     if (P->desc.kind == MPCG_POLICY_QTABLE_TRAIN || P->roll_cap > 0)
       return fail(MPCG_ERR_INVALID, "training policies and rollout logs are not batched (shared state)");

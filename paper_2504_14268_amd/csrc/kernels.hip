@@ -27,12 +27,12 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 
-// The file is compiled as eight objects in parallel (MPCG_KPART = 1..8): the
+// The file is compiled as nine objects in parallel (MPCG_KPART = 1..9): the
 // plain SpMV kernel (1), the plain KB kernels (2), the preconditioned and
 // fp64-rho KB kernels (3, 6), everything else with every host launcher (4),
-// the batched kernels (5), and the tf32 / emulation / bf16-vector variants of
-// the SpMV (7) and of KB (8).  Without MPCG_KPART it is one object holding
-// all of them.
+// the batched kernels (5), the tf32 / emulation / bf16-vector variants of
+// the SpMV (7) and of KB (8), and the single-reduction CG with its launcher
+// (9).  Without MPCG_KPART it is one object holding all of them.
 #ifndef MPCG_KPART
 #define MPCG_KPART 0
 #endif
@@ -2968,5 +2968,522 @@ void launch_policy_decide(const PolicyDev *P, int m, const int64_t *k, const dou
 }
 
 #endif  // part 4
+
+
+#if MPCG_IN_PART(9)
+// ---------------------------------------------------------------------------
+// Single-reduction CG (Chronopoulos and Gear, 1989).  Section 3's iteration
+// rearranged so that its one SpMV, w = A r, is followed by both inner
+// products, gamma = r.r and delta = r.w, whose partials KS1 takes in the
+// SpMV's epilogue; s = A p is carried by a recurrence:
+//   beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old),
+//   p = r + beta p, s = w + beta s, x_lo += alpha p, r -= alpha s.
+// One iteration is two launches with one grid-wide dependency each (three in
+// the main solver) and the same vector traffic: KS1 reads r and writes w,
+// KS2 reads r, w, p, s, x_lo and writes p, s, x_lo, r.  A true-residual
+// replacement folds x_lo into x_hi (in the KS2 before it), replaces r by
+// rd(b - A x_hi), and the KS1 after it also recomputes s = A p.  Fixed
+// actions of the four-format set and q52 storage; no policy, fallback or
+// preconditioner.  Every workgroup of KS2 runs the scalar step identically
+// from KS1's partials; workgroup 0 commits the state to the other half of
+// the double buffer and writes the histories.
+// ---------------------------------------------------------------------------
+
+// KS1 of an iteration: w = A_fs r over row group g with the group partials
+// of gamma and delta at the dot format; with_s: then s = A_fs p.
+template <int FS, int TIER>
+__device__ __forceinline__ void sr_spmv(const SrArgs &a, const SrCtl &S, int g, void *lds, bool with_s) {
+  using V = typename TierT<TIER>::type;
+  using Acc = typename AccT<FS>::type;
+  const V *r, *p;
+  V *w, *sv;
+  if constexpr (TIER) { r = a.v.r64; w = a.v.q64; p = a.v.p64; sv = a.s64; }
+  else { r = a.v.r32; w = a.v.q32; p = a.v.p32; sv = a.s32; }
+  const int fd = S.fd;
+  const int n = a.A.n;
+  const int g0 = g * a.grows;
+  const int grows = min(a.grows, n - g0);
+  V ri[kRPT], rn[kRPT];   // own elements of r: current sub-block, next sub-block
+  int8_t ex[kRPT];
+  double tg[4] = {0.0, 0.0, 0.0, 0.0}, td[4] = {0.0, 0.0, 0.0, 0.0};
+  auto pref = [&](int sb) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      rn[j] = lr < grows ? r[g0 + lr] : (V)0;
+    }
+  };
+  auto pre = [&](int sb) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      ri[j] = rn[j];
+      ex[j] = 0;
+      if constexpr (FS == FP16 || FS == FP8) {
+        if (lr < grows) ex[j] = a.A.rexp[g0 + lr];
+      }
+    }
+  };
+  auto epi = [&](int sb, Acc (&acc)[kRPT]) {
+    V wi[kRPT];
+    bool valid[kRPT];
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      valid[j] = lr < grows;
+      wi[j] = (V)0;
+      if (valid[j]) {
+        if constexpr (FS == FP16 || FS == FP8) wi[j] = (V)ldexp((double)acc[j], (int)ex[j]);
+        else wi[j] = (V)acc[j];
+        w[g0 + lr] = wi[j];
+      }
+    }
+    double s2[kRPT];
+    dot_leaf_multi_rt<kRPT>(fd, ri, ri, valid, s2);
+    const double sg = subtrees_rt<kRPT>(fd, s2);
+    dot_leaf_multi_rt<kRPT>(fd, ri, wi, valid, s2);
+    const double sd = subtrees_rt<kRPT>(fd, s2);
+    tg[0] = sb == 0 ? sg : tg[0];
+    tg[1] = sb == 1 ? sg : tg[1];
+    tg[2] = sb == 2 ? sg : tg[2];
+    tg[3] = sb == 3 ? sg : tg[3];
+    td[0] = sb == 0 ? sd : td[0];
+    td[1] = sb == 1 ? sd : td[1];
+    td[2] = sb == 2 ? sd : td[2];
+    td[3] = sb == 3 ? sd : td[3];
+  };
+  if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{r}, g0, grows, lds, pref, pre, epi);
+  else spmv_group<FS, false>(a.A, GatherPlain<V>{r}, g0, grows, lds, pref, pre, epi);
+  if (threadIdx.x == 0) {
+    a.pg[g] = group_tree(fd, a.grows, tg);
+    a.pd[g] = group_tree(fd, a.grows, td);
+  }
+  if (!with_s) return;
+  __syncthreads();   // the LDS window is staged again
+  int8_t ex2[kRPT];
+  auto pref2 = [](int) {};
+  auto pre2 = [&](int sb) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      ex2[j] = 0;
+      if constexpr (FS == FP16 || FS == FP8) {
+        const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+        if (lr < grows) ex2[j] = a.A.rexp[g0 + lr];
+      }
+    }
+  };
+  auto epi2 = [&](int sb, Acc (&acc)[kRPT]) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      if (lr < grows) {
+        if constexpr (FS == FP16 || FS == FP8) sv[g0 + lr] = (V)ldexp((double)acc[j], (int)ex2[j]);
+        else sv[g0 + lr] = (V)acc[j];
+      }
+    }
+  };
+  if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref2, pre2, epi2);
+  else spmv_group<FS, false>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref2, pre2, epi2);
+}
+
+// KS1 of a start, replacement or final check: r64 = b - A x in fp64 over row
+// group g with the partial of ||r64||^2; r = rd_tier(r64) (not at the final
+// check).  A start reads the caller's x, copies it to x_hi, clears x_lo and
+// takes the partial of ||b||^2 too.
+__device__ __forceinline__ void sr_residual(const SrArgs &a, const SrCtl &S, int g, void *lds) {
+  const int n = a.A.n;
+  const int g0 = g * a.grows;
+  const int grows = min(a.grows, n - g0);
+  const bool start = S.mode == SR_START, fin = S.mode == SR_FINAL;
+  const int tier = S.tier;
+  double bi[kRPT];
+  double t[4] = {0.0, 0.0, 0.0, 0.0}, tb[4] = {0.0, 0.0, 0.0, 0.0};
+  auto pref = [](int) {};
+  auto pre = [&](int sb) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      bi[j] = lr < grows ? a.v.b[g0 + lr] : 0.0;
+    }
+  };
+  auto epi = [&](int sb, double (&acc)[kRPT]) {
+    double leaf[kRPT], leafb[kRPT];
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      leaf[j] = 0.0;
+      leafb[j] = 0.0;
+      if (lr < grows) {
+        const int i = g0 + lr;
+        const double r = bi[j] - acc[j];
+        leaf[j] = r * r;
+        leafb[j] = bi[j] * bi[j];
+        if (start) {
+          a.v.xhi[i] = a.v.xout[i];
+          if (tier) a.v.xlo64[i] = 0.0;
+          else a.v.xlo32[i] = 0.0f;
+        }
+        if (!fin) {
+          if (tier) a.v.r64[i] = r;
+          else a.v.r32[i] = (float)r;
+        }
+      }
+    }
+    double s2[kRPT];
+    block_tree_multi<kRPT>(leaf, s2);
+    const double s = subtrees_rt<kRPT>(FP64, s2);
+    t[0] = sb == 0 ? s : t[0];
+    t[1] = sb == 1 ? s : t[1];
+    t[2] = sb == 2 ? s : t[2];
+    t[3] = sb == 3 ? s : t[3];
+    if (start) {
+      block_tree_multi<kRPT>(leafb, s2);
+      const double sbb = subtrees_rt<kRPT>(FP64, s2);
+      tb[0] = sb == 0 ? sbb : tb[0];
+      tb[1] = sb == 1 ? sbb : tb[1];
+      tb[2] = sb == 2 ? sbb : tb[2];
+      tb[3] = sb == 3 ? sbb : tb[3];
+    }
+  };
+  const double *x = start ? a.v.xout : a.v.xhi;
+  if (a.A.dc) spmv_group<FP64, true>(a.A, GatherPlain<double>{x}, g0, grows, lds, pref, pre, epi);
+  else spmv_group<FP64, false>(a.A, GatherPlain<double>{x}, g0, grows, lds, pref, pre, epi);
+  if (threadIdx.x == 0) {
+    a.pg[g] = group_tree(FP64, a.grows, t);
+    if (start) a.pd[g] = group_tree(FP64, a.grows, tb);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sr1(SrArgs a) {
+  const int g = xcd_group(a.G1);
+  if (g >= a.P1) return;
+  __shared__ double lds[kLdsKa];
+  const SrCtl &S = a.ctl[a.par];
+  const int mode = S.mode;
+  if (mode == SR_ITER || mode == SR_SYNC) {
+    const bool with_s = mode == SR_SYNC && !S.first;
+    switch (S.fs * 2 + S.tier) {
+    case FP16 * 2: sr_spmv<FP16, 0>(a, S, g, lds, with_s); break;
+    case FP16 * 2 + 1: sr_spmv<FP16, 1>(a, S, g, lds, with_s); break;
+    case BF16 * 2: sr_spmv<BF16, 0>(a, S, g, lds, with_s); break;
+    case BF16 * 2 + 1: sr_spmv<BF16, 1>(a, S, g, lds, with_s); break;
+    case FP32 * 2: sr_spmv<FP32, 0>(a, S, g, lds, with_s); break;
+    case FP32 * 2 + 1: sr_spmv<FP32, 1>(a, S, g, lds, with_s); break;
+    case FP64 * 2: sr_spmv<FP64, 0>(a, S, g, lds, with_s); break;
+    case FP64 * 2 + 1: sr_spmv<FP64, 1>(a, S, g, lds, with_s); break;
+    case FP8 * 2: sr_spmv<FP8, 0>(a, S, g, lds, with_s); break;
+    case FP8 * 2 + 1: sr_spmv<FP8, 1>(a, S, g, lds, with_s); break;
+    default: break;
+    }
+  } else if (mode == SR_START || mode == SR_RESID || mode == SR_FINAL) {
+    sr_residual(a, S, g, lds);
+  }
+}
+
+// KS2's operands of one thread (8 consecutive elements of block blk) in the
+// container of the update format.
+template <int FA>
+struct SrVals {
+  using V = typename TierT<FA == FP64>::type;
+  V r[8], w[8], p[8], s[8], x[8];
+};
+
+template <int FA>
+__device__ __forceinline__ void sr_vecs(const SrArgs &a, typename SrVals<FA>::V *&r, typename SrVals<FA>::V *&w,
+                                        typename SrVals<FA>::V *&p, typename SrVals<FA>::V *&s,
+                                        typename SrVals<FA>::V *&xl) {
+  if constexpr (FA == FP64) { r = a.v.r64; w = a.v.q64; p = a.v.p64; s = a.s64; xl = a.v.xlo64; }
+  else { r = a.v.r32; w = a.v.q32; p = a.v.p32; s = a.s32; xl = a.v.xlo32; }
+}
+
+// Issues the loads of r, w, p, s and x_lo (p and s are read on the first step
+// too, where they are not used).
+template <int FA>
+__device__ __forceinline__ void sr_load(const SrArgs &a, int base, SrVals<FA> &v) {
+  using V = typename SrVals<FA>::V;
+  V *r, *w, *p, *s, *xl;
+  sr_vecs<FA>(a, r, w, p, s, xl);
+  const int n = a.A.n;
+  if (base + 8 <= n) {
+    load8(r + base, v.r);
+    load8(w + base, v.w);
+    load8(p + base, v.p);
+    load8(s + base, v.s);
+    load8(xl + base, v.x);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      const bool in = i < n;
+      v.r[j] = in ? r[i] : (V)0;
+      v.w[j] = in ? w[i] : (V)0;
+      v.p[j] = in ? p[i] : (V)0;
+      v.s[j] = in ? s[i] : (V)0;
+      v.x[j] = in ? xl[i] : (V)0;
+    }
+  }
+}
+
+// The direction and recurrence updates (copies on the first step), x_lo and
+// r, and the fold of x_lo into x_hi before a replacement.
+template <int FA>
+__device__ __forceinline__ void sr_update(const SrArgs &a, int base, SrVals<FA> &v, double alpha, double beta,
+                                          bool first, bool fold) {
+  using V = typename SrVals<FA>::V;
+  V *r, *w, *p, *s, *xl;
+  sr_vecs<FA>(a, r, w, p, s, xl);
+  const int n = a.A.n;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const V pn = first ? v.r[j] : xpay_rt<V>(FA, beta, v.p[j], v.r[j]);
+    const V sn = first ? v.w[j] : xpay_rt<V>(FA, beta, v.s[j], v.w[j]);
+    v.x[j] = axpy1<FA>(alpha, pn, v.x[j]);
+    v.r[j] = axpy1<FA>(-alpha, sn, v.r[j]);
+    v.p[j] = pn;
+    v.s[j] = sn;
+  }
+  if (fold) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (base + j < n) fold1(a.v.xhi, base + j, (double)v.x[j]);
+      v.x[j] = (V)0;
+    }
+  }
+  if (base + 8 <= n) {
+    store8(p + base, v.p);
+    store8(s + base, v.s);
+    store8(xl + base, v.x);
+    store8(r + base, v.r);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      if (i < n) {
+        p[i] = v.p[j];
+        s[i] = v.s[j];
+        xl[i] = v.x[j];
+        r[i] = v.r[j];
+      }
+    }
+  }
+}
+
+template <int FA>
+__device__ __forceinline__ void sr_fold(const SrArgs &a, int base, SrVals<FA> &v) {
+  using V = typename SrVals<FA>::V;
+  V *r, *w, *p, *s, *xl;
+  sr_vecs<FA>(a, r, w, p, s, xl);
+  const int n = a.A.n;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int i = base + j;
+    if (i < n) {
+      fold1(a.v.xhi, i, (double)v.x[j]);
+      xl[i] = (V)0;
+    }
+  }
+}
+
+// The state after KS2, identical in every thread.
+struct SrNext {
+  int mode, status, k, nrep;
+  bool upd, zero;
+  double bnorm, last_true, relres, rho, gamma, alpha;
+};
+
+__device__ __forceinline__ SrNext sr_next_of(const SrCtl &S) {
+  SrNext x;
+  x.mode = S.mode;
+  x.status = S.status;
+  x.k = S.k;
+  x.nrep = S.nrep;
+  x.upd = false;
+  x.zero = false;
+  x.bnorm = S.bnorm;
+  x.last_true = S.last_true;
+  x.relres = S.relres_true;
+  x.rho = S.rho_new;
+  x.gamma = 0.0;
+  x.alpha = 0.0;
+  return x;
+}
+
+// KS2 after an iteration's KS1: gamma, delta -> rho (replacement or budget
+// test), beta, alpha (breakdown test), then the updates of block blk, whose
+// operands are loaded before the step.
+template <int FA>
+__device__ __forceinline__ SrNext sr2_iter(const SrArgs &a, const SrCtl &S, int blk, const double (&pg)[8],
+                                           const double (&pd)[8], bool fast) {
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
+  SrVals<FA> v;
+  const bool live = base < a.A.n;
+  __builtin_amdgcn_sched_barrier(0);
+  if (live) sr_load<FA>(a, base, v);
+  __builtin_amdgcn_sched_barrier(0);
+  SrNext x = sr_next_of(S);
+  const bool writer = blk == 0 && threadIdx.x == 0;
+  const int k = S.k;
+  const int fd = S.fd;
+  const bool first = S.first != 0;
+  const double gamma = fast ? tree_preloaded_rt(fd, pg) : reduce_partials_rt(fd, a.pg, a.P1);
+  const double delta = fast ? tree_preloaded_rt(fd, pd) : reduce_partials_rt(fd, a.pd, a.P1);
+  bool fold = false, go = true;
+  if (S.mode == SR_ITER) {
+    x.rho = sqrt(gamma) / S.bnorm;
+    if (writer) a.h.rho[k] = x.rho;
+    if (x.rho <= S.tol) {
+      fold = true;
+      x.mode = SR_RESID;
+      go = false;
+    } else if (k >= S.maxit) {
+      x.status = 1;
+      fold = true;
+      x.mode = SR_FINAL;
+      go = false;
+    }
+  }
+  double alpha = 0.0, beta = 0.0;
+  if (go) {
+    beta = first ? 0.0 : gamma / S.gamma_old;
+    const double den = first ? delta : delta - beta * gamma / S.alpha_old;
+    alpha = gamma / den;
+    if (!(den > 0.0) || !isfinite(alpha) || !isfinite(beta) || !isfinite(gamma)) {
+      x.status = 3;
+      fold = true;
+      x.mode = SR_FINAL;
+    } else {
+      x.upd = true;
+      x.gamma = gamma;
+      x.alpha = alpha;
+      if (writer) {
+        a.h.act[k] = (uint8_t)S.action;
+        a.h.flag[k] = 0;
+      }
+      x.k = k + 1;
+      fold = S.R > 0 && x.k % S.R == 0;
+      x.mode = fold ? SR_RESID : SR_ITER;
+    }
+  }
+  if (live) {
+    if (x.upd) sr_update<FA>(a, base, v, alpha, beta, first, fold);
+    else if (fold) sr_fold<FA>(a, base, v);
+  }
+  return x;
+}
+
+// KS2 after a start, replacement or final check: the true relres and the
+// stop tests; at the stop the caller's x receives x_hi (or 0 when b = 0).
+__device__ __forceinline__ SrNext sr2_resid(const SrArgs &a, const SrCtl &S, int blk, const double (&pg)[8],
+                                            const double (&pd)[8], bool fast) {
+  SrNext x = sr_next_of(S);
+  const bool writer = blk == 0 && threadIdx.x == 0;
+  const int mode = S.mode, k = S.k;
+  const double s64 = fast ? tree_preloaded<double>(pg) : partials_total<double>(a.pg, a.P1);
+  if (mode == SR_START) x.bnorm = sqrt(fast ? tree_preloaded<double>(pd) : partials_total<double>(a.pd, a.P1));
+  bool out = false;
+  if (mode == SR_START && x.bnorm == 0.0) {
+    x.zero = true;
+    out = true;
+    x.status = 0;
+    x.relres = 0.0;
+    x.mode = SR_DONE;
+    if (writer) a.h.rho[0] = 0.0;
+  } else {
+    const double rt = sqrt(s64) / x.bnorm;
+    if (mode == SR_FINAL) {
+      x.relres = rt;
+      out = true;
+      x.mode = SR_DONE;
+    } else {
+      if (writer) {
+        a.h.rho[k] = rt;
+        if (mode == SR_RESID) {
+          if (x.nrep < a.h.cap_rep) {
+            a.h.rep_k[x.nrep] = k;
+            a.h.rep_rho[x.nrep] = rt;
+          }
+          if (k > 0) a.h.flag[k - 1] |= FL_REPLACED;
+        }
+      }
+      if (mode == SR_RESID) x.nrep++;
+      x.last_true = rt;
+      x.rho = rt;
+      x.mode = SR_SYNC;
+      if (rt <= S.tol || !isfinite(rt) || k >= S.maxit) {
+        x.status = rt <= S.tol ? 0 : !isfinite(rt) ? 3 : 1;
+        x.relres = rt;
+        out = true;
+        x.mode = SR_DONE;
+      }
+    }
+  }
+  if (out) {
+    const int n = a.A.n;
+    const int base = blk * kVecBlock + threadIdx.x * kVecPer;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (base + j < n) a.v.xout[base + j] = x.zero ? 0.0 : a.v.xhi[base + j];
+  }
+  return x;
+}
+
+// TIER: the container of the action's update format (a fixed action keeps
+// one tier for the whole solve), so the fp32 kernel holds no fp64 operands.
+template <int TIER>
+__global__ __launch_bounds__(kBlock) void k_sr2(SrArgs a) {
+  __shared__ SrCtl S;
+  const int blk = blockIdx.x;
+  const bool fast = a.P1 <= kVecBlock;
+  double pg[8] = {0, 0, 0, 0, 0, 0, 0, 0}, pd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (fast) {
+    preload_partials(a.pg, a.P1, pg);
+    preload_partials(a.pd, a.P1, pd);
+  }
+  copy_words(&S, &a.ctl[a.par], sizeof(SrCtl));
+  __syncthreads();
+  const int mode = S.mode;
+  SrNext x;
+  if (mode == SR_ITER || mode == SR_SYNC) {
+    if constexpr (TIER) {
+      x = sr2_iter<FP64>(a, S, blk, pg, pd, fast);
+    } else {
+      switch (S.fa) {
+      case FP16: x = sr2_iter<FP16>(a, S, blk, pg, pd, fast); break;
+      case BF16: x = sr2_iter<BF16>(a, S, blk, pg, pd, fast); break;
+      default: x = sr2_iter<FP32>(a, S, blk, pg, pd, fast); break;
+      }
+    }
+  } else if (mode == SR_START || mode == SR_RESID || mode == SR_FINAL) {
+    x = sr2_resid(a, S, blk, pg, pd, fast);
+  } else {
+    x = sr_next_of(S);
+  }
+  __syncthreads();   // every thread has read S
+  if (threadIdx.x == 0) {
+    S.mode = x.mode;
+    S.status = x.status;
+    S.k = x.k;
+    S.nrep = x.nrep;
+    S.bnorm = x.bnorm;
+    S.last_true = x.last_true;
+    S.relres_true = x.relres;
+    S.rho_new = x.rho;
+    if (x.zero) S.zero_solution = 1;
+    if (x.upd) {
+      S.gamma_old = x.gamma;
+      S.alpha_old = x.alpha;
+      S.first = 0;
+    }
+  }
+  __syncthreads();
+  if (blk == 0) copy_words(&a.ctl[a.par ^ 1], &S, sizeof(SrCtl));
+}
+
+void launch_sr_slot(const SrArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_sr1, dim3(a.G1), dim3(kBlock), 0, s, a);
+  if (a.tier) hipLaunchKernelGGL(k_sr2<1>, dim3(a.P2), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL(k_sr2<0>, dim3(a.P2), dim3(kBlock), 0, s, a);
+}
+#endif  // part 9
 
 }  // namespace mpcg

@@ -35,6 +35,8 @@ hipError_t launch_op_dot_noalloc(int n, int fd, int tier, const void *u, const v
 void launch_op_axpy(int n, int fa, double alpha, const void *u, void *y, hipStream_t s);
 // Flat gather of p over the CSR column stream (measurement of the random-access floor).
 void launch_gather_floor(const Mat &A, const float *p, float *sink, hipStream_t s);
+// One slot of the single-reduction CG (KS1 then KS2).
+void launch_sr_slot(const SrArgs &a, hipStream_t s);
 void launch_policy_decide(const PolicyDev *P, int m, const int64_t *k, const double *rho, const int32_t *stag,
                           const float *feat, int32_t *state, int32_t *action, hipStream_t s);
 }  // namespace mpcg
