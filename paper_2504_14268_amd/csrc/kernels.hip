@@ -2989,6 +2989,38 @@ void launch_policy_decide(const PolicyDev *P, int m, const int64_t *k, const dou
 // the double buffer and writes the histories.
 // ---------------------------------------------------------------------------
 
+// The subtree sums of two dots over the same rows, u.v1 and u.v2, in one LDS
+// round (each subtree is summed as by dot_leaf_multi).
+template <int FD, int RPT, typename V>
+__device__ __forceinline__ void dot_leaf_multi2(const V (&u)[RPT], const V (&v1)[RPT], const V (&v2)[RPT],
+                                                const bool (&valid)[RPT], double (&o1)[RPT], double (&o2)[RPT]) {
+  using A = typename AccT<FD>::type;
+  A l[2 * RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    l[j] = valid[j] ? dot_leaf<FD>(u[j], v1[j]) : (A)0;
+    l[RPT + j] = valid[j] ? dot_leaf<FD>(u[j], v2[j]) : (A)0;
+  }
+  double out[2 * RPT];
+  block_tree_multi<2 * RPT>(l, out);
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    o1[j] = out[j];
+    o2[j] = out[RPT + j];
+  }
+}
+
+template <int RPT, typename V>
+__device__ __forceinline__ void dot_leaf_multi2_rt(int fd, const V (&u)[RPT], const V (&v1)[RPT], const V (&v2)[RPT],
+                                                   const bool (&valid)[RPT], double (&o1)[RPT], double (&o2)[RPT]) {
+  switch (fd) {
+  case FP16: dot_leaf_multi2<FP16, RPT>(u, v1, v2, valid, o1, o2); break;
+  case BF16: dot_leaf_multi2<BF16, RPT>(u, v1, v2, valid, o1, o2); break;
+  case FP32: dot_leaf_multi2<FP32, RPT>(u, v1, v2, valid, o1, o2); break;
+  default: dot_leaf_multi2<FP64, RPT>(u, v1, v2, valid, o1, o2); break;
+  }
+}
+
 // KS1 of an iteration: w = A_fs r over row group g with the group partials
 // of gamma and delta at the dot format; with_s: then s = A_fs p.
 template <int FS, int TIER>
@@ -3038,11 +3070,10 @@ __device__ __forceinline__ void sr_spmv(const SrArgs &a, const SrCtl &S, int g, 
         w[g0 + lr] = wi[j];
       }
     }
-    double s2[kRPT];
-    dot_leaf_multi_rt<kRPT>(fd, ri, ri, valid, s2);
-    const double sg = subtrees_rt<kRPT>(fd, s2);
-    dot_leaf_multi_rt<kRPT>(fd, ri, wi, valid, s2);
-    const double sd = subtrees_rt<kRPT>(fd, s2);
+    double s2g[kRPT], s2d[kRPT];
+    dot_leaf_multi2_rt<kRPT>(fd, ri, ri, wi, valid, s2g, s2d);
+    const double sg = subtrees_rt<kRPT>(fd, s2g);
+    const double sd = subtrees_rt<kRPT>(fd, s2d);
     tg[0] = sb == 0 ? sg : tg[0];
     tg[1] = sb == 1 ? sg : tg[1];
     tg[2] = sb == 2 ? sg : tg[2];
