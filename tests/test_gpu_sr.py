@@ -27,9 +27,9 @@ def M():
     return M
 
 
-def run(M, m, A, b, act, tol=1e-8, maxit=3000, R=50, x0=None, spmv_rows=0):
+def run(M, m, A, b, act, tol=1e-8, maxit=3000, R=50, x0=None, spmv_rows=0, index16=0):
     m.set_policy(M.Policy(kind=M.POLICY_FIXED, fixed_action=act))
-    m.set_options(replace_period=R, fallback=False, variant=1, spmv_rows=spmv_rows)
+    m.set_options(replace_period=R, fallback=False, variant=1, spmv_rows=spmv_rows, index16=index16)
     x0 = np.zeros(A.n) if x0 is None else x0
     xd = torch.from_numpy(np.ascontiguousarray(x0, dtype=np.float64)).cuda()
     res = m.solve(torch.from_numpy(np.ascontiguousarray(b, dtype=np.float64)).cuda(), xd, tol=tol, maxit=maxit)
@@ -62,6 +62,17 @@ def test_replacement_periods_and_group_sizes(M, R, rows):
     b = W.rhs(A.n, 3)
     res, info = run(M, M.Matrix(A), A, b, O.action(1, 2, 2), R=R, spmv_rows=rows)
     assert res["status"] == (3 if R == 0 else 0)
+
+
+@pytest.mark.parametrize("f", [(1, 2, 2), (0, 2, 2), (3, 3, 3)], ids=["122", "022", "333"])
+def test_int32_indices_and_initial_guess(M, f):
+    """The SpMV reading 32-bit column indices (index16 = -1) gives the same
+    bits as the oracle, from a nonzero initial guess."""
+    A = W.laplacian_3d(24)
+    b = W.rhs(A.n, 8)
+    x0 = np.random.default_rng(9).uniform(-1.0, 1.0, A.n)
+    res, _ = run(M, M.Matrix(A), A, b, O.action(*f), x0=x0, index16=-1)
+    assert res["index16"] == 0 and res["status"] == 0
 
 
 def test_fp64_matches_the_three_launch_solver(M):
