@@ -8,6 +8,10 @@ Workloads (synthetic, seeded):
     recomputed in fp64 every 50 iterations.  fp64: plain fp64 CG.
   * random SPD, n = 1,000,000, 9..27 nnz/row, N(0,1) values, dominant diagonal,
     log-uniform diagonal scaling (matrix seed 3, b seed 4), same two solvers.
+  Beside the headline: the single-reduction variant of the iteration (both
+  inner products fused into the SpMV, two launches per iteration) with the
+  same actions, q52 matrix storage, 16-bit vector storage, a learned Q-table
+  and Jacobi preconditioning on the random SPD.
 
 A step is one complete solve of the 3D Laplacian in mixed precision, inputs
 resident in HBM.  `value` is its time to solution in ms (lower is better).
