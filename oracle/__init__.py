@@ -104,7 +104,8 @@ class Hist(C.Structure):
         ("roll_done", C.POINTER(C.c_uint8)), ("roll_n", C.c_int32), ("dump_cap", C.c_int32),
         ("hist_alpha", C.POINTER(C.c_double)), ("hist_beta", C.POINTER(C.c_double)),
         ("dump_p", C.POINTER(C.c_double)), ("dump_r", C.POINTER(C.c_double)),
-        ("dump_s", C.POINTER(C.c_double)),
+        ("dump_s", C.POINTER(C.c_double)), ("dump_w", C.POINTER(C.c_double)),
+        ("dump_z", C.POINTER(C.c_double)),
     ]
 
 
@@ -159,6 +160,7 @@ def lib():
         L.orc_cg_plain.restype = C.c_int
         L.orc_cg_sr.argtypes = [i64, ip, ip, dp, dp, dp, dp, C.c_int, C.POINTER(Params), C.POINTER(Result),
                                 C.POINTER(Hist)]
+        L.orc_cg_pipe.argtypes = L.orc_cg_sr.argtypes
         L.orc_cg_plain.argtypes = [i64, ip, ip, dp, dp, dp, d, C.c_int32, ip, dp]
         _lib = L
     return _lib
@@ -437,6 +439,18 @@ def cg_sr(A, b, action, x0=None, tol=1e-8, maxit=1000, replace_period=0, order=O
     both inner products per iteration) with a fixed action.  dump > 0 keeps
     alpha, beta and the p, r, s used by the first `dump` iterations.
     Returns (x, info dict with histories)."""
+    return _cg_variant("orc_cg_sr", A, b, action, x0, tol, maxit, replace_period, order, dump)
+
+
+def cg_pipe(A, b, action, x0=None, tol=1e-8, maxit=1000, replace_period=0, order=ORDER_PAIRWISE, dump=0):
+    """Run the oracle's pipelined CG (Ghysels-Vanroose: w = A r and z = A s by
+    recurrence, the SpMV q = A w independent of the inner products) with a
+    fixed action.  dump > 0 keeps alpha, beta and the p, r, s, w, z of the
+    first `dump` iterations.  Returns (x, info dict with histories)."""
+    return _cg_variant("orc_cg_pipe", A, b, action, x0, tol, maxit, replace_period, order, dump)
+
+
+def _cg_variant(fn, A, b, action, x0, tol, maxit, replace_period, order, dump):
     n = A.n
     b = _f64(b)
     x0 = np.zeros(n) if x0 is None else _f64(x0)
@@ -455,14 +469,16 @@ def cg_sr(A, b, action, x0=None, tol=1e-8, maxit=1000, replace_period=0, order=O
     dumps = None
     if dump > 0:
         dumps = dict(alpha=np.full(dump, np.nan), beta=np.full(dump, np.nan),
-                     p=np.zeros((dump, n)), r=np.zeros((dump, n)), s=np.zeros((dump, n)))
+                     p=np.zeros((dump, n)), r=np.zeros((dump, n)), s=np.zeros((dump, n)),
+                     w=np.zeros((dump, n)), z=np.zeros((dump, n)))
         h.dump_cap = dump
         h.hist_alpha, h.hist_beta = _p(dumps["alpha"]), _p(dumps["beta"])
         h.dump_p, h.dump_r, h.dump_s = _p(dumps["p"]), _p(dumps["r"]), _p(dumps["s"])
-    rc = lib().orc_cg_sr(n, _p(_i32(A.row_ptr), C.c_int32), _p(_i32(A.col), C.c_int32), _p(_f64(A.val)),
+        h.dump_w, h.dump_z = _p(dumps["w"]), _p(dumps["z"])
+    rc = getattr(lib(), fn)(n, _p(_i32(A.row_ptr), C.c_int32), _p(_i32(A.col), C.c_int32), _p(_f64(A.val)),
                          _p(b), _p(x0), _p(x), int(action), C.byref(prm), C.byref(res), C.byref(h))
     if rc != 0:
-        raise ValueError(f"single-reduction CG takes actions 0..79, not {action}")
+        raise ValueError(f"the single-reduction and pipelined CG take actions 0..79, not {action}")
     k = res.iters
     nrep = min(res.n_replace, rep_cap)
     info = dict(status=res.status, iters=k, n_replace=res.n_replace, fallback_at=res.fallback_at,

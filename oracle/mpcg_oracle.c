@@ -717,8 +717,12 @@ typedef struct {
     double *hist_beta;         /* [dump_cap] or NULL */
     double *dump_p;            /* [dump_cap][n] direction used by iteration k, or NULL */
     double *dump_r;            /* [dump_cap][n] residual r at the start of iteration k, or NULL */
-    double *dump_s;            /* single-reduction CG: [dump_cap][n] s (the recurrence
-                                  for A p) used by iteration k, or NULL */
+    double *dump_s;            /* single-reduction and pipelined CG: [dump_cap][n] s
+                                  (the recurrence for A p) used by iteration k, or NULL */
+    double *dump_w;            /* pipelined CG: [dump_cap][n] w (for A r) at the start
+                                  of iteration k, or NULL */
+    double *dump_z;            /* pipelined CG: [dump_cap][n] z (for A s) used by
+                                  iteration k, or NULL */
 } orc_hist;
 
 /* Stagnation flag of the state (a reading: the paper's state has no such
@@ -1249,6 +1253,146 @@ done:
     res->n_replace = nrep;
 out:
     free(xhi); free(xlo); free(r); free(w); free(p); free(sv); free(r64);
+    mat_free(&A);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pipelined CG (Ghysels and Vanroose, 2014).                                */
+/* ------------------------------------------------------------------------ */
+/* The single-reduction iteration with w = A r also carried by a recurrence,
+ * so that the SpMV of an iteration, q = A w, does not depend on its inner
+ * products gamma = r.r and delta = w.r (which can then overlap it):
+ *   beta, alpha as in the single-reduction iteration,
+ *   z = q + beta z (z = A s),  s = w + beta s (s = A p),  p = r + beta p,
+ *   x += alpha p,  r -= alpha s,  w -= alpha z.
+ * In exact arithmetic the iterates are those of section 3's CG.  Formats as
+ * in orc_cg_sr: the SpMV at f_s, both inner products at f_d, the six updates
+ * at f_a, alpha and beta in fp64, x = x_hi + x_lo.  A start computes
+ * r = rd(b - A x), then w = A r; the first step copies z = q, s = w, p = r.
+ * A replacement (every R iterations, and when the recursive rho_k is <= tol)
+ * folds x_lo, sets r = rd(b - A x_hi), then w = A r and s = A p, then z = A s
+ * (all at f_s), the residual replacement of Cools et al. (2018) for this
+ * iteration.  Stops, breakdown, histories and cost_sum as in orc_cg_sr. */
+int orc_cg_pipe(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                const double *b, const double *x0, double *x_out, int action,
+                const orc_params *prm, orc_result *res, orc_hist *h)
+{
+    memset(res, 0, sizeof(*res));
+    res->fallback_at = -1;
+    h->roll_n = 0;
+    if (action < 0 || action >= 80) return -1;
+    orc_mat A;
+    mat_build(&A, n, rp, ci, v);
+    size_t bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *xhi = malloc(bytes), *xlo = malloc(bytes), *r = malloc(bytes), *w = malloc(bytes);
+    double *p = malloc(bytes), *sv = malloc(bytes), *z = malloc(bytes), *q = malloc(bytes);
+    double *r64 = malloc(bytes);
+    const int fs = act_fs(action), fd = act_fd(action), fa = act_fa(action);
+    const int tier = fa == F64 ? 1 : 0;
+    const int R = prm->replace_period;
+    const int order = prm->dot_order;
+    double *hist_rho = h->hist_rho;
+    int64_t k = 0;
+    int nrep = 0, status = -1;
+    double gamma_old = 0.0, alpha_old = 0.0, last_true = 0.0;
+
+    double bnorm = sqrt(orc_dot(n, b, b, F64, order));
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x_out[i] = 0.0;
+        hist_rho[0] = 0.0;
+        res->status = 0;
+        goto out;
+    }
+    for (int64_t i = 0; i < n; ++i) { xhi[i] = x0[i]; xlo[i] = 0.0; }
+
+    mat_residual(&A, b, xhi, r64);
+    last_true = sqrt(orc_dot(n, r64, r64, F64, order)) / bnorm;
+    hist_rho[0] = last_true;
+    if (last_true <= prm->tol) { status = 0; goto done; }
+    if (!isfinite(last_true)) { status = 3; goto done; }
+    if (prm->maxit <= 0) { status = 1; goto done; }
+    for (int64_t i = 0; i < n; ++i) r[i] = rd_tier(r64[i], tier);
+    mat_spmv(&A, fs, tier, r, w);                          /* w = A r */
+    int first = 1, sync = 1;   /* sync: the first pass after a start or replacement */
+
+    for (;;) {
+        const double gamma = orc_dot(n, r, r, fd, order);
+        const double delta = orc_dot(n, w, r, fd, order);
+        mat_spmv(&A, fs, tier, w, q);                      /* q = A w */
+        if (sync && !first) mat_spmv(&A, fs, tier, sv, z); /* z = A s again */
+        int replace = 0;
+        if (!sync) {
+            const double rho = sqrt(gamma) / bnorm;
+            hist_rho[k] = rho;
+            if (rho <= prm->tol) replace = 1;
+            else if (k >= prm->maxit) { status = 1; break; }
+        }
+        if (!replace) {
+            sync = 0;
+            const double beta = first ? 0.0 : gamma / gamma_old;
+            const double den = first ? delta : delta - beta * gamma / alpha_old;
+            const double alpha = gamma / den;
+            if (!(den > 0.0) || !isfinite(alpha) || !isfinite(beta) || !isfinite(gamma)) { status = 3; break; }
+            if (k < h->dump_cap && h->hist_alpha) h->hist_alpha[k] = alpha;
+            if (k < h->dump_cap && h->hist_beta) h->hist_beta[k] = beta;
+            if (k < h->dump_cap && h->dump_w) memcpy(&h->dump_w[k * n], w, bytes);
+            if (first) {
+                memcpy(z, q, bytes);
+                memcpy(sv, w, bytes);
+                memcpy(p, r, bytes);
+            } else {
+                xpay(n, beta, q, z, fa);
+                xpay(n, beta, w, sv, fa);
+                xpay(n, beta, r, p, fa);
+            }
+            if (k < h->dump_cap && h->dump_p) memcpy(&h->dump_p[k * n], p, bytes);
+            if (k < h->dump_cap && h->dump_r) memcpy(&h->dump_r[k * n], r, bytes);
+            if (k < h->dump_cap && h->dump_s) memcpy(&h->dump_s[k * n], sv, bytes);
+            if (k < h->dump_cap && h->dump_z) memcpy(&h->dump_z[k * n], z, bytes);
+            orc_axpy(n, alpha, p, xlo, fa);
+            orc_axpy(n, -alpha, sv, r, fa);
+            orc_axpy(n, -alpha, z, w, fa);
+            h->hist_act[k] = (uint8_t)action;
+            h->hist_flag[k] = 0;
+            gamma_old = gamma;
+            alpha_old = alpha;
+            first = 0;
+            k += 1;
+            replace = R > 0 && k % R == 0;
+        }
+        if (replace) {
+            fold(n, xhi, xlo);
+            mat_residual(&A, b, xhi, r64);
+            const double rt = sqrt(orc_dot(n, r64, r64, F64, order)) / bnorm;
+            if (nrep < h->rep_cap) { h->rep_k[nrep] = (int32_t)k; h->rep_rho[nrep] = rt; }
+            nrep++;
+            if (k > 0) h->hist_flag[k - 1] |= FL_REPLACED;
+            hist_rho[k] = rt;
+            last_true = rt;
+            if (rt <= prm->tol) { status = 0; break; }
+            if (!isfinite(rt)) { status = 3; break; }
+            if (k >= prm->maxit) { status = 1; break; }
+            for (int64_t i = 0; i < n; ++i) r[i] = rd_tier(r64[i], tier);
+            mat_spmv(&A, fs, tier, r, w);                  /* w = A r */
+            mat_spmv(&A, fs, tier, p, sv);                 /* s = A p */
+            sync = 1;
+        }
+    }
+done:
+    fold(n, xhi, xlo);
+    for (int64_t i = 0; i < n; ++i) x_out[i] = xhi[i];
+    if (status == 0) {
+        res->relres_true = last_true;
+    } else {
+        mat_residual(&A, b, xhi, r64);
+        res->relres_true = sqrt(orc_dot(n, r64, r64, F64, order)) / bnorm;
+    }
+    res->status = status;
+    res->iters = (int32_t)k;
+    res->n_replace = nrep;
+out:
+    free(xhi); free(xlo); free(r); free(w); free(p); free(sv); free(z); free(q); free(r64);
     mat_free(&A);
     return 0;
 }
