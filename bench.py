@@ -8,9 +8,9 @@ Workloads (synthetic, seeded):
     recomputed in fp64 every 50 iterations.  fp64: plain fp64 CG.
   * random SPD, n = 1,000,000, 9..27 nnz/row, N(0,1) values, dominant diagonal,
     log-uniform diagonal scaling (matrix seed 3, b seed 4), same two solvers.
-  Beside the headline: the single-reduction variant of the iteration (both
-  inner products fused into the SpMV, two launches per iteration) with the
-  same actions, q52 matrix storage, 16-bit vector storage, a learned Q-table
+  Beside the headline: the single-reduction and pipelined variants of the
+  iteration (two launches per iteration each) with the same actions, q52
+  matrix storage, 16-bit vector storage, a learned Q-table
   and Jacobi preconditioning on the random SPD.
 
 A step is one complete solve of the 3D Laplacian in mixed precision, inputs
@@ -727,6 +727,20 @@ def main():
     sr["fp64"]["speedup_vs_three_launch_fp64"] = round(fp64_ms / sr["fp64"]["ms"], 3)
     log(f"[bench] single-reduction CG: {sr}")
 
+    # pipelined CG (w = A r and z = A s by recurrence as well); its recurrences
+    # need replacements every 20 iterations with the mixed action
+    pc = {}
+    for name, pol, R in (("mixed", pol_mixed, 20), ("fp64", pol_fp64, 50)):
+        solve(pol, R, variant=2)
+        runs = [solve(pol, R, variant=2) for _ in range(max(1, args.steps // 2))]
+        rs = runs[-1]
+        pc[name] = {"replace_period": R, "ms": round(float(np.median([r["time_ms"] for r in runs])), 3),
+                    "iters": rs["iters"], "status": rs["status"], "n_replace": rs["n_replace"],
+                    "relres_true": rs["relres_true"]}
+    pc["mixed"]["speedup_vs_three_launch_mixed"] = round(dev_ms / pc["mixed"]["ms"], 3)
+    pc["fp64"]["speedup_vs_three_launch_fp64"] = round(fp64_ms / pc["fp64"]["ms"], 3)
+    log(f"[bench] pipelined CG: {pc}")
+
     # profiled solves: HIP events around every launch of the same kernels
     rp = solve(pol_mixed, 50, profile=True)
     prof = m.profile()
@@ -812,6 +826,9 @@ def main():
         "single_reduction": dict(
             variant="Chronopoulos-Gear CG: SpMV w = A r with both inner products fused, s = A p by "
                     "recurrence, two launches per iteration", **sr),
+        "pipelined": dict(
+            variant="Ghysels-Vanroose CG: SpMV q = A w independent of the inner products, w = A r and "
+                    "z = A s by recurrence, six vector updates, two launches per iteration", **pc),
         "vector_storage_16bit": {
             "action": "SpMV bf16, dot fp32, updates bf16, R=50, 200 iterations",
             "fp32_containers": v16[0], "bf16_containers": v16[1],

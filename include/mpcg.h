@@ -195,15 +195,21 @@ typedef struct {
                                   w = A r followed by both inner products,
                                   gamma = r.r and delta = r.w, s = A p carried
                                   by a recurrence, two launches per iteration;
-                                  in exact arithmetic the iterates of variant
-                                  0.  A replacement also recomputes s = A p.
-                                  Fixed policies with actions 0..79 only; not
-                                  with fallback, precond, stop_rule, rho_fp64,
+                                  2: pipelined CG (Ghysels and Vanroose, 2014):
+                                  w = A r and z = A s carried by recurrences
+                                  too, so the iteration's SpMV q = A w does
+                                  not wait for its inner products; two
+                                  launches per iteration, six vector updates.
+                                  In exact arithmetic both give the iterates
+                                  of variant 0.  A replacement also recomputes
+                                  s = A p (and w = A r, z = A s).  Fixed
+                                  policies with actions 0..79 only; not with
+                                  fallback, precond, stop_rule, rho_fp64,
                                   emulate, vec16, profile or batched solves.
-                                  Low-precision updates make the recurrence
-                                  for s drift faster than section 3's
-                                  iteration; breakdown then ends the solve
-                                  with status MPCG_BREAKDOWN.                   */
+                                  Low-precision arithmetic makes the
+                                  recurrences drift faster than section 3's
+                                  iteration (variant 2 most); breakdown then
+                                  ends the solve with status MPCG_BREAKDOWN.  */
 } mpcg_solve_opts;
 
 /* Per-kernel timing of the last solve made with opts.profile = 1.  One CG

@@ -468,7 +468,8 @@ class Matrix:
 
     def set_options(self, replace_period=50, fallback=False, chunk=0, profile=False, spmv_rows=0, index16=0,
                     precond=0, stop_rule=0, rho_fp64=0, emulate=0, vec16=0, variant=0):
-        """variant 1: single-reduction CG (Chronopoulos-Gear), two launches per iteration."""
+        """variant 1: single-reduction CG (Chronopoulos-Gear); 2: pipelined CG
+        (Ghysels-Vanroose); both two launches per iteration, fixed actions."""
         o = SolveOpts(replace_period, int(fallback), chunk, int(profile), spmv_rows, index16, int(precond),
                       int(stop_rule), int(rho_fp64), int(emulate), int(vec16), int(variant))
         _check(lib().mpcg_set_options(self.h, C.byref(o)), "set_options")

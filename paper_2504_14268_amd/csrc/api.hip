@@ -290,6 +290,8 @@ struct mpcg_matrix {
   float *d_minv = nullptr;     // Jacobi preconditioner: fp32 of 1 / a_ii
   float *d_s32 = nullptr;      // single-reduction CG: s, the recurrence for A p
   double *d_s64 = nullptr;
+  float *d_w32 = nullptr, *d_z32 = nullptr;    // pipelined CG: w (A r) and z (A s)
+  double *d_w64 = nullptr, *d_z64 = nullptr;
   SrCtl *d_sr = nullptr;       // single-reduction CG: [2] control blocks
   SrCtl *h_sr = nullptr;       // pinned [3]: the start state and the state after each chunk
   Ctl *d_ctl = nullptr;        // [2]
@@ -344,6 +346,7 @@ struct mpcg_matrix {
     dfree(d_part0); dfree(d_part1); dfree(d_part2); dfree(d_scalar); dfree(d_ctl); dfree(d_pol);
     dfree(d_part1b); dfree(d_part2b); dfree(d_minv);
     dfree(d_s32); dfree(d_s64); dfree(d_sr);
+    dfree(d_w32); dfree(d_z32); dfree(d_w64); dfree(d_z64);
     if (h_sr) (void)hipHostFree(h_sr);
     h_sr = nullptr;
     dfree(d_hrho); dfree(d_reprho); dfree(d_hact); dfree(d_hflag); dfree(d_repk); dfree(d_slotlog);
@@ -523,9 +526,10 @@ struct ChunkPlan {
   }
 };
 
-// Single-reduction CG (opts.variant = 1): one slot is KS1 (SpMV w = A r with
-// the partials of r.r and r.w, or an fp64 residual) and KS2 (scalar step and
-// the vector updates); the device decides each slot's phase, the host only
+// Single-reduction CG (opts.variant = 1) and pipelined CG (variant 2): one
+// slot is KS1 (the iteration's SpMV with the partials of r.r and r.w, or an
+// fp64 residual, or the pipelined sync SpMVs) and KS2 (scalar step and the
+// vector updates); the device decides each slot's phase, the host only
 // enqueues chunks of slots and polls the control block between them.
 static int solve_sr(mpcg_matrix *A, mpcg_policy *P, const double *b, double *x, double tol, int32_t maxit,
                     mpcg_result *res) {
@@ -536,6 +540,13 @@ static int solve_sr(mpcg_matrix *A, mpcg_policy *P, const double *b, double *x, 
     HIP_TRY(dmalloc(&A->d_s64, n));
     HIP_TRY(dmalloc(&A->d_sr, 2));
     HIP_TRY(hipHostMalloc((void **)&A->h_sr, 3 * sizeof(SrCtl), hipHostMallocDefault));
+  }
+  const bool pipe = A->opts.variant == 2;
+  if (pipe && !A->d_w32) {
+    HIP_TRY(dmalloc(&A->d_w32, n));
+    HIP_TRY(dmalloc(&A->d_z32, n));
+    HIP_TRY(dmalloc(&A->d_w64, n));
+    HIP_TRY(dmalloc(&A->d_z64, n));
   }
   const int act = P->desc.fixed_action;
   SrCtl &c = A->h_sr[2];
@@ -550,6 +561,7 @@ static int solve_sr(mpcg_matrix *A, mpcg_policy *P, const double *b, double *x, 
   c.fd = act_fd(act);
   c.fa = act_fa(act);
   c.tier = c.fa == FP64 ? 1 : 0;
+  c.pipe = pipe ? 1 : 0;
   c.tol = tol;
   HIP_TRY(hipMemcpyAsync(A->d_sr, &c, sizeof(SrCtl), hipMemcpyHostToDevice, st));
 
@@ -568,6 +580,11 @@ static int solve_sr(mpcg_matrix *A, mpcg_policy *P, const double *b, double *x, 
   a.G1 = k.G1;
   a.P2 = k.P2;
   a.tier = c.tier;
+  a.pipe = c.pipe;
+  a.w32 = A->d_w32;
+  a.z32 = A->d_z32;
+  a.w64 = A->d_w64;
+  a.z64 = A->d_z64;
 
   const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
   // a start, one slot per iteration, up to two more per replacement, a final check
@@ -602,7 +619,8 @@ static int solve_sr(mpcg_matrix *A, mpcg_policy *P, const double *b, double *x, 
   HIP_TRY(hipStreamSynchronize(st));
   SrCtl &f = A->h_sr[2];
   HIP_TRY(hipMemcpy(&f, A->d_sr + (slots & 1), sizeof(SrCtl), hipMemcpyDeviceToHost));
-  if (f.mode != SR_DONE) return fail(MPCG_ERR_DEVICE, "single-reduction solver did not reach a final state");
+  if (f.mode != SR_DONE)
+    return fail(MPCG_ERR_DEVICE, "single-reduction / pipelined solver did not reach a final state");
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, A->ev_start, A->ev_end));
   std::memset(res, 0, sizeof(*res));
@@ -1048,12 +1066,12 @@ int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *o) {
   if (o->vec16 != 0 && o->vec16 != 1) return fail(MPCG_ERR_INVALID, "vec16 must be 0 or 1");
   if (o->vec16 && (o->precond || o->rho_fp64 || o->emulate))
     return fail(MPCG_ERR_INVALID, "vec16 runs without the preconditioner, fp64 rho and the emulation reading");
-  if (o->variant != 0 && o->variant != 1) return fail(MPCG_ERR_INVALID, "variant must be 0 or 1");
-  if (o->variant == 1 &&
+  if (o->variant < 0 || o->variant > 2) return fail(MPCG_ERR_INVALID, "variant must be 0, 1 or 2");
+  if (o->variant != 0 &&
       (o->fallback || o->precond || o->stop_rule || o->rho_fp64 || o->emulate || o->vec16 || o->profile))
     return fail(MPCG_ERR_INVALID,
-                "the single-reduction variant runs without fallback, precond, stop_rule, rho_fp64, emulate, "
-                "vec16 and profile");
+                "the single-reduction and pipelined variants run without fallback, precond, stop_rule, "
+                "rho_fp64, emulate, vec16 and profile");
   A->opts = *o;
   return MPCG_OK;
 }
@@ -1107,11 +1125,11 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
   if (P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
   if (A->opts.emulate && P->desc.kind == MPCG_POLICY_FIXED && act_fs(P->desc.fixed_action) == FP8)
     return fail(MPCG_ERR_INVALID, "the emulation reading has no q52 SpMV (Table 1's q52 is storage only here)");
-  if (A->opts.variant == 1 && (P->desc.kind != MPCG_POLICY_FIXED || P->desc.fixed_action >= 80))
-    return fail(MPCG_ERR_INVALID, "the single-reduction variant takes a fixed policy with an action 0..79");
+  if (A->opts.variant != 0 && (P->desc.kind != MPCG_POLICY_FIXED || P->desc.fixed_action >= 80))
+    return fail(MPCG_ERR_INVALID, "the single-reduction and pipelined variants take a fixed policy with an action 0..79");
   hipStream_t st = A->stream;
   HIP_TRY(hipStreamSynchronize(st));   // staging buffers below are reused
-  if (A->opts.variant == 1) return solve_sr(A, P, b, x, tol, maxit, res);
+  if (A->opts.variant != 0) return solve_sr(A, P, b, x, tol, maxit, res);
 
   rc = upload_start(A, P, tol, maxit, st);
   if (rc) return rc;

@@ -3021,6 +3021,42 @@ __device__ __forceinline__ void dot_leaf_multi2_rt(int fd, const V (&u)[RPT], co
   }
 }
 
+// y = A_fs x over row group g, rounded to the tier (a second SpMV of a
+// KS1: s = A p, z = A s, w = A r; no partials).
+template <int FS, int TIER>
+__device__ __forceinline__ void sr_spmv_plain(const SrArgs &a, int g, void *lds, const typename TierT<TIER>::type *x,
+                                              typename TierT<TIER>::type *y) {
+  using V = typename TierT<TIER>::type;
+  using Acc = typename AccT<FS>::type;
+  const int n = a.A.n;
+  const int g0 = g * a.grows;
+  const int grows = min(a.grows, n - g0);
+  int8_t ex[kRPT];
+  auto pref = [](int) {};
+  auto pre = [&](int sb) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      ex[j] = 0;
+      if constexpr (FS == FP16 || FS == FP8) {
+        const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+        if (lr < grows) ex[j] = a.A.rexp[g0 + lr];
+      }
+    }
+  };
+  auto epi = [&](int sb, Acc (&acc)[kRPT]) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      if (lr < grows) {
+        if constexpr (FS == FP16 || FS == FP8) y[g0 + lr] = (V)ldexp((double)acc[j], (int)ex[j]);
+        else y[g0 + lr] = (V)acc[j];
+      }
+    }
+  };
+  if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{x}, g0, grows, lds, pref, pre, epi);
+  else spmv_group<FS, false>(a.A, GatherPlain<V>{x}, g0, grows, lds, pref, pre, epi);
+}
+
 // KS1 of an iteration: w = A_fs r over row group g with the group partials
 // of gamma and delta at the dot format; with_s: then s = A_fs p.
 template <int FS, int TIER>
@@ -3091,30 +3127,99 @@ __device__ __forceinline__ void sr_spmv(const SrArgs &a, const SrCtl &S, int g, 
   }
   if (!with_s) return;
   __syncthreads();   // the LDS window is staged again
-  int8_t ex2[kRPT];
-  auto pref2 = [](int) {};
-  auto pre2 = [&](int sb) {
-#pragma unroll
-    for (int j = 0; j < kRPT; ++j) {
-      ex2[j] = 0;
-      if constexpr (FS == FP16 || FS == FP8) {
-        const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
-        if (lr < grows) ex2[j] = a.A.rexp[g0 + lr];
-      }
-    }
-  };
-  auto epi2 = [&](int sb, Acc (&acc)[kRPT]) {
+  sr_spmv_plain<FS, TIER>(a, g, lds, p, sv);
+}
+
+// KS1 of a pipelined iteration: q = A_fs w over row group g with the group
+// partials of gamma = r.r and delta = w.r at the dot format; with_z: then
+// z = A_fs s (the first iteration after a replacement).
+template <int FS, int TIER>
+__device__ __forceinline__ void pc_spmv(const SrArgs &a, const SrCtl &S, int g, void *lds, bool with_z) {
+  using V = typename TierT<TIER>::type;
+  using Acc = typename AccT<FS>::type;
+  const V *r, *w, *sv;
+  V *q, *z;
+  if constexpr (TIER) { r = a.v.r64; w = a.w64; sv = a.s64; q = a.v.q64; z = a.z64; }
+  else { r = a.v.r32; w = a.w32; sv = a.s32; q = a.v.q32; z = a.z32; }
+  const int fd = S.fd;
+  const int n = a.A.n;
+  const int g0 = g * a.grows;
+  const int grows = min(a.grows, n - g0);
+  V ri[kRPT], rn[kRPT], wi[kRPT], wn[kRPT];   // own elements of r and w: current, next sub-block
+  int8_t ex[kRPT];
+  double tg[4] = {0.0, 0.0, 0.0, 0.0}, td[4] = {0.0, 0.0, 0.0, 0.0};
+  auto pref = [&](int sb) {
 #pragma unroll
     for (int j = 0; j < kRPT; ++j) {
       const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
-      if (lr < grows) {
-        if constexpr (FS == FP16 || FS == FP8) sv[g0 + lr] = (V)ldexp((double)acc[j], (int)ex2[j]);
-        else sv[g0 + lr] = (V)acc[j];
+      rn[j] = lr < grows ? r[g0 + lr] : (V)0;
+      wn[j] = lr < grows ? w[g0 + lr] : (V)0;
+    }
+  };
+  auto pre = [&](int sb) {
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      ri[j] = rn[j];
+      wi[j] = wn[j];
+      ex[j] = 0;
+      if constexpr (FS == FP16 || FS == FP8) {
+        if (lr < grows) ex[j] = a.A.rexp[g0 + lr];
       }
     }
   };
-  if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref2, pre2, epi2);
-  else spmv_group<FS, false>(a.A, GatherPlain<V>{p}, g0, grows, lds, pref2, pre2, epi2);
+  auto epi = [&](int sb, Acc (&acc)[kRPT]) {
+    bool valid[kRPT];
+#pragma unroll
+    for (int j = 0; j < kRPT; ++j) {
+      const int lr = sb * kKaRows + threadIdx.x + j * kRowsPerBlock;
+      valid[j] = lr < grows;
+      if (valid[j]) {
+        if constexpr (FS == FP16 || FS == FP8) q[g0 + lr] = (V)ldexp((double)acc[j], (int)ex[j]);
+        else q[g0 + lr] = (V)acc[j];
+      }
+    }
+    double s2g[kRPT], s2d[kRPT];
+    dot_leaf_multi2_rt<kRPT>(fd, ri, ri, wi, valid, s2g, s2d);
+    const double sg = subtrees_rt<kRPT>(fd, s2g);
+    const double sd = subtrees_rt<kRPT>(fd, s2d);
+    tg[0] = sb == 0 ? sg : tg[0];
+    tg[1] = sb == 1 ? sg : tg[1];
+    tg[2] = sb == 2 ? sg : tg[2];
+    tg[3] = sb == 3 ? sg : tg[3];
+    td[0] = sb == 0 ? sd : td[0];
+    td[1] = sb == 1 ? sd : td[1];
+    td[2] = sb == 2 ? sd : td[2];
+    td[3] = sb == 3 ? sd : td[3];
+  };
+  if (a.A.dc) spmv_group<FS, true>(a.A, GatherPlain<V>{w}, g0, grows, lds, pref, pre, epi);
+  else spmv_group<FS, false>(a.A, GatherPlain<V>{w}, g0, grows, lds, pref, pre, epi);
+  if (threadIdx.x == 0) {
+    a.pg[g] = group_tree(fd, a.grows, tg);
+    a.pd[g] = group_tree(fd, a.grows, td);
+  }
+  if (!with_z) return;
+  __syncthreads();
+  sr_spmv_plain<FS, TIER>(a, g, lds, sv, z);
+}
+
+// KS1 after a start or replacement of the pipelined iteration: w = A_fs r,
+// and s = A_fs p unless the next step is the first.
+template <int FS, int TIER>
+__device__ __forceinline__ void pc_sync(const SrArgs &a, const SrCtl &S, int g, void *lds) {
+  if constexpr (TIER) {
+    sr_spmv_plain<FS, 1>(a, g, lds, a.v.r64, a.w64);
+    if (!S.first) {
+      __syncthreads();
+      sr_spmv_plain<FS, 1>(a, g, lds, a.v.p64, a.s64);
+    }
+  } else {
+    sr_spmv_plain<FS, 0>(a, g, lds, a.v.r32, a.w32);
+    if (!S.first) {
+      __syncthreads();
+      sr_spmv_plain<FS, 0>(a, g, lds, a.v.p32, a.s32);
+    }
+  }
 }
 
 // KS1 of a start, replacement or final check: r64 = b - A x in fp64 over row
@@ -3185,12 +3290,41 @@ __device__ __forceinline__ void sr_residual(const SrArgs &a, const SrCtl &S, int
   }
 }
 
+#define MPCG_PC_CASES(FN, ...)                          \
+  switch (S.fs * 2 + S.tier) {                          \
+  case FP16 * 2: FN<FP16, 0>(__VA_ARGS__); break;       \
+  case FP16 * 2 + 1: FN<FP16, 1>(__VA_ARGS__); break;   \
+  case BF16 * 2: FN<BF16, 0>(__VA_ARGS__); break;       \
+  case BF16 * 2 + 1: FN<BF16, 1>(__VA_ARGS__); break;   \
+  case FP32 * 2: FN<FP32, 0>(__VA_ARGS__); break;       \
+  case FP32 * 2 + 1: FN<FP32, 1>(__VA_ARGS__); break;   \
+  case FP64 * 2: FN<FP64, 0>(__VA_ARGS__); break;       \
+  case FP64 * 2 + 1: FN<FP64, 1>(__VA_ARGS__); break;   \
+  case FP8 * 2: FN<FP8, 0>(__VA_ARGS__); break;         \
+  case FP8 * 2 + 1: FN<FP8, 1>(__VA_ARGS__); break;     \
+  default: break;                                       \
+  }
+
+// PIPE: the pipelined iteration's KS1 (a separate kernel, so the
+// single-reduction one keeps its registers).
+template <bool PIPE>
 __global__ __launch_bounds__(kBlock) void k_sr1(SrArgs a) {
   const int g = xcd_group(a.G1);
   if (g >= a.P1) return;
   __shared__ double lds[kLdsKa];
   const SrCtl &S = a.ctl[a.par];
   const int mode = S.mode;
+  if constexpr (PIPE) {
+    if (mode == SR_ITER) {
+      const bool with_z = S.sync && !S.first;
+      MPCG_PC_CASES(pc_spmv, a, S, g, lds, with_z)
+    } else if (mode == PC_W) {
+      MPCG_PC_CASES(pc_sync, a, S, g, lds)
+    } else if (mode == SR_START || mode == SR_RESID || mode == SR_FINAL) {
+      sr_residual(a, S, g, lds);
+    }
+    return;
+  }
   if (mode == SR_ITER || mode == SR_SYNC) {
     const bool with_s = mode == SR_SYNC && !S.first;
     switch (S.fs * 2 + S.tier) {
@@ -3317,7 +3451,7 @@ __device__ __forceinline__ void sr_fold(const SrArgs &a, int base, SrVals<FA> &v
 
 // The state after KS2, identical in every thread.
 struct SrNext {
-  int mode, status, k, nrep;
+  int mode, status, k, nrep, sync;
   bool upd, zero;
   double bnorm, last_true, relres, rho, gamma, alpha;
 };
@@ -3328,6 +3462,7 @@ __device__ __forceinline__ SrNext sr_next_of(const SrCtl &S) {
   x.status = S.status;
   x.k = S.k;
   x.nrep = S.nrep;
+  x.sync = S.sync;
   x.upd = false;
   x.zero = false;
   x.bnorm = S.bnorm;
@@ -3402,6 +3537,177 @@ __device__ __forceinline__ SrNext sr2_iter(const SrArgs &a, const SrCtl &S, int 
   return x;
 }
 
+// The pipelined iteration's KS2 operands of one thread: q, z, w, s, r, p, x_lo.
+template <int FA>
+struct PcVals {
+  using V = typename TierT<FA == FP64>::type;
+  V q[8], z[8], w[8], s[8], r[8], p[8], x[8];
+};
+
+template <int FA>
+struct PcPtr {
+  using V = typename TierT<FA == FP64>::type;
+  V *q, *z, *w, *s, *r, *p, *x;
+  __device__ explicit PcPtr(const SrArgs &a) {
+    if constexpr (FA == FP64) { q = a.v.q64; z = a.z64; w = a.w64; s = a.s64; r = a.v.r64; p = a.v.p64; x = a.v.xlo64; }
+    else { q = a.v.q32; z = a.z32; w = a.w32; s = a.s32; r = a.v.r32; p = a.v.p32; x = a.v.xlo32; }
+  }
+};
+
+template <int FA>
+__device__ __forceinline__ void pc_load(const SrArgs &a, int base, PcVals<FA> &v) {
+  using V = typename PcVals<FA>::V;
+  const PcPtr<FA> P(a);
+  const int n = a.A.n;
+  if (base + 8 <= n) {
+    load8(P.q + base, v.q);
+    load8(P.z + base, v.z);
+    load8(P.w + base, v.w);
+    load8(P.s + base, v.s);
+    load8(P.r + base, v.r);
+    load8(P.p + base, v.p);
+    load8(P.x + base, v.x);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      const bool in = i < n;
+      v.q[j] = in ? P.q[i] : (V)0;
+      v.z[j] = in ? P.z[i] : (V)0;
+      v.w[j] = in ? P.w[i] : (V)0;
+      v.s[j] = in ? P.s[i] : (V)0;
+      v.r[j] = in ? P.r[i] : (V)0;
+      v.p[j] = in ? P.p[i] : (V)0;
+      v.x[j] = in ? P.x[i] : (V)0;
+    }
+  }
+}
+
+// z = q + beta z, s = w + beta s, p = r + beta p (copies on the first step),
+// x_lo += alpha p, r -= alpha s, w -= alpha z; the fold before a replacement.
+template <int FA>
+__device__ __forceinline__ void pc_update(const SrArgs &a, int base, PcVals<FA> &v, double alpha, double beta,
+                                          bool first, bool fold) {
+  using V = typename PcVals<FA>::V;
+  const PcPtr<FA> P(a);
+  const int n = a.A.n;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const V zn = first ? v.q[j] : xpay_rt<V>(FA, beta, v.z[j], v.q[j]);
+    const V sn = first ? v.w[j] : xpay_rt<V>(FA, beta, v.s[j], v.w[j]);
+    const V pn = first ? v.r[j] : xpay_rt<V>(FA, beta, v.p[j], v.r[j]);
+    v.x[j] = axpy1<FA>(alpha, pn, v.x[j]);
+    v.r[j] = axpy1<FA>(-alpha, sn, v.r[j]);
+    v.w[j] = axpy1<FA>(-alpha, zn, v.w[j]);
+    v.z[j] = zn;
+    v.s[j] = sn;
+    v.p[j] = pn;
+  }
+  if (fold) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (base + j < n) fold1(a.v.xhi, base + j, (double)v.x[j]);
+      v.x[j] = (V)0;
+    }
+  }
+  if (base + 8 <= n) {
+    store8(P.z + base, v.z);
+    store8(P.s + base, v.s);
+    store8(P.p + base, v.p);
+    store8(P.x + base, v.x);
+    store8(P.r + base, v.r);
+    store8(P.w + base, v.w);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j;
+      if (i < n) {
+        P.z[i] = v.z[j];
+        P.s[i] = v.s[j];
+        P.p[i] = v.p[j];
+        P.x[i] = v.x[j];
+        P.r[i] = v.r[j];
+        P.w[i] = v.w[j];
+      }
+    }
+  }
+}
+
+// KS2 after a pipelined iteration's KS1: gamma, delta -> rho (replacement or
+// budget test, except on the first iteration after a start or replacement),
+// beta, alpha (breakdown test), then the updates of block blk.
+template <int FA>
+__device__ __forceinline__ SrNext pc2_iter(const SrArgs &a, const SrCtl &S, int blk, const double (&pg)[8],
+                                           const double (&pd)[8], bool fast) {
+  const int base = blk * kVecBlock + threadIdx.x * kVecPer;
+  PcVals<FA> v;
+  const bool live = base < a.A.n;
+  __builtin_amdgcn_sched_barrier(0);
+  if (live) pc_load<FA>(a, base, v);
+  __builtin_amdgcn_sched_barrier(0);
+  SrNext x = sr_next_of(S);
+  const bool writer = blk == 0 && threadIdx.x == 0;
+  const int k = S.k;
+  const int fd = S.fd;
+  const bool first = S.first != 0;
+  const double gamma = fast ? tree_preloaded_rt(fd, pg) : reduce_partials_rt(fd, a.pg, a.P1);
+  const double delta = fast ? tree_preloaded_rt(fd, pd) : reduce_partials_rt(fd, a.pd, a.P1);
+  bool fold = false, go = true;
+  if (!S.sync) {
+    x.rho = sqrt(gamma) / S.bnorm;
+    if (writer) a.h.rho[k] = x.rho;
+    if (x.rho <= S.tol) {
+      fold = true;
+      x.mode = SR_RESID;
+      go = false;
+    } else if (k >= S.maxit) {
+      x.status = 1;
+      fold = true;
+      x.mode = SR_FINAL;
+      go = false;
+    }
+  }
+  double alpha = 0.0, beta = 0.0;
+  if (go) {
+    beta = first ? 0.0 : gamma / S.gamma_old;
+    const double den = first ? delta : delta - beta * gamma / S.alpha_old;
+    alpha = gamma / den;
+    if (!(den > 0.0) || !isfinite(alpha) || !isfinite(beta) || !isfinite(gamma)) {
+      x.status = 3;
+      fold = true;
+      x.mode = SR_FINAL;
+    } else {
+      x.upd = true;
+      x.sync = 0;
+      x.gamma = gamma;
+      x.alpha = alpha;
+      if (writer) {
+        a.h.act[k] = (uint8_t)S.action;
+        a.h.flag[k] = 0;
+      }
+      x.k = k + 1;
+      fold = S.R > 0 && x.k % S.R == 0;
+      x.mode = fold ? SR_RESID : SR_ITER;
+    }
+  }
+  if (live) {
+    if (x.upd) {
+      pc_update<FA>(a, base, v, alpha, beta, first, fold);
+    } else if (fold) {
+      const PcPtr<FA> P(a);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int i = base + j;
+        if (i < a.A.n) {
+          fold1(a.v.xhi, i, (double)v.x[j]);
+          P.x[i] = (typename PcVals<FA>::V)0;
+        }
+      }
+    }
+  }
+  return x;
+}
+
 // KS2 after a start, replacement or final check: the true relres and the
 // stop tests; at the stop the caller's x receives x_hi (or 0 when b = 0).
 __device__ __forceinline__ SrNext sr2_resid(const SrArgs &a, const SrCtl &S, int blk, const double (&pg)[8],
@@ -3439,7 +3745,7 @@ __device__ __forceinline__ SrNext sr2_resid(const SrArgs &a, const SrCtl &S, int
       if (mode == SR_RESID) x.nrep++;
       x.last_true = rt;
       x.rho = rt;
-      x.mode = SR_SYNC;
+      x.mode = S.pipe ? PC_W : SR_SYNC;
       if (rt <= S.tol || !isfinite(rt) || k >= S.maxit) {
         x.status = rt <= S.tol ? 0 : !isfinite(rt) ? 3 : 1;
         x.relres = rt;
@@ -3459,8 +3765,9 @@ __device__ __forceinline__ SrNext sr2_resid(const SrArgs &a, const SrCtl &S, int
 }
 
 // TIER: the container of the action's update format (a fixed action keeps
-// one tier for the whole solve), so the fp32 kernel holds no fp64 operands.
-template <int TIER>
+// one tier for the whole solve), so the fp32 kernel holds no fp64 operands;
+// PIPE: the pipelined iteration.
+template <int TIER, bool PIPE>
 __global__ __launch_bounds__(kBlock) void k_sr2(SrArgs a) {
   __shared__ SrCtl S;
   const int blk = blockIdx.x;
@@ -3474,7 +3781,23 @@ __global__ __launch_bounds__(kBlock) void k_sr2(SrArgs a) {
   __syncthreads();
   const int mode = S.mode;
   SrNext x;
-  if (mode == SR_ITER || mode == SR_SYNC) {
+  if (PIPE && mode == SR_ITER) {
+    if constexpr (PIPE) {
+      if constexpr (TIER) {
+        x = pc2_iter<FP64>(a, S, blk, pg, pd, fast);
+      } else {
+        switch (S.fa) {
+        case FP16: x = pc2_iter<FP16>(a, S, blk, pg, pd, fast); break;
+        case BF16: x = pc2_iter<BF16>(a, S, blk, pg, pd, fast); break;
+        default: x = pc2_iter<FP32>(a, S, blk, pg, pd, fast); break;
+        }
+      }
+    }
+  } else if (PIPE && mode == PC_W) {
+    x = sr_next_of(S);
+    x.mode = SR_ITER;
+    x.sync = 1;
+  } else if (!PIPE && (mode == SR_ITER || mode == SR_SYNC)) {
     if constexpr (TIER) {
       x = sr2_iter<FP64>(a, S, blk, pg, pd, fast);
     } else {
@@ -3499,6 +3822,7 @@ __global__ __launch_bounds__(kBlock) void k_sr2(SrArgs a) {
     S.last_true = x.last_true;
     S.relres_true = x.relres;
     S.rho_new = x.rho;
+    S.sync = x.sync;
     if (x.zero) S.zero_solution = 1;
     if (x.upd) {
       S.gamma_old = x.gamma;
@@ -3511,10 +3835,17 @@ __global__ __launch_bounds__(kBlock) void k_sr2(SrArgs a) {
 }
 
 void launch_sr_slot(const SrArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_sr1, dim3(a.G1), dim3(kBlock), 0, s, a);
-  if (a.tier) hipLaunchKernelGGL(k_sr2<1>, dim3(a.P2), dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL(k_sr2<0>, dim3(a.P2), dim3(kBlock), 0, s, a);
+  if (a.pipe) {
+    hipLaunchKernelGGL(k_sr1<true>, dim3(a.G1), dim3(kBlock), 0, s, a);
+    if (a.tier) hipLaunchKernelGGL((k_sr2<1, true>), dim3(a.P2), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_sr2<0, true>), dim3(a.P2), dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_sr1<false>, dim3(a.G1), dim3(kBlock), 0, s, a);
+    if (a.tier) hipLaunchKernelGGL((k_sr2<1, false>), dim3(a.P2), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_sr2<0, false>), dim3(a.P2), dim3(kBlock), 0, s, a);
+  }
 }
+#undef MPCG_PC_CASES
 #endif  // part 9
 
 }  // namespace mpcg

@@ -133,17 +133,23 @@ struct KArgs {
   int slot;            // index of this slot (with slot_log)
 };
 
-// Single-reduction CG (Chronopoulos and Gear): two launches per iteration.
-// KS1 (row groups, like KA) runs w = A_fs r with the partials of gamma = r.r
-// and delta = r.w, or an fp64 residual; KS2 (vector blocks, like KB) runs the
-// replicated scalar step and the four vector updates.  Phases of a slot:
-enum { SR_START = 0, SR_ITER = 1, SR_SYNC = 2, SR_RESID = 3, SR_FINAL = 4, SR_DONE = 5 };
+// Single-reduction CG (Chronopoulos and Gear) and pipelined CG (Ghysels and
+// Vanroose): two launches per iteration.  KS1 (row groups, like KA) runs the
+// iteration's SpMV (w = A_fs r, or q = A_fs w when pipelined) with the
+// partials of gamma = r.r and delta = r.w, or an fp64 residual; KS2 (vector
+// blocks, like KB) runs the replicated scalar step and the vector updates.
+// Phases of a slot (PC_W: the pipelined iteration's w = A r and s = A p after
+// a start or replacement):
+enum { SR_START = 0, SR_ITER = 1, SR_SYNC = 2, SR_RESID = 3, SR_FINAL = 4, SR_DONE = 5, PC_W = 6 };
 
 struct SrCtl {
   int32_t mode, k, maxit, R;
   int32_t status, nrep, first, tier;   // first: the next update takes beta = 0 (p = r, s = w)
   int32_t action, fs, fd, fa;
-  int32_t zero_solution, pad_[3];
+  int32_t zero_solution;
+  int32_t pipe;     // 1: pipelined CG
+  int32_t sync;     // pipelined: the next iteration is the first after a start or replacement
+  int32_t pad_;
   double tol, bnorm, gamma_old, alpha_old, rho_new, last_true, relres_true, pad2_;
 };
 
@@ -152,12 +158,15 @@ struct SrArgs {
   Vecs v;            // r, p, x_lo in the container of the update format; q holds w = A r
   float *s32;        // s, the recurrence for A p
   double *s64;
+  float *w32, *z32;  // pipelined: w (for A r) and z (for A s) by recurrence; q holds A w
+  double *w64, *z64;
   SrCtl *ctl;        // [2]: slot j's KS1 and KS2 read ctl[j & 1], KS2's workgroup 0 writes ctl[(j + 1) & 1]
   Hist h;
   double *pg, *pd;   // KS1 partials: gamma (or ||r64||^2) and delta (or ||b||^2), one per row group
   int P1, grows, G1, P2;
   int par;           // slot parity
   int tier;          // 1: the update format is fp64 (fp64 containers)
+  int pipe;          // 1: the pipelined iteration's kernels
 };
 
 // One system of a batched solve: its kernel arguments (its own control block,
