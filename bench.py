@@ -578,8 +578,8 @@ def main():
     ap.add_argument("--counters-maxit", type=int, default=5000,
                     help="iteration budget of the counter run's solve")
     ap.add_argument("--counters-fp64", action="store_true", help="counter run with the fp64 action")
-    ap.add_argument("--counters-variant", type=int, choices=[0, 1], default=0,
-                    help="counter run with the single-reduction CG (1)")
+    ap.add_argument("--counters-variant", type=int, choices=[0, 1, 2], default=0,
+                    help="counter run with the single-reduction (1) or pipelined (2) CG")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU only (--gpus {args.gpus} requested); "
@@ -642,7 +642,8 @@ def main():
         pol = pol_fp64 if args.counters_fp64 else pol_mixed
         fs, vb = (M.FP64, 8) if args.counters_fp64 else (M.BF16, 4)
         m.set_policy(pol)
-        m.set_options(replace_period=0 if args.counters_fp64 else 50, fallback=False, variant=args.counters_variant)
+        R = 0 if args.counters_fp64 else 20 if args.counters_variant == 2 else 50
+        m.set_options(replace_period=R, fallback=False, variant=args.counters_variant)
         r = m.solve(bd, xd, tol=tol, maxit=args.counters_maxit)
         print(json.dumps({"counters_run": True, "system": A.name, "n": A.n, "nnz": A.nnz,
                           "action": "fp64" if args.counters_fp64 else "mixed", "variant": args.counters_variant,
