@@ -21,6 +21,7 @@
 // order every hand-off.  Policies whose step writes shared state (Q-learning
 // updates, rollout logs) or evaluates the MLP run each step once, in a
 // one-block kernel (KS) before KB and before KX.  The host only enqueues launches.
+// Part 9 holds two-launch variants of the iteration for fixed actions.
 #include <hip/hip_ext.h>
 
 #include <mutex>
@@ -31,8 +32,9 @@
 // plain SpMV kernel (1), the plain KB kernels (2), the preconditioned and
 // fp64-rho KB kernels (3, 6), everything else with every host launcher (4),
 // the batched kernels (5), the tf32 / emulation / bf16-vector variants of
-// the SpMV (7) and of KB (8), and the single-reduction CG with its launcher
-// (9).  Without MPCG_KPART it is one object holding all of them.
+// the SpMV (7) and of KB (8), and the single-reduction and pipelined CG with
+// their launcher (9).  Without MPCG_KPART it is one object holding all of
+// them.
 #ifndef MPCG_KPART
 #define MPCG_KPART 0
 #endif
@@ -2982,11 +2984,16 @@ void launch_policy_decide(const PolicyDev *P, int m, const int64_t *k, const dou
 // the main solver) and the same vector traffic: KS1 reads r and writes w,
 // KS2 reads r, w, p, s, x_lo and writes p, s, x_lo, r.  A true-residual
 // replacement folds x_lo into x_hi (in the KS2 before it), replaces r by
-// rd(b - A x_hi), and the KS1 after it also recomputes s = A p.  Fixed
-// actions of the four-format set and q52 storage; no policy, fallback or
-// preconditioner.  Every workgroup of KS2 runs the scalar step identically
-// from KS1's partials; workgroup 0 commits the state to the other half of
-// the double buffer and writes the histories.
+// rd(b - A x_hi), and the KS1 after it also recomputes s = A p.
+// Pipelined CG (Ghysels and Vanroose, 2014), the PIPE kernels: w = A r and
+// z = A s are recurrences too, KS1 runs q = A w with the partials of r.r and
+// w.r, KS2 the six updates z = q + beta z, s = w + beta s, p = r + beta p,
+// x_lo += alpha p, r -= alpha s, w -= alpha z; after a start or replacement
+// a sync phase computes w = A r and s = A p, and the next KS1 also z = A s.
+// Both: fixed actions of the four-format set and q52 storage; no policy,
+// fallback or preconditioner.  Every workgroup of KS2 runs the scalar step
+// identically from KS1's partials; workgroup 0 commits the state to the
+// other half of the double buffer and writes the histories.
 // ---------------------------------------------------------------------------
 
 // The subtree sums of two dots over the same rows, u.v1 and u.v2, in one LDS
