@@ -1127,6 +1127,8 @@ int mpcg_solve(mpcg_matrix *A, const double *b, double *x, double tol, int32_t m
     return fail(MPCG_ERR_INVALID, "the emulation reading has no q52 SpMV (Table 1's q52 is storage only here)");
   if (A->opts.variant != 0 && (P->desc.kind != MPCG_POLICY_FIXED || P->desc.fixed_action >= 80))
     return fail(MPCG_ERR_INVALID, "the single-reduction and pipelined variants take a fixed policy with an action 0..79");
+  if (A->opts.variant != 0 && P->roll_cap > 0)
+    return fail(MPCG_ERR_INVALID, "the single-reduction and pipelined variants log no rollouts");
   hipStream_t st = A->stream;
   HIP_TRY(hipStreamSynchronize(st));   // staging buffers below are reused
   if (A->opts.variant != 0) return solve_sr(A, P, b, x, tol, maxit, res);

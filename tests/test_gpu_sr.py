@@ -154,3 +154,8 @@ def test_refusals(M, variant):
     m.set_policy(M.Policy(kind=M.POLICY_FIXED, fixed_action=26))
     with pytest.raises(M.MPCGError):
         M.solve_batched([(m, b, x)], tol=1e-8, maxit=100)
+    logging = M.Policy(kind=M.POLICY_FIXED, fixed_action=26)
+    logging.rollouts_enable(64)
+    m.set_policy(logging)
+    with pytest.raises(M.MPCGError):
+        m.solve(b, x, tol=1e-8, maxit=100)
