@@ -587,8 +587,9 @@ static int solve_sr(mpcg_matrix *A, mpcg_policy *P, const double *b, double *x, 
   a.z64 = A->d_z64;
 
   const int chunk = A->opts.chunk > 0 ? A->opts.chunk : 32;
-  // a start, one slot per iteration, up to two more per replacement, a final check
-  const int64_t max_slots = 3 * (int64_t)maxit + 16;
+  // a start, one slot per iteration, up to two more per replacement (three
+  // when pipelined: the sync phase), a final check
+  const int64_t max_slots = (pipe ? 4 : 3) * (int64_t)maxit + 16;
   int64_t slots = 0;
   int ci = 0;
   ChunkPlan plan{chunk, tol};
