@@ -320,6 +320,9 @@ int mpcg_residual_thresholds(int32_t b_res, double eps_min, double *out);
  * mpcg_residual_thresholds.  Errors: MPCG_ERR_INVALID for a bad kind, action,
  * bin parameter or eps_min. */
 int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out);
+/* Waits for the solves on the streams of the matrices the policy is set on,
+ * and detaches it from them (they fall back to their default fixed fp64
+ * policy). */
 int mpcg_policy_destroy(mpcg_policy *P);
 /* Host double[n_states*64] in/out, n_states = b_res*b_it*2. */
 int mpcg_policy_set_qtable(mpcg_policy *P, const double *q);
@@ -347,7 +350,9 @@ int mpcg_policy_rollouts_reset(mpcg_policy *P);
 int mpcg_policy_decide(mpcg_policy *P, int32_t m, const int64_t *k, const double *rho,
                        const int32_t *stag, const float *feat, int32_t *state, int32_t *action);
 
-/* Attaches a policy (not owned; must outlive the solves).  NULL: fixed fp64. */
+/* Attaches a policy (not owned; must outlive the solves).  NULL: fixed fp64.
+ * The policy's table and log calls wait for the streams of the matrices it is
+ * attached to; mpcg_destroy of a matrix detaches it. */
 int mpcg_set_policy(mpcg_matrix *A, mpcg_policy *P);
 int mpcg_set_options(mpcg_matrix *A, const mpcg_solve_opts *opts);
 

@@ -17,6 +17,7 @@
 #include <tuple>
 #include <new>
 #include <numeric>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -193,6 +194,7 @@ int residual_thresholds(int b_res, double eps_min, double *out) {
 // ---------------------------------------------------------------------------
 struct mpcg_policy {
   mpcg_policy_desc desc{};
+  std::set<mpcg_matrix *> users;   // matrices whose mpcg_set_policy attached this policy
   double edges[kMaxEdges] = {};   // residual-bin thresholds derived from b_res, eps_min
   int n_states = 0;
   double *d_q = nullptr;
@@ -361,6 +363,16 @@ struct mpcg_matrix {
     if (defpol) { defpol->release(); delete defpol; defpol = nullptr; }
   }
 };
+
+// Waits for the work on the streams of the matrices a policy is attached to
+// (a policy's tables and logs are written by their solves).
+static int sync_users(mpcg_policy *P) {
+  for (mpcg_matrix *A : P->users) {
+    const hipError_t e = hipStreamSynchronize(A->stream);
+    if (e != hipSuccess) return fail(MPCG_ERR_DEVICE, std::string("policy sync: ") + hipGetErrorString(e));
+  }
+  return MPCG_OK;
+}
 
 static void default_desc(mpcg_policy_desc *d) {
   std::memset(d, 0, sizeof(*d));
@@ -800,6 +812,7 @@ int mpcg_create_csr(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
 int mpcg_destroy(mpcg_matrix *A) {
   if (!A) return MPCG_OK;
   if (A->stream) (void)hipStreamSynchronize(A->stream);
+  if (A->pol) A->pol->users.erase(A);
   A->release();
   delete A;
   return MPCG_OK;
@@ -897,7 +910,9 @@ int mpcg_policy_create(const mpcg_policy_desc *desc, mpcg_policy **out) {
 
 int mpcg_policy_destroy(mpcg_policy *P) {
   if (!P) return MPCG_OK;
-  (void)hipDeviceSynchronize();
+  (void)sync_users(P);
+  for (mpcg_matrix *A : P->users) A->pol = nullptr;   // back to the matrix's default policy
+  P->users.clear();
   P->release();
   delete P;
   return MPCG_OK;
@@ -930,7 +945,10 @@ int mpcg_policy_set_qtable(mpcg_policy *P, const double *q) {
 
 int mpcg_policy_get_qtable(mpcg_policy *P, double *q) {
   if (!P || !q) return fail(MPCG_ERR_INVALID, "NULL argument");
-  HIP_TRY(hipDeviceSynchronize());
+  {
+    const int rc = sync_users(P);
+    if (rc) return rc;
+  }
   HIP_TRY(hipMemcpy(q, P->d_q, sizeof(double) * (size_t)P->n_states * kNAct, hipMemcpyDeviceToHost));
   return MPCG_OK;
 }
@@ -962,7 +980,10 @@ int mpcg_policy_set_mlp(mpcg_policy *P, const float *W1, const float *b1, const 
 
 int mpcg_policy_rollouts_enable(mpcg_policy *P, int32_t capacity) {
   if (!P || capacity < 0) return fail(MPCG_ERR_INVALID, "bad argument");
-  HIP_TRY(hipDeviceSynchronize());
+  {
+    const int rc = sync_users(P);
+    if (rc) return rc;
+  }
   dfree(P->d_rf); dfree(P->d_rn); dfree(P->d_rr); dfree(P->d_ra); dfree(P->d_rd);
   P->roll_cap = 0;
   if (capacity > 0) {
@@ -979,7 +1000,10 @@ int mpcg_policy_rollouts_enable(mpcg_policy *P, int32_t capacity) {
 
 int mpcg_policy_rollouts_count(mpcg_policy *P, int32_t *n) {
   if (!P || !n) return fail(MPCG_ERR_INVALID, "NULL argument");
-  HIP_TRY(hipDeviceSynchronize());
+  {
+    const int rc = sync_users(P);
+    if (rc) return rc;
+  }
   HIP_TRY(hipMemcpy(n, P->d_rcount, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (*n > P->roll_cap) *n = P->roll_cap;
   return MPCG_OK;
@@ -987,7 +1011,10 @@ int mpcg_policy_rollouts_count(mpcg_policy *P, int32_t *n) {
 
 int mpcg_policy_rollouts_reset(mpcg_policy *P) {
   if (!P) return fail(MPCG_ERR_INVALID, "P is NULL");
-  HIP_TRY(hipDeviceSynchronize());
+  {
+    const int rc = sync_users(P);
+    if (rc) return rc;
+  }
   HIP_TRY(hipMemset(P->d_rcount, 0, sizeof(int32_t)));
   return MPCG_OK;
 }
@@ -1050,7 +1077,9 @@ int mpcg_policy_decide(mpcg_policy *P, int32_t m, const int64_t *k, const double
 int mpcg_set_policy(mpcg_matrix *A, mpcg_policy *P) {
   if (!A) return fail(MPCG_ERR_INVALID, "A is NULL");
   if (P && P->desc.kind == MPCG_POLICY_MLP && !P->has_mlp) return fail(MPCG_ERR_INVALID, "MLP policy has no weights");
+  if (A->pol) A->pol->users.erase(A);
   A->pol = P;
+  if (P) P->users.insert(A);
   return MPCG_OK;
 }
 
