@@ -446,6 +446,23 @@ class Matrix:
         self.h = h
         self.policy = None
 
+    @classmethod
+    def from_device(cls, row_ptr, col, val, stream=None) -> "Matrix":
+        """A CSR matrix whose arrays are already on the device: torch tensors
+        (int32 row_ptr[n+1], int32 col[nnz], float64 val[nnz], contiguous)."""
+        for t, dt in ((row_ptr, "torch.int32"), (col, "torch.int32"), (val, "torch.float64")):
+            assert t.is_cuda and t.is_contiguous() and str(t.dtype) == dt, "device CSR arrays of the stated types"
+        self = cls.__new__(cls)
+        self.n = int(row_ptr.numel()) - 1
+        self.nnz = int(col.numel())
+        self._stream = stream
+        h = C.c_void_p()
+        _check(lib().mpcg_create_csr(self.n, self.nnz, _t_ptr(row_ptr), _t_ptr(col), _t_ptr(val), 1,
+                                     _stream_handle(stream), C.byref(h)), "mpcg_create_csr")
+        self.h = h
+        self.policy = None
+        return self
+
     def close(self):
         if getattr(self, "h", None) and _lib is not None:
             lib().mpcg_destroy(self.h)
