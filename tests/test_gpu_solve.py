@@ -277,5 +277,7 @@ def test_full_size_first_iterations(M, which):
     m = M.Matrix(A)
     p = np.random.default_rng(5).standard_normal(A.n).astype(np.float32)
     q = torch.empty(A.n, dtype=torch.float32, device="cuda")
-    m.op_spmv(M.BF16, 0, torch.from_numpy(p).cuda(), q)
-    assert np.array_equal(q.cpu().numpy(), O.spmv(A, p.astype(np.float64), O.BF16, False).astype(np.float32))
+    # the benchmark's bf16 storage, and fp16 and q52 with their row scales
+    for fmt in (M.BF16, M.FP16, M.Q52):
+        m.op_spmv(fmt, 0, torch.from_numpy(p).cuda(), q)
+        assert np.array_equal(q.cpu().numpy(), O.spmv(A, p.astype(np.float64), fmt, False).astype(np.float32)), fmt
