@@ -921,6 +921,27 @@ def main():
         out["random_spd"]["jacobi"] = {**pj, "speedup_vs_fp64_jacobi": round(pj["fp64"]["ms"] / pj["mixed"]["ms"], 3),
                                        "speedup_vs_unpreconditioned_fp64": round(rr["fp64"]["ms"] / pj["mixed"]["ms"], 1)}
 
+    # the small fp64 case: plain fp64 CG on the 2D 5-point Laplacian 64x64
+    # (n = 4096), b ~ U[-1,1] seed 1, x0 = 0, tol 1e-8, maxit 2000; at this
+    # size an iteration is launch-bound, which the two-launch variant shows
+    S = W.laplacian_2d(64)
+    msm = M.Matrix(S)
+    bsm = torch.from_numpy(W.rhs(S.n, 1)).cuda()
+    small = {"n": S.n, "nnz": S.nnz}
+    for name, variant in (("three_launch", 0), ("single_reduction", 1)):
+        msm.set_policy(pol_fp64)
+        msm.set_options(replace_period=0, fallback=False, variant=variant)
+        runs = []
+        for _ in range(4):
+            xsm = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+            runs.append(msm.solve(bsm, xsm, tol=1e-8, maxit=2000))
+        r = runs[-1]
+        ms_small = float(np.median([q["time_ms"] for q in runs[1:]]))
+        small[name] = {"ms": round(ms_small, 3), "iters": r["iters"], "status": r["status"],
+                       "relres_true": r["relres_true"], "us_per_iteration": round(1e3 * ms_small / max(1, r["iters"]), 2)}
+    log(f"[bench] 2D Laplacian 64^2 fp64: {small}")
+    out["laplacian_2d_64_fp64"] = small
+
     if not args.no_cpu:
         import oracle as O
 
