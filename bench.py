@@ -485,6 +485,17 @@ def qlearning_experiment(args, M, W, torch) -> dict:
         g = M.Policy(kind=M.POLICY_QTABLE, cost=cost_table(cost), decision_period=D, per_op=per_op)
         g.set_qtable(P.qtable())
         greedy[lab] = g
+        if args.spmv_only and per_op == 1:
+            # the learned SpMV table; the dot and update tables masked so that
+            # their greedy choice is fp32 (columns 4 + d and 8 + d of a row)
+            q = P.qtable().copy()
+            for j in (1, 2):
+                for d in range(4):
+                    if d != M.FP32:
+                        q[:, 4 * j + d] = -1e300
+            gm = M.Policy(kind=M.POLICY_QTABLE, cost=cost_table(cost), decision_period=D, per_op=per_op)
+            gm.set_qtable(q)
+            greedy[lab + "_spmv_only"] = gm
     labels = ["fp64", "fixed_mixed"] + [f"learned_{lab}" for lab in greedy]
     rows = []
     for sd in held:
@@ -546,6 +557,9 @@ def main():
                          "or Chw, the cost per format measured on this GPU; D the decision period; per_op 1 for "
                          "one Q-table per operation); default: C1 and C2 with section 4.1's weights, a joint "
                          "table, decisions every iteration")
+    ap.add_argument("--spmv-only", action="store_true",
+                    help="with per-operation tables: also evaluate each learned SpMV table with the dot and "
+                         "update tables masked to fp32 (a labelled variation)")
     ap.add_argument("--heldout-n-hi", type=float, default=5e5, help="largest held-out system size")
     ap.add_argument("--heldout-seed0", type=int, default=2000, help="first held-out seed of the MLP experiment")
     ap.add_argument("--paper", action="store_true",
