@@ -321,6 +321,24 @@ def mlp_experiment(args, M, W, torch) -> dict:
     pols = {"fp64": M.Policy(kind=M.POLICY_FIXED, fixed_action=63),
             "fixed_mixed": M.Policy(kind=M.POLICY_FIXED, fixed_action=M.action(M.BF16, M.FP32, M.FP32)),
             "qtable": greedy, "mlp_untrained": untrained, "mlp": mlp_pol}
+    if args.spmv_only:
+        # labelled variation: the learned choice restricted to the SpMV format,
+        # dots and updates in fp32 (the other actions masked: -2^100 on the
+        # network's output bias, -1e300 in the table)
+        keep = [M.action(fs, M.FP32, M.FP32) for fs in (M.FP16, M.BF16, M.FP32, M.FP64)]
+        masked = np.ones(64, dtype=bool)
+        masked[keep] = False
+        pm = net.params()
+        pm["b3"] = pm["b3"].copy()
+        pm["b3"][masked] = np.float32(-2.0 ** 100)
+        mlp_sp = M.Policy(kind=M.POLICY_MLP)
+        M.Mlp(pm).to_policy(mlp_sp)
+        q = P.qtable().copy()
+        q[:, masked] = -1e300
+        q_sp = M.Policy(kind=M.POLICY_QTABLE, cost="C1")
+        q_sp.set_qtable(q)
+        pols["qtable_spmv_only"] = q_sp
+        pols["mlp_spmv_only"] = mlp_sp
     s0 = args.heldout_seed0
     out["heldout"] = {"seeds": [s0, s0 + args.heldout_systems - 1], "n_hi": args.heldout_n_hi,
                       "maxit": args.eval_maxit}
@@ -558,8 +576,9 @@ def main():
                          "one Q-table per operation); default: C1 and C2 with section 4.1's weights, a joint "
                          "table, decisions every iteration")
     ap.add_argument("--spmv-only", action="store_true",
-                    help="with per-operation tables: also evaluate each learned SpMV table with the dot and "
-                         "update tables masked to fp32 (a labelled variation)")
+                    help="also evaluate the learned policies restricted to the SpMV format, dots and updates "
+                         "masked to fp32 (a labelled variation; per-operation tables in --qlearning, the "
+                         "joint table and the network in --mlp)")
     ap.add_argument("--heldout-n-hi", type=float, default=5e5, help="largest held-out system size")
     ap.add_argument("--heldout-seed0", type=int, default=2000, help="first held-out seed of the MLP experiment")
     ap.add_argument("--paper", action="store_true",
