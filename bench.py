@@ -902,6 +902,26 @@ def main():
                           "action_mix": mix_of(M, h["actions"]),
                           "speedup_vs_fp64": round(fp64_ms / float(np.median([r["time_ms"] for r in lr_runs[1:]])), 3)}
         log(f"[bench] learned: {out['learned']}")
+        # the same table restricted to the SpMV format (dots and updates in
+        # fp32; the other actions masked), a labelled variation
+        keep = [M.action(fs, M.FP32, M.FP32) for fs in (M.FP16, M.BF16, M.FP32, M.FP64)]
+        qm = P_l.qtable().copy()
+        qm[:, [a for a in range(64) if a not in keep]] = -1e300
+        gm = M.Policy(kind=M.POLICY_QTABLE, cost="C1")
+        gm.set_qtable(qm)
+        m.set_policy(gm)
+        m.set_options(replace_period=50, fallback=True)
+        sp_runs = []
+        for _ in range(max(1, args.steps // 2) + 1):
+            xd.zero_()
+            sp_runs.append(m.solve(bd, xd, tol=tol, maxit=5000))
+        rs = sp_runs[-1]
+        ms_sp = float(np.median([r["time_ms"] for r in sp_runs[1:]]))
+        out["learned"]["spmv_only"] = {"policy": "the same table, SpMV format learned, dots and updates in fp32",
+                                       "ms": round(ms_sp, 3), "iters": rs["iters"], "status": rs["status"],
+                                       "relres_true": rs["relres_true"], "action_mix": mix_of(M, m.history()["actions"]),
+                                       "speedup_vs_fp64": round(fp64_ms / ms_sp, 3)}
+        log(f"[bench] learned, SpMV only: {out['learned']['spmv_only']}")
         m.set_policy(pol_mixed)
 
     if not args.no_rspd:
