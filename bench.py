@@ -503,14 +503,19 @@ def qlearning_experiment(args, M, W, torch) -> dict:
         g = M.Policy(kind=M.POLICY_QTABLE, cost=cost_table(cost), decision_period=D, per_op=per_op)
         g.set_qtable(P.qtable())
         greedy[lab] = g
-        if args.spmv_only and per_op == 1:
-            # the learned SpMV table; the dot and update tables masked so that
-            # their greedy choice is fp32 (columns 4 + d and 8 + d of a row)
+        if args.spmv_only and per_op in (0, 1):
             q = P.qtable().copy()
-            for j in (1, 2):
-                for d in range(4):
-                    if d != M.FP32:
-                        q[:, 4 * j + d] = -1e300
+            if per_op == 1:
+                # the learned SpMV table; the dot and update tables masked so
+                # that their greedy choice is fp32 (columns 4 + d and 8 + d)
+                for j in (1, 2):
+                    for d in range(4):
+                        if d != M.FP32:
+                            q[:, 4 * j + d] = -1e300
+            else:
+                # the joint table restricted to the four (f_s, fp32, fp32) actions
+                keep = [M.action(fs, M.FP32, M.FP32) for fs in (M.FP16, M.BF16, M.FP32, M.FP64)]
+                q[:, [a for a in range(64) if a not in keep]] = -1e300
             gm = M.Policy(kind=M.POLICY_QTABLE, cost=cost_table(cost), decision_period=D, per_op=per_op)
             gm.set_qtable(q)
             greedy[lab + "_spmv_only"] = gm
@@ -577,8 +582,8 @@ def main():
                          "table, decisions every iteration")
     ap.add_argument("--spmv-only", action="store_true",
                     help="also evaluate the learned policies restricted to the SpMV format, dots and updates "
-                         "masked to fp32 (a labelled variation; per-operation tables in --qlearning, the "
-                         "joint table and the network in --mlp)")
+                         "masked to fp32 (a labelled variation; the joint and per-operation tables in "
+                         "--qlearning, the joint table and the network in --mlp)")
     ap.add_argument("--heldout-n-hi", type=float, default=5e5, help="largest held-out system size")
     ap.add_argument("--heldout-seed0", type=int, default=2000, help="first held-out seed of the MLP experiment")
     ap.add_argument("--paper", action="store_true",
